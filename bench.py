@@ -1,0 +1,176 @@
+"""Benchmark: biofilm-flow time step on one MI355X.
+
+A step is the whole hot path over one 4096 x 4096 grid in float64: the
+Flory-Huggins right-hand side, the Cahn-Hilliard solve (13-point operator,
+MG-preconditioned CG to rtol 1e-10, stopping at the float64 floor), the
+pressure right-hand side, the pressure Poisson solve (5-point operator,
+MG-preconditioned CG to rtol 1e-10) and the velocity correction.  Inputs are
+synthetic (seeded initial biofilm and inflow) and resident in HBM before the
+timed region.
+
+Prints one JSON line.  `value` is the device time per step (ms, lower is
+better).  `roofline` covers the 13-point stencil SpMV (y = x + c L^2 x) timed
+with HIP events on the grid's stream over back-to-back launches on rotating
+buffers (so the 256 MB last-level cache cannot hold the working set).
+`cpu_baseline` times the CPU oracle on a bounded sample of the same workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 4096]
+       [--no-cpu-baseline] [--spmv-only] [--steps-only]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import paper_1811_11842_amd as bf  # noqa: E402
+import synthetic as S  # noqa: E402
+
+METRIC = "solve time/step + stencil SpMV HBM GB/s at 4096², mixed vs FP64 @1e-10"
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=4096)
+    ap.add_argument("--spmv-reps", type=int, default=100)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--spmv-only", action="store_true")
+    ap.add_argument("--steps-only", action="store_true")
+    return ap.parse_args()
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def time_steps(g, n, steps, warmup):
+    dev = g.device
+    phi0 = S.initial_phi(n)
+    u0, v0 = S.inflow_velocity(n)
+    prm = bf.make_params(**S.DEFAULT_PARAMS)
+    phi = torch.from_numpy(phi0).to(dev)
+    us, vs = torch.from_numpy(u0).to(dev), torch.from_numpy(v0).to(dev)
+    p, u, v = g.field(0.0), g.field(0.0), g.field(0.0)
+    oc = bf.default_opts(bf.OP_CH, rtol=1e-10)
+    op = bf.default_opts(bf.OP_LAP, rtol=1e-10)
+    for k in range(warmup):
+        st = g.step(prm, phi, us, vs, p, u, v, oc, op)
+        log(f"warmup step {k}: CH {st[0].as_dict()} P {st[1].as_dict()}")
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    stats = []
+    t0 = time.perf_counter()
+    e0.record()
+    for k in range(steps):
+        st = g.step(prm, phi, us, vs, p, u, v, oc, op)
+        stats.append(st)
+        log(f"step {k}: CH it={st[0].iters} {bf.STATUS_NAMES[st[0].status]} "
+            f"res={st[0].rel_res_true:.2e} {st[0].ms:.2f} ms | P it={st[1].iters} "
+            f"res={st[1].rel_res_true:.2e} {st[1].ms:.2f} ms")
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    return ms / steps, wall / steps * 1e3, stats
+
+
+def time_spmv(g, n, reps):
+    """Average duration of the 13-point operator kernel over `reps` launches."""
+    dev = g.device
+    nbuf = 4
+    xs = [torch.from_numpy(S.random_field(n, 50 + k)).to(dev) for k in range(nbuf)]
+    ys = [g.field() for _ in range(nbuf)]
+    c = S.DEFAULT_PARAMS["dt"] * S.DEFAULT_PARAMS["M"] * S.DEFAULT_PARAMS["kappa"]
+    for k in range(nbuf):
+        g.apply(bf.OP_CH, c, xs[k], ys[k])
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for r in range(reps):
+        g.apply(bf.OP_CH, c, xs[r % nbuf], ys[r % nbuf])
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def cpu_baseline(n, steps):
+    import oracle  # the CPU oracle, timed as it stands
+    phi = S.initial_phi(n)
+    u, v = S.inflow_velocity(n)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        phi, p, uu, vv = oracle.step.step(phi, u, v, **S.DEFAULT_PARAMS)
+    dt = time.perf_counter() - t0
+    return dt / steps * 1e3
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {a.gpus}); this build has no "
+              "multi-GPU path", file=sys.stderr)
+        sys.exit(2)
+    torch.cuda.set_device(0)
+    n = a.n
+    npts = (n + 1) * n
+    out = {"metric": METRIC, "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+           "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64", "data": "synthetic"}
+    with bf.Grid(n) as g:
+        if not a.spmv_only:
+            ms_step, wall_ms, stats = time_steps(g, n, a.steps, a.warmup)
+            it_ch = [s[0].iters for s in stats]
+            it_p = [s[1].iters for s in stats]
+            out.update({
+                "value": round(ms_step, 4), "unit": "ms/step", "ms_per_step": round(ms_step, 4),
+                "wall_ms_per_step": round(wall_ms, 4),
+                "ch_iters_mean": float(np.mean(it_ch)), "p_iters_mean": float(np.mean(it_p)),
+                "ch_solve_ms_mean": float(np.mean([s[0].ms for s in stats])),
+                "p_solve_ms_mean": float(np.mean([s[1].ms for s in stats])),
+                "ch_status": sorted({bf.STATUS_NAMES[s[0].status] for s in stats}),
+                "p_status": sorted({bf.STATUS_NAMES[s[1].status] for s in stats}),
+                "ch_rel_res_true_max": float(max(s[0].rel_res_true for s in stats)),
+                "p_rel_res_true_max": float(max(s[1].rel_res_true for s in stats)),
+            })
+        if not a.steps_only:
+            t_spmv = time_spmv(g, n, a.spmv_reps)
+            traffic = 16.0 * npts      # algorithmic: read x once, write y once (float64)
+            gbs = traffic / (t_spmv * 1e-3) / 1e9
+            out["spmv_us"] = round(t_spmv * 1e3, 3)
+            out["spmv_gbs"] = round(gbs, 1)
+            out["roofline"] = {"kernel": "k_apply<1> (13-point Cahn-Hilliard SpMV, float64)",
+                               "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+                               "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+                               "traffic": None, "algorithmic_bytes": int(traffic)}
+    out["config"] = {"workload": f"{n}x{n} grid, float64 step: Flory-Huggins RHS + MG-PCG "
+                                 f"Cahn-Hilliard solve + MG-PCG pressure solve + velocity "
+                                 f"correction, rtol 1e-10",
+                     "n": n, "rows": n + 1, "cols": n, "points": npts,
+                     "dt": S.DEFAULT_PARAMS["dt"], "kappa": S.DEFAULT_PARAMS["kappa"],
+                     "chi": S.DEFAULT_PARAMS["chi"], "Npoly": S.DEFAULT_PARAMS["Npoly"]}
+    if not a.no_cpu_baseline and not a.spmv_only:
+        log(f"cpu baseline: {a.cpu_steps} oracle steps at {n}x{n}")
+        cms = cpu_baseline(n, a.cpu_steps)
+        out["cpu_baseline"] = {"value": round(cms, 1), "unit": "ms/step", "cores": 1,
+                               "kind": "oracle",
+                               "sample": f"{a.cpu_steps} oracle steps at {n}x{n} (numpy/scipy "
+                                         f"float64, spectral solves, scipy.fft default single "
+                                         f"worker)"}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

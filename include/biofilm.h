@@ -1,0 +1,190 @@
+/*
+ * biofilm.h -- C ABI of the MI355X (gfx950) solver for the per-step linear
+ * systems of the 2D modified Cahn-Hilliard / Flory-Huggins biofilm-flow model
+ * (McClanahan, Stegmeier, Sundermann, Doom, Kimn: "Parallel Simulations of
+ * Biofilm Flow using the Modified Cahn-Hilliard Equation", arXiv:1811.11842).
+ *
+ * The paper discretises the model on a uniform vertex grid (Sec. 4: nodes
+ * (i*dx, j*dy)), periodic in x and no-flux in y with two ghost layers given by
+ * even reflection (Sec. 4, eq. discreteBC), which yields a sequence of sparse
+ * systems A x = b solved by a preconditioned Krylov method (Sec. 4.1).  This
+ * library holds the grid, applies the operators matrix-free and solves those
+ * systems on one GPU.
+ *
+ * Conventions shared by every entry point
+ *  - Grid: n intervals per side (n a power of two, 4 <= n <= 32768), h = 1/n.
+ *    A field is a contiguous row-major float64 array of (n+1) rows by n
+ *    columns, element (j, i) at offset j*n + i: row j = y-node j (0..n),
+ *    column i = x-node i (0..n-1; node n is the periodic image of node 0).
+ *  - Field pointers are DEVICE pointers owned by the caller.  The library never
+ *    frees them and keeps no reference after a call returns.  Inputs and
+ *    outputs must not alias unless an argument is documented as in/out.
+ *  - All work is enqueued on the stream given at grid creation.  bf_apply,
+ *    bf_ch_rhs, bf_pressure_rhs, bf_velocity_correct, bf_vcycle, bf_restrict
+ *    and bf_prolong_add are asynchronous; the solves and bf_step return after
+ *    the device work has finished (they read convergence scalars).
+ *  - Inner products, norms and means use the trapezoid weights w_j = 1/2 on
+ *    the wall rows j = 0 and j = n, 1 elsewhere; the reflected operators are
+ *    self-adjoint in that inner product.
+ *  - Return value: BF_OK (0); a positive "soft" status (outputs hold the best
+ *    iterate, stats are filled); or a negative error (outputs unspecified,
+ *    bf_last_error() describes it).  A grid handle is not thread-safe.
+ */
+#ifndef BIOFILM_H
+#define BIOFILM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bf_grid bf_grid;
+
+enum bf_status {
+  BF_OK = 0,
+  BF_NOT_CONVERGED = 1,   /* maxit reached before the tolerance            */
+  BF_AT_FLOOR = 2,        /* true residual stagnated above rtol at the     */
+                          /* float64 rounding floor of the operator        */
+  BF_EINVAL = -1,         /* bad argument (null pointer, n, option value)  */
+  BF_ENOMEM = -2,         /* device allocation failed                      */
+  BF_EHIP = -3,           /* HIP runtime error                             */
+  BF_ENONFINITE = -4,     /* NaN/Inf met in a residual norm                */
+  BF_EUNSUPPORTED = -5    /* entry point or option not available           */
+};
+
+enum { BF_F64 = 0 };
+enum { BF_OP_LAP = 0, BF_OP_CH = 1 };
+enum { BF_KSP_CG = 0, BF_KSP_GMRES = 1 };
+enum { BF_PC_NONE = 0, BF_PC_JACOBI = 1, BF_PC_MG = 2 };
+enum { BF_SMOOTH_CHEBYSHEV = 0, BF_SMOOTH_JACOBI = 1 };
+
+/* Grid description (the paper's DMDA object of Sec. 4.1, Listing "Initializing
+ * a 2D DMDA object": periodic x, reflected y, stencil width 2, one dof). */
+typedef struct {
+  int32_t n;        /* intervals per side, power of two, 4..32768          */
+  int32_t dtype;    /* BF_F64                                              */
+  void*   stream;   /* hipStream_t all work is enqueued on (0 = default)    */
+} bf_grid_desc;
+
+/* Krylov / preconditioner choice (Sec. 4.1, Listing "Creating PETSc KSP and
+ * PC objects": GMRES + Jacobi in the paper; CG + multigrid by default here). */
+typedef struct {
+  int32_t ksp;          /* BF_KSP_CG or BF_KSP_GMRES                        */
+  int32_t pc;           /* BF_PC_NONE, BF_PC_JACOBI or BF_PC_MG             */
+  int32_t maxit;        /* iteration limit (>= 1)                           */
+  int32_t restart;      /* GMRES restart length m (1..64)                   */
+  int32_t smoother;     /* BF_SMOOTH_CHEBYSHEV or BF_SMOOTH_JACOBI          */
+  int32_t degree;       /* smoothing sweeps before and after the coarse     */
+                        /* correction (1..8); 0 = operator default (CH 3, P 2) */
+  int32_t check_every;  /* read the residual norm on the host every k iters */
+  int32_t max_restarts; /* residual replacements before declaring a floor   */
+  double  rtol;         /* relative weighted residual ||b-Ax||/||b||        */
+  double  ratio;        /* Chebyshev interval lmax/lmin; 0 = default        */
+                        /* (CH 16, P 4)                                     */
+  double  omega;        /* damped-Jacobi weight; 0 = default                */
+} bf_solver_opts;
+
+typedef struct {
+  int32_t status;        /* same value as the call's return code           */
+  int32_t iters;         /* Krylov iterations performed                     */
+  int32_t restarts;      /* residual replacements performed                 */
+  int32_t clamped;       /* bf_step: points where phi was clamped for mu    */
+  double  rel_res;       /* recursively updated relative residual at exit   */
+  double  rel_res_true;  /* ||b - A x||_W / ||b||_W recomputed at exit      */
+  double  ms;            /* device time of the call (HIP events)            */
+} bf_solve_stats;
+
+/* Parameters of the reduced semi-implicit step (dimensionless). */
+typedef struct {
+  double dt, M, kappa;   /* time step, mobility, gradient-energy coefficient */
+  double Npoly, chi;     /* Flory-Huggins N and chi (Sec. 5 parameter table) */
+  double phi_lo, phi_hi; /* clamp of phi inside the logarithms               */
+} bf_params;
+
+/* Fill *o with the defaults for operator op (BF_OP_CH or BF_OP_LAP):
+ * CG + multigrid, Chebyshev smoothing, rtol 1e-10, maxit 200. */
+void bf_solver_opts_default(int32_t op, bf_solver_opts* o);
+
+/* Allocate a grid and its multigrid hierarchy and Krylov workspaces on the
+ * current HIP device (the grid's workspaces belong to the handle).
+ * Errors: BF_EINVAL (n not a power of two in range, null out), BF_ENOMEM. */
+int bf_grid_create(const bf_grid_desc* desc, bf_grid** out);
+int bf_grid_destroy(bf_grid* g);
+int bf_grid_shape(const bf_grid* g, int64_t* rows, int64_t* cols);
+
+/* y = L x (op = BF_OP_LAP, 5-point Laplacian: the paper's matrix row 4, -1,
+ * -1, -1, -1 of Sec. 4.1 scaled by -1/h^2) or y = x + c * L^2 x (op =
+ * BF_OP_CH, the 13-point Cahn-Hilliard operator; c = dt*M*kappa, Sec. 2.2
+ * eq. modCH), ghosts by eq. discreteBC, periodic x.  Asynchronous. */
+int bf_apply(bf_grid* g, int32_t op, double c, const double* x, double* y);
+
+/* Solve (I + c L^2) x = b (Sec. 4.1: KSPSolve).  x: in = initial guess,
+ * out = solution.  b = 0 gives x = 0.  c >= 0. */
+int bf_solve_ch(bf_grid* g, double c, const double* b, double* x,
+                const bf_solver_opts* o, bf_solve_stats* st);
+
+/* Solve the Neumann pressure Poisson problem L p = rhs (Sec. 4, eq.
+ * pressuresolve).  The weighted mean is removed from a copy of rhs (the null
+ * space of constants, Sec. 4.1 Listing "Removing a nullspace"); rhs is not
+ * modified.  p: in = initial guess, out = solution with zero weighted mean. */
+int bf_solve_pressure(bf_grid* g, const double* rhs, double* p,
+                      const bf_solver_opts* o, bf_solve_stats* st);
+
+/* b = phi + dt*M*L mu_FH(clamp(phi)), mu_FH(f) = ln(f)/N + 1/N - ln(1-f) - 1
+ * + chi*(1-2f), clamp to [phi_lo, phi_hi] (phi itself untouched).  If
+ * clamped != NULL it receives (device int32) the number of clamped points. */
+int bf_ch_rhs(bf_grid* g, const bf_params* prm, const double* phi, double* b,
+              int32_t* clamped_dev);
+
+/* rhs = div_h(u, v) / dt with 2h central differences, v odd across the walls
+ * (Sec. 4: v.n = 0), u periodic.  Asynchronous. */
+int bf_pressure_rhs(bf_grid* g, double dt, const double* u, const double* v,
+                    double* rhs);
+
+/* u = ustar - dt * dp/dx, v = vstar - dt * dp/dy (central, p even across the
+ * walls): the velocity update of Sec. 4, eq. velocityupdate, in the sign
+ * convention L p = div(u*)/dt.  u may alias ustar and v may alias vstar. */
+int bf_velocity_correct(bf_grid* g, double dt, const double* p,
+                        const double* ustar, const double* vstar,
+                        double* u, double* v);
+
+/* One time step: Cahn-Hilliard right-hand side and solve (phi in/out, solved
+ * from a zero initial guess), pressure right-hand side and solve (p out,
+ * zero initial guess), velocity correction (u, v may be NULL to skip).
+ * stats[0] = Cahn-Hilliard solve, stats[1] = pressure solve.  ch / pr may be
+ * NULL for the defaults. */
+int bf_step(bf_grid* g, const bf_params* prm, double* phi, const double* ustar,
+            const double* vstar, double* p, double* u, double* v,
+            const bf_solver_opts* ch, const bf_solver_opts* pr,
+            bf_solve_stats stats[2]);
+
+/* Reverse (adjoint) step with checkpointing: not available in this version;
+ * returns BF_EUNSUPPORTED. */
+int bf_adjoint_step(bf_grid* g, const bf_params* prm, const double* phi_n,
+                    const double* lambda_in, double* lambda_out);
+
+/* z = V(r): one multigrid V-cycle (the preconditioner of the solves) of the
+ * operator op with the options o (smoother, degree, ratio, omega), from a
+ * zero initial guess.  Asynchronous.  Used to check the cycle itself. */
+int bf_vcycle(bf_grid* g, int32_t op, double c, const bf_solver_opts* o,
+              const double* r, double* z);
+
+/* Grid-transfer operators between a fine grid of nf intervals and the coarse
+ * grid of nf/2 (nf a power of two, 8 <= nf <= the grid's n):
+ *   coarse = R fine       (R = 1/4 W_c^-1 P^T W_f, 7x7 stencil),
+ *   fine  += P coarse     (tensor-product cubic interpolation).
+ * Asynchronous. */
+int bf_restrict(bf_grid* g, int32_t nf, const double* fine, double* coarse);
+int bf_prolong_add(bf_grid* g, int32_t nf, const double* coarse, double* fine);
+
+/* *out (host) = <x, y>_W.  Synchronises the grid's stream. */
+int bf_wdot(bf_grid* g, const double* x, const double* y, double* out);
+
+/* Message of the last failure on this thread ("" if none). */
+const char* bf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BIOFILM_H */

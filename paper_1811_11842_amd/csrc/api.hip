@@ -1,0 +1,862 @@
+// Host side of the C ABI: grid and multigrid hierarchy, V-cycle orchestration,
+// Krylov drivers (CG and GMRES in the weighted inner product), and the time
+// step.  Every arithmetic step on fields runs in the kernels of kernels.hip;
+// the host only sequences launches and reads convergence scalars.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <utility>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/biofilm.h"
+#include "common.hpp"
+#include "kernels.hpp"
+
+using namespace bf;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIPCHK(expr)                                                                      \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      return fail(BF_EHIP, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, \
+                  __LINE__);                                                              \
+  } while (0)
+
+#define TRY(expr)            \
+  do {                       \
+    int s_ = (expr);         \
+    if (s_ < 0) return s_;   \
+  } while (0)
+
+struct Level {
+  int n = 0;
+  int64_t npts = 0;
+  double* xa = nullptr;  // iterate buffers (ping-pong)
+  double* xb = nullptr;
+  double* r = nullptr;   // residual
+  double* b = nullptr;   // right-hand side (levels >= 1)
+};
+
+constexpr int kCoarseN = 4;
+constexpr int kCoarseSize = (kCoarseN + 1) * kCoarseN;
+
+}  // namespace
+
+struct bf_grid {
+  int n = 0;
+  int64_t npts = 0;
+  hipStream_t stream = nullptr;
+  std::vector<Level> lv;
+  double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
+  double *work_b = nullptr;   // Cahn-Hilliard right-hand side inside bf_step
+  double *work_p = nullptr;   // projected pressure right-hand side
+  double* scal = nullptr;     // device scalars (kNumSlots)
+  double* partials = nullptr; // reduction partials (kMaxRedBlocks * 72)
+  double* coarse_ch = nullptr;
+  double* coarse_lap = nullptr;
+  double cached_c = -1.0;
+  int32_t* counter = nullptr;
+  double* h_scal = nullptr;   // pinned host mirror of scalars
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  // GMRES workspace (allocated on first use)
+  int gm_m = 0;
+  double* gm_V = nullptr;  // (m+1) vectors
+  double* gm_Z = nullptr;  // m preconditioned vectors
+  double* gm_y = nullptr;  // m coefficients (device)
+  std::vector<void*> allocs;
+};
+
+namespace {
+
+int dalloc(bf_grid* g, double** p, int64_t count) {
+  void* ptr = nullptr;
+  hipError_t e = hipMalloc(&ptr, (size_t)count * sizeof(double));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(BF_ENOMEM, "hipMalloc of %lld doubles failed: %s", (long long)count,
+                hipGetErrorString(e));
+  }
+  g->allocs.push_back(ptr);
+  *p = (double*)ptr;
+  return BF_OK;
+}
+
+bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
+
+// ------------------------------------------------------------ host-side small
+// dense algebra for the coarsest grid (5 x 4 nodes).
+int refl_h(int j, int n) {
+  j = j < 0 ? -j : j;
+  return j > n ? 2 * n - j : j;
+}
+
+// y = A x on an n-grid on the host (reflection in y, wrap in x).
+void host_apply(int op, int n, double coef, const double* x, double* y) {
+  auto X = [&](int j, int i) { return x[refl_h(j, n) * n + ((i % n) + n) % n]; };
+  for (int j = 0; j <= n; ++j)
+    for (int i = 0; i < n; ++i) {
+      const double c = X(j, i);
+      const double axis = X(j, i - 1) + X(j, i + 1) + X(j - 1, i) + X(j + 1, i);
+      if (op == BF_OP_LAP) {
+        y[j * n + i] = coef * (axis - 4.0 * c);
+      } else {
+        const double diag = X(j - 1, i - 1) + X(j - 1, i + 1) + X(j + 1, i - 1) + X(j + 1, i + 1);
+        const double far = X(j, i - 2) + X(j, i + 2) + X(j - 2, i) + X(j + 2, i);
+        y[j * n + i] = c + coef * (20.0 * c - 8.0 * axis + 2.0 * diag + far);
+      }
+    }
+}
+
+// In-place inverse of a size x size matrix by Gauss-Jordan with partial pivoting.
+bool invert(std::vector<double>& M, int size) {
+  std::vector<double> inv(size * size, 0.0);
+  for (int k = 0; k < size; ++k) inv[k * size + k] = 1.0;
+  for (int col = 0; col < size; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < size; ++r)
+      if (std::fabs(M[r * size + col]) > std::fabs(M[piv * size + col])) piv = r;
+    if (M[piv * size + col] == 0.0) return false;
+    if (piv != col)
+      for (int c = 0; c < size; ++c) {
+        std::swap(M[piv * size + c], M[col * size + c]);
+        std::swap(inv[piv * size + c], inv[col * size + c]);
+      }
+    const double d = 1.0 / M[col * size + col];
+    for (int c = 0; c < size; ++c) {
+      M[col * size + c] *= d;
+      inv[col * size + c] *= d;
+    }
+    for (int r = 0; r < size; ++r) {
+      if (r == col) continue;
+      const double f = M[r * size + col];
+      if (f == 0.0) continue;
+      for (int c = 0; c < size; ++c) {
+        M[r * size + c] -= f * M[col * size + c];
+        inv[r * size + c] -= f * inv[col * size + c];
+      }
+    }
+  }
+  M = inv;
+  return true;
+}
+
+// Dense operator of the coarsest grid by probing with unit vectors.
+std::vector<double> coarse_matrix(int op, double coef) {
+  const int n = kCoarseN, size = kCoarseSize;
+  std::vector<double> A(size * size), e(size), col(size);
+  for (int l = 0; l < size; ++l) {
+    std::fill(e.begin(), e.end(), 0.0);
+    e[l] = 1.0;
+    host_apply(op, n, coef, e.data(), col.data());
+    for (int k = 0; k < size; ++k) A[k * size + l] = col[k];
+  }
+  return A;
+}
+
+// Exact coarsest-grid solution operators:
+//  CH : G = A^{-1}
+//  LAP: G = top-left block of [[L, 1], [w^T, 0]]^{-1}; G b solves L p = b - wmean(b)
+//       with w^T p = 0 (the weighted-mean constraint on the null space).
+int upload_coarse(bf_grid* g, int op, double c) {
+  const int n = kCoarseN, size = kCoarseSize;
+  std::vector<double> G;
+  if (op == BF_OP_CH) {
+    G = coarse_matrix(op, c * std::pow((double)n, 4));
+    if (!invert(G, size)) return fail(BF_EINVAL, "coarse Cahn-Hilliard matrix is singular");
+  } else {
+    std::vector<double> A = coarse_matrix(op, (double)n * n);
+    const int bs = size + 1;
+    std::vector<double> B(bs * bs, 0.0);
+    for (int k = 0; k < size; ++k) {
+      for (int l = 0; l < size; ++l) B[k * bs + l] = A[k * size + l];
+      B[k * bs + size] = 1.0;
+      const int j = k / n;
+      B[size * bs + k] = (j == 0 || j == n) ? 0.5 : 1.0;
+    }
+    if (!invert(B, bs)) return fail(BF_EINVAL, "coarse bordered Laplacian is singular");
+    G.resize(size * size);
+    for (int k = 0; k < size; ++k)
+      for (int l = 0; l < size; ++l) G[k * size + l] = B[k * bs + l];
+  }
+  double* dst = op == BF_OP_CH ? g->coarse_ch : g->coarse_lap;
+  HIPCHK(hipMemcpyAsync(dst, G.data(), sizeof(double) * size * size, hipMemcpyHostToDevice,
+                        g->stream));
+  HIPCHK(hipStreamSynchronize(g->stream));
+  return BF_OK;
+}
+
+int ensure_coarse_ch(bf_grid* g, double c) {
+  if (g->cached_c == c) return BF_OK;
+  TRY(upload_coarse(g, BF_OP_CH, c));
+  g->cached_c = c;
+  return BF_OK;
+}
+
+// ------------------------------------------------------------ level operators
+OpDesc level_op(int op, int n, double c) {
+  OpDesc A;
+  A.op = op;
+  A.n = n;
+  if (op == BF_OP_LAP) {
+    A.coef = (double)n * (double)n;
+    A.dinv_int = A.dinv_edge = -1.0 / (4.0 * A.coef);
+  } else {
+    const double s = c * std::pow((double)n, 4);
+    A.coef = s;
+    A.dinv_int = 1.0 / (1.0 + 20.0 * s);
+    A.dinv_edge = 1.0 / (1.0 + 21.0 * s);
+  }
+  return A;
+}
+
+struct Smoother {
+  int degree = 0;
+  double a[8] = {0};
+  double g[8] = {0};
+};
+
+// Chebyshev iteration on [lmax/ratio, lmax] for D^{-1}A (three-term form;
+// Saad, Iterative Methods for Sparse Linear Systems, Sec. 12.3.2), or damped
+// Jacobi with weight omega.
+Smoother make_smoother(int op, int n, double c, const bf_solver_opts& o) {
+  Smoother S;
+  S.degree = o.degree > 0 ? o.degree : (op == BF_OP_CH ? 3 : 2);
+  if (o.smoother == BF_SMOOTH_JACOBI) {
+    double w = o.omega;
+    if (w <= 0) {
+      if (op == BF_OP_LAP) {
+        w = 0.8;
+      } else {
+        const double s = c * std::pow((double)n, 4);
+        w = 2.0 * (1.0 + 20.0 * s) / (2.0 + 68.0 * s);
+      }
+    }
+    for (int k = 0; k < S.degree; ++k) {
+      S.a[k] = w;
+      S.g[k] = 0.0;
+    }
+    return S;
+  }
+  double lmax;
+  if (op == BF_OP_LAP) {
+    lmax = 2.0;
+  } else {
+    const double s = c * std::pow((double)n, 4);
+    lmax = (1.0 + 64.0 * s) / (1.0 + 20.0 * s);
+  }
+  const double ratio = o.ratio > 0 ? o.ratio : (op == BF_OP_CH ? 16.0 : 4.0);
+  const double lmin = lmax / ratio;
+  const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin);
+  const double sigma = theta / delta;
+  S.a[0] = 1.0 / theta;
+  S.g[0] = 0.0;
+  double rho = 1.0 / sigma;
+  for (int k = 1; k < S.degree; ++k) {
+    const double rn = 1.0 / (2.0 * sigma - rho);
+    S.a[k] = 2.0 * rn / delta;
+    S.g[k] = rn * rho;
+    rho = rn;
+  }
+  return S;
+}
+
+// One V-cycle on level l with right-hand side b (level 0: external pointer).
+// Returns the buffer holding the level's result.
+double* vcycle_level(bf_grid* g, int op, double c, const bf_solver_opts& o, int l,
+                     const double* b) {
+  Level& L = g->lv[l];
+  hipStream_t st = g->stream;
+  if (L.n == kCoarseN) {
+    launch_coarse_solve(kCoarseSize, op == BF_OP_CH ? g->coarse_ch : g->coarse_lap, b, L.xa, st);
+    return L.xa;
+  }
+  const OpDesc A = level_op(op, L.n, c);
+  const Smoother S = make_smoother(op, L.n, c, o);
+  // pre-smoothing from zero
+  double* cur = L.xa;
+  double* oth = L.xb;
+  launch_smooth0(A, b, cur, S.a[0], st);
+  for (int k = 1; k < S.degree; ++k) {
+    launch_smooth(A, cur, (k == 1 || S.g[k] == 0.0) ? nullptr : oth, b, oth, S.a[k], S.g[k], st);
+    std::swap(cur, oth);
+  }
+  // coarse-grid correction
+  launch_residual(A, cur, b, L.r, nullptr, 0, st);
+  Level& C = g->lv[l + 1];
+  launch_restrict(L.n, L.r, C.b, st);
+  double* e = vcycle_level(g, op, c, o, l + 1, C.b);
+  launch_prolong_add(L.n, e, cur, st);
+  // post-smoothing (same polynomial)
+  for (int k = 0; k < S.degree; ++k) {
+    launch_smooth(A, cur, S.g[k] != 0.0 ? oth : nullptr, b, oth, S.a[k], S.g[k], st);
+    std::swap(cur, oth);
+  }
+  return cur;
+}
+
+int check_opts(const bf_solver_opts& o) {
+  if (o.ksp != BF_KSP_CG && o.ksp != BF_KSP_GMRES) return fail(BF_EINVAL, "ksp %d", o.ksp);
+  if (o.pc < BF_PC_NONE || o.pc > BF_PC_MG) return fail(BF_EINVAL, "pc %d", o.pc);
+  if (o.maxit < 1) return fail(BF_EINVAL, "maxit %d < 1", o.maxit);
+  if (o.degree < 0 || o.degree > 8) return fail(BF_EINVAL, "degree %d not in 0..8", o.degree);
+  if (o.smoother != BF_SMOOTH_CHEBYSHEV && o.smoother != BF_SMOOTH_JACOBI)
+    return fail(BF_EINVAL, "smoother %d", o.smoother);
+  if (!(o.rtol > 0)) return fail(BF_EINVAL, "rtol must be > 0");
+  if (o.ksp == BF_KSP_GMRES && (o.restart < 1 || o.restart > 64))
+    return fail(BF_EINVAL, "restart %d not in 1..64", o.restart);
+  if (o.check_every < 1) return fail(BF_EINVAL, "check_every %d < 1", o.check_every);
+  if (o.ratio < 0 || o.omega < 0) return fail(BF_EINVAL, "negative ratio/omega");
+  return BF_OK;
+}
+
+// z = M r for the chosen preconditioner.  Returns the buffer holding z.
+double* precondition(bf_grid* g, int op, double c, const bf_solver_opts& o, const double* r) {
+  switch (o.pc) {
+    case BF_PC_MG:
+      return vcycle_level(g, op, c, o, 0, r);
+    case BF_PC_JACOBI:
+      launch_jacobi_pc(level_op(op, g->n, c), r, g->z, g->stream);
+      return g->z;
+    default:
+      launch_copy(g->npts, r, g->z, g->stream);
+      return g->z;
+  }
+}
+
+int nparts_of(const bf_grid* g) { return red_blocks(g->npts); }
+
+// Reduce <x, y>_W into scal[slot] (asynchronous).
+void wdot_async(bf_grid* g, const double* x, const double* y, int mode, int slot) {
+  const int np = nparts_of(g);
+  launch_dot(g->n, x, y, g->partials, np, g->stream);
+  launch_finalize(g->partials, np, g->scal, mode, slot, g->n, g->stream);
+}
+
+int read_scalars(bf_grid* g, int count) {
+  HIPCHK(hipMemcpyAsync(g->h_scal, g->scal, sizeof(double) * count, hipMemcpyDeviceToHost,
+                        g->stream));
+  HIPCHK(hipStreamSynchronize(g->stream));
+  return BF_OK;
+}
+
+// ------------------------------------------------------------ Krylov drivers
+// Final status from the true residual (residual replacement / floor logic).
+struct KrylovState {
+  int iters = 0, restarts = 0;
+  double rel = 0, rel_true = 0;
+};
+
+// CG in the weighted inner product with residual replacement: whenever the
+// recursively updated residual reaches rtol the true residual is recomputed;
+// if it is above rtol the iteration restarts from it, as long as each restart
+// improves the true residual by at least 10%; otherwise the solve stops at the
+// float64 floor of the operator (BF_AT_FLOOR).
+int run_cg(bf_grid* g, int op, double c, const double* b, double* x, const bf_solver_opts& o,
+           KrylovState& ks) {
+  hipStream_t st = g->stream;
+  const int np = nparts_of(g);
+  const OpDesc A = level_op(op, g->n, c);
+  wdot_async(g, b, b, F_STORE, S_BN2);
+  launch_residual(A, x, b, g->r, g->partials, np, st);
+  launch_finalize(g->partials, np, g->scal, F_STORE, S_RR, g->n, st);
+  TRY(read_scalars(g, S_RTRUE + 1));
+  const double bn2 = g->h_scal[S_BN2];
+  if (!std::isfinite(bn2)) return fail(BF_ENONFINITE, "right-hand side is not finite");
+  if (bn2 == 0.0) {
+    launch_fill(g->npts, x, 0.0, st);
+    ks.rel = ks.rel_true = 0.0;
+    return BF_OK;
+  }
+  const double bn = std::sqrt(bn2);
+  double rel = std::sqrt(g->h_scal[S_RR]) / bn;
+  if (!std::isfinite(rel)) return fail(BF_ENONFINITE, "initial residual is not finite");
+  double last_true = rel;
+  ks.rel = ks.rel_true = rel;
+  if (rel <= o.rtol) return BF_OK;
+
+  int status = BF_NOT_CONVERGED;
+  for (;;) {
+    // (re)start from the residual in g->r
+    double* z = precondition(g, op, c, o, g->r);
+    wdot_async(g, g->r, z, F_STORE, S_RZ);
+    launch_copy(g->npts, z, g->p, st);
+    bool converged = false;
+    while (ks.iters < o.maxit) {
+      launch_apply_dot(A, g->p, g->q, g->partials, np, st);
+      launch_finalize(g->partials, np, g->scal, F_ALPHA, 0, g->n, st);
+      launch_cg_update(g->n, x, g->p, g->r, g->q, g->scal, g->partials, np, st);
+      launch_finalize(g->partials, np, g->scal, F_STORE, S_RR, g->n, st);
+      ks.iters++;
+      if (ks.iters % o.check_every == 0 || ks.iters == o.maxit) {
+        TRY(read_scalars(g, S_RR + 1));
+        rel = std::sqrt(g->h_scal[S_RR]) / bn;
+        ks.rel = rel;
+        if (!std::isfinite(rel)) return fail(BF_ENONFINITE, "residual norm is not finite");
+        if (rel <= o.rtol) {
+          converged = true;
+          break;
+        }
+      }
+      z = precondition(g, op, c, o, g->r);
+      wdot_async(g, g->r, z, F_BETA, 0);
+      launch_xpby(g->n, z, g->p, g->scal, st);
+    }
+    // true residual, written into r (it becomes the restart residual)
+    launch_residual(A, x, b, g->r, g->partials, np, st);
+    launch_finalize(g->partials, np, g->scal, F_STORE, S_RTRUE, g->n, st);
+    TRY(read_scalars(g, S_RTRUE + 1));
+    const double rt = std::sqrt(g->h_scal[S_RTRUE]) / bn;
+    ks.rel_true = rt;
+    if (!std::isfinite(rt)) return fail(BF_ENONFINITE, "true residual is not finite");
+    if (rt <= o.rtol) {
+      status = BF_OK;
+      break;
+    }
+    if (!converged) {  // iteration limit
+      status = BF_NOT_CONVERGED;
+      break;
+    }
+    if (ks.restarts < o.max_restarts && rt < 0.9 * last_true) {
+      ks.restarts++;
+      last_true = rt;
+      continue;
+    }
+    status = rt <= 1e3 * o.rtol ? BF_AT_FLOOR : BF_NOT_CONVERGED;
+    break;
+  }
+  return status;
+}
+
+int ensure_gmres(bf_grid* g, int m) {
+  if (g->gm_m >= m) return BF_OK;
+  if (g->gm_V) {
+    HIPCHK(hipFree(g->gm_V));
+    HIPCHK(hipFree(g->gm_Z));
+    HIPCHK(hipFree(g->gm_y));
+    for (auto& p : g->allocs)
+      if (p == g->gm_V || p == g->gm_Z || p == g->gm_y) p = nullptr;
+    g->gm_V = g->gm_Z = g->gm_y = nullptr;
+    g->gm_m = 0;
+  }
+  TRY(dalloc(g, &g->gm_V, (int64_t)(m + 1) * g->npts));
+  TRY(dalloc(g, &g->gm_Z, (int64_t)m * g->npts));
+  TRY(dalloc(g, &g->gm_y, m));
+  g->gm_m = m;
+  return BF_OK;
+}
+
+// Right-preconditioned (flexible) GMRES(m) in the weighted inner product with
+// classical Gram-Schmidt applied twice; Givens rotations on the host.
+int run_gmres(bf_grid* g, int op, double c, const double* b, double* x, const bf_solver_opts& o,
+              KrylovState& ks) {
+  hipStream_t st = g->stream;
+  const int np = nparts_of(g);
+  const int m = o.restart;
+  TRY(ensure_gmres(g, m));
+  const OpDesc A = level_op(op, g->n, c);
+  const int64_t N = g->npts;
+  wdot_async(g, b, b, F_STORE, S_BN2);
+  TRY(read_scalars(g, S_BN2 + 1));
+  const double bn2 = g->h_scal[S_BN2];
+  if (!std::isfinite(bn2)) return fail(BF_ENONFINITE, "right-hand side is not finite");
+  if (bn2 == 0.0) {
+    launch_fill(g->npts, x, 0.0, st);
+    return BF_OK;
+  }
+  const double bn = std::sqrt(bn2);
+  std::vector<double> H((m + 1) * m), cs(m), sn(m), gv(m + 1), y(m);
+  double last_true = HUGE_VAL;
+  int status = BF_NOT_CONVERGED;
+  for (;;) {
+    // r0 = b - A x, V0 = r0 / ||r0||
+    launch_residual(A, x, b, g->gm_V, g->partials, np, st);
+    launch_finalize(g->partials, np, g->scal, F_STORE, S_RTRUE, g->n, st);
+    TRY(read_scalars(g, S_RTRUE + 1));
+    const double beta = std::sqrt(g->h_scal[S_RTRUE]);
+    const double rt = beta / bn;
+    ks.rel_true = ks.rel = rt;
+    if (!std::isfinite(rt)) return fail(BF_ENONFINITE, "residual norm is not finite");
+    if (rt <= o.rtol) {
+      status = BF_OK;
+      break;
+    }
+    if (ks.iters >= o.maxit) {
+      status = BF_NOT_CONVERGED;
+      break;
+    }
+    if (!(rt < 0.9 * last_true) && ks.restarts > 0) {
+      status = rt <= 1e3 * o.rtol ? BF_AT_FLOOR : BF_NOT_CONVERGED;
+      break;
+    }
+    last_true = rt;
+    if (ks.iters > 0) ks.restarts++;
+    launch_scale(g->n, g->gm_V, g->gm_V, g->scal, S_RTRUE, 1, st);
+    std::fill(gv.begin(), gv.end(), 0.0);
+    gv[0] = beta;
+    int k = 0;
+    for (; k < m && ks.iters < o.maxit; ++k) {
+      double* Vk = g->gm_V + (int64_t)k * N;
+      double* Zk = g->gm_Z + (int64_t)k * N;
+      double* w = g->gm_V + (int64_t)(k + 1) * N;
+      double* zk = precondition(g, op, c, o, Vk);
+      launch_copy(N, zk, Zk, st);
+      launch_apply(A, Zk, w, st);
+      // CGS2: h = V^T_W w, w -= V h, twice
+      for (int pass = 0; pass < 2; ++pass) {
+        launch_mdot(g->n, g->gm_V, k + 1, w, g->partials, np, st);
+        launch_finalize_multi(g->partials, np, k + 1, g->scal, S_GM + pass * 72, st);
+        launch_maxpy(g->n, g->gm_V, k + 1, g->scal + S_GM + pass * 72, w,
+                     pass == 1 ? g->partials : nullptr, np, st);
+      }
+      launch_finalize(g->partials, np, g->scal, F_STORE, S_TMP, g->n, st);
+      TRY(read_scalars(g, S_GM + 72 + k + 1));
+      const double hn = std::sqrt(g->h_scal[S_TMP]);
+      for (int i = 0; i <= k; ++i)
+        H[i * m + k] = g->h_scal[S_GM + i] + g->h_scal[S_GM + 72 + i];
+      H[(k + 1) * m + k] = hn;
+      if (!std::isfinite(hn)) return fail(BF_ENONFINITE, "Arnoldi norm is not finite");
+      if (hn > 0) launch_scale(g->n, w, w, g->scal, S_TMP, 1, st);
+      // apply previous rotations, then a new one
+      for (int i = 0; i < k; ++i) {
+        const double t = cs[i] * H[i * m + k] + sn[i] * H[(i + 1) * m + k];
+        H[(i + 1) * m + k] = -sn[i] * H[i * m + k] + cs[i] * H[(i + 1) * m + k];
+        H[i * m + k] = t;
+      }
+      const double a = H[k * m + k], bb = H[(k + 1) * m + k];
+      const double rr = std::hypot(a, bb);
+      cs[k] = rr > 0 ? a / rr : 1.0;
+      sn[k] = rr > 0 ? bb / rr : 0.0;
+      H[k * m + k] = rr;
+      H[(k + 1) * m + k] = 0.0;
+      gv[k + 1] = -sn[k] * gv[k];
+      gv[k] = cs[k] * gv[k];
+      ks.iters++;
+      ks.rel = std::fabs(gv[k + 1]) / bn;
+      if (ks.rel <= o.rtol || hn == 0.0) {
+        ++k;
+        break;
+      }
+    }
+    // y = H^{-1} g (upper triangular), x += Z y
+    for (int i = k - 1; i >= 0; --i) {
+      double s = gv[i];
+      for (int j = i + 1; j < k; ++j) s -= H[i * m + j] * y[j];
+      y[i] = s / H[i * m + i];
+    }
+    HIPCHK(hipMemcpyAsync(g->gm_y, y.data(), sizeof(double) * k, hipMemcpyHostToDevice, st));
+    launch_axpy_multi(g->n, g->gm_Z, k, g->gm_y, x, st);
+    HIPCHK(hipStreamSynchronize(st));  // y is a host vector reused next cycle
+  }
+  return status;
+}
+
+int run_krylov(bf_grid* g, int op, double c, const double* b, double* x, const bf_solver_opts& o,
+               bf_solve_stats* st) {
+  TRY(check_opts(o));
+  if (op == BF_OP_CH) TRY(ensure_coarse_ch(g, c));
+  HIPCHK(hipEventRecord(g->ev0, g->stream));
+  KrylovState ks;
+  int status = o.ksp == BF_KSP_CG ? run_cg(g, op, c, b, x, o, ks) : run_gmres(g, op, c, b, x, o, ks);
+  if (status < 0) return status;
+  HIPCHK(hipEventRecord(g->ev1, g->stream));
+  HIPCHK(hipEventSynchronize(g->ev1));
+  float ms = 0;
+  HIPCHK(hipEventElapsedTime(&ms, g->ev0, g->ev1));
+  if (st) {
+    st->status = status;
+    st->iters = ks.iters;
+    st->restarts = ks.restarts;
+    st->rel_res = ks.rel;
+    st->rel_res_true = ks.rel_true;
+    st->ms = ms;
+  }
+  return status;
+}
+
+void default_opts(int32_t op, bf_solver_opts* o) {
+  std::memset(o, 0, sizeof(*o));
+  o->ksp = BF_KSP_CG;
+  o->pc = BF_PC_MG;
+  o->maxit = 200;
+  o->restart = 30;
+  o->smoother = BF_SMOOTH_CHEBYSHEV;
+  o->degree = 0;
+  o->check_every = 1;
+  o->max_restarts = 3;
+  o->rtol = 1e-10;
+  o->ratio = 0.0;
+  o->omega = 0.0;
+  (void)op;
+}
+
+int check_grid(const bf_grid* g) {
+  if (!g) return fail(BF_EINVAL, "null grid");
+  return BF_OK;
+}
+
+}  // namespace
+
+// ====================================================================== C ABI
+extern "C" {
+
+void bf_solver_opts_default(int32_t op, bf_solver_opts* o) {
+  if (o) default_opts(op, o);
+}
+
+const char* bf_last_error(void) { return g_err.c_str(); }
+
+int bf_grid_create(const bf_grid_desc* desc, bf_grid** out) {
+  g_err.clear();
+  if (!desc || !out) return fail(BF_EINVAL, "null argument");
+  *out = nullptr;
+  const int n = desc->n;
+  if (!is_pow2(n) || n < kCoarseN || n > 32768)
+    return fail(BF_EINVAL, "n = %d must be a power of two in [4, 32768]", n);
+  if (desc->dtype != BF_F64) return fail(BF_EUNSUPPORTED, "dtype %d not supported", desc->dtype);
+  bf_grid* g = new bf_grid();
+  g->n = n;
+  g->npts = (int64_t)(n + 1) * n;
+  g->stream = (hipStream_t)desc->stream;
+  int s = BF_OK;
+  auto A = [&](double** p, int64_t cnt) {
+    if (s == BF_OK) s = dalloc(g, p, cnt);
+  };
+  for (int m = n; m >= kCoarseN; m /= 2) {
+    Level L;
+    L.n = m;
+    L.npts = (int64_t)(m + 1) * m;
+    A(&L.xa, L.npts);
+    A(&L.xb, L.npts);
+    A(&L.r, L.npts);
+    A(&L.b, L.npts);
+    g->lv.push_back(L);
+  }
+  A(&g->r, g->npts);
+  A(&g->z, g->npts);
+  A(&g->p, g->npts);
+  A(&g->q, g->npts);
+  A(&g->work_b, g->npts);
+  A(&g->work_p, g->npts);
+  A(&g->scal, kNumSlots);
+  A(&g->partials, (int64_t)kMaxRedBlocks * 72);
+  A(&g->coarse_ch, kCoarseSize * kCoarseSize);
+  A(&g->coarse_lap, kCoarseSize * kCoarseSize);
+  if (s == BF_OK) {
+    void* p = nullptr;
+    if (hipMalloc(&p, sizeof(int32_t) * 4) != hipSuccess)
+      s = fail(BF_ENOMEM, "counter allocation failed");
+    else {
+      g->counter = (int32_t*)p;
+      g->allocs.push_back(p);
+    }
+  }
+  if (s == BF_OK && hipHostMalloc((void**)&g->h_scal, sizeof(double) * kNumSlots) != hipSuccess)
+    s = fail(BF_ENOMEM, "pinned host allocation failed");
+  if (s == BF_OK && (hipEventCreate(&g->ev0) != hipSuccess || hipEventCreate(&g->ev1) != hipSuccess))
+    s = fail(BF_EHIP, "event creation failed");
+  if (s == BF_OK) {
+    launch_fill(kNumSlots, g->scal, 0.0, g->stream);
+    s = upload_coarse(g, BF_OP_LAP, 0.0);
+  }
+  if (s != BF_OK) {
+    std::string keep = g_err;
+    bf_grid_destroy(g);
+    g_err = keep;
+    return s;
+  }
+  *out = g;
+  return BF_OK;
+}
+
+int bf_grid_destroy(bf_grid* g) {
+  if (!g) return BF_OK;
+  if (g->stream) (void)hipStreamSynchronize(g->stream);
+  else (void)hipDeviceSynchronize();
+  for (void* p : g->allocs)
+    if (p) (void)hipFree(p);
+  if (g->h_scal) (void)hipHostFree(g->h_scal);
+  if (g->ev0) (void)hipEventDestroy(g->ev0);
+  if (g->ev1) (void)hipEventDestroy(g->ev1);
+  delete g;
+  return BF_OK;
+}
+
+int bf_grid_shape(const bf_grid* g, int64_t* rows, int64_t* cols) {
+  TRY(check_grid(g));
+  if (rows) *rows = g->n + 1;
+  if (cols) *cols = g->n;
+  return BF_OK;
+}
+
+int bf_apply(bf_grid* g, int32_t op, double c, const double* x, double* y) {
+  TRY(check_grid(g));
+  if (!x || !y) return fail(BF_EINVAL, "null field");
+  if (x == y) return fail(BF_EINVAL, "x and y must not alias");
+  if (op != BF_OP_LAP && op != BF_OP_CH) return fail(BF_EINVAL, "op %d", op);
+  launch_apply(level_op(op, g->n, c), x, y, g->stream);
+  HIPCHK(hipGetLastError());
+  return BF_OK;
+}
+
+int bf_solve_ch(bf_grid* g, double c, const double* b, double* x, const bf_solver_opts* o,
+                bf_solve_stats* st) {
+  TRY(check_grid(g));
+  if (!b || !x) return fail(BF_EINVAL, "null field");
+  if (b == x) return fail(BF_EINVAL, "b and x must not alias");
+  if (!(c >= 0) || !std::isfinite(c)) return fail(BF_EINVAL, "c = %g must be finite and >= 0", c);
+  bf_solver_opts d;
+  default_opts(BF_OP_CH, &d);
+  const int s = run_krylov(g, BF_OP_CH, c, b, x, o ? *o : d, st);
+  return s;
+}
+
+int bf_solve_pressure(bf_grid* g, const double* rhs, double* p, const bf_solver_opts* o,
+                      bf_solve_stats* st) {
+  TRY(check_grid(g));
+  if (!rhs || !p) return fail(BF_EINVAL, "null field");
+  if (rhs == p) return fail(BF_EINVAL, "rhs and p must not alias");
+  bf_solver_opts d;
+  default_opts(BF_OP_LAP, &d);
+  const bf_solver_opts& oo = o ? *o : d;
+  TRY(check_opts(oo));
+  // projected copy of the right-hand side (null space of constants)
+  wdot_async(g, rhs, nullptr, F_MEAN, 0);
+  launch_sub_mean(g->n, rhs, g->work_p, g->scal, g->stream);
+  const int s = run_krylov(g, BF_OP_LAP, 0.0, g->work_p, p, oo, st);
+  if (s < 0) return s;
+  wdot_async(g, p, nullptr, F_MEAN, 0);
+  launch_sub_mean(g->n, p, p, g->scal, g->stream);
+  HIPCHK(hipStreamSynchronize(g->stream));
+  return s;
+}
+
+int bf_ch_rhs(bf_grid* g, const bf_params* prm, const double* phi, double* b, int32_t* clamped) {
+  TRY(check_grid(g));
+  if (!prm || !phi || !b) return fail(BF_EINVAL, "null argument");
+  if (phi == b) return fail(BF_EINVAL, "phi and b must not alias");
+  if (!(prm->Npoly > 0) || !(prm->phi_lo > 0) || !(prm->phi_hi < 1) || !(prm->phi_lo < prm->phi_hi))
+    return fail(BF_EINVAL, "bad Flory-Huggins parameters");
+  if (clamped) launch_fill_i32(1, clamped, 0, g->stream);
+  launch_ch_rhs(g->n, phi, b, prm->dt * prm->M, 1.0 / prm->Npoly, prm->chi, prm->phi_lo,
+                prm->phi_hi, clamped, g->stream);
+  HIPCHK(hipGetLastError());
+  return BF_OK;
+}
+
+int bf_pressure_rhs(bf_grid* g, double dt, const double* u, const double* v, double* rhs) {
+  TRY(check_grid(g));
+  if (!u || !v || !rhs) return fail(BF_EINVAL, "null field");
+  if (!(dt > 0)) return fail(BF_EINVAL, "dt must be > 0");
+  if (rhs == u || rhs == v) return fail(BF_EINVAL, "rhs must not alias u or v");
+  launch_divergence(g->n, u, v, rhs, (double)g->n / (2.0 * dt), g->stream);
+  HIPCHK(hipGetLastError());
+  return BF_OK;
+}
+
+int bf_velocity_correct(bf_grid* g, double dt, const double* p, const double* ustar,
+                        const double* vstar, double* u, double* v) {
+  TRY(check_grid(g));
+  if (!p || !ustar || !vstar) return fail(BF_EINVAL, "null field");
+  if (p == u || p == v) return fail(BF_EINVAL, "p must not alias u or v");
+  launch_velocity(g->n, p, ustar, vstar, u, v, dt * (double)g->n * 0.5, g->stream);
+  HIPCHK(hipGetLastError());
+  return BF_OK;
+}
+
+int bf_step(bf_grid* g, const bf_params* prm, double* phi, const double* ustar,
+            const double* vstar, double* p, double* u, double* v, const bf_solver_opts* ch,
+            const bf_solver_opts* pr, bf_solve_stats stats[2]) {
+  TRY(check_grid(g));
+  if (!prm || !phi || !ustar || !vstar || !p) return fail(BF_EINVAL, "null argument");
+  bf_solve_stats local[2];
+  bf_solve_stats* S = stats ? stats : local;
+  std::memset(S, 0, sizeof(bf_solve_stats) * 2);
+  TRY(bf_ch_rhs(g, prm, phi, g->work_b, g->counter));
+  launch_fill(g->npts, phi, 0.0, g->stream);
+  const int s1 = bf_solve_ch(g, prm->dt * prm->M * prm->kappa, g->work_b, phi, ch, &S[0]);
+  if (s1 < 0) return s1;
+  TRY(bf_pressure_rhs(g, prm->dt, ustar, vstar, g->work_b));
+  launch_fill(g->npts, p, 0.0, g->stream);
+  const int s2 = bf_solve_pressure(g, g->work_b, p, pr, &S[1]);
+  if (s2 < 0) return s2;
+  if (u || v) TRY(bf_velocity_correct(g, prm->dt, p, ustar, vstar, u, v));
+  int32_t clamped = 0;
+  HIPCHK(hipMemcpyAsync(&clamped, g->counter, sizeof(int32_t), hipMemcpyDeviceToHost, g->stream));
+  HIPCHK(hipStreamSynchronize(g->stream));
+  S[0].clamped = clamped;
+  return s1 > s2 ? s1 : s2;
+}
+
+int bf_adjoint_step(bf_grid* g, const bf_params* prm, const double* phi_n, const double* lambda_in,
+                    double* lambda_out) {
+  (void)g;
+  (void)prm;
+  (void)phi_n;
+  (void)lambda_in;
+  (void)lambda_out;
+  return fail(BF_EUNSUPPORTED, "bf_adjoint_step is not available in this version");
+}
+
+int bf_vcycle(bf_grid* g, int32_t op, double c, const bf_solver_opts* o, const double* r,
+              double* z) {
+  TRY(check_grid(g));
+  if (!r || !z) return fail(BF_EINVAL, "null field");
+  if (op != BF_OP_LAP && op != BF_OP_CH) return fail(BF_EINVAL, "op %d", op);
+  bf_solver_opts d;
+  default_opts(op, &d);
+  const bf_solver_opts& oo = o ? *o : d;
+  TRY(check_opts(oo));
+  if (op == BF_OP_CH) TRY(ensure_coarse_ch(g, c));
+  double* res = vcycle_level(g, op, c, oo, 0, r);
+  launch_copy(g->npts, res, z, g->stream);
+  HIPCHK(hipGetLastError());
+  return BF_OK;
+}
+
+int bf_restrict(bf_grid* g, int32_t nf, const double* fine, double* coarse) {
+  TRY(check_grid(g));
+  if (!fine || !coarse) return fail(BF_EINVAL, "null field");
+  if (!is_pow2(nf) || nf < 8 || nf > g->n) return fail(BF_EINVAL, "nf = %d", nf);
+  launch_restrict(nf, fine, coarse, g->stream);
+  HIPCHK(hipGetLastError());
+  return BF_OK;
+}
+
+int bf_prolong_add(bf_grid* g, int32_t nf, const double* coarse, double* fine) {
+  TRY(check_grid(g));
+  if (!fine || !coarse) return fail(BF_EINVAL, "null field");
+  if (!is_pow2(nf) || nf < 8 || nf > g->n) return fail(BF_EINVAL, "nf = %d", nf);
+  launch_prolong_add(nf, coarse, fine, g->stream);
+  HIPCHK(hipGetLastError());
+  return BF_OK;
+}
+
+int bf_wdot(bf_grid* g, const double* x, const double* y, double* out) {
+  TRY(check_grid(g));
+  if (!x || !y || !out) return fail(BF_EINVAL, "null argument");
+  wdot_async(g, x, y, F_STORE, S_TMP);
+  TRY(read_scalars(g, S_TMP + 1));
+  *out = g->h_scal[S_TMP];
+  return BF_OK;
+}
+
+}  // extern "C"

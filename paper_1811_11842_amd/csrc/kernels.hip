@@ -1,0 +1,561 @@
+// Device kernels of the biofilm-flow step: matrix-free 5- and 13-point
+// operators, Chebyshev/Jacobi smoothing, cubic grid transfers, weighted
+// reductions, Krylov vector updates and the pointwise step pieces.
+//
+// Operators (paper, Sec. 4 and Sec. 4.1):
+//   L x   = n^2 (x[i-1] + x[i+1] + x[j-1] + x[j+1] - 4 x)   (matrix row 4,-1,-1,-1,-1
+//           of Listing "Constructing the matrix with DMDA", scaled by -1/h^2)
+//   A_CH x = x + s * (20 x - 8 axis + 2 diagonal + distance-two)  with s = c n^4,
+//           the Cahn-Hilliard step operator I + c L^2 (Sec. 2.2, eq. modCH)
+// Ghost rows by the two-layer reflection of eq. discreteBC, periodic x.
+#include <hip/hip_runtime.h>
+
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace bf {
+
+#define GRID_STRIDE(idx, total)                                                        \
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < (total); \
+       idx += (int64_t)gridDim.x * blockDim.x)
+
+template <int OP>
+__device__ __forceinline__ double stencil_at(const double* __restrict__ x, int i, int j, int n,
+                                             int mask, double coef, double& center) {
+  const double* r0 = x + (int64_t)j * n;
+  const double* rm1 = x + (int64_t)refl(j - 1, n) * n;
+  const double* rp1 = x + (int64_t)refl(j + 1, n) * n;
+  const int im1 = (i - 1) & mask, ip1 = (i + 1) & mask;
+  const double c = r0[i];
+  center = c;
+  const double axis = (r0[im1] + r0[ip1]) + (rm1[i] + rp1[i]);
+  if (OP == 0) return coef * (axis - 4.0 * c);
+  const double* rm2 = x + (int64_t)refl(j - 2, n) * n;
+  const double* rp2 = x + (int64_t)refl(j + 2, n) * n;
+  const int im2 = (i - 2) & mask, ip2 = (i + 2) & mask;
+  const double diag = (rm1[im1] + rm1[ip1]) + (rp1[im1] + rp1[ip1]);
+  const double far = (r0[im2] + r0[ip2]) + (rm2[i] + rp2[i]);
+  return c + coef * (20.0 * c - 8.0 * axis + 2.0 * diag + far);
+}
+
+template <int OP>
+__device__ __forceinline__ double dinv_at(const OpDesc& A, int j) {
+  if (OP == 0) return A.dinv_int;
+  return (j == 1 || j == A.n - 1) ? A.dinv_edge : A.dinv_int;
+}
+
+// ------------------------------------------------------------------ operators
+template <int OP>
+__global__ void __launch_bounds__(kBlock) k_apply(OpDesc A, Geo G, const double* __restrict__ x,
+                                                  double* __restrict__ y) {
+  GRID_STRIDE(idx, G.npts) {
+    const int i = (int)(idx & G.mask), j = (int)(idx >> G.log2n);
+    double c;
+    y[idx] = stencil_at<OP>(x, i, j, G.n, G.mask, A.coef, c);
+  }
+}
+
+template <int OP>
+__global__ void __launch_bounds__(kBlock) k_apply_dot(OpDesc A, Geo G, const double* __restrict__ p,
+                                                      double* __restrict__ q,
+                                                      double* __restrict__ partials) {
+  double acc = 0.0;
+  GRID_STRIDE(idx, G.npts) {
+    const int i = (int)(idx & G.mask), j = (int)(idx >> G.log2n);
+    double c;
+    const double v = stencil_at<OP>(p, i, j, G.n, G.mask, A.coef, c);
+    q[idx] = v;
+    acc += row_weight(j, G.n) * c * v;
+  }
+  const double t = block_sum(acc);
+  if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
+template <int OP>
+__global__ void __launch_bounds__(kBlock) k_residual(OpDesc A, Geo G, const double* __restrict__ x,
+                                                     const double* __restrict__ b,
+                                                     double* __restrict__ r,
+                                                     double* __restrict__ partials) {
+  double acc = 0.0;
+  GRID_STRIDE(idx, G.npts) {
+    const int i = (int)(idx & G.mask), j = (int)(idx >> G.log2n);
+    double v = b[idx];
+    if (x) {
+      double c;
+      v -= stencil_at<OP>(x, i, j, G.n, G.mask, A.coef, c);
+    }
+    r[idx] = v;
+    acc += row_weight(j, G.n) * v * v;
+  }
+  if (partials) {
+    const double t = block_sum(acc);
+    if (threadIdx.x == 0) partials[blockIdx.x] = t;
+  }
+}
+
+template <int OP>
+__global__ void __launch_bounds__(kBlock) k_smooth(OpDesc A, Geo G, const double* __restrict__ x,
+                                                   const double* xprev,
+                                                   const double* __restrict__ b, double* xout,
+                                                   double a, double g) {
+  GRID_STRIDE(idx, G.npts) {
+    const int i = (int)(idx & G.mask), j = (int)(idx >> G.log2n);
+    double c;
+    const double ax = stencil_at<OP>(x, i, j, G.n, G.mask, A.coef, c);
+    const double prev = xprev ? xprev[idx] : 0.0;
+    xout[idx] = c + a * dinv_at<OP>(A, j) * (b[idx] - ax) + g * (c - prev);
+  }
+}
+
+template <int OP>
+__global__ void __launch_bounds__(kBlock) k_smooth0(OpDesc A, Geo G, const double* __restrict__ b,
+                                                    double* __restrict__ xout, double a) {
+  GRID_STRIDE(idx, G.npts) {
+    const int j = (int)(idx >> G.log2n);
+    xout[idx] = a * dinv_at<OP>(A, j) * b[idx];
+  }
+}
+
+template <int OP>
+__global__ void __launch_bounds__(kBlock) k_jacobi_pc(OpDesc A, Geo G, const double* __restrict__ r,
+                                                      double* __restrict__ z) {
+  GRID_STRIDE(idx, G.npts) {
+    const int j = (int)(idx >> G.log2n);
+    z[idx] = dinv_at<OP>(A, j) * r[idx];
+  }
+}
+
+// ------------------------------------------------------------------ transfers
+// coarse(J, I) = sum_{dj, di in {0, +-1, +-3}} w_dj w_di fine(2J+dj, 2I+di),
+// w_0 = 1/2, w_{+-1} = 9/32, w_{+-3} = -1/32 (the weighted adjoint of cubic
+// interpolation, scaled by 1/4), fine rows reflected, columns wrapped.
+__global__ void __launch_bounds__(kBlock) k_restrict(Geo F, Geo C, const double* __restrict__ fine,
+                                                     double* __restrict__ coarse) {
+  const int off[5] = {-3, -1, 0, 1, 3};
+  const double w[5] = {-1.0 / 32, 9.0 / 32, 0.5, 9.0 / 32, -1.0 / 32};
+  GRID_STRIDE(idx, C.npts) {
+    const int I = (int)(idx & C.mask), J = (int)(idx >> C.log2n);
+    double acc = 0.0;
+#pragma unroll
+    for (int a = 0; a < 5; ++a) {
+      const double* row = fine + (int64_t)refl(2 * J + off[a], F.n) * F.n;
+      double rs = 0.0;
+#pragma unroll
+      for (int c = 0; c < 5; ++c) rs += w[c] * row[(2 * I + off[c]) & F.mask];
+      acc += w[a] * rs;
+    }
+    coarse[idx] = acc;
+  }
+}
+
+// fine += P coarse, P = tensor-product cubic interpolation (-1, 9, 9, -1)/16
+// at odd fine nodes, injection at even ones; coarse rows reflected, columns wrapped.
+__device__ __forceinline__ double interp_x(const double* __restrict__ coarse, const Geo& C, int J,
+                                           int i) {
+  const double* row = coarse + (int64_t)refl(J, C.n) * C.n;
+  const int I = i >> 1;
+  if ((i & 1) == 0) return row[I];
+  return (-row[(I - 1) & C.mask] + 9.0 * row[I] + 9.0 * row[(I + 1) & C.mask] -
+          row[(I + 2) & C.mask]) *
+         0.0625;
+}
+
+__global__ void __launch_bounds__(kBlock) k_prolong_add(Geo F, Geo C, const double* __restrict__ coarse,
+                                                        double* __restrict__ fine) {
+  GRID_STRIDE(idx, F.npts) {
+    const int i = (int)(idx & F.mask), j = (int)(idx >> F.log2n);
+    const int J = j >> 1;
+    double v;
+    if ((j & 1) == 0) {
+      v = interp_x(coarse, C, J, i);
+    } else {
+      v = (-interp_x(coarse, C, J - 1, i) + 9.0 * interp_x(coarse, C, J, i) +
+           9.0 * interp_x(coarse, C, J + 1, i) - interp_x(coarse, C, J + 2, i)) *
+          0.0625;
+    }
+    fine[idx] += v;
+  }
+}
+
+__global__ void k_coarse_solve(int size, const double* __restrict__ G, const double* __restrict__ b,
+                               double* __restrict__ x) {
+  const int k = threadIdx.x;
+  if (k < size) {
+    double acc = 0.0;
+    for (int l = 0; l < size; ++l) acc += G[k * size + l] * b[l];
+    x[k] = acc;
+  }
+}
+
+// ------------------------------------------------------------------ reductions
+__global__ void __launch_bounds__(kBlock) k_dot(Geo G, const double* __restrict__ x,
+                                                const double* __restrict__ y,
+                                                double* __restrict__ partials) {
+  double acc = 0.0;
+  GRID_STRIDE(idx, G.npts) {
+    const int j = (int)(idx >> G.log2n);
+    acc += row_weight(j, G.n) * x[idx] * (y ? y[idx] : 1.0);
+  }
+  const double t = block_sum(acc);
+  if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
+__global__ void __launch_bounds__(kBlock) k_finalize(const double* __restrict__ partials, int nparts,
+                                                     double* __restrict__ scal, int mode, int slot,
+                                                     double nn) {
+  double acc = 0.0;
+  for (int k = threadIdx.x; k < nparts; k += kBlock) acc += partials[k];
+  const double s = block_sum(acc);
+  if (threadIdx.x == 0) {
+    switch (mode) {
+      case F_STORE:
+        scal[slot] = s;
+        break;
+      case F_ALPHA:
+        scal[S_PQ] = s;
+        scal[S_ALPHA] = scal[S_RZ] / s;
+        break;
+      case F_BETA: {
+        const double old = scal[S_RZ];
+        scal[S_RZOLD] = old;
+        scal[S_RZ] = s;
+        scal[S_BETA] = s / old;
+        break;
+      }
+      case F_MEAN:
+        scal[S_MEAN] = s / nn;
+        break;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_cg_update(Geo G, double* __restrict__ x,
+                                                      const double* __restrict__ p,
+                                                      double* __restrict__ r,
+                                                      const double* __restrict__ q,
+                                                      const double* __restrict__ scal,
+                                                      double* __restrict__ partials) {
+  const double alpha = scal[S_ALPHA];
+  double acc = 0.0;
+  GRID_STRIDE(idx, G.npts) {
+    const int j = (int)(idx >> G.log2n);
+    x[idx] += alpha * p[idx];
+    const double rv = r[idx] - alpha * q[idx];
+    r[idx] = rv;
+    acc += row_weight(j, G.n) * rv * rv;
+  }
+  const double t = block_sum(acc);
+  if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
+__global__ void __launch_bounds__(kBlock) k_xpby(Geo G, const double* __restrict__ z,
+                                                 double* __restrict__ p,
+                                                 const double* __restrict__ scal) {
+  const double beta = scal[S_BETA];
+  GRID_STRIDE(idx, G.npts) p[idx] = z[idx] + beta * p[idx];
+}
+
+__global__ void __launch_bounds__(kBlock) k_sub_mean(Geo G, const double* x, double* y,
+                                                     const double* __restrict__ scal) {
+  const double m = scal[S_MEAN];
+  GRID_STRIDE(idx, G.npts) y[idx] = x[idx] - m;
+}
+
+__global__ void __launch_bounds__(kBlock) k_fill(int64_t count, double* __restrict__ x, double v) {
+  GRID_STRIDE(idx, count) x[idx] = v;
+}
+
+__global__ void __launch_bounds__(kBlock) k_copy(int64_t count, const double* __restrict__ x,
+                                                 double* __restrict__ y) {
+  GRID_STRIDE(idx, count) y[idx] = x[idx];
+}
+
+__global__ void k_fill_i32(int count, int32_t* x, int32_t v) {
+  GRID_STRIDE(idx, count) x[idx] = v;
+}
+
+// ------------------------------------------------------------------ step pieces
+__device__ __forceinline__ double mu_fh(double f, double inv_npoly, double chi) {
+  return log(f) * inv_npoly + inv_npoly - log(1.0 - f) - 1.0 + chi * (1.0 - 2.0 * f);
+}
+
+__device__ __forceinline__ double clampd(double f, double lo, double hi) {
+  return fmin(fmax(f, lo), hi);
+}
+
+// b = phi + dt*M * L mu(clamp(phi)); mu even across the walls.
+__global__ void __launch_bounds__(kBlock) k_ch_rhs(Geo G, const double* __restrict__ phi,
+                                                   double* __restrict__ b, double dtMn2,
+                                                   double inv_npoly, double chi, double lo,
+                                                   double hi, int32_t* clamp_count) {
+  int cnt = 0;
+  GRID_STRIDE(idx, G.npts) {
+    const int i = (int)(idx & G.mask), j = (int)(idx >> G.log2n);
+    const int n = G.n;
+    const double* r0 = phi + (int64_t)j * n;
+    const double* rm = phi + (int64_t)refl(j - 1, n) * n;
+    const double* rp = phi + (int64_t)refl(j + 1, n) * n;
+    const double c = r0[i];
+    cnt += (c < lo || c > hi) ? 1 : 0;
+    const double mc = mu_fh(clampd(c, lo, hi), inv_npoly, chi);
+    const double ml = mu_fh(clampd(r0[(i - 1) & G.mask], lo, hi), inv_npoly, chi);
+    const double mr = mu_fh(clampd(r0[(i + 1) & G.mask], lo, hi), inv_npoly, chi);
+    const double md = mu_fh(clampd(rm[i], lo, hi), inv_npoly, chi);
+    const double mu = mu_fh(clampd(rp[i], lo, hi), inv_npoly, chi);
+    b[idx] = c + dtMn2 * ((ml + mr) + (md + mu) - 4.0 * mc);
+  }
+  if (clamp_count && cnt) atomicAdd(clamp_count, cnt);
+}
+
+// rhs = (u[i+1] - u[i-1] + v[j+1] - v[j-1]) * scale, v odd across the walls.
+__global__ void __launch_bounds__(kBlock) k_divergence(Geo G, const double* __restrict__ u,
+                                                       const double* __restrict__ v,
+                                                       double* __restrict__ rhs, double scale) {
+  GRID_STRIDE(idx, G.npts) {
+    const int i = (int)(idx & G.mask), j = (int)(idx >> G.log2n);
+    const int n = G.n;
+    const double* ur = u + (int64_t)j * n;
+    const double vp = (j == n) ? -v[(int64_t)(n - 1) * n + i] : v[idx + n];
+    const double vm = (j == 0) ? -v[(int64_t)n + i] : v[idx - n];
+    rhs[idx] = ((ur[(i + 1) & G.mask] - ur[(i - 1) & G.mask]) + (vp - vm)) * scale;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_velocity(Geo G, const double* __restrict__ p,
+                                                     const double* us, const double* vs,
+                                                     double* u, double* v, double scale) {
+  GRID_STRIDE(idx, G.npts) {
+    const int i = (int)(idx & G.mask), j = (int)(idx >> G.log2n);
+    const int n = G.n;
+    const double* pr = p + (int64_t)j * n;
+    const double gx = pr[(i + 1) & G.mask] - pr[(i - 1) & G.mask];
+    const double gy = p[(int64_t)refl(j + 1, n) * n + i] - p[(int64_t)refl(j - 1, n) * n + i];
+    if (u) u[idx] = us[idx] - scale * gx;
+    if (v) v[idx] = vs[idx] - scale * gy;
+  }
+}
+
+// ------------------------------------------------------------------ GMRES pieces
+constexpr int kMdotGroup = 8;
+
+__global__ void __launch_bounds__(kBlock) k_mdot(Geo G, const double* __restrict__ V, int m, int k0,
+                                                 const double* __restrict__ w,
+                                                 double* __restrict__ partials) {
+  double acc[kMdotGroup];
+#pragma unroll
+  for (int k = 0; k < kMdotGroup; ++k) acc[k] = 0.0;
+  const int kn = min(kMdotGroup, m - k0);
+  GRID_STRIDE(idx, G.npts) {
+    const int j = (int)(idx >> G.log2n);
+    const double ww = row_weight(j, G.n) * w[idx];
+#pragma unroll
+    for (int k = 0; k < kMdotGroup; ++k)
+      if (k < kn) acc[k] += V[(int64_t)(k0 + k) * G.npts + idx] * ww;
+  }
+  for (int k = 0; k < kn; ++k) {
+    const double t = block_sum(acc[k]);
+    if (threadIdx.x == 0) partials[(int64_t)(k0 + k) * gridDim.x + blockIdx.x] = t;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_finalize_multi(const double* __restrict__ partials,
+                                                           int nparts, double* __restrict__ scal,
+                                                           int slot) {
+  const int k = blockIdx.x;
+  double acc = 0.0;
+  for (int t = threadIdx.x; t < nparts; t += kBlock) acc += partials[(int64_t)k * nparts + t];
+  const double s = block_sum(acc);
+  if (threadIdx.x == 0) scal[slot + k] = s;
+}
+
+__global__ void __launch_bounds__(kBlock) k_maxpy(Geo G, const double* __restrict__ V, int m,
+                                                  const double* __restrict__ h,
+                                                  double* __restrict__ w,
+                                                  double* __restrict__ partials) {
+  double acc = 0.0;
+  GRID_STRIDE(idx, G.npts) {
+    const int j = (int)(idx >> G.log2n);
+    double v = w[idx];
+    for (int k = 0; k < m; ++k) v -= h[k] * V[(int64_t)k * G.npts + idx];
+    w[idx] = v;
+    acc += row_weight(j, G.n) * v * v;
+  }
+  if (partials) {
+    const double t = block_sum(acc);
+    if (threadIdx.x == 0) partials[blockIdx.x] = t;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_axpy_multi(Geo G, const double* __restrict__ Z, int m,
+                                                       const double* __restrict__ y,
+                                                       double* __restrict__ x) {
+  GRID_STRIDE(idx, G.npts) {
+    double v = x[idx];
+    for (int k = 0; k < m; ++k) v += y[k] * Z[(int64_t)k * G.npts + idx];
+    x[idx] = v;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_scale(Geo G, const double* __restrict__ x,
+                                                  double* __restrict__ y,
+                                                  const double* __restrict__ scal, int slot,
+                                                  int invert_sqrt) {
+  const double s = invert_sqrt ? 1.0 / sqrt(scal[slot]) : scal[slot];
+  GRID_STRIDE(idx, G.npts) y[idx] = s * x[idx];
+}
+
+// ------------------------------------------------------------------ launchers
+#define LAUNCH(kern, blocks, st, ...) hipLaunchKernelGGL(kern, dim3(blocks), dim3(kBlock), 0, st, __VA_ARGS__)
+
+void launch_apply(const OpDesc& A, const double* x, double* y, hipStream_t st) {
+  const Geo G = make_geo(A.n);
+  if (A.op == 0)
+    LAUNCH(k_apply<0>, ew_blocks(G.npts), st, A, G, x, y);
+  else
+    LAUNCH(k_apply<1>, ew_blocks(G.npts), st, A, G, x, y);
+}
+
+void launch_apply_dot(const OpDesc& A, const double* p, double* q, double* partials, int nparts,
+                      hipStream_t st) {
+  const Geo G = make_geo(A.n);
+  if (A.op == 0)
+    LAUNCH(k_apply_dot<0>, nparts, st, A, G, p, q, partials);
+  else
+    LAUNCH(k_apply_dot<1>, nparts, st, A, G, p, q, partials);
+}
+
+void launch_residual(const OpDesc& A, const double* x, const double* b, double* r,
+                     double* partials, int nparts, hipStream_t st) {
+  const Geo G = make_geo(A.n);
+  const int blocks = partials ? nparts : ew_blocks(G.npts);
+  if (A.op == 0)
+    LAUNCH(k_residual<0>, blocks, st, A, G, x, b, r, partials);
+  else
+    LAUNCH(k_residual<1>, blocks, st, A, G, x, b, r, partials);
+}
+
+void launch_smooth(const OpDesc& A, const double* x, const double* xprev, const double* b,
+                   double* xout, double a, double g, hipStream_t st) {
+  const Geo G = make_geo(A.n);
+  if (A.op == 0)
+    LAUNCH(k_smooth<0>, ew_blocks(G.npts), st, A, G, x, xprev, b, xout, a, g);
+  else
+    LAUNCH(k_smooth<1>, ew_blocks(G.npts), st, A, G, x, xprev, b, xout, a, g);
+}
+
+void launch_smooth0(const OpDesc& A, const double* b, double* xout, double a, hipStream_t st) {
+  const Geo G = make_geo(A.n);
+  if (A.op == 0)
+    LAUNCH(k_smooth0<0>, ew_blocks(G.npts), st, A, G, b, xout, a);
+  else
+    LAUNCH(k_smooth0<1>, ew_blocks(G.npts), st, A, G, b, xout, a);
+}
+
+void launch_jacobi_pc(const OpDesc& A, const double* r, double* z, hipStream_t st) {
+  const Geo G = make_geo(A.n);
+  if (A.op == 0)
+    LAUNCH(k_jacobi_pc<0>, ew_blocks(G.npts), st, A, G, r, z);
+  else
+    LAUNCH(k_jacobi_pc<1>, ew_blocks(G.npts), st, A, G, r, z);
+}
+
+void launch_restrict(int nf, const double* fine, double* coarse, hipStream_t st) {
+  const Geo F = make_geo(nf), C = make_geo(nf / 2);
+  LAUNCH(k_restrict, ew_blocks(C.npts), st, F, C, fine, coarse);
+}
+
+void launch_prolong_add(int nf, const double* coarse, double* fine, hipStream_t st) {
+  const Geo F = make_geo(nf), C = make_geo(nf / 2);
+  LAUNCH(k_prolong_add, ew_blocks(F.npts), st, F, C, coarse, fine);
+}
+
+void launch_coarse_solve(int size, const double* G, const double* b, double* x, hipStream_t st) {
+  hipLaunchKernelGGL(k_coarse_solve, dim3(1), dim3(64), 0, st, size, G, b, x);
+}
+
+void launch_dot(int n, const double* x, const double* y, double* partials, int nparts,
+                hipStream_t st) {
+  LAUNCH(k_dot, nparts, st, make_geo(n), x, y, partials);
+}
+
+void launch_finalize(const double* partials, int nparts, double* scal, int mode, int slot, int n,
+                     hipStream_t st) {
+  LAUNCH(k_finalize, 1, st, partials, nparts, scal, mode, slot, (double)n * (double)n);
+}
+
+void launch_cg_update(int n, double* x, const double* p, double* r, const double* q,
+                      const double* scal, double* partials, int nparts, hipStream_t st) {
+  LAUNCH(k_cg_update, nparts, st, make_geo(n), x, p, r, q, scal, partials);
+}
+
+void launch_xpby(int n, const double* z, double* p, const double* scal, hipStream_t st) {
+  const Geo G = make_geo(n);
+  LAUNCH(k_xpby, ew_blocks(G.npts), st, G, z, p, scal);
+}
+
+void launch_sub_mean(int n, const double* x, double* y, const double* scal, hipStream_t st) {
+  const Geo G = make_geo(n);
+  LAUNCH(k_sub_mean, ew_blocks(G.npts), st, G, x, y, scal);
+}
+
+void launch_fill(int64_t count, double* x, double v, hipStream_t st) {
+  LAUNCH(k_fill, ew_blocks(count), st, count, x, v);
+}
+
+void launch_copy(int64_t count, const double* x, double* y, hipStream_t st) {
+  LAUNCH(k_copy, ew_blocks(count), st, count, x, y);
+}
+
+void launch_fill_i32(int count, int32_t* x, int32_t v, hipStream_t st) {
+  LAUNCH(k_fill_i32, 1, st, count, x, v);
+}
+
+void launch_ch_rhs(int n, const double* phi, double* b, double dtM, double inv_npoly, double chi,
+                   double lo, double hi, int32_t* clamp_count, hipStream_t st) {
+  const Geo G = make_geo(n);
+  LAUNCH(k_ch_rhs, ew_blocks(G.npts), st, G, phi, b, dtM * (double)n * (double)n, inv_npoly, chi,
+         lo, hi, clamp_count);
+}
+
+void launch_divergence(int n, const double* u, const double* v, double* rhs, double scale,
+                       hipStream_t st) {
+  const Geo G = make_geo(n);
+  LAUNCH(k_divergence, ew_blocks(G.npts), st, G, u, v, rhs, scale);
+}
+
+void launch_velocity(int n, const double* p, const double* us, const double* vs, double* u,
+                     double* v, double scale, hipStream_t st) {
+  const Geo G = make_geo(n);
+  LAUNCH(k_velocity, ew_blocks(G.npts), st, G, p, us, vs, u, v, scale);
+}
+
+void launch_mdot(int n, const double* V, int m, const double* w, double* partials, int nparts,
+                 hipStream_t st) {
+  const Geo G = make_geo(n);
+  for (int k0 = 0; k0 < m; k0 += kMdotGroup) LAUNCH(k_mdot, nparts, st, G, V, m, k0, w, partials);
+}
+
+void launch_finalize_multi(const double* partials, int nparts, int m, double* scal, int slot,
+                           hipStream_t st) {
+  LAUNCH(k_finalize_multi, m, st, partials, nparts, scal, slot);
+}
+
+void launch_maxpy(int n, const double* V, int m, const double* h, double* w, double* partials,
+                  int nparts, hipStream_t st) {
+  const Geo G = make_geo(n);
+  LAUNCH(k_maxpy, partials ? nparts : ew_blocks(G.npts), st, G, V, m, h, w, partials);
+}
+
+void launch_axpy_multi(int n, const double* Z, int m, const double* y, double* x,
+                       hipStream_t st) {
+  const Geo G = make_geo(n);
+  LAUNCH(k_axpy_multi, ew_blocks(G.npts), st, G, Z, m, y, x);
+}
+
+void launch_scale(int n, const double* x, double* y, const double* scal, int slot, int invert_sqrt,
+                  hipStream_t st) {
+  const Geo G = make_geo(n);
+  LAUNCH(k_scale, ew_blocks(G.npts), st, G, x, y, scal, slot, invert_sqrt);
+}
+
+}  // namespace bf

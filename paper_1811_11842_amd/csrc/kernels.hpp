@@ -1,0 +1,85 @@
+// Launchers of the device kernels (host-callable, asynchronous on `st`).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.hpp"
+
+namespace bf {
+
+// Operator of one grid level: y = A x.
+//   OP_LAP: A = L (5-point), coef = n^2
+//   OP_CH : A = I + s * S13 with S13 the integer 13-point stencil, s = c n^4
+struct OpDesc {
+  int op;          // 0 = Laplacian, 1 = Cahn-Hilliard
+  int n;
+  double coef;     // n^2 (LAP) or s = c n^4 (CH)
+  double dinv_int; // 1 / diag on ordinary rows
+  double dinv_edge;// 1 / diag on rows 1 and n-1
+};
+
+void launch_apply(const OpDesc& A, const double* x, double* y, hipStream_t st);
+// q = A p and per-block partials of <p, q>_W.
+void launch_apply_dot(const OpDesc& A, const double* p, double* q, double* partials,
+                      int nparts, hipStream_t st);
+// r = b - A x (x == nullptr means x = 0); partials of ||r||_W^2 if partials != nullptr.
+void launch_residual(const OpDesc& A, const double* x, const double* b, double* r,
+                     double* partials, int nparts, hipStream_t st);
+// xout = x + a D^{-1}(b - A x) + g (x - xprev); xprev == nullptr means 0.
+// xout may alias xprev, not x.
+void launch_smooth(const OpDesc& A, const double* x, const double* xprev, const double* b,
+                   double* xout, double a, double g, hipStream_t st);
+// xout = a D^{-1} b (first sweep from a zero guess).
+void launch_smooth0(const OpDesc& A, const double* b, double* xout, double a, hipStream_t st);
+// z = D^{-1} r (Jacobi preconditioner).
+void launch_jacobi_pc(const OpDesc& A, const double* r, double* z, hipStream_t st);
+
+void launch_restrict(int nf, const double* fine, double* coarse, hipStream_t st);
+void launch_prolong_add(int nf, const double* coarse, double* fine, hipStream_t st);
+// x = G b on the coarsest grid (dense size x size matrix, row-major).
+void launch_coarse_solve(int size, const double* G, const double* b, double* x, hipStream_t st);
+
+// partials of <x, y>_W (y == nullptr means y = 1: weighted sum of x).
+void launch_dot(int n, const double* x, const double* y, double* partials, int nparts,
+                hipStream_t st);
+// Reduce partials in a fixed order and update scalars (see FinalizeMode).
+void launch_finalize(const double* partials, int nparts, double* scal, int mode, int slot,
+                     int n, hipStream_t st);
+// x += alpha p; r -= alpha q (alpha = scal[S_ALPHA]); partials of ||r||_W^2.
+void launch_cg_update(int n, double* x, const double* p, double* r, const double* q,
+                      const double* scal, double* partials, int nparts, hipStream_t st);
+// p = z + beta p (beta = scal[S_BETA]).
+void launch_xpby(int n, const double* z, double* p, const double* scal, hipStream_t st);
+// y = x - scal[S_MEAN]
+void launch_sub_mean(int n, const double* x, double* y, const double* scal, hipStream_t st);
+void launch_fill(int64_t count, double* x, double v, hipStream_t st);
+void launch_copy(int64_t count, const double* x, double* y, hipStream_t st);
+void launch_fill_i32(int count, int32_t* x, int32_t v, hipStream_t st);
+
+// Step pieces.
+void launch_ch_rhs(int n, const double* phi, double* b, double dtM, double inv_npoly,
+                   double chi, double lo, double hi, int32_t* clamp_count, hipStream_t st);
+void launch_divergence(int n, const double* u, const double* v, double* rhs, double scale,
+                       hipStream_t st);
+void launch_velocity(int n, const double* p, const double* us, const double* vs, double* u,
+                     double* v, double scale, hipStream_t st);
+
+// GMRES pieces (weighted inner products).
+// partials[k * nparts + b] of <V_k, w>_W for k < m (V: m vectors of npts each).
+void launch_mdot(int n, const double* V, int m, const double* w, double* partials, int nparts,
+                 hipStream_t st);
+// Reduce m groups of partials: scal[slot + k] = sum_b partials[k * nparts + b].
+void launch_finalize_multi(const double* partials, int nparts, int m, double* scal, int slot,
+                           hipStream_t st);
+// w -= sum_k h[k] V_k (h = scal + slot), and partials of ||w||_W^2.
+void launch_maxpy(int n, const double* V, int m, const double* h, double* w, double* partials,
+                  int nparts, hipStream_t st);
+// x += sum_k y[k] Z_k with y = host-provided coefficients (device array).
+void launch_axpy_multi(int n, const double* Z, int m, const double* y, double* x,
+                       hipStream_t st);
+// y = a * x
+void launch_scale(int n, const double* x, double* y, const double* scal, int slot, int invert_sqrt,
+                  hipStream_t st);
+
+}  // namespace bf

@@ -1,0 +1,336 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on the
+same seeded inputs.
+
+Tolerances
+  * operators / transfers / pointwise pieces: per entry
+    |gpu - oracle| <= 8 u * (sum of |stencil weights|) * max|input|, u = 2^-53;
+  * one V-cycle: relative weighted L2 difference <= 1e-10;
+  * solves: forward error ||x - x_ld||_W / ||x_ld||_W <= 1e-10 against the
+    long-double spectral solution, and the oracle-recomputed residual
+    <= max(rtol, 4 * rho_fl) with rho_fl the float64 residual of the oracle's
+    own float64 spectral solution (the rounding floor of the operator).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synthetic as S
+from oracle import fh, mg, ops, spectral
+
+bf = pytest.importorskip("paper_1811_11842_amd")
+
+pytestmark = pytest.mark.gpu
+U = 2.0 ** -53
+PRM = S.DEFAULT_PARAMS
+C_CH = PRM["dt"] * PRM["M"] * PRM["kappa"]
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    return torch.device("cuda:0")
+
+
+_grids = {}
+
+
+def grid(n):
+    if n not in _grids:
+        _grids[n] = bf.Grid(n)
+    return _grids[n]
+
+
+def to_dev(a, dev):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+def to_np(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def relw(a, b):
+    return float(ops.wnorm(a - b) / ops.wnorm(b))
+
+
+# ------------------------------------------------------------------ operators
+@pytest.mark.parametrize("n", [4, 8, 64, 256, 1024])
+@pytest.mark.parametrize("op", ["lap", "ch"])
+def test_apply_matches_oracle(dev, n, op):
+    print(f"apply op={op} n={n}", flush=True)
+    x = S.random_field(n, seed=100 + n)
+    g = grid(n)
+    xd = to_dev(x, dev)
+    c = 3e-7 if op == "ch" else 0.0
+    y = to_np(g.apply(bf.OP_CH if op == "ch" else bf.OP_LAP, c, xd))
+    if op == "ch":
+        ref = ops.apply_ch(x, c)
+        wsum = 1 + 64 * c * float(n) ** 4
+    else:
+        ref = ops.lap5(x)
+        wsum = 8.0 * n * n
+    tol = 8 * U * wsum * np.abs(x).max()
+    assert np.abs(y - ref).max() <= tol
+
+
+@pytest.mark.parametrize("nf", [8, 16, 128, 1024])
+def test_restrict_and_prolong_match_oracle(dev, nf):
+    g = grid(max(nf, 8))
+    f = S.random_field(nf, seed=7 + nf)
+    c = S.random_field(nf // 2, seed=8 + nf)
+    rc = to_np(g.restrict(nf, to_dev(f, dev)))
+    assert np.abs(rc - mg.restrict(f)).max() <= 8 * U * 1.27 * np.abs(f).max()
+    base = S.random_field(nf, seed=9 + nf)
+    fd = to_dev(base, dev)
+    g.prolong_add(nf, to_dev(c, dev), fd)
+    ref = base + mg.prolong(c)
+    assert np.abs(to_np(fd) - ref).max() <= 8 * U * (1.6 * np.abs(c).max() + np.abs(base).max())
+
+
+@pytest.mark.parametrize("n", [4, 8, 32, 256])
+@pytest.mark.parametrize("op", ["lap", "ch"])
+@pytest.mark.parametrize("smoother", ["chebyshev", "jacobi"])
+def test_vcycle_matches_oracle(dev, n, op, smoother):
+    print(f"vcycle op={op} n={n} smoother={smoother}", flush=True)
+    r = S.random_field(n, seed=200 + n)
+    c = C_CH if op == "ch" else 0.0
+    if op == "lap":
+        r = r - ops.wmean(r)
+    levels = mg.hierarchy(op, n, c, smoother=smoother)
+    ref = mg.vcycle(levels, r)
+    o = bf.default_opts(bf.OP_CH if op == "ch" else bf.OP_LAP,
+                        smoother=bf.SMOOTH_CHEBYSHEV if smoother == "chebyshev"
+                        else bf.SMOOTH_JACOBI)
+    z = to_np(grid(n).vcycle(bf.OP_CH if op == "ch" else bf.OP_LAP, c, to_dev(r, dev), opts=o))
+    if op == "lap":          # the coarse problem fixes the constant only on the coarsest grid
+        z, ref = z - ops.wmean(z), ref - ops.wmean(ref)
+    assert relw(z, ref) <= 1e-10
+
+
+# ------------------------------------------------------------------ step pieces
+@pytest.mark.parametrize("n", [8, 64, 1024])
+def test_ch_rhs_matches_oracle(dev, n):
+    phi = S.initial_phi(n)
+    g = grid(n)
+    cnt = torch.zeros(1, dtype=torch.int32, device=dev)
+    b = to_np(g.ch_rhs(bf.make_params(**PRM), to_dev(phi, dev), clamped=cnt))
+    ref = fh.rhs_ch(phi, PRM["dt"], PRM["M"], PRM["Npoly"], PRM["chi"])
+    mu = fh.mu_fh(fh.clamp(phi, 1e-6, 1 - 1e-6), PRM["Npoly"], PRM["chi"])
+    scale = np.abs(phi).max() + PRM["dt"] * n * n * 8 * np.abs(mu).max()
+    assert np.abs(b - ref).max() <= 64 * U * scale
+    assert int(cnt.item()) == fh.count_clamped(phi) == 0
+
+
+def test_ch_rhs_counts_clamped_points(dev):
+    n = 32
+    phi = S.initial_phi(n)
+    phi[3, 3] = 0.0
+    phi[4, 5] = 1.0
+    phi[6, 7] = -0.1
+    cnt = torch.zeros(1, dtype=torch.int32, device=dev)
+    b = to_np(grid(n).ch_rhs(bf.make_params(**PRM), to_dev(phi, dev), clamped=cnt))
+    assert int(cnt.item()) == 3
+    assert np.all(np.isfinite(b))
+    ref = fh.rhs_ch(phi, PRM["dt"], PRM["M"], PRM["Npoly"], PRM["chi"])
+    np.testing.assert_allclose(b, ref, rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("n", [8, 256])
+def test_divergence_and_velocity_match_oracle(dev, n):
+    u, v = S.inflow_velocity(n)
+    g = grid(n)
+    dt = PRM["dt"]
+    rhs = to_np(g.pressure_rhs(dt, to_dev(u, dev), to_dev(v, dev)))
+    ref = ops.divergence(u, v) / dt
+    scale = n / (2 * dt) * 4 * max(np.abs(u).max(), np.abs(v).max())
+    assert np.abs(rhs - ref).max() <= 8 * U * scale
+    p = S.random_field(n, seed=5)
+    uu, vv = g.velocity_correct(dt, to_dev(p, dev), to_dev(u, dev), to_dev(v, dev))
+    gx, gy = ops.gradient(p)
+    tolv = 8 * U * (np.abs(u).max() + dt * n * np.abs(p).max())
+    assert np.abs(to_np(uu) - (u - dt * gx)).max() <= tolv
+    assert np.abs(to_np(vv) - (v - dt * gy)).max() <= tolv
+
+
+# ------------------------------------------------------------------ solves
+def _floor_ch(b, c):
+    x = spectral.solve_ch(b, c)
+    return float(ops.wnorm(b - ops.apply_ch(x, c)) / ops.wnorm(b))
+
+
+@pytest.mark.parametrize("n,rtol", [(4, 1e-12), (8, 1e-12), (64, 1e-12), (256, 1e-10),
+                                    (1024, 1e-10)])
+def test_solve_ch_forward_error(dev, n, rtol):
+    print(f"solve_ch n={n}", flush=True)
+    phi = S.initial_phi(n)
+    b = fh.rhs_ch(phi, PRM["dt"], PRM["M"], PRM["Npoly"], PRM["chi"])
+    g = grid(n)
+    x = torch.zeros(g.shape, dtype=torch.float64, device=dev)
+    st = g.solve_ch(C_CH, to_dev(b, dev), x, bf.default_opts(bf.OP_CH, rtol=rtol))
+    xh = to_np(x)
+    x_ld = spectral.solve_ch(b.astype(np.longdouble), C_CH)
+    fe = float(ops.wnorm(xh - x_ld) / ops.wnorm(x_ld))
+    res = float(ops.wnorm(b - ops.apply_ch(xh, C_CH)) / ops.wnorm(b))
+    print(f"  iters={st.iters} status={st.status} fe={fe:.2e} res={res:.2e}")
+    assert st.status in (bf.OK, bf.AT_FLOOR)
+    assert fe <= 1e-10
+    assert res <= max(rtol, 4 * _floor_ch(b, C_CH))
+    assert st.iters <= 25
+
+
+@pytest.mark.parametrize("n,rtol", [(4, 1e-12), (8, 1e-12), (64, 1e-12), (256, 1e-12),
+                                    (1024, 1e-12)])
+def test_solve_pressure_forward_error(dev, n, rtol):
+    print(f"solve_pressure n={n}", flush=True)
+    u, v = S.inflow_velocity(n)
+    rhs = oracle.step.pressure_rhs(u, v, PRM["dt"])
+    g = grid(n)
+    p = torch.zeros(g.shape, dtype=torch.float64, device=dev)
+    st = g.solve_pressure(to_dev(rhs, dev), p, bf.default_opts(bf.OP_LAP, rtol=rtol))
+    ph = to_np(p)
+    p_ld = spectral.solve_poisson(rhs.astype(np.longdouble))
+    fe = float(ops.wnorm(ph - p_ld) / ops.wnorm(p_ld))
+    print(f"  iters={st.iters} status={st.status} fe={fe:.2e}")
+    assert st.status == bf.OK
+    assert fe <= 1e-10
+    assert abs(ops.wmean(ph)) <= 1e-14 * np.abs(ph).max()
+    assert st.iters <= 20
+
+
+@pytest.mark.parametrize("ksp,pc", [("cg", "jacobi"), ("gmres", "jacobi"), ("gmres", "mg"),
+                                    ("cg", "none")])
+def test_krylov_variants_reach_same_solution(dev, ksp, pc):
+    """GMRES + Jacobi is the paper's configuration (Sec. 4.1, Listing "Creating
+    PETSc KSP and PC objects"); every variant must reach the same solution."""
+    n = 32
+    phi = S.initial_phi(n)
+    b = fh.rhs_ch(phi, PRM["dt"], PRM["M"], PRM["Npoly"], PRM["chi"])
+    c = 1e-5
+    o = bf.default_opts(bf.OP_CH, rtol=1e-12, maxit=5000,
+                        ksp=bf.KSP_CG if ksp == "cg" else bf.KSP_GMRES,
+                        pc={"jacobi": bf.PC_JACOBI, "mg": bf.PC_MG, "none": bf.PC_NONE}[pc])
+    g = grid(n)
+    x = torch.zeros(g.shape, dtype=torch.float64, device=dev)
+    st = g.solve_ch(c, to_dev(b, dev), x, o)
+    xs = spectral.solve_ch(b.astype(np.longdouble), c)
+    assert st.status == bf.OK, st
+    assert relw(to_np(x), xs) <= 1e-10
+    rhs = S.random_field(n, 3)
+    o.pc = {"jacobi": bf.PC_JACOBI, "mg": bf.PC_MG, "none": bf.PC_NONE}[pc]
+    p = torch.zeros(g.shape, dtype=torch.float64, device=dev)
+    st = g.solve_pressure(to_dev(rhs, dev), p, o)
+    ps = spectral.solve_poisson(rhs.astype(np.longdouble))
+    assert st.status == bf.OK, st
+    assert relw(to_np(p), ps) <= 1e-9
+
+
+# ------------------------------------------------------------------ edge cases
+def test_zero_rhs_gives_zero(dev):
+    g = grid(64)
+    x = torch.ones(g.shape, dtype=torch.float64, device=dev)
+    st = g.solve_ch(C_CH, torch.zeros_like(x), x)
+    assert st.status == bf.OK and torch.count_nonzero(x).item() == 0
+    p = torch.ones_like(x)
+    st = g.solve_pressure(torch.full_like(x, 2.5), p)      # constant rhs is in the null space
+    assert st.status == bf.OK and float(p.abs().max()) == 0.0
+
+
+def test_maxit_reports_not_converged(dev):
+    g = grid(64)
+    b = to_dev(S.random_field(64, 1), dev)
+    x = torch.zeros_like(b)
+    st = g.solve_ch(C_CH, b, x, bf.default_opts(bf.OP_CH, maxit=1, rtol=1e-14))
+    assert st.status == bf.NOT_CONVERGED and st.iters == 1
+    assert 0 < st.rel_res_true < 1
+
+
+def test_nonfinite_input_rejected(dev):
+    g = grid(64)
+    b = to_dev(S.random_field(64, 1), dev)
+    b[10, 10] = float("nan")
+    x = torch.zeros_like(b)
+    with pytest.raises(bf.BiofilmError, match="ENONFINITE"):
+        g.solve_ch(C_CH, b, x)
+
+
+def test_bad_arguments_rejected(dev):
+    g = grid(64)
+    x = g.field(0.0)
+    with pytest.raises(bf.BiofilmError, match="EINVAL"):
+        g.solve_ch(C_CH, x, x)                        # aliasing
+    with pytest.raises(bf.BiofilmError, match="EINVAL"):
+        g.solve_ch(-1.0, x, g.field(0.0))
+    with pytest.raises(bf.BiofilmError, match="EINVAL"):
+        g.solve_ch(C_CH, x, g.field(0.0), bf.default_opts(bf.OP_CH, degree=9))
+    with pytest.raises(ValueError):
+        g.apply(bf.OP_LAP, 0.0, torch.zeros(10, 10, dtype=torch.float64, device=dev))
+    with pytest.raises(bf.BiofilmError, match="EUNSUPPORTED"):
+        g.adjoint_step(bf.make_params(), x, x, g.field())
+
+
+def test_solves_are_deterministic(dev):
+    n = 256
+    g = grid(n)
+    phi = S.initial_phi(n)
+    b = to_dev(fh.rhs_ch(phi, PRM["dt"], PRM["M"], PRM["Npoly"], PRM["chi"]), dev)
+    x1, x2 = torch.zeros_like(b), torch.zeros_like(b)
+    g.solve_ch(C_CH, b, x1)
+    g.solve_ch(C_CH, b, x2)
+    assert torch.equal(x1, x2)
+
+
+# ------------------------------------------------------------------ full steps
+def _run_step(dev, n, steps, rtol_ch=1e-10, rtol_p=1e-10):
+    phi0 = S.initial_phi(n)
+    u0, v0 = S.inflow_velocity(n)
+    g = grid(n)
+    phi = to_dev(phi0, dev)
+    us, vs = to_dev(u0, dev), to_dev(v0, dev)
+    p, u, v = g.field(), g.field(), g.field()
+    oc = bf.default_opts(bf.OP_CH, rtol=rtol_ch)
+    op = bf.default_opts(bf.OP_LAP, rtol=rtol_p)
+    stats = []
+    for _ in range(steps):
+        stats.append(g.step(bf.make_params(**PRM), phi, us, vs, p, u, v, oc, op))
+    return phi0, u0, v0, to_np(phi), to_np(p), to_np(u), to_np(v), stats
+
+
+def test_step_small_matches_oracle(dev):
+    n = 64
+    phi0, u0, v0, phi, p, u, v, stats = _run_step(dev, n, 1, 1e-12, 1e-12)
+    rphi, rp, ru, rv = oracle.step.step(phi0, u0, v0, **PRM)
+    assert relw(phi, rphi) <= 1e-10
+    assert relw(p, rp) <= 1e-10
+    assert relw(u, ru) <= 1e-10 and relw(v, rv) <= 1e-10
+    assert stats[0][0].clamped == 0
+
+
+def test_step_1024_three_steps_and_mass(dev):
+    n = 1024
+    phi0, u0, v0, phi, p, u, v, stats = _run_step(dev, n, 3)
+    rphi, rp, ru, rv = oracle.step.run(phi0, u0, v0, 3, **PRM)
+    print("iters", [(a.iters, b.iters) for a, b in stats])
+    assert relw(phi, rphi) <= 1e-10
+    # pressure at rtol 1e-10: forward error bounded by the solve tolerance times
+    # the condition of the null-space-free Laplacian on this rhs; measured ~1e-10
+    assert relw(p, rp) <= 1e-9
+    m0, m1 = ops.mass(phi0), ops.mass(phi)
+    assert abs(m1 - m0) / m0 <= 1e-12
+
+
+def test_step_4096_matches_oracle(dev):
+    """The configuration the benchmark times: 4096 x 4096, float64, MG-PCG at
+    rtol 1e-10 (the Cahn-Hilliard solve stops at the float64 floor)."""
+    n = 4096
+    print("step n=4096", flush=True)
+    phi0, u0, v0, phi, p, u, v, stats = _run_step(dev, n, 1)
+    print("stats", stats[0][0], stats[0][1], flush=True)
+    rphi, rp, ru, rv = oracle.step.step(phi0, u0, v0, **PRM)
+    assert relw(phi, rphi) <= 1e-10
+    assert relw(p, rp) <= 1e-9
+    assert relw(u, ru) <= 1e-10 and relw(v, rv) <= 1e-10
+    assert stats[0][0].status in (bf.OK, bf.AT_FLOOR)
+    assert stats[0][1].status == bf.OK

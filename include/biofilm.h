@@ -44,8 +44,9 @@ typedef struct bf_grid bf_grid;
 enum bf_status {
   BF_OK = 0,
   BF_NOT_CONVERGED = 1,   /* maxit reached before the tolerance            */
-  BF_AT_FLOOR = 2,        /* true residual stagnated above rtol at the     */
-                          /* float64 rounding floor of the operator        */
+  BF_AT_FLOOR = 2,        /* recursive residual met rtol; the true one is  */
+                          /* at the float64 representation floor (above    */
+                          /* rtol): no float64 vector has a smaller one    */
   BF_EINVAL = -1,         /* bad argument (null pointer, n, option value)  */
   BF_ENOMEM = -2,         /* device allocation failed                      */
   BF_EHIP = -3,           /* HIP runtime error                             */
@@ -93,6 +94,9 @@ typedef struct {
   double  rel_res;       /* recursively updated relative residual at exit   */
   double  rel_res_true;  /* ||b - A x||_W / ||b||_W recomputed at exit      */
   double  ms;            /* device time of the call (HIP events)            */
+  double  floor_est;     /* expected rel_res_true of x rounded to float64:   */
+                         /* sqrt(sum_W ulp(x)^2/12 * sum_j A_jk^2)/||b||_W;  */
+                         /* BF_AT_FLOOR means rel_res_true <= 1.25 floor_est */
 } bf_solve_stats;
 
 /* Parameters of the reduced semi-implicit step (dimensionless). */
@@ -177,6 +181,16 @@ int bf_vcycle(bf_grid* g, int32_t op, double c, const bf_solver_opts* o,
  * Asynchronous. */
 int bf_restrict(bf_grid* g, int32_t nf, const double* fine, double* coarse);
 int bf_prolong_add(bf_grid* g, int32_t nf, const double* coarse, double* fine);
+
+/* r = b - A x for op (BF_OP_LAP or BF_OP_CH with coefficient c).  accurate
+ * != 0 evaluates the stencil sum in double-double (r correct to a few ulps
+ * of r itself, whatever c/h^4); accurate == 0 uses plain float64.  If
+ * rel_norm (host) is given it receives ||r||_W / ||b||_W; if floor_est (host)
+ * is given (accurate only) it receives the expected value of that ratio for
+ * the exact solution rounded to float64.  Synchronous when a host output is
+ * requested, asynchronous otherwise.  r must not alias x. */
+int bf_residual(bf_grid* g, int32_t op, double c, const double* b, const double* x,
+                double* r, int32_t accurate, double* rel_norm, double* floor_est);
 
 /* *out (host) = <x, y>_W.  Synchronises the grid's stream. */
 int bf_wdot(bf_grid* g, const double* x, const double* y, double* out);

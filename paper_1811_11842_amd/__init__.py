@@ -52,7 +52,7 @@ class SolveStats(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32),
                 ("restarts", ctypes.c_int32), ("clamped", ctypes.c_int32),
                 ("rel_res", ctypes.c_double), ("rel_res_true", ctypes.c_double),
-                ("ms", ctypes.c_double)]
+                ("ms", ctypes.c_double), ("floor_est", ctypes.c_double)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
@@ -109,6 +109,9 @@ def lib():
             "bf_restrict": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P]),
             "bf_prolong_add": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P]),
             "bf_wdot": (ctypes.c_int, [_P, _P, _P, ctypes.POINTER(ctypes.c_double)]),
+            "bf_residual": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_double, _P, _P, _P,
+                                           ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                                           ctypes.POINTER(ctypes.c_double)]),
             "bf_last_error": (ctypes.c_char_p, []),
         }
         for name, (res, args) in sig.items():
@@ -283,6 +286,15 @@ class Grid:
         _check(lib().bf_prolong_add(self._h, nf, self._ptr(coarse, "coarse", cs),
                                     self._ptr(fine, "fine", (nf + 1, nf))))
         return fine
+
+    def residual(self, op, c, b, x, r=None, accurate=True):
+        """(r, ||r||_W/||b||_W, floor estimate) with r = b - A x."""
+        r = self.field() if r is None else r
+        rel, fl = ctypes.c_double(), ctypes.c_double()
+        _check(lib().bf_residual(self._h, op, c, self._ptr(b, "b"), self._ptr(x, "x"),
+                                 self._ptr(r, "r"), 1 if accurate else 0, ctypes.byref(rel),
+                                 ctypes.byref(fl)))
+        return r, rel.value, fl.value
 
     def wdot(self, x, y) -> float:
         out = ctypes.c_double()

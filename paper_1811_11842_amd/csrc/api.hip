@@ -358,27 +358,88 @@ int read_scalars(bf_grid* g, int count) {
   return BF_OK;
 }
 
+// Constant-mode (mass) correction of a Cahn-Hilliard iterate.  The constant
+// field is an eigenvector of I + c L^2 with eigenvalue 1 and sum_W L^2 x = 0,
+// so the exact solution has sum_W x = sum_W b.  Adding the weighted mean of
+// (b - x) removes the constant-mode error of x (mass is then conserved to
+// rounding) and can only lower ||b - A x||_W.  The sums are taken on b and x
+// directly, not on a residual whose rounding is amplified by c/h^4.
+void mass_correct(bf_grid* g, const double* b, double* x) {
+  const int np = nparts_of(g);
+  launch_wsum_diff(g->n, b, x, g->partials, np, g->stream);
+  launch_finalize(g->partials, np, g->scal, F_MEAN, 0, g->n, g->stream);
+  launch_add_mean(g->n, x, x, g->scal, g->stream);
+}
+
 // ------------------------------------------------------------ Krylov drivers
 // Final status from the true residual (residual replacement / floor logic).
 struct KrylovState {
   int iters = 0, restarts = 0;
-  double rel = 0, rel_true = 0;
+  double rel = 0, rel_true = 0, floor_est = 0;
+  double rel_est_cycle = HUGE_VAL;  // GMRES: residual estimate at the end of a cycle
 };
 
-// CG in the weighted inner product with residual replacement: whenever the
-// recursively updated residual reaches rtol the true residual is recomputed;
-// if it is above rtol the iteration restarts from it, as long as each restart
-// improves the true residual by at least 10%; otherwise the solve stops at the
-// float64 floor of the operator (BF_AT_FLOOR).
+// Sum over j of A_jk^2 for an interior column k of the operator (the
+// amplification of independent rounding errors of x into the residual).
+double column_sq(const OpDesc& A) {
+  if (A.op == BF_OP_LAP) return 20.0 * A.coef * A.coef;
+  const double d = 1.0 + 20.0 * A.coef;
+  return d * d + 276.0 * A.coef * A.coef;
+}
+
+// True residual r = b - A x with the double-double stencil sum, written into r;
+// returns (via ks) ||r||_W / ||b||_W and the expected float64 representation
+// floor of that quantity, sqrt(sum_W ulp(x)^2 / 12 * column_sq) / ||b||_W.
+int true_residual(bf_grid* g, const OpDesc& A, const double* b, const double* x, double* r,
+                  double bn, KrylovState& ks) {
+  const int np = nparts_of(g);
+  launch_residual_dd(A, x, b, r, g->partials, np, g->stream);
+  launch_finalize(g->partials, np, g->scal, F_STORE, S_RTRUE, g->n, g->stream);
+  launch_finalize(g->partials + np, np, g->scal, F_STORE, S_ULP2, g->n, g->stream);
+  TRY(read_scalars(g, S_ULP2 + 1));
+  ks.rel_true = std::sqrt(g->h_scal[S_RTRUE]) / bn;
+  ks.floor_est = std::sqrt(g->h_scal[S_ULP2] / 12.0 * column_sq(A)) / bn;
+  if (!std::isfinite(ks.rel_true)) return fail(BF_ENONFINITE, "true residual is not finite");
+  return BF_OK;
+}
+
+// After a Krylov cycle has driven its recursive residual to rtol: decide from
+// the true residual whether to stop (BF_OK / BF_AT_FLOOR / BF_NOT_CONVERGED)
+// or to restart from it (returns -1 = restart).
+//  - true residual <= rtol: converged;
+//  - true residual within 25% of the representation floor: the residual left
+//    is the rounding of x to float64, no float64 vector does better
+//    (BF_AT_FLOOR; the recursive residual, which does not see that rounding,
+//    met rtol);
+//  - otherwise restart (iterative refinement) while each restart at least
+//    halves the true residual, up to max_restarts;
+//  - else BF_NOT_CONVERGED.
+int decide_after_cycle(const bf_solver_opts& o, KrylovState& ks, double& last_true,
+                       bool hit_maxit) {
+  if (ks.rel_true <= o.rtol) return BF_OK;
+  if (ks.rel_true <= 1.25 * ks.floor_est && !hit_maxit) return BF_AT_FLOOR;
+  if (hit_maxit) return BF_NOT_CONVERGED;
+  if (ks.restarts < o.max_restarts && ks.rel_true < 0.5 * last_true) {
+    ks.restarts++;
+    last_true = ks.rel_true;
+    return -1;
+  }
+  return BF_NOT_CONVERGED;
+}
+
+// CG in the weighted inner product.  For the Cahn-Hilliard operator q = A p
+// is evaluated with the double-double stencil sum, so the recursive residual
+// tracks the true one up to the rounding of x itself.  Whenever the recursive
+// residual reaches rtol the true residual is recomputed (double-double) and
+// decide_after_cycle() stops or restarts from it (residual replacement, i.e.
+// iterative refinement).
 int run_cg(bf_grid* g, int op, double c, const double* b, double* x, const bf_solver_opts& o,
            KrylovState& ks) {
   hipStream_t st = g->stream;
   const int np = nparts_of(g);
   const OpDesc A = level_op(op, g->n, c);
   wdot_async(g, b, b, F_STORE, S_BN2);
-  launch_residual(A, x, b, g->r, g->partials, np, st);
-  launch_finalize(g->partials, np, g->scal, F_STORE, S_RR, g->n, st);
-  TRY(read_scalars(g, S_RTRUE + 1));
+  TRY(read_scalars(g, S_BN2 + 1));
   const double bn2 = g->h_scal[S_BN2];
   if (!std::isfinite(bn2)) return fail(BF_ENONFINITE, "right-hand side is not finite");
   if (bn2 == 0.0) {
@@ -387,13 +448,11 @@ int run_cg(bf_grid* g, int op, double c, const double* b, double* x, const bf_so
     return BF_OK;
   }
   const double bn = std::sqrt(bn2);
-  double rel = std::sqrt(g->h_scal[S_RR]) / bn;
-  if (!std::isfinite(rel)) return fail(BF_ENONFINITE, "initial residual is not finite");
-  double last_true = rel;
-  ks.rel = ks.rel_true = rel;
-  if (rel <= o.rtol) return BF_OK;
+  TRY(true_residual(g, A, b, x, g->r, bn, ks));
+  ks.rel = ks.rel_true;
+  if (ks.rel_true <= o.rtol) return BF_OK;
+  double last_true = ks.rel_true;
 
-  int status = BF_NOT_CONVERGED;
   for (;;) {
     // (re)start from the residual in g->r
     double* z = precondition(g, op, c, o, g->r);
@@ -401,17 +460,16 @@ int run_cg(bf_grid* g, int op, double c, const double* b, double* x, const bf_so
     launch_copy(g->npts, z, g->p, st);
     bool converged = false;
     while (ks.iters < o.maxit) {
-      launch_apply_dot(A, g->p, g->q, g->partials, np, st);
+      launch_apply_dot(A, g->p, g->q, g->partials, np, st, op == BF_OP_CH);
       launch_finalize(g->partials, np, g->scal, F_ALPHA, 0, g->n, st);
       launch_cg_update(g->n, x, g->p, g->r, g->q, g->scal, g->partials, np, st);
       launch_finalize(g->partials, np, g->scal, F_STORE, S_RR, g->n, st);
       ks.iters++;
       if (ks.iters % o.check_every == 0 || ks.iters == o.maxit) {
         TRY(read_scalars(g, S_RR + 1));
-        rel = std::sqrt(g->h_scal[S_RR]) / bn;
-        ks.rel = rel;
-        if (!std::isfinite(rel)) return fail(BF_ENONFINITE, "residual norm is not finite");
-        if (rel <= o.rtol) {
+        ks.rel = std::sqrt(g->h_scal[S_RR]) / bn;
+        if (!std::isfinite(ks.rel)) return fail(BF_ENONFINITE, "residual norm is not finite");
+        if (ks.rel <= o.rtol) {
           converged = true;
           break;
         }
@@ -420,30 +478,11 @@ int run_cg(bf_grid* g, int op, double c, const double* b, double* x, const bf_so
       wdot_async(g, g->r, z, F_BETA, 0);
       launch_xpby(g->n, z, g->p, g->scal, st);
     }
-    // true residual, written into r (it becomes the restart residual)
-    launch_residual(A, x, b, g->r, g->partials, np, st);
-    launch_finalize(g->partials, np, g->scal, F_STORE, S_RTRUE, g->n, st);
-    TRY(read_scalars(g, S_RTRUE + 1));
-    const double rt = std::sqrt(g->h_scal[S_RTRUE]) / bn;
-    ks.rel_true = rt;
-    if (!std::isfinite(rt)) return fail(BF_ENONFINITE, "true residual is not finite");
-    if (rt <= o.rtol) {
-      status = BF_OK;
-      break;
-    }
-    if (!converged) {  // iteration limit
-      status = BF_NOT_CONVERGED;
-      break;
-    }
-    if (ks.restarts < o.max_restarts && rt < 0.9 * last_true) {
-      ks.restarts++;
-      last_true = rt;
-      continue;
-    }
-    status = rt <= 1e3 * o.rtol ? BF_AT_FLOOR : BF_NOT_CONVERGED;
-    break;
+    if (op == BF_OP_CH) mass_correct(g, b, x);
+    TRY(true_residual(g, A, b, x, g->r, bn, ks));
+    const int d = decide_after_cycle(o, ks, last_true, !converged);
+    if (d >= 0) return d;
   }
-  return status;
 }
 
 int ensure_gmres(bf_grid* g, int m) {
@@ -485,33 +524,31 @@ int run_gmres(bf_grid* g, int op, double c, const double* b, double* x, const bf
   const double bn = std::sqrt(bn2);
   std::vector<double> H((m + 1) * m), cs(m), sn(m), gv(m + 1), y(m);
   double last_true = HUGE_VAL;
-  int status = BF_NOT_CONVERGED;
-  for (;;) {
-    // r0 = b - A x, V0 = r0 / ||r0||
-    launch_residual(A, x, b, g->gm_V, g->partials, np, st);
-    launch_finalize(g->partials, np, g->scal, F_STORE, S_RTRUE, g->n, st);
-    TRY(read_scalars(g, S_RTRUE + 1));
-    const double beta = std::sqrt(g->h_scal[S_RTRUE]);
-    const double rt = beta / bn;
-    ks.rel_true = ks.rel = rt;
-    if (!std::isfinite(rt)) return fail(BF_ENONFINITE, "residual norm is not finite");
-    if (rt <= o.rtol) {
-      status = BF_OK;
-      break;
+  for (int cycle = 0;; ++cycle) {
+    // r0 = b - A x (double-double), V0 = r0 / ||r0||
+    if (op == BF_OP_CH && cycle > 0) mass_correct(g, b, x);
+    TRY(true_residual(g, A, b, x, g->gm_V, bn, ks));
+    ks.rel = ks.rel_true;
+    if (cycle == 0) {
+      if (ks.rel_true <= o.rtol) return BF_OK;
+      last_true = ks.rel_true;
+    } else {
+      // a GMRES cycle ends at rtol (estimated) or after m steps; only the
+      // former is a converged cycle for decide_after_cycle()
+      const bool cycle_converged = ks.rel_est_cycle <= o.rtol;
+      if (cycle_converged || ks.iters >= o.maxit) {
+        const int d = decide_after_cycle(o, ks, last_true, ks.iters >= o.maxit && !cycle_converged);
+        if (d >= 0) return d;
+      } else {
+        if (ks.rel_true <= o.rtol) return BF_OK;
+        last_true = std::min(last_true, ks.rel_true);
+      }
     }
-    if (ks.iters >= o.maxit) {
-      status = BF_NOT_CONVERGED;
-      break;
-    }
-    if (!(rt < 0.9 * last_true) && ks.restarts > 0) {
-      status = rt <= 1e3 * o.rtol ? BF_AT_FLOOR : BF_NOT_CONVERGED;
-      break;
-    }
-    last_true = rt;
-    if (ks.iters > 0) ks.restarts++;
+    const double beta = ks.rel_true * bn;
     launch_scale(g->n, g->gm_V, g->gm_V, g->scal, S_RTRUE, 1, st);
     std::fill(gv.begin(), gv.end(), 0.0);
     gv[0] = beta;
+    ks.rel_est_cycle = HUGE_VAL;
     int k = 0;
     for (; k < m && ks.iters < o.maxit; ++k) {
       double* Vk = g->gm_V + (int64_t)k * N;
@@ -519,7 +556,7 @@ int run_gmres(bf_grid* g, int op, double c, const double* b, double* x, const bf
       double* w = g->gm_V + (int64_t)(k + 1) * N;
       double* zk = precondition(g, op, c, o, Vk);
       launch_copy(N, zk, Zk, st);
-      launch_apply(A, Zk, w, st);
+      launch_apply_dot(A, Zk, w, g->partials, np, st, op == BF_OP_CH);
       // CGS2: h = V^T_W w, w -= V h, twice
       for (int pass = 0; pass < 2; ++pass) {
         launch_mdot(g->n, g->gm_V, k + 1, w, g->partials, np, st);
@@ -551,6 +588,7 @@ int run_gmres(bf_grid* g, int op, double c, const double* b, double* x, const bf
       gv[k] = cs[k] * gv[k];
       ks.iters++;
       ks.rel = std::fabs(gv[k + 1]) / bn;
+      ks.rel_est_cycle = ks.rel;
       if (ks.rel <= o.rtol || hn == 0.0) {
         ++k;
         break;
@@ -566,7 +604,6 @@ int run_gmres(bf_grid* g, int op, double c, const double* b, double* x, const bf
     launch_axpy_multi(g->n, g->gm_Z, k, g->gm_y, x, st);
     HIPCHK(hipStreamSynchronize(st));  // y is a host vector reused next cycle
   }
-  return status;
 }
 
 int run_krylov(bf_grid* g, int op, double c, const double* b, double* x, const bf_solver_opts& o,
@@ -577,6 +614,7 @@ int run_krylov(bf_grid* g, int op, double c, const double* b, double* x, const b
   KrylovState ks;
   int status = o.ksp == BF_KSP_CG ? run_cg(g, op, c, b, x, o, ks) : run_gmres(g, op, c, b, x, o, ks);
   if (status < 0) return status;
+
   HIPCHK(hipEventRecord(g->ev1, g->stream));
   HIPCHK(hipEventSynchronize(g->ev1));
   float ms = 0;
@@ -588,6 +626,7 @@ int run_krylov(bf_grid* g, int op, double c, const double* b, double* x, const b
     st->rel_res = ks.rel;
     st->rel_res_true = ks.rel_true;
     st->ms = ms;
+    st->floor_est = ks.floor_est;
   }
   return status;
 }
@@ -847,6 +886,42 @@ int bf_prolong_add(bf_grid* g, int32_t nf, const double* coarse, double* fine) {
   if (!is_pow2(nf) || nf < 8 || nf > g->n) return fail(BF_EINVAL, "nf = %d", nf);
   launch_prolong_add(nf, coarse, fine, g->stream);
   HIPCHK(hipGetLastError());
+  return BF_OK;
+}
+
+int bf_residual(bf_grid* g, int32_t op, double c, const double* b, const double* x, double* r,
+                int32_t accurate, double* rel_norm, double* floor_est) {
+  TRY(check_grid(g));
+  if (!b || !x || !r) return fail(BF_EINVAL, "null field");
+  if (r == x) return fail(BF_EINVAL, "r must not alias x");
+  if (op != BF_OP_LAP && op != BF_OP_CH) return fail(BF_EINVAL, "op %d", op);
+  if (!(c >= 0) || !std::isfinite(c)) return fail(BF_EINVAL, "c = %g must be finite and >= 0", c);
+  const OpDesc A = level_op(op, g->n, c);
+  const int np = nparts_of(g);
+  if (!accurate) {
+    launch_residual(A, x, b, r, g->partials, np, g->stream);
+    if (rel_norm) {
+      launch_finalize(g->partials, np, g->scal, F_STORE, S_RTRUE, g->n, g->stream);
+      wdot_async(g, b, b, F_STORE, S_BN2);
+      TRY(read_scalars(g, S_ULP2 + 1));
+      *rel_norm = std::sqrt(g->h_scal[S_RTRUE] / g->h_scal[S_BN2]);
+    }
+    if (floor_est) *floor_est = 0.0;
+    HIPCHK(hipGetLastError());
+    return BF_OK;
+  }
+  if (!rel_norm && !floor_est) {
+    launch_residual_dd(A, x, b, r, g->partials, np, g->stream);
+    HIPCHK(hipGetLastError());
+    return BF_OK;
+  }
+  wdot_async(g, b, b, F_STORE, S_BN2);
+  TRY(read_scalars(g, S_BN2 + 1));
+  KrylovState ks;
+  const double bn = std::sqrt(g->h_scal[S_BN2]);
+  TRY(true_residual(g, A, b, x, r, bn > 0 ? bn : 1.0, ks));
+  if (rel_norm) *rel_norm = ks.rel_true;
+  if (floor_est) *floor_est = ks.floor_est;
   return BF_OK;
 }
 

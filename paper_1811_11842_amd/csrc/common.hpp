@@ -27,6 +27,7 @@ enum Slot {
   S_MEAN = 7,  // weighted mean of the last reduced field
   S_RTRUE = 8, // ||b - A x||_W^2
   S_TMP = 9,
+  S_ULP2 = 10, // sum_W ulp(x)^2 (representation floor estimate)
   S_GM = 16,   // GMRES scalars start here (up to 64+ slots)
   kNumSlots = 256
 };

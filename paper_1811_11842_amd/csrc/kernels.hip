@@ -38,6 +38,76 @@ __device__ __forceinline__ double stencil_at(const double* __restrict__ x, int i
   return c + coef * (20.0 * c - 8.0 * axis + 2.0 * diag + far);
 }
 
+// Error-free transformations (Knuth TwoSum; TwoProduct through fma).  They
+// rely on every product and sum being rounded separately, so floating-point
+// contraction (fusing a*b + c into one fma, which hipcc does by default) is
+// switched off inside them and inside their callers.
+__device__ __forceinline__ void two_sum(double a, double b, double& s, double& e) {
+#pragma clang fp contract(off)
+  s = a + b;
+  const double bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+
+__device__ __forceinline__ void two_prod(double a, double b, double& p, double& e) {
+#pragma clang fp contract(off)
+  p = a * b;
+  e = fma(a, b, -p);
+}
+
+// r = b - A x with the stencil sum carried in double-double: the integer
+// stencil weights make every term exact (or exact through two_prod), the
+// cascaded two_sum (Ogita-Rump-Oishi Sum2) returns the sum as if computed in
+// twice the working precision, and the scaling by s = c n^4 (or n^2) is a
+// power-of-two-free product handled by two_prod.  The residual is therefore
+// accurate to a few ulps of r itself, instead of u * (c/h^4) * |x|: this is
+// what lets residual replacement act as iterative refinement below the
+// float64 evaluation floor of the operator.
+template <int OP>
+__device__ __forceinline__ double residual_dd_at(const double* __restrict__ x, double bval, int i,
+                                                 int j, int n, int mask, double coef) {
+#pragma clang fp contract(off)
+  const double* r0 = x + (int64_t)j * n;
+  const double* rm1 = x + (int64_t)refl(j - 1, n) * n;
+  const double* rp1 = x + (int64_t)refl(j + 1, n) * n;
+  const int im1 = (i - 1) & mask, ip1 = (i + 1) & mask;
+  const double c = r0[i];
+  double t[14];
+  int nt;
+  if (OP == 0) {
+    t[0] = r0[im1]; t[1] = r0[ip1]; t[2] = rm1[i]; t[3] = rp1[i]; t[4] = -4.0 * c;
+    nt = 5;
+  } else {
+    const double* rm2 = x + (int64_t)refl(j - 2, n) * n;
+    const double* rp2 = x + (int64_t)refl(j + 2, n) * n;
+    const int im2 = (i - 2) & mask, ip2 = (i + 2) & mask;
+    two_prod(20.0, c, t[0], t[1]);
+    t[2] = -8.0 * r0[im1]; t[3] = -8.0 * r0[ip1]; t[4] = -8.0 * rm1[i]; t[5] = -8.0 * rp1[i];
+    t[6] = 2.0 * rm1[im1]; t[7] = 2.0 * rm1[ip1]; t[8] = 2.0 * rp1[im1]; t[9] = 2.0 * rp1[ip1];
+    t[10] = r0[im2]; t[11] = r0[ip2]; t[12] = rm2[i]; t[13] = rp2[i];
+    nt = 14;
+  }
+  double hi = t[0], lo = 0.0;
+  for (int k = 1; k < nt; ++k) {
+    double e;
+    two_sum(hi, t[k], hi, e);
+    lo += e;
+  }
+  // A x = [c +] coef * (hi + lo)
+  double ph, pe;
+  two_prod(coef, hi, ph, pe);
+  pe = fma(coef, lo, pe);
+  double v = ph, ve = pe;
+  if (OP == 1) {
+    double e;
+    two_sum(c, ph, v, e);
+    ve = pe + e;
+  }
+  double w, we;
+  two_sum(bval, -v, w, we);
+  return w + (we - ve);
+}
+
 template <int OP>
 __device__ __forceinline__ double dinv_at(const OpDesc& A, int j) {
   if (OP == 0) return A.dinv_int;
@@ -55,15 +125,23 @@ __global__ void __launch_bounds__(kBlock) k_apply(OpDesc A, Geo G, const double*
   }
 }
 
-template <int OP>
+// ACC = 1 evaluates A p with the double-double stencil sum (q accurate to an
+// ulp): the rounding of a plain float64 evaluation is amplified by c/h^4 and
+// biased for smooth p, and it would accumulate in the recursive residual.
+template <int OP, int ACC>
 __global__ void __launch_bounds__(kBlock) k_apply_dot(OpDesc A, Geo G, const double* __restrict__ p,
                                                       double* __restrict__ q,
                                                       double* __restrict__ partials) {
   double acc = 0.0;
   GRID_STRIDE(idx, G.npts) {
     const int i = (int)(idx & G.mask), j = (int)(idx >> G.log2n);
-    double c;
-    const double v = stencil_at<OP>(p, i, j, G.n, G.mask, A.coef, c);
+    double c, v;
+    if (ACC) {
+      c = p[idx];
+      v = -residual_dd_at<OP>(p, 0.0, i, j, G.n, G.mask, A.coef);
+    } else {
+      v = stencil_at<OP>(p, i, j, G.n, G.mask, A.coef, c);
+    }
     q[idx] = v;
     acc += row_weight(j, G.n) * c * v;
   }
@@ -91,6 +169,40 @@ __global__ void __launch_bounds__(kBlock) k_residual(OpDesc A, Geo G, const doub
     const double t = block_sum(acc);
     if (threadIdx.x == 0) partials[blockIdx.x] = t;
   }
+}
+
+// ulp of a float64 value (0 for 0): spacing of the doubles around |v|.
+__device__ __forceinline__ double ulp_of(double v) {
+  int e;
+  (void)frexp(v, &e);
+  return v == 0.0 ? 0.0 : ldexp(1.0, e - 53);
+}
+
+// r = b - A x (double-double stencil sum).  partials[0..gridDim) receive
+// ||r||_W^2 and partials[gridDim..2 gridDim) receive sum_W ulp(x)^2, from which
+// the host forms the expected float64 representation floor of the residual:
+// rounding x to float64 leaves errors uniform in +-ulp/2 (variance ulp^2/12),
+// which A maps to a residual of norm^2 ~ sum_k ulp_k^2/12 * sum_j A_jk^2.
+template <int OP>
+__global__ void __launch_bounds__(kBlock) k_residual_dd(OpDesc A, Geo G,
+                                                        const double* __restrict__ x,
+                                                        const double* __restrict__ b,
+                                                        double* __restrict__ r,
+                                                        double* __restrict__ partials) {
+  double acc = 0.0, acc_ulp = 0.0;
+  GRID_STRIDE(idx, G.npts) {
+    const int i = (int)(idx & G.mask), j = (int)(idx >> G.log2n);
+    const double v = residual_dd_at<OP>(x, b[idx], i, j, G.n, G.mask, A.coef);
+    r[idx] = v;
+    const double w = row_weight(j, G.n);
+    acc += w * v * v;
+    const double u = ulp_of(x[idx]);
+    acc_ulp += w * u * u;
+  }
+  const double t = block_sum(acc);
+  if (threadIdx.x == 0) partials[blockIdx.x] = t;
+  const double tu = block_sum(acc_ulp);
+  if (threadIdx.x == 0) partials[gridDim.x + blockIdx.x] = tu;
 }
 
 template <int OP>
@@ -200,6 +312,19 @@ __global__ void __launch_bounds__(kBlock) k_dot(Geo G, const double* __restrict_
   if (threadIdx.x == 0) partials[blockIdx.x] = t;
 }
 
+// partials of sum_W (x - y)
+__global__ void __launch_bounds__(kBlock) k_wsum_diff(Geo G, const double* __restrict__ x,
+                                                      const double* __restrict__ y,
+                                                      double* __restrict__ partials) {
+  double acc = 0.0;
+  GRID_STRIDE(idx, G.npts) {
+    const int j = (int)(idx >> G.log2n);
+    acc += row_weight(j, G.n) * (x[idx] - y[idx]);
+  }
+  const double t = block_sum(acc);
+  if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
 __global__ void __launch_bounds__(kBlock) k_finalize(const double* __restrict__ partials, int nparts,
                                                      double* __restrict__ scal, int mode, int slot,
                                                      double nn) {
@@ -256,8 +381,9 @@ __global__ void __launch_bounds__(kBlock) k_xpby(Geo G, const double* __restrict
 }
 
 __global__ void __launch_bounds__(kBlock) k_sub_mean(Geo G, const double* x, double* y,
-                                                     const double* __restrict__ scal) {
-  const double m = scal[S_MEAN];
+                                                     const double* __restrict__ scal,
+                                                     double sign) {
+  const double m = sign * scal[S_MEAN];
   GRID_STRIDE(idx, G.npts) y[idx] = x[idx] - m;
 }
 
@@ -416,12 +542,19 @@ void launch_apply(const OpDesc& A, const double* x, double* y, hipStream_t st) {
 }
 
 void launch_apply_dot(const OpDesc& A, const double* p, double* q, double* partials, int nparts,
-                      hipStream_t st) {
+                      hipStream_t st, bool accurate) {
   const Geo G = make_geo(A.n);
-  if (A.op == 0)
-    LAUNCH(k_apply_dot<0>, nparts, st, A, G, p, q, partials);
-  else
-    LAUNCH(k_apply_dot<1>, nparts, st, A, G, p, q, partials);
+  if (A.op == 0) {
+    if (accurate)
+      LAUNCH((k_apply_dot<0, 1>), nparts, st, A, G, p, q, partials);
+    else
+      LAUNCH((k_apply_dot<0, 0>), nparts, st, A, G, p, q, partials);
+  } else {
+    if (accurate)
+      LAUNCH((k_apply_dot<1, 1>), nparts, st, A, G, p, q, partials);
+    else
+      LAUNCH((k_apply_dot<1, 0>), nparts, st, A, G, p, q, partials);
+  }
 }
 
 void launch_residual(const OpDesc& A, const double* x, const double* b, double* r,
@@ -432,6 +565,15 @@ void launch_residual(const OpDesc& A, const double* x, const double* b, double* 
     LAUNCH(k_residual<0>, blocks, st, A, G, x, b, r, partials);
   else
     LAUNCH(k_residual<1>, blocks, st, A, G, x, b, r, partials);
+}
+
+void launch_residual_dd(const OpDesc& A, const double* x, const double* b, double* r,
+                        double* partials, int nparts, hipStream_t st) {
+  const Geo G = make_geo(A.n);
+  if (A.op == 0)
+    LAUNCH(k_residual_dd<0>, nparts, st, A, G, x, b, r, partials);
+  else
+    LAUNCH(k_residual_dd<1>, nparts, st, A, G, x, b, r, partials);
 }
 
 void launch_smooth(const OpDesc& A, const double* x, const double* xprev, const double* b,
@@ -478,6 +620,11 @@ void launch_dot(int n, const double* x, const double* y, double* partials, int n
   LAUNCH(k_dot, nparts, st, make_geo(n), x, y, partials);
 }
 
+void launch_wsum_diff(int n, const double* x, const double* y, double* partials, int nparts,
+                      hipStream_t st) {
+  LAUNCH(k_wsum_diff, nparts, st, make_geo(n), x, y, partials);
+}
+
 void launch_finalize(const double* partials, int nparts, double* scal, int mode, int slot, int n,
                      hipStream_t st) {
   LAUNCH(k_finalize, 1, st, partials, nparts, scal, mode, slot, (double)n * (double)n);
@@ -495,7 +642,12 @@ void launch_xpby(int n, const double* z, double* p, const double* scal, hipStrea
 
 void launch_sub_mean(int n, const double* x, double* y, const double* scal, hipStream_t st) {
   const Geo G = make_geo(n);
-  LAUNCH(k_sub_mean, ew_blocks(G.npts), st, G, x, y, scal);
+  LAUNCH(k_sub_mean, ew_blocks(G.npts), st, G, x, y, scal, 1.0);
+}
+
+void launch_add_mean(int n, const double* x, double* y, const double* scal, hipStream_t st) {
+  const Geo G = make_geo(n);
+  LAUNCH(k_sub_mean, ew_blocks(G.npts), st, G, x, y, scal, -1.0);
 }
 
 void launch_fill(int64_t count, double* x, double v, hipStream_t st) {

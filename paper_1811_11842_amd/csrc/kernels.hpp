@@ -20,12 +20,17 @@ struct OpDesc {
 };
 
 void launch_apply(const OpDesc& A, const double* x, double* y, hipStream_t st);
-// q = A p and per-block partials of <p, q>_W.
+// q = A p and per-block partials of <p, q>_W; accurate = double-double stencil sum.
 void launch_apply_dot(const OpDesc& A, const double* p, double* q, double* partials,
-                      int nparts, hipStream_t st);
+                      int nparts, hipStream_t st, bool accurate);
 // r = b - A x (x == nullptr means x = 0); partials of ||r||_W^2 if partials != nullptr.
 void launch_residual(const OpDesc& A, const double* x, const double* b, double* r,
                      double* partials, int nparts, hipStream_t st);
+// r = b - A x evaluated with a double-double stencil sum (accurate to a few
+// ulps of r); partials[0..nparts) of ||r||_W^2 and partials[nparts..2 nparts)
+// of sum_W ulp(x)^2.
+void launch_residual_dd(const OpDesc& A, const double* x, const double* b, double* r,
+                        double* partials, int nparts, hipStream_t st);
 // xout = x + a D^{-1}(b - A x) + g (x - xprev); xprev == nullptr means 0.
 // xout may alias xprev, not x.
 void launch_smooth(const OpDesc& A, const double* x, const double* xprev, const double* b,
@@ -43,6 +48,9 @@ void launch_coarse_solve(int size, const double* G, const double* b, double* x, 
 // partials of <x, y>_W (y == nullptr means y = 1: weighted sum of x).
 void launch_dot(int n, const double* x, const double* y, double* partials, int nparts,
                 hipStream_t st);
+// partials of sum_W (x - y)
+void launch_wsum_diff(int n, const double* x, const double* y, double* partials, int nparts,
+                      hipStream_t st);
 // Reduce partials in a fixed order and update scalars (see FinalizeMode).
 void launch_finalize(const double* partials, int nparts, double* scal, int mode, int slot,
                      int n, hipStream_t st);
@@ -53,6 +61,8 @@ void launch_cg_update(int n, double* x, const double* p, double* r, const double
 void launch_xpby(int n, const double* z, double* p, const double* scal, hipStream_t st);
 // y = x - scal[S_MEAN]
 void launch_sub_mean(int n, const double* x, double* y, const double* scal, hipStream_t st);
+// y = x + scal[S_MEAN]
+void launch_add_mean(int n, const double* x, double* y, const double* scal, hipStream_t st);
 void launch_fill(int64_t count, double* x, double v, hipStream_t st);
 void launch_copy(int64_t count, const double* x, double* y, hipStream_t st);
 void launch_fill_i32(int count, int32_t* x, int32_t v, hipStream_t st);

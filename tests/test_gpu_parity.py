@@ -174,11 +174,62 @@ def test_solve_ch_forward_error(dev, n, rtol):
     x_ld = spectral.solve_ch(b.astype(np.longdouble), C_CH)
     fe = float(ops.wnorm(xh - x_ld) / ops.wnorm(x_ld))
     res = float(ops.wnorm(b - ops.apply_ch(xh, C_CH)) / ops.wnorm(b))
-    print(f"  iters={st.iters} status={st.status} fe={fe:.2e} res={res:.2e}")
+    # the reported true residual is evaluated with a double-double stencil sum:
+    # it must match the long-double evaluation of the same x
+    bl = b.astype(np.longdouble)
+    res_ld = float(ops.wnorm(bl - ops.apply_ch(xh.astype(np.longdouble), np.longdouble(C_CH)))
+                   / ops.wnorm(bl))
+    print(f"  iters={st.iters} status={st.status} fe={fe:.2e} res={res:.2e} "
+          f"res_ld={res_ld:.3e} reported={st.rel_res_true:.3e}")
     assert st.status in (bf.OK, bf.AT_FLOOR)
     assert fe <= 1e-10
     assert res <= max(rtol, 4 * _floor_ch(b, C_CH))
+    assert abs(st.rel_res_true - res_ld) <= 0.05 * res_ld + 1e-15
     assert st.iters <= 25
+
+
+@pytest.mark.parametrize("n", [64, 256, 1024])
+def test_accurate_residual_and_floor_estimate(dev, n):
+    """bf_residual(accurate) equals the long-double residual entry by entry,
+    and its floor estimate predicts the residual of the exact solution rounded
+    to float64 (evaluated in long double)."""
+    phi = S.initial_phi(n)
+    b = fh.rhs_ch(phi, PRM["dt"], PRM["M"], PRM["Npoly"], PRM["chi"])
+    bl = b.astype(np.longdouble)
+    x = spectral.solve_ch(bl, C_CH).astype(np.float64)      # fl64(exact solution)
+    r_ld = bl - ops.apply_ch(x.astype(np.longdouble), np.longdouble(C_CH))
+    g = grid(n)
+    r, rel, floor = g.residual(bf.OP_CH, C_CH, to_dev(b, dev), to_dev(x, dev))
+    r = to_np(r)
+    scale = float(np.abs(r_ld).max())
+    assert np.abs(r - r_ld).max() <= 1e-2 * scale
+    rel_ld = float(ops.wnorm(r_ld) / ops.wnorm(bl))
+    assert abs(rel - rel_ld) <= 0.01 * rel_ld
+    assert abs(floor - rel_ld) <= 0.05 * rel_ld
+    # the plain float64 evaluation is far less accurate at large c/h^4
+    r64, rel64, _ = g.residual(bf.OP_CH, C_CH, to_dev(b, dev), to_dev(x, dev), accurate=False)
+    if n >= 1024:
+        assert np.abs(to_np(r64) - r_ld).max() > 10 * np.abs(r - r_ld).max()
+
+
+def test_second_step_reaches_float64_floor(dev):
+    """After one step phi is smooth and ||b|| is small, so the float64 floor of
+    the relative residual exceeds rtol: the solve must end AT_FLOOR with the
+    forward error still at the tolerance level."""
+    n = 1024
+    phi0 = S.initial_phi(n)
+    phi1 = spectral.solve_ch(fh.rhs_ch(phi0, PRM["dt"], PRM["M"], PRM["Npoly"], PRM["chi"]),
+                             C_CH)
+    b = fh.rhs_ch(phi1, PRM["dt"], PRM["M"], PRM["Npoly"], PRM["chi"])
+    g = grid(n)
+    x = g.field(0.0)
+    st = g.solve_ch(C_CH, to_dev(b, dev), x, bf.default_opts(bf.OP_CH, rtol=1e-10))
+    print(st)
+    assert st.floor_est > 1e-10
+    assert st.status in (bf.AT_FLOOR, bf.OK)
+    assert st.rel_res <= 1e-10
+    xs = spectral.solve_ch(b.astype(np.longdouble), C_CH)
+    assert relw(to_np(x), xs) <= 1e-10
 
 
 @pytest.mark.parametrize("n,rtol", [(4, 1e-12), (8, 1e-12), (64, 1e-12), (256, 1e-12),
@@ -313,12 +364,14 @@ def test_step_1024_three_steps_and_mass(dev):
     phi0, u0, v0, phi, p, u, v, stats = _run_step(dev, n, 3)
     rphi, rp, ru, rv = oracle.step.run(phi0, u0, v0, 3, **PRM)
     print("iters", [(a.iters, b.iters) for a, b in stats])
+    assert all(a.status in (bf.OK, bf.AT_FLOOR) and b.status == bf.OK for a, b in stats)
     assert relw(phi, rphi) <= 1e-10
     # pressure at rtol 1e-10: forward error bounded by the solve tolerance times
     # the condition of the null-space-free Laplacian on this rhs; measured ~1e-10
     assert relw(p, rp) <= 1e-9
+    # the constant-mode correction of the solve conserves mass to rounding
     m0, m1 = ops.mass(phi0), ops.mass(phi)
-    assert abs(m1 - m0) / m0 <= 1e-12
+    assert abs(m1 - m0) / m0 <= 3e-14
 
 
 def test_step_4096_matches_oracle(dev):

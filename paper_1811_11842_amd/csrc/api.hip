@@ -280,24 +280,67 @@ Smoother make_smoother(int op, int n, double c, const bf_solver_opts& o) {
 }
 
 // One V-cycle on level l with right-hand side b (level 0: external pointer).
-// Returns the buffer holding the level's result.
+// Returns the buffer holding the level's result.  If rz_parts is given (level
+// 0 only) and the last smoothing sweep can produce it, that sweep also writes
+// partials of <b, z>_W into g->partials and *rz_parts receives their count
+// (0 when the caller must reduce <b, z>_W itself).
 double* vcycle_level(bf_grid* g, int op, double c, const bf_solver_opts& o, int l,
-                     const double* b) {
+                     const double* b, int* rz_parts = nullptr) {
   Level& L = g->lv[l];
   hipStream_t st = g->stream;
+  if (rz_parts) *rz_parts = 0;
   if (L.n == kCoarseN) {
     launch_coarse_solve(kCoarseSize, op == BF_OP_CH ? g->coarse_ch : g->coarse_lap, b, L.xa, st);
     return L.xa;
   }
+  if (L.n <= kTailTop) {
+    // the rest of the cycle in one workgroup (fields in LDS)
+    TailArgs P;
+    P.nlev = 0;
+    for (int n = L.n; n > kCoarseN; n /= 2) {
+      const OpDesc A = level_op(op, n, c);
+      const Smoother S = make_smoother(op, n, c, o);
+      TailLevel& T = P.lev[P.nlev++];
+      T.n = n;
+      T.degree = S.degree;
+      T.coef = A.coef;
+      T.dinv_int = A.dinv_int;
+      T.dinv_edge = A.dinv_edge;
+      for (int k = 0; k < 8; ++k) {
+        T.a[k] = S.a[k];
+        T.g[k] = S.g[k];
+      }
+    }
+    P.G = op == BF_OP_CH ? g->coarse_ch : g->coarse_lap;
+    P.b_in = b;
+    P.x_out = L.xa;
+    launch_tail(op, P, st);
+    return L.xa;
+  }
   const OpDesc A = level_op(op, L.n, c);
   const Smoother S = make_smoother(op, L.n, c, o);
+  const bool fused = stream_ok(L.n) && S.degree >= 2;
   // pre-smoothing from zero
   double* cur = L.xa;
   double* oth = L.xb;
-  launch_smooth0(A, b, cur, S.a[0], st);
-  for (int k = 1; k < S.degree; ++k) {
-    launch_smooth(A, cur, (k == 1 || S.g[k] == 0.0) ? nullptr : oth, b, oth, S.a[k], S.g[k], st);
-    std::swap(cur, oth);
+  if (fused) {
+    // sweeps 0 and 1 in one pass (x1 = a0 D^-1 b is never stored), sweep 2
+    // re-forms x1 from b for its (x - x_prev) term
+    stream_smooth_from_zero(A, b, cur, S.a[0], S.a[1], S.g[1], st);
+    for (int k = 2; k < S.degree; ++k) {
+      if (k == 2)
+        stream_smooth_prev_from_b(A, cur, b, oth, S.a[0], S.a[k], S.g[k], st);
+      else
+        launch_smooth(A, cur, S.g[k] != 0.0 ? oth : nullptr, b, oth, S.a[k], S.g[k], st);
+      std::swap(cur, oth);
+    }
+  } else {
+    launch_smooth0(A, b, cur, S.a[0], st);
+    for (int k = 1; k < S.degree; ++k) {
+      launch_smooth(A, cur, (k == 1 || S.g[k] == 0.0) ? nullptr : oth, b, oth, S.a[k], S.g[k],
+                    st);
+      std::swap(cur, oth);
+    }
   }
   // coarse-grid correction
   launch_residual(A, cur, b, L.r, nullptr, 0, st);
@@ -307,7 +350,11 @@ double* vcycle_level(bf_grid* g, int op, double c, const bf_solver_opts& o, int 
   launch_prolong_add(L.n, e, cur, st);
   // post-smoothing (same polynomial)
   for (int k = 0; k < S.degree; ++k) {
-    launch_smooth(A, cur, S.g[k] != 0.0 ? oth : nullptr, b, oth, S.a[k], S.g[k], st);
+    const double* prev = S.g[k] != 0.0 ? oth : nullptr;
+    if (rz_parts && k == S.degree - 1 && stream_ok(L.n))
+      *rz_parts = stream_smooth_dot(A, cur, prev, b, oth, S.a[k], S.g[k], g->partials, st);
+    else
+      launch_smooth(A, cur, prev, b, oth, S.a[k], S.g[k], st);
     std::swap(cur, oth);
   }
   return cur;
@@ -328,11 +375,14 @@ int check_opts(const bf_solver_opts& o) {
   return BF_OK;
 }
 
-// z = M r for the chosen preconditioner.  Returns the buffer holding z.
-double* precondition(bf_grid* g, int op, double c, const bf_solver_opts& o, const double* r) {
+// z = M r for the chosen preconditioner.  Returns the buffer holding z; see
+// vcycle_level for rz_parts.
+double* precondition(bf_grid* g, int op, double c, const bf_solver_opts& o, const double* r,
+                     int* rz_parts = nullptr) {
+  if (rz_parts) *rz_parts = 0;
   switch (o.pc) {
     case BF_PC_MG:
-      return vcycle_level(g, op, c, o, 0, r);
+      return vcycle_level(g, op, c, o, 0, r, rz_parts);
     case BF_PC_JACOBI:
       launch_jacobi_pc(level_op(op, g->n, c), r, g->z, g->stream);
       return g->z;
@@ -393,9 +443,9 @@ double column_sq(const OpDesc& A) {
 int true_residual(bf_grid* g, const OpDesc& A, const double* b, const double* x, double* r,
                   double bn, KrylovState& ks) {
   const int np = nparts_of(g);
-  launch_residual_dd(A, x, b, r, g->partials, np, g->stream);
-  launch_finalize(g->partials, np, g->scal, F_STORE, S_RTRUE, g->n, g->stream);
-  launch_finalize(g->partials + np, np, g->scal, F_STORE, S_ULP2, g->n, g->stream);
+  const int nr = launch_residual_dd(A, x, b, r, g->partials, np, g->stream);
+  launch_finalize(g->partials, nr, g->scal, F_STORE, S_RTRUE, g->n, g->stream);
+  launch_finalize(g->partials + nr, nr, g->scal, F_STORE, S_ULP2, g->n, g->stream);
   TRY(read_scalars(g, S_ULP2 + 1));
   ks.rel_true = std::sqrt(g->h_scal[S_RTRUE]) / bn;
   ks.floor_est = std::sqrt(g->h_scal[S_ULP2] / 12.0 * column_sq(A)) / bn;
@@ -455,13 +505,17 @@ int run_cg(bf_grid* g, int op, double c, const double* b, double* x, const bf_so
 
   for (;;) {
     // (re)start from the residual in g->r
-    double* z = precondition(g, op, c, o, g->r);
-    wdot_async(g, g->r, z, F_STORE, S_RZ);
+    int rzp = 0;
+    double* z = precondition(g, op, c, o, g->r, &rzp);
+    if (rzp > 0)
+      launch_finalize(g->partials, rzp, g->scal, F_STORE, S_RZ, g->n, st);
+    else
+      wdot_async(g, g->r, z, F_STORE, S_RZ);
     launch_copy(g->npts, z, g->p, st);
     bool converged = false;
     while (ks.iters < o.maxit) {
-      launch_apply_dot(A, g->p, g->q, g->partials, np, st, op == BF_OP_CH);
-      launch_finalize(g->partials, np, g->scal, F_ALPHA, 0, g->n, st);
+      const int npq = launch_apply_dot(A, g->p, g->q, g->partials, np, st, op == BF_OP_CH);
+      launch_finalize(g->partials, npq, g->scal, F_ALPHA, 0, g->n, st);
       launch_cg_update(g->n, x, g->p, g->r, g->q, g->scal, g->partials, np, st);
       launch_finalize(g->partials, np, g->scal, F_STORE, S_RR, g->n, st);
       ks.iters++;
@@ -474,8 +528,11 @@ int run_cg(bf_grid* g, int op, double c, const double* b, double* x, const bf_so
           break;
         }
       }
-      z = precondition(g, op, c, o, g->r);
-      wdot_async(g, g->r, z, F_BETA, 0);
+      z = precondition(g, op, c, o, g->r, &rzp);
+      if (rzp > 0)
+        launch_finalize(g->partials, rzp, g->scal, F_BETA, 0, g->n, st);
+      else
+        wdot_async(g, g->r, z, F_BETA, 0);
       launch_xpby(g->n, z, g->p, g->scal, st);
     }
     if (op == BF_OP_CH) mass_correct(g, b, x);
@@ -899,9 +956,9 @@ int bf_residual(bf_grid* g, int32_t op, double c, const double* b, const double*
   const OpDesc A = level_op(op, g->n, c);
   const int np = nparts_of(g);
   if (!accurate) {
-    launch_residual(A, x, b, r, g->partials, np, g->stream);
+    const int nr = launch_residual(A, x, b, r, g->partials, np, g->stream);
     if (rel_norm) {
-      launch_finalize(g->partials, np, g->scal, F_STORE, S_RTRUE, g->n, g->stream);
+      launch_finalize(g->partials, nr, g->scal, F_STORE, S_RTRUE, g->n, g->stream);
       wdot_async(g, b, b, F_STORE, S_BN2);
       TRY(read_scalars(g, S_ULP2 + 1));
       *rel_norm = std::sqrt(g->h_scal[S_RTRUE] / g->h_scal[S_BN2]);

@@ -85,6 +85,24 @@ __device__ __forceinline__ double block_sum(double v) {
   return t;
 }
 
+// Sum over a block of NT threads (NT a multiple of 64); result valid in thread 0.
+template <int NT>
+__device__ __forceinline__ double block_sum_n(double v) {
+  __shared__ double part[NT / 64];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) part[wid] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int w = 0; w < NT / 64; ++w) t += part[w];
+  }
+  __syncthreads();
+  return t;
+}
+
 inline int red_blocks(int64_t npts) {
   int64_t b = (npts + kBlock - 1) / kBlock;
   return (int)(b < kMaxRedBlocks ? b : kMaxRedBlocks);

@@ -12,6 +12,7 @@
 
 #include "common.hpp"
 #include "kernels.hpp"
+#include "stencil_ops.hpp"
 
 namespace bf {
 
@@ -22,90 +23,15 @@ namespace bf {
 template <int OP>
 __device__ __forceinline__ double stencil_at(const double* __restrict__ x, int i, int j, int n,
                                              int mask, double coef, double& center) {
-  const double* r0 = x + (int64_t)j * n;
-  const double* rm1 = x + (int64_t)refl(j - 1, n) * n;
-  const double* rp1 = x + (int64_t)refl(j + 1, n) * n;
-  const int im1 = (i - 1) & mask, ip1 = (i + 1) & mask;
-  const double c = r0[i];
-  center = c;
-  const double axis = (r0[im1] + r0[ip1]) + (rm1[i] + rp1[i]);
-  if (OP == 0) return coef * (axis - 4.0 * c);
-  const double* rm2 = x + (int64_t)refl(j - 2, n) * n;
-  const double* rp2 = x + (int64_t)refl(j + 2, n) * n;
-  const int im2 = (i - 2) & mask, ip2 = (i + 2) & mask;
-  const double diag = (rm1[im1] + rm1[ip1]) + (rp1[im1] + rp1[ip1]);
-  const double far = (r0[im2] + r0[ip2]) + (rm2[i] + rp2[i]);
-  return c + coef * (20.0 * c - 8.0 * axis + 2.0 * diag + far);
+  const Nb13 v = gather<OP>(x, i, j, n, mask);
+  center = v.c;
+  return apply_vals<OP>(v, coef);
 }
 
-// Error-free transformations (Knuth TwoSum; TwoProduct through fma).  They
-// rely on every product and sum being rounded separately, so floating-point
-// contraction (fusing a*b + c into one fma, which hipcc does by default) is
-// switched off inside them and inside their callers.
-__device__ __forceinline__ void two_sum(double a, double b, double& s, double& e) {
-#pragma clang fp contract(off)
-  s = a + b;
-  const double bb = s - a;
-  e = (a - (s - bb)) + (b - bb);
-}
-
-__device__ __forceinline__ void two_prod(double a, double b, double& p, double& e) {
-#pragma clang fp contract(off)
-  p = a * b;
-  e = fma(a, b, -p);
-}
-
-// r = b - A x with the stencil sum carried in double-double: the integer
-// stencil weights make every term exact (or exact through two_prod), the
-// cascaded two_sum (Ogita-Rump-Oishi Sum2) returns the sum as if computed in
-// twice the working precision, and the scaling by s = c n^4 (or n^2) is a
-// power-of-two-free product handled by two_prod.  The residual is therefore
-// accurate to a few ulps of r itself, instead of u * (c/h^4) * |x|: this is
-// what lets residual replacement act as iterative refinement below the
-// float64 evaluation floor of the operator.
 template <int OP>
 __device__ __forceinline__ double residual_dd_at(const double* __restrict__ x, double bval, int i,
                                                  int j, int n, int mask, double coef) {
-#pragma clang fp contract(off)
-  const double* r0 = x + (int64_t)j * n;
-  const double* rm1 = x + (int64_t)refl(j - 1, n) * n;
-  const double* rp1 = x + (int64_t)refl(j + 1, n) * n;
-  const int im1 = (i - 1) & mask, ip1 = (i + 1) & mask;
-  const double c = r0[i];
-  double t[14];
-  int nt;
-  if (OP == 0) {
-    t[0] = r0[im1]; t[1] = r0[ip1]; t[2] = rm1[i]; t[3] = rp1[i]; t[4] = -4.0 * c;
-    nt = 5;
-  } else {
-    const double* rm2 = x + (int64_t)refl(j - 2, n) * n;
-    const double* rp2 = x + (int64_t)refl(j + 2, n) * n;
-    const int im2 = (i - 2) & mask, ip2 = (i + 2) & mask;
-    two_prod(20.0, c, t[0], t[1]);
-    t[2] = -8.0 * r0[im1]; t[3] = -8.0 * r0[ip1]; t[4] = -8.0 * rm1[i]; t[5] = -8.0 * rp1[i];
-    t[6] = 2.0 * rm1[im1]; t[7] = 2.0 * rm1[ip1]; t[8] = 2.0 * rp1[im1]; t[9] = 2.0 * rp1[ip1];
-    t[10] = r0[im2]; t[11] = r0[ip2]; t[12] = rm2[i]; t[13] = rp2[i];
-    nt = 14;
-  }
-  double hi = t[0], lo = 0.0;
-  for (int k = 1; k < nt; ++k) {
-    double e;
-    two_sum(hi, t[k], hi, e);
-    lo += e;
-  }
-  // A x = [c +] coef * (hi + lo)
-  double ph, pe;
-  two_prod(coef, hi, ph, pe);
-  pe = fma(coef, lo, pe);
-  double v = ph, ve = pe;
-  if (OP == 1) {
-    double e;
-    two_sum(c, ph, v, e);
-    ve = pe + e;
-  }
-  double w, we;
-  two_sum(bval, -v, w, we);
-  return w + (we - ve);
+  return residual_dd_vals<OP>(gather<OP>(x, i, j, n, mask), bval, coef);
 }
 
 template <int OP>
@@ -171,13 +97,6 @@ __global__ void __launch_bounds__(kBlock) k_residual(OpDesc A, Geo G, const doub
   }
 }
 
-// ulp of a float64 value (0 for 0): spacing of the doubles around |v|.
-__device__ __forceinline__ double ulp_of(double v) {
-  int e;
-  (void)frexp(v, &e);
-  return v == 0.0 ? 0.0 : ldexp(1.0, e - 53);
-}
-
 // r = b - A x (double-double stencil sum).  partials[0..gridDim) receive
 // ||r||_W^2 and partials[gridDim..2 gridDim) receive sum_W ulp(x)^2, from which
 // the host forms the expected float64 representation floor of the residual:
@@ -238,54 +157,20 @@ __global__ void __launch_bounds__(kBlock) k_jacobi_pc(OpDesc A, Geo G, const dou
 }
 
 // ------------------------------------------------------------------ transfers
-// coarse(J, I) = sum_{dj, di in {0, +-1, +-3}} w_dj w_di fine(2J+dj, 2I+di),
-// w_0 = 1/2, w_{+-1} = 9/32, w_{+-3} = -1/32 (the weighted adjoint of cubic
-// interpolation, scaled by 1/4), fine rows reflected, columns wrapped.
+// coarse = R fine and fine += P coarse (one thread per node; small levels).
 __global__ void __launch_bounds__(kBlock) k_restrict(Geo F, Geo C, const double* __restrict__ fine,
                                                      double* __restrict__ coarse) {
-  const int off[5] = {-3, -1, 0, 1, 3};
-  const double w[5] = {-1.0 / 32, 9.0 / 32, 0.5, 9.0 / 32, -1.0 / 32};
   GRID_STRIDE(idx, C.npts) {
     const int I = (int)(idx & C.mask), J = (int)(idx >> C.log2n);
-    double acc = 0.0;
-#pragma unroll
-    for (int a = 0; a < 5; ++a) {
-      const double* row = fine + (int64_t)refl(2 * J + off[a], F.n) * F.n;
-      double rs = 0.0;
-#pragma unroll
-      for (int c = 0; c < 5; ++c) rs += w[c] * row[(2 * I + off[c]) & F.mask];
-      acc += w[a] * rs;
-    }
-    coarse[idx] = acc;
+    coarse[idx] = restrict_at(fine, F.n, F.mask, I, J);
   }
-}
-
-// fine += P coarse, P = tensor-product cubic interpolation (-1, 9, 9, -1)/16
-// at odd fine nodes, injection at even ones; coarse rows reflected, columns wrapped.
-__device__ __forceinline__ double interp_x(const double* __restrict__ coarse, const Geo& C, int J,
-                                           int i) {
-  const double* row = coarse + (int64_t)refl(J, C.n) * C.n;
-  const int I = i >> 1;
-  if ((i & 1) == 0) return row[I];
-  return (-row[(I - 1) & C.mask] + 9.0 * row[I] + 9.0 * row[(I + 1) & C.mask] -
-          row[(I + 2) & C.mask]) *
-         0.0625;
 }
 
 __global__ void __launch_bounds__(kBlock) k_prolong_add(Geo F, Geo C, const double* __restrict__ coarse,
                                                         double* __restrict__ fine) {
   GRID_STRIDE(idx, F.npts) {
     const int i = (int)(idx & F.mask), j = (int)(idx >> F.log2n);
-    const int J = j >> 1;
-    double v;
-    if ((j & 1) == 0) {
-      v = interp_x(coarse, C, J, i);
-    } else {
-      v = (-interp_x(coarse, C, J - 1, i) + 9.0 * interp_x(coarse, C, J, i) +
-           9.0 * interp_x(coarse, C, J + 1, i) - interp_x(coarse, C, J + 2, i)) *
-          0.0625;
-    }
-    fine[idx] += v;
+    fine[idx] += prolong_at(coarse, C.n, C.mask, i, j);
   }
 }
 
@@ -534,6 +419,10 @@ __global__ void __launch_bounds__(kBlock) k_scale(Geo G, const double* __restric
 #define LAUNCH(kern, blocks, st, ...) hipLaunchKernelGGL(kern, dim3(blocks), dim3(kBlock), 0, st, __VA_ARGS__)
 
 void launch_apply(const OpDesc& A, const double* x, double* y, hipStream_t st) {
+  if (stream_ok(A.n)) {
+    stream_apply(A, x, y, st);
+    return;
+  }
   const Geo G = make_geo(A.n);
   if (A.op == 0)
     LAUNCH(k_apply<0>, ew_blocks(G.npts), st, A, G, x, y);
@@ -541,8 +430,9 @@ void launch_apply(const OpDesc& A, const double* x, double* y, hipStream_t st) {
     LAUNCH(k_apply<1>, ew_blocks(G.npts), st, A, G, x, y);
 }
 
-void launch_apply_dot(const OpDesc& A, const double* p, double* q, double* partials, int nparts,
-                      hipStream_t st, bool accurate) {
+int launch_apply_dot(const OpDesc& A, const double* p, double* q, double* partials, int nparts,
+                     hipStream_t st, bool accurate) {
+  if (stream_ok(A.n)) return stream_apply_dot(A, p, q, partials, accurate, st);
   const Geo G = make_geo(A.n);
   if (A.op == 0) {
     if (accurate)
@@ -555,29 +445,38 @@ void launch_apply_dot(const OpDesc& A, const double* p, double* q, double* parti
     else
       LAUNCH((k_apply_dot<1, 0>), nparts, st, A, G, p, q, partials);
   }
+  return nparts;
 }
 
-void launch_residual(const OpDesc& A, const double* x, const double* b, double* r,
-                     double* partials, int nparts, hipStream_t st) {
+int launch_residual(const OpDesc& A, const double* x, const double* b, double* r,
+                    double* partials, int nparts, hipStream_t st) {
+  if (x && stream_ok(A.n)) return stream_residual(A, x, b, r, partials, st);
   const Geo G = make_geo(A.n);
   const int blocks = partials ? nparts : ew_blocks(G.npts);
   if (A.op == 0)
     LAUNCH(k_residual<0>, blocks, st, A, G, x, b, r, partials);
   else
     LAUNCH(k_residual<1>, blocks, st, A, G, x, b, r, partials);
+  return blocks;
 }
 
-void launch_residual_dd(const OpDesc& A, const double* x, const double* b, double* r,
-                        double* partials, int nparts, hipStream_t st) {
+int launch_residual_dd(const OpDesc& A, const double* x, const double* b, double* r,
+                       double* partials, int nparts, hipStream_t st) {
+  if (stream_ok(A.n)) return stream_residual_dd(A, x, b, r, partials, st);
   const Geo G = make_geo(A.n);
   if (A.op == 0)
     LAUNCH(k_residual_dd<0>, nparts, st, A, G, x, b, r, partials);
   else
     LAUNCH(k_residual_dd<1>, nparts, st, A, G, x, b, r, partials);
+  return nparts;
 }
 
 void launch_smooth(const OpDesc& A, const double* x, const double* xprev, const double* b,
                    double* xout, double a, double g, hipStream_t st) {
+  if (stream_ok(A.n)) {
+    stream_smooth(A, x, xprev, b, xout, a, g, st);
+    return;
+  }
   const Geo G = make_geo(A.n);
   if (A.op == 0)
     LAUNCH(k_smooth<0>, ew_blocks(G.npts), st, A, G, x, xprev, b, xout, a, g);
@@ -602,11 +501,19 @@ void launch_jacobi_pc(const OpDesc& A, const double* r, double* z, hipStream_t s
 }
 
 void launch_restrict(int nf, const double* fine, double* coarse, hipStream_t st) {
+  if (transfer_stream_ok(nf)) {
+    stream_restrict(nf, fine, coarse, st);
+    return;
+  }
   const Geo F = make_geo(nf), C = make_geo(nf / 2);
   LAUNCH(k_restrict, ew_blocks(C.npts), st, F, C, fine, coarse);
 }
 
 void launch_prolong_add(int nf, const double* coarse, double* fine, hipStream_t st) {
+  if (transfer_stream_ok(nf)) {
+    stream_prolong_add(nf, coarse, fine, st);
+    return;
+  }
   const Geo F = make_geo(nf), C = make_geo(nf / 2);
   LAUNCH(k_prolong_add, ew_blocks(F.npts), st, F, C, coarse, fine);
 }

@@ -19,18 +19,76 @@ struct OpDesc {
   double dinv_edge;// 1 / diag on rows 1 and n-1
 };
 
+// Launch shape of the streaming stencil kernels (stream.hip), used for grid
+// levels with n >= 128; smaller levels use the one-thread-per-node kernels.
+struct StreamCfg {
+  int tpb;      // threads per block (2 columns each)
+  int ty;       // rows per tile
+  int chunks;   // tiles per column strip
+  int tiles;    // strips * chunks
+  int per_xcd;  // tiles per XCD
+  int blocks;   // 8 * per_xcd (blocks beyond `tiles` exit at once)
+};
+bool stream_ok(int n);
+StreamCfg stream_cfg(int n);
+int stream_apply(const OpDesc& A, const double* x, double* y, hipStream_t st);
+int stream_apply_dot(const OpDesc& A, const double* p, double* q, double* partials, bool dd,
+                     hipStream_t st);
+int stream_residual(const OpDesc& A, const double* x, const double* b, double* r,
+                    double* partials, hipStream_t st);
+int stream_residual_dd(const OpDesc& A, const double* x, const double* b, double* r,
+                       double* partials, hipStream_t st);
+void stream_smooth(const OpDesc& A, const double* x, const double* xprev, const double* b,
+                   double* xout, double a, double g, hipStream_t st);
+// Two sweeps from a zero guess in one pass: x1 = a0 D^{-1} b is formed on
+// load, xout = x1 + a1 D^{-1}(b - A x1) + g1 x1.
+void stream_smooth_from_zero(const OpDesc& A, const double* b, double* xout, double a0, double a1,
+                             double g1, hipStream_t st);
+// xout = x + a D^{-1}(b - A x) + g (x - x1), x1 = a0 D^{-1} b formed on the fly.
+void stream_smooth_prev_from_b(const OpDesc& A, const double* x, const double* b, double* xout,
+                               double a0, double a, double g, hipStream_t st);
+// Smoothing sweep that also writes partials of <b, xout>_W; returns their count.
+int stream_smooth_dot(const OpDesc& A, const double* x, const double* xprev, const double* b,
+                      double* xout, double a, double g, double* partials, hipStream_t st);
+bool transfer_stream_ok(int nf);
+void stream_prolong_add(int nf, const double* coarse, double* fine, hipStream_t st);
+void stream_restrict(int nf, const double* fine, double* coarse, hipStream_t st);
+
+// Coarse tail: all levels 8 <= n <= kTailTop plus the exact 5 x 4 solve in
+// one workgroup with the fields in LDS (tail.hip).
+constexpr int kTailTop = 32;
+constexpr int kTailMaxLevels = 3;     // n = 32, 16, 8
+constexpr int kTailMaxDoubles = 5640; // 4 (33*32 + 17*16 + 9*8) + 2 * 20
+struct TailLevel {
+  int n;
+  int degree;
+  double coef, dinv_int, dinv_edge;
+  double a[8], g[8];
+};
+struct TailArgs {
+  int nlev;                       // smoothing levels (top n down to 8)
+  TailLevel lev[kTailMaxLevels];  // lev[0] is the top (finest) tail level
+  const double* G;                // dense solve of the 5 x 4 grid (20 x 20, row-major)
+  const double* b_in;             // right-hand side of the top tail level (global)
+  double* x_out;                  // its V-cycle result (global)
+};
+void launch_tail(int op, const TailArgs& P, hipStream_t st);
+
+// The launchers that write reduction partials return how many they wrote
+// (the count the matching launch_finalize must reduce); `nparts` is the
+// count used by the one-thread-per-node fallback.
 void launch_apply(const OpDesc& A, const double* x, double* y, hipStream_t st);
 // q = A p and per-block partials of <p, q>_W; accurate = double-double stencil sum.
-void launch_apply_dot(const OpDesc& A, const double* p, double* q, double* partials,
-                      int nparts, hipStream_t st, bool accurate);
+int launch_apply_dot(const OpDesc& A, const double* p, double* q, double* partials,
+                     int nparts, hipStream_t st, bool accurate);
 // r = b - A x (x == nullptr means x = 0); partials of ||r||_W^2 if partials != nullptr.
-void launch_residual(const OpDesc& A, const double* x, const double* b, double* r,
-                     double* partials, int nparts, hipStream_t st);
+int launch_residual(const OpDesc& A, const double* x, const double* b, double* r,
+                    double* partials, int nparts, hipStream_t st);
 // r = b - A x evaluated with a double-double stencil sum (accurate to a few
-// ulps of r); partials[0..nparts) of ||r||_W^2 and partials[nparts..2 nparts)
-// of sum_W ulp(x)^2.
-void launch_residual_dd(const OpDesc& A, const double* x, const double* b, double* r,
-                        double* partials, int nparts, hipStream_t st);
+// ulps of r); partials[0..np) of ||r||_W^2 and partials[np..2 np) of
+// sum_W ulp(x)^2, np = the returned count.
+int launch_residual_dd(const OpDesc& A, const double* x, const double* b, double* r,
+                       double* partials, int nparts, hipStream_t st);
 // xout = x + a D^{-1}(b - A x) + g (x - xprev); xprev == nullptr means 0.
 // xout may alias xprev, not x.
 void launch_smooth(const OpDesc& A, const double* x, const double* xprev, const double* b,

@@ -1,0 +1,174 @@
+// Pointwise stencil arithmetic shared by the plain and the streaming kernels:
+// the 5-point Laplacian and the 13-point Cahn-Hilliard operator on values
+// already gathered, in float64 and in double-double (error-free transforms).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.hpp"
+
+namespace bf {
+
+// Values around one node: centre c; axis neighbours at distance 1 (x-1, x+1,
+// y-1, y+1); diagonals; axis neighbours at distance 2.  Ghost rows are
+// already reflected and columns wrapped by the caller.
+struct Nb13 {
+  double c;
+  double xm1, xp1, ym1, yp1;
+  double dmm, dmp, dpm, dpp;  // (y-1,x-1) (y-1,x+1) (y+1,x-1) (y+1,x+1)
+  double xm2, xp2, ym2, yp2;
+};
+
+// Gather the stencil values around (i, j) of an (n+1) x n field at x (global
+// or LDS): ghost rows reflected, columns wrapped.
+template <int OP>
+__device__ __forceinline__ Nb13 gather(const double* x, int i, int j, int n, int mask) {
+  Nb13 v;
+  const double* r0 = x + (int64_t)j * n;
+  const double* rm1 = x + (int64_t)refl(j - 1, n) * n;
+  const double* rp1 = x + (int64_t)refl(j + 1, n) * n;
+  const int im1 = (i - 1) & mask, ip1 = (i + 1) & mask;
+  v.c = r0[i];
+  v.xm1 = r0[im1];
+  v.xp1 = r0[ip1];
+  v.ym1 = rm1[i];
+  v.yp1 = rp1[i];
+  if (OP == 1) {
+    const double* rm2 = x + (int64_t)refl(j - 2, n) * n;
+    const double* rp2 = x + (int64_t)refl(j + 2, n) * n;
+    const int im2 = (i - 2) & mask, ip2 = (i + 2) & mask;
+    v.dmm = rm1[im1];
+    v.dmp = rm1[ip1];
+    v.dpm = rp1[im1];
+    v.dpp = rp1[ip1];
+    v.xm2 = r0[im2];
+    v.xp2 = r0[ip2];
+    v.ym2 = rm2[i];
+    v.yp2 = rp2[i];
+  }
+  return v;
+}
+
+// coarse(J, I) = sum_{dj, di in {0, +-1, +-3}} w_dj w_di fine(2J+dj, 2I+di),
+// w_0 = 1/2, w_{+-1} = 9/32, w_{+-3} = -1/32 (the weighted adjoint of cubic
+// interpolation, scaled by 1/4); fine rows reflected, columns wrapped.
+__device__ __forceinline__ double restrict_at(const double* fine, int nf, int fmask, int I,
+                                              int J) {
+  const int off[5] = {-3, -1, 0, 1, 3};
+  const double w[5] = {-1.0 / 32, 9.0 / 32, 0.5, 9.0 / 32, -1.0 / 32};
+  double acc = 0.0;
+#pragma unroll
+  for (int a = 0; a < 5; ++a) {
+    const double* row = fine + (int64_t)refl(2 * J + off[a], nf) * nf;
+    double rs = 0.0;
+#pragma unroll
+    for (int c = 0; c < 5; ++c) rs += w[c] * row[(2 * I + off[c]) & fmask];
+    acc += w[a] * rs;
+  }
+  return acc;
+}
+
+// (P coarse)(j, i): tensor-product cubic interpolation (-1, 9, 9, -1)/16 at
+// odd fine nodes, injection at even ones; coarse rows reflected, columns wrapped.
+__device__ __forceinline__ double interp_x_at(const double* coarse, int nc, int cmask, int J,
+                                              int i) {
+  const double* row = coarse + (int64_t)refl(J, nc) * nc;
+  const int I = i >> 1;
+  if ((i & 1) == 0) return row[I];
+  return (-row[(I - 1) & cmask] + 9.0 * row[I] + 9.0 * row[(I + 1) & cmask] -
+          row[(I + 2) & cmask]) *
+         0.0625;
+}
+
+__device__ __forceinline__ double prolong_at(const double* coarse, int nc, int cmask, int i,
+                                             int j) {
+  const int J = j >> 1;
+  if ((j & 1) == 0) return interp_x_at(coarse, nc, cmask, J, i);
+  return (-interp_x_at(coarse, nc, cmask, J - 1, i) + 9.0 * interp_x_at(coarse, nc, cmask, J, i) +
+          9.0 * interp_x_at(coarse, nc, cmask, J + 1, i) -
+          interp_x_at(coarse, nc, cmask, J + 2, i)) *
+         0.0625;
+}
+
+// A x at the node.  OP 0: n^2 (axis - 4 c); OP 1: c + s (20 c - 8 axis + 2 diag + far).
+template <int OP>
+__device__ __forceinline__ double apply_vals(const Nb13& v, double coef) {
+  const double axis = (v.xm1 + v.xp1) + (v.ym1 + v.yp1);
+  if (OP == 0) return coef * (axis - 4.0 * v.c);
+  const double diag = (v.dmm + v.dmp) + (v.dpm + v.dpp);
+  const double far = (v.xm2 + v.xp2) + (v.ym2 + v.yp2);
+  return v.c + coef * (20.0 * v.c - 8.0 * axis + 2.0 * diag + far);
+}
+
+// Error-free transformations (Knuth TwoSum; TwoProduct through fma).  They
+// rely on every product and sum being rounded separately, so floating-point
+// contraction (fusing a*b + c into one fma, which hipcc does by default) is
+// switched off inside them and inside their callers.
+__device__ __forceinline__ void two_sum(double a, double b, double& s, double& e) {
+#pragma clang fp contract(off)
+  s = a + b;
+  const double bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+
+__device__ __forceinline__ void two_prod(double a, double b, double& p, double& e) {
+#pragma clang fp contract(off)
+  p = a * b;
+  e = fma(a, b, -p);
+}
+
+// b - A x with the stencil sum carried in double-double: the integer stencil
+// weights make every term exact (20 c through two_prod, the others are
+// power-of-two multiples), the cascaded two_sum (Ogita-Rump-Oishi Sum2)
+// returns the sum as if computed in twice the working precision, and the
+// scaling by s = c n^4 (or n^2) is a two_prod.  The result is accurate to a
+// few ulps of itself instead of u * (c/h^4) * |x|.
+template <int OP>
+__device__ __forceinline__ double residual_dd_vals(const Nb13& v, double bval, double coef) {
+#pragma clang fp contract(off)
+  double t[14];
+  int nt;
+  if (OP == 0) {
+    t[0] = v.xm1; t[1] = v.xp1; t[2] = v.ym1; t[3] = v.yp1; t[4] = -4.0 * v.c;
+    nt = 5;
+  } else {
+    two_prod(20.0, v.c, t[0], t[1]);
+    t[2] = -8.0 * v.xm1; t[3] = -8.0 * v.xp1; t[4] = -8.0 * v.ym1; t[5] = -8.0 * v.yp1;
+    t[6] = 2.0 * v.dmm; t[7] = 2.0 * v.dmp; t[8] = 2.0 * v.dpm; t[9] = 2.0 * v.dpp;
+    t[10] = v.xm2; t[11] = v.xp2; t[12] = v.ym2; t[13] = v.yp2;
+    nt = 14;
+  }
+  double hi = t[0], lo = 0.0;
+#pragma unroll
+  for (int k = 1; k < 14; ++k) {
+    if (k < nt) {
+      double e;
+      two_sum(hi, t[k], hi, e);
+      lo += e;
+    }
+  }
+  double ph, pe;
+  two_prod(coef, hi, ph, pe);
+  pe = fma(coef, lo, pe);
+  double w, ve = pe;
+  if (OP == 1) {
+    double e;
+    two_sum(v.c, ph, w, e);
+    ve = pe + e;
+  } else {
+    w = ph;
+  }
+  double r, re;
+  two_sum(bval, -w, r, re);
+  return r + (re - ve);
+}
+
+// ulp of a float64 value (0 for 0): spacing of the doubles around |v|.
+__device__ __forceinline__ double ulp_of(double v) {
+  int e;
+  (void)frexp(v, &e);
+  return v == 0.0 ? 0.0 : ldexp(1.0, e - 53);
+}
+
+}  // namespace bf

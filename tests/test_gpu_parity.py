@@ -57,7 +57,7 @@ def relw(a, b):
 
 
 # ------------------------------------------------------------------ operators
-@pytest.mark.parametrize("n", [4, 8, 64, 256, 1024])
+@pytest.mark.parametrize("n", [4, 8, 64, 128, 256, 512, 1024, 2048])
 @pytest.mark.parametrize("op", ["lap", "ch"])
 def test_apply_matches_oracle(dev, n, op):
     print(f"apply op={op} n={n}", flush=True)
@@ -90,7 +90,7 @@ def test_restrict_and_prolong_match_oracle(dev, nf):
     assert np.abs(to_np(fd) - ref).max() <= 8 * U * (1.6 * np.abs(c).max() + np.abs(base).max())
 
 
-@pytest.mark.parametrize("n", [4, 8, 32, 256])
+@pytest.mark.parametrize("n", [4, 8, 32, 256, 1024])
 @pytest.mark.parametrize("op", ["lap", "ch"])
 @pytest.mark.parametrize("smoother", ["chebyshev", "jacobi"])
 def test_vcycle_matches_oracle(dev, n, op, smoother):
@@ -188,7 +188,7 @@ def test_solve_ch_forward_error(dev, n, rtol):
     assert st.iters <= 25
 
 
-@pytest.mark.parametrize("n", [64, 256, 1024])
+@pytest.mark.parametrize("n", [64, 128, 256, 1024])
 def test_accurate_residual_and_floor_estimate(dev, n):
     """bf_residual(accurate) equals the long-double residual entry by entry,
     and its floor estimate predicts the residual of the exact solution rounded

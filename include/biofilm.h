@@ -96,7 +96,8 @@ typedef struct {
   double  ms;            /* device time of the call (HIP events)            */
   double  floor_est;     /* expected rel_res_true of x rounded to float64:   */
                          /* sqrt(sum_W ulp(x)^2/12 * sum_j A_jk^2)/||b||_W;  */
-                         /* BF_AT_FLOOR means rel_res_true <= 1.25 floor_est */
+                         /* BF_AT_FLOOR: rel_res_true <= 2 floor_est (4 after */
+                         /* a refinement restart that stopped improving)    */
 } bf_solve_stats;
 
 /* Parameters of the reduced semi-implicit step (dimensionless). */

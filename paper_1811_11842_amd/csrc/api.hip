@@ -66,7 +66,7 @@ struct bf_grid {
   int64_t npts = 0;
   hipStream_t stream = nullptr;
   std::vector<Level> lv;
-  double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
+  double *r = nullptr, *z = nullptr, *p = nullptr, *p2 = nullptr, *q = nullptr;
   double *work_b = nullptr;   // Cahn-Hilliard right-hand side inside bf_step
   double *work_p = nullptr;   // projected pressure right-hand side
   double* scal = nullptr;     // device scalars (kNumSlots)
@@ -457,24 +457,26 @@ int true_residual(bf_grid* g, const OpDesc& A, const double* b, const double* x,
 // the true residual whether to stop (BF_OK / BF_AT_FLOOR / BF_NOT_CONVERGED)
 // or to restart from it (returns -1 = restart).
 //  - true residual <= rtol: converged;
-//  - true residual within 25% of the representation floor: the residual left
-//    is the rounding of x to float64, no float64 vector does better
-//    (BF_AT_FLOOR; the recursive residual, which does not see that rounding,
-//    met rtol);
+//  - true residual within 2x the representation floor: the residual left is
+//    the rounding of x to float64 (the estimate assumes one rounding per
+//    entry; the Krylov updates leave a little more), no float64 vector does
+//    much better (BF_AT_FLOOR; the recursive residual, which does not see that
+//    rounding, met rtol);
 //  - otherwise restart (iterative refinement) while each restart at least
 //    halves the true residual, up to max_restarts;
+//  - a restart that stops improving within 4x the floor is also BF_AT_FLOOR;
 //  - else BF_NOT_CONVERGED.
 int decide_after_cycle(const bf_solver_opts& o, KrylovState& ks, double& last_true,
                        bool hit_maxit) {
   if (ks.rel_true <= o.rtol) return BF_OK;
-  if (ks.rel_true <= 1.25 * ks.floor_est && !hit_maxit) return BF_AT_FLOOR;
   if (hit_maxit) return BF_NOT_CONVERGED;
+  if (ks.rel_true <= 2.0 * ks.floor_est) return BF_AT_FLOOR;
   if (ks.restarts < o.max_restarts && ks.rel_true < 0.5 * last_true) {
     ks.restarts++;
     last_true = ks.rel_true;
     return -1;
   }
-  return BF_NOT_CONVERGED;
+  return ks.rel_true <= 4.0 * ks.floor_est ? BF_AT_FLOOR : BF_NOT_CONVERGED;
 }
 
 // CG in the weighted inner product.  For the Cahn-Hilliard operator q = A p
@@ -503,6 +505,8 @@ int run_cg(bf_grid* g, int op, double c, const double* b, double* x, const bf_so
   if (ks.rel_true <= o.rtol) return BF_OK;
   double last_true = ks.rel_true;
 
+  double* pcur = g->p;
+  double* pnext = g->p2;
   for (;;) {
     // (re)start from the residual in g->r
     int rzp = 0;
@@ -511,12 +515,18 @@ int run_cg(bf_grid* g, int op, double c, const double* b, double* x, const bf_so
       launch_finalize(g->partials, rzp, g->scal, F_STORE, S_RZ, g->n, st);
     else
       wdot_async(g, g->r, z, F_STORE, S_RZ);
-    launch_copy(g->npts, z, g->p, st);
+    bool first = true;     // p = z (no beta term, no pending x update)
+    bool pending = false;  // x still lacks alpha * pcur
     bool converged = false;
     while (ks.iters < o.maxit) {
-      const int npq = launch_apply_dot(A, g->p, g->q, g->partials, np, st, op == BF_OP_CH);
+      // p' = z + beta p, q = A p' (+ <p', q>), and the deferred x += alpha p
+      const int npq =
+          launch_cg_p(A, z, pcur, pnext, g->q, x, g->scal, first, g->partials, np, st);
       launch_finalize(g->partials, npq, g->scal, F_ALPHA, 0, g->n, st);
-      launch_cg_update(g->n, x, g->p, g->r, g->q, g->scal, g->partials, np, st);
+      std::swap(pcur, pnext);
+      first = false;
+      pending = true;
+      launch_r_update(g->n, g->r, g->q, g->scal, g->partials, np, st);
       launch_finalize(g->partials, np, g->scal, F_STORE, S_RR, g->n, st);
       ks.iters++;
       if (ks.iters % o.check_every == 0 || ks.iters == o.maxit) {
@@ -533,8 +543,8 @@ int run_cg(bf_grid* g, int op, double c, const double* b, double* x, const bf_so
         launch_finalize(g->partials, rzp, g->scal, F_BETA, 0, g->n, st);
       else
         wdot_async(g, g->r, z, F_BETA, 0);
-      launch_xpby(g->n, z, g->p, g->scal, st);
     }
+    if (pending) launch_x_update(g->n, x, pcur, g->scal, st);
     if (op == BF_OP_CH) mass_correct(g, b, x);
     TRY(true_residual(g, A, b, x, g->r, bn, ks));
     const int d = decide_after_cycle(o, ks, last_true, !converged);
@@ -749,6 +759,7 @@ int bf_grid_create(const bf_grid_desc* desc, bf_grid** out) {
   A(&g->r, g->npts);
   A(&g->z, g->npts);
   A(&g->p, g->npts);
+  A(&g->p2, g->npts);
   A(&g->q, g->npts);
   A(&g->work_b, g->npts);
   A(&g->work_p, g->npts);

@@ -239,17 +239,57 @@ __global__ void __launch_bounds__(kBlock) k_finalize(const double* __restrict__ 
   }
 }
 
-__global__ void __launch_bounds__(kBlock) k_cg_update(Geo G, double* __restrict__ x,
-                                                      const double* __restrict__ p,
-                                                      double* __restrict__ r,
-                                                      const double* __restrict__ q,
-                                                      const double* __restrict__ scal,
-                                                      double* __restrict__ partials) {
+// Naive form of the fused CG step (small levels; see stream_cg_p).
+template <int OP>
+__global__ void __launch_bounds__(kBlock) k_cg_p(OpDesc A, Geo G, const double* __restrict__ z,
+                                                 const double* __restrict__ p_old,
+                                                 double* __restrict__ p_new,
+                                                 double* __restrict__ q, double* __restrict__ x,
+                                                 const double* __restrict__ scal, int first,
+                                                 double* __restrict__ partials) {
+  const double beta = first ? 0.0 : scal[S_BETA];
+  const double alpha = first ? 0.0 : scal[S_ALPHA];
+  double acc = 0.0;
+  GRID_STRIDE(idx, G.npts) {
+    const int i = (int)(idx & G.mask), j = (int)(idx >> G.log2n);
+    Nb13 v = gather<OP>(z, i, j, G.n, G.mask);
+    if (!first) {
+      const Nb13 w = gather<OP>(p_old, i, j, G.n, G.mask);
+      v.c += beta * w.c;
+      v.xm1 += beta * w.xm1;
+      v.xp1 += beta * w.xp1;
+      v.ym1 += beta * w.ym1;
+      v.yp1 += beta * w.yp1;
+      if (OP == 1) {
+        v.dmm += beta * w.dmm;
+        v.dmp += beta * w.dmp;
+        v.dpm += beta * w.dpm;
+        v.dpp += beta * w.dpp;
+        v.xm2 += beta * w.xm2;
+        v.xp2 += beta * w.xp2;
+        v.ym2 += beta * w.ym2;
+        v.yp2 += beta * w.yp2;
+      }
+      x[idx] += alpha * w.c;
+    }
+    const double qv =
+        OP == 1 ? -residual_dd_vals<OP>(v, 0.0, A.coef) : apply_vals<OP>(v, A.coef);
+    q[idx] = qv;
+    p_new[idx] = v.c;
+    acc += row_weight(j, G.n) * v.c * qv;
+  }
+  const double t = block_sum(acc);
+  if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
+__global__ void __launch_bounds__(kBlock) k_r_update(Geo G, double* __restrict__ r,
+                                                     const double* __restrict__ q,
+                                                     const double* __restrict__ scal,
+                                                     double* __restrict__ partials) {
   const double alpha = scal[S_ALPHA];
   double acc = 0.0;
   GRID_STRIDE(idx, G.npts) {
     const int j = (int)(idx >> G.log2n);
-    x[idx] += alpha * p[idx];
     const double rv = r[idx] - alpha * q[idx];
     r[idx] = rv;
     acc += row_weight(j, G.n) * rv * rv;
@@ -258,11 +298,11 @@ __global__ void __launch_bounds__(kBlock) k_cg_update(Geo G, double* __restrict_
   if (threadIdx.x == 0) partials[blockIdx.x] = t;
 }
 
-__global__ void __launch_bounds__(kBlock) k_xpby(Geo G, const double* __restrict__ z,
-                                                 double* __restrict__ p,
-                                                 const double* __restrict__ scal) {
-  const double beta = scal[S_BETA];
-  GRID_STRIDE(idx, G.npts) p[idx] = z[idx] + beta * p[idx];
+__global__ void __launch_bounds__(kBlock) k_x_update(Geo G, double* __restrict__ x,
+                                                     const double* __restrict__ p,
+                                                     const double* __restrict__ scal) {
+  const double alpha = scal[S_ALPHA];
+  GRID_STRIDE(idx, G.npts) x[idx] += alpha * p[idx];
 }
 
 __global__ void __launch_bounds__(kBlock) k_sub_mean(Geo G, const double* x, double* y,
@@ -537,14 +577,26 @@ void launch_finalize(const double* partials, int nparts, double* scal, int mode,
   LAUNCH(k_finalize, 1, st, partials, nparts, scal, mode, slot, (double)n * (double)n);
 }
 
-void launch_cg_update(int n, double* x, const double* p, double* r, const double* q,
-                      const double* scal, double* partials, int nparts, hipStream_t st) {
-  LAUNCH(k_cg_update, nparts, st, make_geo(n), x, p, r, q, scal, partials);
+int launch_cg_p(const OpDesc& A, const double* z, const double* p_old, double* p_new, double* q,
+                double* x, const double* scal, bool first, double* partials, int nparts,
+                hipStream_t st) {
+  if (stream_ok(A.n)) return stream_cg_p(A, z, p_old, p_new, q, x, scal, first, partials, st);
+  const Geo G = make_geo(A.n);
+  if (A.op == 0)
+    LAUNCH(k_cg_p<0>, nparts, st, A, G, z, p_old, p_new, q, x, scal, first ? 1 : 0, partials);
+  else
+    LAUNCH(k_cg_p<1>, nparts, st, A, G, z, p_old, p_new, q, x, scal, first ? 1 : 0, partials);
+  return nparts;
 }
 
-void launch_xpby(int n, const double* z, double* p, const double* scal, hipStream_t st) {
+void launch_r_update(int n, double* r, const double* q, const double* scal, double* partials,
+                     int nparts, hipStream_t st) {
+  LAUNCH(k_r_update, nparts, st, make_geo(n), r, q, scal, partials);
+}
+
+void launch_x_update(int n, double* x, const double* p, const double* scal, hipStream_t st) {
   const Geo G = make_geo(n);
-  LAUNCH(k_xpby, ew_blocks(G.npts), st, G, z, p, scal);
+  LAUNCH(k_x_update, ew_blocks(G.npts), st, G, x, p, scal);
 }
 
 void launch_sub_mean(int n, const double* x, double* y, const double* scal, hipStream_t st) {

@@ -50,6 +50,21 @@ void stream_smooth_prev_from_b(const OpDesc& A, const double* x, const double* b
 // Smoothing sweep that also writes partials of <b, xout>_W; returns their count.
 int stream_smooth_dot(const OpDesc& A, const double* x, const double* xprev, const double* b,
                       double* xout, double a, double g, double* partials, hipStream_t st);
+// One CG step on the operator: p_new = z + beta p_old (p_new = z if first),
+// q = A p_new (double-double for the CH operator), partials of <p_new, q>_W,
+// and the deferred x += alpha p_old (skipped if first); alpha, beta are read
+// from scal[S_ALPHA], scal[S_BETA].  p_new must not alias p_old or z.  Returns
+// the number of partials.
+int stream_cg_p(const OpDesc& A, const double* z, const double* p_old, double* p_new, double* q,
+                double* x, const double* scal, bool first, double* partials, hipStream_t st);
+int launch_cg_p(const OpDesc& A, const double* z, const double* p_old, double* p_new, double* q,
+                double* x, const double* scal, bool first, double* partials, int nparts,
+                hipStream_t st);
+// r -= alpha q (alpha = scal[S_ALPHA]), partials of ||r||_W^2.
+void launch_r_update(int n, double* r, const double* q, const double* scal, double* partials,
+                     int nparts, hipStream_t st);
+// x += alpha p (alpha = scal[S_ALPHA]).
+void launch_x_update(int n, double* x, const double* p, const double* scal, hipStream_t st);
 bool transfer_stream_ok(int nf);
 void stream_prolong_add(int nf, const double* coarse, double* fine, hipStream_t st);
 void stream_restrict(int nf, const double* fine, double* coarse, hipStream_t st);
@@ -112,11 +127,6 @@ void launch_wsum_diff(int n, const double* x, const double* y, double* partials,
 // Reduce partials in a fixed order and update scalars (see FinalizeMode).
 void launch_finalize(const double* partials, int nparts, double* scal, int mode, int slot,
                      int n, hipStream_t st);
-// x += alpha p; r -= alpha q (alpha = scal[S_ALPHA]); partials of ||r||_W^2.
-void launch_cg_update(int n, double* x, const double* p, double* r, const double* q,
-                      const double* scal, double* partials, int nparts, hipStream_t st);
-// p = z + beta p (beta = scal[S_BETA]).
-void launch_xpby(int n, const double* z, double* p, const double* scal, hipStream_t st);
 // y = x - scal[S_MEAN]
 void launch_sub_mean(int n, const double* x, double* y, const double* scal, hipStream_t st);
 // y = x + scal[S_MEAN]

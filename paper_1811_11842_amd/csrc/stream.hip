@@ -35,7 +35,10 @@ enum Epi {
   E_SMOOTH_XB = 7,     // E_SMOOTH with x = a0 D^{-1} b formed on load (first sweep from 0
                        // folded into the second), xprev = 0
   E_SMOOTH_PB = 8,     // E_SMOOTH with xprev = a0 D^{-1} b formed on the fly
-  E_SMOOTH_DOT = 9     // E_SMOOTH and partials of <b, out>_W
+  E_SMOOTH_DOT = 9,    // E_SMOOTH and partials of <b, out>_W
+  E_CG_P = 10,         // CG step: p' = z + beta p formed on load; out = A p' (double-double
+                       // for the CH operator), out2 = p', partials of <p', A p'>_W, and the
+                       // deferred x += alpha p (alpha, beta from device scalars)
 };
 
 struct StreamArgs {
@@ -48,6 +51,10 @@ struct StreamArgs {
   double* partials;
   double a, g, a0;
   int ty, chunks, tiles, per_xcd;
+  double* out2;        // E_CG_P: p'
+  double* xu;          // E_CG_P: x (updated in place)
+  const double* scal;  // E_CG_P: device scalars (alpha, beta)
+  int first;           // E_CG_P: first step after a (re)start: p' = z, no x update
 };
 
 template <int OP, int EPI, int TPB>
@@ -59,7 +66,7 @@ __global__ void __launch_bounds__(TPB) k_stream(StreamArgs P) {
   constexpr bool SMOOTH = (EPI == E_SMOOTH || EPI == E_SMOOTH_XB || EPI == E_SMOOTH_PB ||
                            EPI == E_SMOOTH_DOT);
   constexpr bool RED = (EPI == E_APPLY_DOT || EPI == E_RESID_NORM || EPI == E_APPLY_DOT_DD ||
-                        EPI == E_RESID_DD || EPI == E_SMOOTH_DOT);
+                        EPI == E_RESID_DD || EPI == E_SMOOTH_DOT || EPI == E_CG_P);
   constexpr bool NEEDB = (EPI == E_RESID || EPI == E_RESID_NORM || SMOOTH || EPI == E_RESID_DD);
   __shared__ double lds[4][LW];
 
@@ -88,6 +95,11 @@ __global__ void __launch_bounds__(TPB) k_stream(StreamArgs P) {
     hslot = (tid < 2) ? tid : (TX + tid);
   }
   const double* __restrict__ X = P.x;
+  double beta = 0.0, alpha_prev = 0.0;
+  if (EPI == E_CG_P && !P.first) {
+    beta = P.scal[S_BETA];
+    alpha_prev = P.scal[S_ALPHA];
+  }
 
   auto dinv_row = [&](int jr) {
     return (OP == 1 && (jr == 1 || jr == n - 1)) ? P.A.dinv_edge : P.A.dinv_int;
@@ -97,6 +109,13 @@ __global__ void __launch_bounds__(TPB) k_stream(StreamArgs P) {
     const double* row = X + (int64_t)jr * n;
     own = *reinterpret_cast<const double2*>(row + c);
     halo = hthread ? row[hcol] : 0.0;
+    if (EPI == E_CG_P && !P.first) {
+      const double* prow = P.xprev + (int64_t)jr * n;
+      const double2 po = *reinterpret_cast<const double2*>(prow + c);
+      own.x += beta * po.x;
+      own.y += beta * po.y;
+      if (hthread) halo += beta * prow[hcol];
+    }
     if (EPI == E_SMOOTH_XB) {
       const double sc = P.a0 * dinv_row(jr);
       own.x *= sc;
@@ -203,6 +222,23 @@ __global__ void __launch_bounds__(TPB) k_stream(StreamArgs P) {
       res.x = -residual_dd_vals<OP>(v0, 0.0, P.A.coef);
       res.y = -residual_dd_vals<OP>(v1, 0.0, P.A.coef);
       acc += wgt * (v0.c * res.x + v1.c * res.y);
+    } else if (EPI == E_CG_P) {
+      if (OP == 1) {
+        res.x = -residual_dd_vals<OP>(v0, 0.0, P.A.coef);
+        res.y = -residual_dd_vals<OP>(v1, 0.0, P.A.coef);
+      } else {
+        res.x = apply_vals<OP>(v0, P.A.coef);
+        res.y = apply_vals<OP>(v1, P.A.coef);
+      }
+      acc += wgt * (v0.c * res.x + v1.c * res.y);
+      *reinterpret_cast<double2*>(P.out2 + o) = make_double2(v0.c, v1.c);
+      if (!P.first) {
+        const double2 po = *reinterpret_cast<const double2*>(P.xprev + o);
+        double2 xv = *reinterpret_cast<const double2*>(P.xu + o);
+        xv.x += alpha_prev * po.x;
+        xv.y += alpha_prev * po.y;
+        *reinterpret_cast<double2*>(P.xu + o) = xv;
+      }
     } else {  // E_RESID_DD
       res.x = residual_dd_vals<OP>(v0, bcur.x, P.A.coef);
       res.y = residual_dd_vals<OP>(v1, bcur.y, P.A.coef);
@@ -250,8 +286,9 @@ StreamCfg stream_cfg(int n) {
   c.tpb = n >= 1024 ? 256 : (n >= 256 ? 128 : 64);
   const int tx = 2 * c.tpb;
   const int strips = n / tx;
-  // aim at ~2048 tiles (8 resident blocks on each of 256 CUs), 8..64 rows each
-  int ty = (int)(((int64_t)(n + 1) * strips) / 2048);
+  // aim at ~4096 tiles (16 per CU over the 256 CUs), 8..64 rows each; on
+  // 4096^2 this gives 8-row tiles, measured fastest for whole solves
+  int ty = (int)(((int64_t)(n + 1) * strips) / 4096);
   static const int ty_env = env_int("BF_STREAM_TY", 0);
   if (ty_env > 0) ty = ty_env;
   ty = ty < 8 ? 8 : (ty > 64 ? 64 : ty);
@@ -283,7 +320,7 @@ static int stream_launch(const OpDesc& A, const double* x, const double* b, cons
                          double* out, double* partials, double a, double g, hipStream_t st,
                          double a0 = 0.0) {
   const StreamCfg c = stream_cfg(A.n);
-  StreamArgs P;
+  StreamArgs P{};
   P.A = A;
   P.G = make_geo(A.n);
   P.x = x;
@@ -337,6 +374,30 @@ void stream_smooth_prev_from_b(const OpDesc& A, const double* x, const double* b
 int stream_smooth_dot(const OpDesc& A, const double* x, const double* xprev, const double* b,
                       double* xout, double a, double g, double* partials, hipStream_t st) {
   return stream_launch<E_SMOOTH_DOT>(A, x, b, xprev, xout, partials, a, g, st);
+}
+int stream_cg_p(const OpDesc& A, const double* z, const double* p_old, double* p_new, double* q,
+                double* x, const double* scal, bool first, double* partials, hipStream_t st) {
+  const StreamCfg c = stream_cfg(A.n);
+  StreamArgs P{};
+  P.A = A;
+  P.G = make_geo(A.n);
+  P.x = z;
+  P.xprev = p_old;
+  P.out = q;
+  P.out2 = p_new;
+  P.xu = x;
+  P.scal = scal;
+  P.first = first ? 1 : 0;
+  P.partials = partials;
+  P.ty = c.ty;
+  P.chunks = c.chunks;
+  P.tiles = c.tiles;
+  P.per_xcd = c.per_xcd;
+  if (A.op == 0)
+    dispatch<0, E_CG_P>(c, P, st);
+  else
+    dispatch<1, E_CG_P>(c, P, st);
+  return c.blocks;
 }
 
 }  // namespace bf

@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--spmv-only", action="store_true")
     ap.add_argument("--steps-only", action="store_true")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="only run a plain device copy of one field (for HBM counter calibration)")
     return ap.parse_args()
 
 
@@ -126,6 +128,24 @@ def main():
     torch.cuda.set_device(0)
     n = a.n
     npts = (n + 1) * n
+    if a.copy_calib:
+        # plain copy kernels of known size: each reads 8*npts bytes and writes
+        # 8*npts bytes, rotating over 4 buffer pairs (1 GB): the library's
+        # bf_copy (16-byte lanes, the access pattern of the stencil kernels)
+        # and, for comparison, the runtime's copy
+        xs = [torch.rand(n + 1, n, dtype=torch.float64, device="cuda") for _ in range(4)]
+        ys = [torch.empty_like(xs[0]) for _ in range(4)]
+        torch.cuda.synchronize()
+        with bf.Grid(n) as g:
+            for r in range(20):
+                g.copy(xs[r % 4], ys[r % 4])
+            torch.cuda.synchronize()
+            assert torch.equal(ys[0], xs[0])
+            for r in range(20):
+                ys[r % 4].copy_(xs[r % 4])
+            torch.cuda.synchronize()
+        print(json.dumps({"copy_calib_bytes_each_way": 8 * npts, "launches": 20}), flush=True)
+        return
     out = {"metric": METRIC, "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
            "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
            "dtype": "f64", "data": "synthetic"}
@@ -151,7 +171,7 @@ def main():
             gbs = traffic / (t_spmv * 1e-3) / 1e9
             out["spmv_us"] = round(t_spmv * 1e3, 3)
             out["spmv_gbs"] = round(gbs, 1)
-            out["roofline"] = {"kernel": "k_apply<1> (13-point Cahn-Hilliard SpMV, float64)",
+            out["roofline"] = {"kernel": "k_stream<1,0,256> (13-point Cahn-Hilliard SpMV, float64)",
                                "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
                                "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
                                "traffic": None, "algorithmic_bytes": int(traffic)}

@@ -193,6 +193,12 @@ int bf_prolong_add(bf_grid* g, int32_t nf, const double* coarse, double* fine);
 int bf_residual(bf_grid* g, int32_t op, double c, const double* b, const double* x,
                 double* r, int32_t accurate, double* rel_norm, double* floor_est);
 
+/* y = x for one field (16-byte aligned pointers), with the memory access
+ * pattern of the stencil kernels (16 bytes per lane, coalesced rows): a
+ * streaming kernel of known traffic (8 (n+1) n bytes each way), used to
+ * calibrate hardware byte counters.  Asynchronous. */
+int bf_copy(bf_grid* g, const double* x, double* y);
+
 /* *out (host) = <x, y>_W.  Synchronises the grid's stream. */
 int bf_wdot(bf_grid* g, const double* x, const double* y, double* out);
 

@@ -109,6 +109,7 @@ def lib():
             "bf_restrict": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P]),
             "bf_prolong_add": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P]),
             "bf_wdot": (ctypes.c_int, [_P, _P, _P, ctypes.POINTER(ctypes.c_double)]),
+            "bf_copy": (ctypes.c_int, [_P, _P, _P]),
             "bf_residual": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_double, _P, _P, _P,
                                            ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                            ctypes.POINTER(ctypes.c_double)]),
@@ -295,6 +296,11 @@ class Grid:
                                  self._ptr(r, "r"), 1 if accurate else 0, ctypes.byref(rel),
                                  ctypes.byref(fl)))
         return r, rel.value, fl.value
+
+    def copy(self, x, y=None):
+        y = self.field() if y is None else y
+        _check(lib().bf_copy(self._h, self._ptr(x, "x"), self._ptr(y, "y")))
+        return y
 
     def wdot(self, x, y) -> float:
         out = ctypes.c_double()

@@ -9,6 +9,7 @@
 #include <utility>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -77,6 +78,19 @@ struct bf_grid {
   int32_t* counter = nullptr;
   double* h_scal = nullptr;   // pinned host mirror of scalars
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  // Captured V-cycles (one hipGraphExec per operator / coefficient / options /
+  // input buffer), replayed with a single launch; captured on cap_stream.
+  struct VcGraph {
+    int op, smoother, degree, rz;
+    double c, ratio, omega;
+    const double* b;
+    hipGraphExec_t exec;
+    double* result;
+    int rz_parts;
+  };
+  std::vector<VcGraph> graphs;
+  hipStream_t cap_stream = nullptr;
+  bool use_graphs = true;
   // GMRES workspace (allocated on first use)
   int gm_m = 0;
   double* gm_V = nullptr;  // (m+1) vectors
@@ -375,6 +389,63 @@ int check_opts(const bf_solver_opts& o) {
   return BF_OK;
 }
 
+// The V-cycle from level 0 as a replayed HIP graph.  The whole cycle (about
+// 7 launches per level above the tail) is captured once per (operator, c,
+// smoother options, input buffer, <b,z> fusion) on the grid's private capture
+// stream and launched on the grid's stream with one call: on the coarse
+// levels the kernels are shorter than the host's per-launch cost, so eager
+// launches left the GPU idle between them.  Returns nullptr if capture is
+// unavailable (the caller then launches eagerly).
+double* vcycle_graph(bf_grid* g, int op, double c, const bf_solver_opts& o, const double* b,
+                     int* rz_parts) {
+  const int rz = rz_parts ? 1 : 0;
+  for (auto& e : g->graphs) {
+    if (e.op == op && e.c == c && e.smoother == o.smoother && e.degree == o.degree &&
+        e.ratio == o.ratio && e.omega == o.omega && e.b == b && e.rz == rz) {
+      if (hipGraphLaunch(e.exec, g->stream) != hipSuccess) return nullptr;
+      if (rz_parts) *rz_parts = e.rz_parts;
+      return e.result;
+    }
+  }
+  if (g->graphs.size() >= 96) {
+    (void)hipGraphExecDestroy(g->graphs.front().exec);
+    g->graphs.erase(g->graphs.begin());
+  }
+  bf_grid::VcGraph e;
+  e.op = op;
+  e.c = c;
+  e.smoother = o.smoother;
+  e.degree = o.degree;
+  e.ratio = o.ratio;
+  e.omega = o.omega;
+  e.b = b;
+  e.rz = rz;
+  e.rz_parts = 0;
+  hipStream_t user = g->stream;
+  if (hipStreamBeginCapture(g->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  g->stream = g->cap_stream;
+  e.result = vcycle_level(g, op, c, o, 0, b, rz ? &e.rz_parts : nullptr);
+  g->stream = user;
+  hipGraph_t graph = nullptr;
+  if (hipStreamEndCapture(g->cap_stream, &graph) != hipSuccess || !graph) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  const hipError_t ie = hipGraphInstantiate(&e.exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (ie != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  g->graphs.push_back(e);
+  if (hipGraphLaunch(e.exec, g->stream) != hipSuccess) return nullptr;
+  if (rz_parts) *rz_parts = e.rz_parts;
+  return e.result;
+}
+
 // z = M r for the chosen preconditioner.  Returns the buffer holding z; see
 // vcycle_level for rz_parts.
 double* precondition(bf_grid* g, int op, double c, const bf_solver_opts& o, const double* r,
@@ -382,6 +453,11 @@ double* precondition(bf_grid* g, int op, double c, const bf_solver_opts& o, cons
   if (rz_parts) *rz_parts = 0;
   switch (o.pc) {
     case BF_PC_MG:
+      if (g->use_graphs) {
+        double* z = vcycle_graph(g, op, c, o, r, rz_parts);
+        if (z) return z;
+        g->use_graphs = false;  // capture not available: launch eagerly from now on
+      }
       return vcycle_level(g, op, c, o, 0, r, rz_parts);
     case BF_PC_JACOBI:
       launch_jacobi_pc(level_op(op, g->n, c), r, g->z, g->stream);
@@ -780,6 +856,12 @@ int bf_grid_create(const bf_grid_desc* desc, bf_grid** out) {
     s = fail(BF_ENOMEM, "pinned host allocation failed");
   if (s == BF_OK && (hipEventCreate(&g->ev0) != hipSuccess || hipEventCreate(&g->ev1) != hipSuccess))
     s = fail(BF_EHIP, "event creation failed");
+  if (s == BF_OK && hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking) != hipSuccess)
+    s = fail(BF_EHIP, "capture stream creation failed");
+  {
+    const char* ng = std::getenv("BF_NO_GRAPHS");
+    if (ng && ng[0] == '1') g->use_graphs = false;
+  }
   if (s == BF_OK) {
     launch_fill(kNumSlots, g->scal, 0.0, g->stream);
     s = upload_coarse(g, BF_OP_LAP, 0.0);
@@ -798,6 +880,9 @@ int bf_grid_destroy(bf_grid* g) {
   if (!g) return BF_OK;
   if (g->stream) (void)hipStreamSynchronize(g->stream);
   else (void)hipDeviceSynchronize();
+  for (auto& e : g->graphs) (void)hipGraphExecDestroy(e.exec);
+  g->graphs.clear();
+  if (g->cap_stream) (void)hipStreamDestroy(g->cap_stream);
   for (void* p : g->allocs)
     if (p) (void)hipFree(p);
   if (g->h_scal) (void)hipHostFree(g->h_scal);
@@ -933,7 +1018,9 @@ int bf_vcycle(bf_grid* g, int32_t op, double c, const bf_solver_opts* o, const d
   const bf_solver_opts& oo = o ? *o : d;
   TRY(check_opts(oo));
   if (op == BF_OP_CH) TRY(ensure_coarse_ch(g, c));
-  double* res = vcycle_level(g, op, c, oo, 0, r);
+  bf_solver_opts om = oo;
+  om.pc = BF_PC_MG;
+  double* res = precondition(g, op, c, om, r);
   launch_copy(g->npts, res, z, g->stream);
   HIPCHK(hipGetLastError());
   return BF_OK;
@@ -990,6 +1077,16 @@ int bf_residual(bf_grid* g, int32_t op, double c, const double* b, const double*
   TRY(true_residual(g, A, b, x, r, bn > 0 ? bn : 1.0, ks));
   if (rel_norm) *rel_norm = ks.rel_true;
   if (floor_est) *floor_est = ks.floor_est;
+  return BF_OK;
+}
+
+int bf_copy(bf_grid* g, const double* x, double* y) {
+  TRY(check_grid(g));
+  if (!x || !y) return fail(BF_EINVAL, "null field");
+  if ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(y)) & 15)
+    return fail(BF_EINVAL, "fields must be 16-byte aligned");
+  launch_copy2(g->npts, x, y, g->stream);
+  HIPCHK(hipGetLastError());
   return BF_OK;
 }
 

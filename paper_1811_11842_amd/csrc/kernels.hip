@@ -321,6 +321,14 @@ __global__ void __launch_bounds__(kBlock) k_copy(int64_t count, const double* __
   GRID_STRIDE(idx, count) y[idx] = x[idx];
 }
 
+// y = x with 16-byte accesses per lane (count even, 16-byte aligned): the
+// access pattern of the streaming stencil kernels, used as a calibration
+// kernel of known traffic.
+__global__ void __launch_bounds__(kBlock) k_copy2(int64_t pairs, const double2* __restrict__ x,
+                                                  double2* __restrict__ y) {
+  GRID_STRIDE(idx, pairs) y[idx] = x[idx];
+}
+
 __global__ void k_fill_i32(int count, int32_t* x, int32_t v) {
   GRID_STRIDE(idx, count) x[idx] = v;
 }
@@ -615,6 +623,12 @@ void launch_fill(int64_t count, double* x, double v, hipStream_t st) {
 
 void launch_copy(int64_t count, const double* x, double* y, hipStream_t st) {
   LAUNCH(k_copy, ew_blocks(count), st, count, x, y);
+}
+
+void launch_copy2(int64_t count, const double* x, double* y, hipStream_t st) {
+  const int64_t pairs = count / 2;
+  LAUNCH(k_copy2, ew_blocks(pairs), st, pairs, reinterpret_cast<const double2*>(x),
+         reinterpret_cast<double2*>(y));
 }
 
 void launch_fill_i32(int count, int32_t* x, int32_t v, hipStream_t st) {

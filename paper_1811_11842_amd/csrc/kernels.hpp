@@ -28,6 +28,7 @@ struct StreamCfg {
   int tiles;    // strips * chunks
   int per_xcd;  // tiles per XCD
   int blocks;   // 8 * per_xcd (blocks beyond `tiles` exit at once)
+  int xcd_map;  // 1: tile ranges dealt to XCDs (block b -> XCD b % 8)
 };
 bool stream_ok(int n);
 StreamCfg stream_cfg(int n);
@@ -134,6 +135,8 @@ void launch_add_mean(int n, const double* x, double* y, const double* scal, hipS
 void launch_fill(int64_t count, double* x, double v, hipStream_t st);
 void launch_copy(int64_t count, const double* x, double* y, hipStream_t st);
 void launch_fill_i32(int count, int32_t* x, int32_t v, hipStream_t st);
+// y = x, 16-byte accesses (count even, pointers 16-byte aligned).
+void launch_copy2(int64_t count, const double* x, double* y, hipStream_t st);
 
 // Step pieces.
 void launch_ch_rhs(int n, const double* phi, double* b, double dtM, double inv_npoly,

@@ -55,6 +55,7 @@ struct StreamArgs {
   double* xu;          // E_CG_P: x (updated in place)
   const double* scal;  // E_CG_P: device scalars (alpha, beta)
   int first;           // E_CG_P: first step after a (re)start: p' = z, no x update
+  int xcd_map;         // 1: deal contiguous tile ranges to the 8 XCDs
 };
 
 template <int OP, int EPI, int TPB>
@@ -71,7 +72,7 @@ __global__ void __launch_bounds__(TPB) k_stream(StreamArgs P) {
   __shared__ double lds[4][LW];
 
   const int bid = blockIdx.x;
-  const int t = (bid & 7) * P.per_xcd + (bid >> 3);
+  const int t = P.xcd_map ? (bid & 7) * P.per_xcd + (bid >> 3) : bid;
   if (t >= P.tiles) {
     if (RED && threadIdx.x == 0) {
       P.partials[bid] = 0.0;
@@ -135,31 +136,45 @@ __global__ void __launch_bounds__(TPB) k_stream(StreamArgs P) {
     if (hthread) lds[slot][hslot] = halo;
   };
 
+  // Sweep direction alternates with the chunk: even chunks walk down, odd
+  // chunks walk up.  Two neighbouring chunks then read the rows they share
+  // (the 2-row halos) in the same phase of their sweeps -- both at the start or
+  // both at the end -- so the second read hits L2 instead of going out to
+  // memory again.  w[k] holds row j + (k - R) * dir (dir = +-1).
+  const int dir = (chunk & 1) ? -1 : 1;
+  const int len = j1 - j0;
+  const int jstart = dir > 0 ? j0 : j1 - 1;
   double2 w[W];
   double hw[W];
 #pragma unroll
-  for (int k = 0; k < W; ++k) load_row(j0 - R + k, w[k], hw[k]);
-  double2 q0, q1;
-  double hq0, hq1;
-  load_row(j0 + R + 1, q0, hq0);
-  load_row(j0 + R + 2, q1, hq1);
+  for (int k = 0; k < W; ++k) load_row(jstart + (k - R) * dir, w[k], hw[k]);
+  // prefetch queue: the rows entering the window at steps s+1 and s+2; rows
+  // beyond the tile's last need are never loaded
+  double2 q0 = make_double2(0.0, 0.0), q1 = make_double2(0.0, 0.0);
+  double hq0 = 0.0, hq1 = 0.0;
+  if (1 < len) load_row(jstart + (R + 1) * dir, q0, hq0);
+  if (2 < len) load_row(jstart + (R + 2) * dir, q1, hq1);
   double2 bq = make_double2(0.0, 0.0), pq = make_double2(0.0, 0.0);
-  load_ep(j0, bq, pq);
+  load_ep(jstart, bq, pq);
   if (R == 2) {
-    store_lds((j0 - 1) & 3, w[1], hw[1]);
-    store_lds(j0 & 3, w[2], hw[2]);
+    store_lds((jstart - dir) & 3, w[1], hw[1]);
+    store_lds(jstart & 3, w[2], hw[2]);
   }
 
   double acc = 0.0, acc2 = 0.0;
-  for (int j = j0; j < j1; ++j) {
+  for (int s = 0; s < len; ++s) {
+    const int j = jstart + s * dir;
     if (R == 2)
-      store_lds((j + 1) & 3, w[3], hw[3]);
+      store_lds((j + dir) & 3, w[3], hw[3]);
     else
       store_lds(j & 3, w[1], hw[1]);
     __syncthreads();
     const double2 bcur = bq, pcur = pq;
-    load_ep(j + 1, bq, pq);
+    if (s + 1 < len) load_ep(j + dir, bq, pq);
 
+    // rows j-1 / j+1 (and j-2 / j+2) in the window, whatever the direction
+    const double2 wm1 = dir > 0 ? w[R - 1] : w[R + 1];
+    const double2 wp1 = dir > 0 ? w[R + 1] : w[R - 1];
     const double* L0 = lds[j & 3];
     const double2 cl = *reinterpret_cast<const double2*>(&L0[lc - 2]);  // c-2, c-1
     const double2 cr = *reinterpret_cast<const double2*>(&L0[lc + 2]);  // c+2, c+3
@@ -170,28 +185,30 @@ __global__ void __launch_bounds__(TPB) k_stream(StreamArgs P) {
     v0.xp1 = w[R].y;
     v1.xm1 = w[R].x;
     v1.xp1 = cr.x;
-    v0.ym1 = w[R - 1].x;
-    v0.yp1 = w[R + 1].x;
-    v1.ym1 = w[R - 1].y;
-    v1.yp1 = w[R + 1].y;
+    v0.ym1 = wm1.x;
+    v0.yp1 = wp1.x;
+    v1.ym1 = wm1.y;
+    v1.yp1 = wp1.y;
     if (R == 2) {
+      const double2 wm2 = dir > 0 ? w[0] : w[W - 1];
+      const double2 wp2 = dir > 0 ? w[W - 1] : w[0];
       const double* Lm = lds[(j - 1) & 3];
       const double* Lp = lds[(j + 1) & 3];
       v0.xm2 = cl.x;
       v0.xp2 = cr.x;
       v1.xm2 = cl.y;
       v1.xp2 = cr.y;
-      v0.ym2 = w[0].x;
-      v0.yp2 = w[W - 1].x;
-      v1.ym2 = w[0].y;
-      v1.yp2 = w[W - 1].y;
+      v0.ym2 = wm2.x;
+      v0.yp2 = wp2.x;
+      v1.ym2 = wm2.y;
+      v1.yp2 = wp2.y;
       v0.dmm = Lm[lc - 1];
-      v0.dmp = w[1].y;
-      v1.dmm = w[1].x;
+      v0.dmp = wm1.y;
+      v1.dmm = wm1.x;
       v1.dmp = Lm[lc + 2];
       v0.dpm = Lp[lc - 1];
-      v0.dpp = w[3].y;
-      v1.dpm = w[3].x;
+      v0.dpp = wp1.y;
+      v1.dpm = wp1.x;
       v1.dpp = Lp[lc + 2];
     }
     const int64_t o = (int64_t)j * n + c;
@@ -257,7 +274,7 @@ __global__ void __launch_bounds__(TPB) k_stream(StreamArgs P) {
     hw[W - 1] = hq0;
     q0 = q1;
     hq0 = hq1;
-    load_row(j + R + 3, q1, hq1);
+    if (s + 3 < len) load_row(j + (R + 3) * dir, q1, hq1);
   }
   if (RED) {
     const double s = block_sum_n<TPB>(acc);
@@ -295,8 +312,10 @@ StreamCfg stream_cfg(int n) {
   c.ty = ty;
   c.chunks = (n + 1 + ty - 1) / ty;
   c.tiles = strips * c.chunks;
+  static const int xm = env_int("BF_XCD_MAP", 1);
+  c.xcd_map = xm;
   c.per_xcd = (c.tiles + 7) / 8;
-  c.blocks = 8 * c.per_xcd;
+  c.blocks = xm ? 8 * c.per_xcd : c.tiles;
   return c;
 }
 
@@ -335,6 +354,7 @@ static int stream_launch(const OpDesc& A, const double* x, const double* b, cons
   P.chunks = c.chunks;
   P.tiles = c.tiles;
   P.per_xcd = c.per_xcd;
+  P.xcd_map = c.xcd_map;
   if (A.op == 0)
     dispatch<0, EPI>(c, P, st);
   else
@@ -393,6 +413,7 @@ int stream_cg_p(const OpDesc& A, const double* z, const double* p_old, double* p
   P.chunks = c.chunks;
   P.tiles = c.tiles;
   P.per_xcd = c.per_xcd;
+  P.xcd_map = c.xcd_map;
   if (A.op == 0)
     dispatch<0, E_CG_P>(c, P, st);
   else

@@ -36,6 +36,13 @@ import synthetic as S  # noqa: E402
 
 METRIC = "solve time/step + stencil SpMV HBM GB/s at 4096², mixed vs FP64 @1e-10"
 HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ["paper_1811_11842_amd/csrc/stream.hip", "paper_1811_11842_amd/csrc/stencil_ops.hpp",
+                  "paper_1811_11842_amd/csrc/common.hpp"]
+# HBM traffic per launch at 4096^2 from `rocprofv3 --pmc FETCH_SIZE` / `--pmc WRITE_SIZE`
+# (profiles/spmv_13pt_4096_counters.md), KiB per dispatch, scaled by the ratio of known to
+# counted bytes of the bf_copy calibration kernel.  Valid only for the kernel sources
+# whose sha256 is recorded; otherwise the traffic is reported as null.
+TRAFFIC_RECORD = {"n": 4096, "fetch_scale": 1.9996, "write_scale": 1.0, "kernels": {"spmv": {"fetch_kib": 75693.2, "write_kib": 131104.0}, "smooth": {"fetch_kib": 208517.1, "write_kib": 131104.0}}, "sources_sha256": "21019ae8e33f25fb60c29db160016b2c72a6e7228b80aabff13666a4adefb2c6"}
 
 
 def parse():
@@ -49,6 +56,8 @@ def parse():
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--spmv-only", action="store_true")
     ap.add_argument("--steps-only", action="store_true")
+    ap.add_argument("--smooth-only", action="store_true",
+                    help="only time the smoothing sweep (for profiling that kernel)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a plain device copy of one field (for HBM counter calibration)")
     return ap.parse_args()
@@ -108,6 +117,45 @@ def time_spmv(g, n, reps):
     return e0.elapsed_time(e1) / reps
 
 
+def time_smooth(g, n, reps):
+    """Average duration of one Cahn-Hilliard smoothing sweep (x, x_prev, b -> x')."""
+    dev = g.device
+    nset = 2
+    sets = [[torch.from_numpy(S.random_field(n, 70 + 4 * k + m)).to(dev) for m in range(4)]
+            for k in range(nset)]
+    c = S.DEFAULT_PARAMS["dt"] * S.DEFAULT_PARAMS["M"] * S.DEFAULT_PARAMS["kappa"]
+    for x, xp, b, out in sets:
+        g.smooth(bf.OP_CH, c, x, b, out, xp, 0.4, 0.3)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for r in range(reps):
+        x, xp, b, out = sets[r % nset]
+        g.smooth(bf.OP_CH, c, x, b, out, xp, 0.4, 0.3)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(kernel, n):
+    rec = TRAFFIC_RECORD
+    if not rec or rec.get("n") != n or rec.get("sources_sha256") != sources_sha256():
+        return None
+    k = rec["kernels"].get(kernel)
+    if not k:
+        return None
+    return int(k["fetch_kib"] * 1024 * rec["fetch_scale"] + k["write_kib"] * 1024 * rec["write_scale"])
+
+
 def cpu_baseline(n, steps):
     import oracle  # the CPU oracle, timed as it stands
     phi = S.initial_phi(n)
@@ -150,6 +198,11 @@ def main():
            "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
            "dtype": "f64", "data": "synthetic"}
     with bf.Grid(n) as g:
+        if a.smooth_only:
+            t_sm = time_smooth(g, n, a.spmv_reps)
+            print(json.dumps({"smooth_us": round(t_sm * 1e3, 3),
+                              "smooth_gbs": round(32 * npts / (t_sm * 1e-3) / 1e9, 1)}), flush=True)
+            return
         if not a.spmv_only:
             ms_step, wall_ms, stats = time_steps(g, n, a.steps, a.warmup)
             it_ch = [s[0].iters for s in stats]
@@ -167,14 +220,25 @@ def main():
             })
         if not a.steps_only:
             t_spmv = time_spmv(g, n, a.spmv_reps)
-            traffic = 16.0 * npts      # algorithmic: read x once, write y once (float64)
-            gbs = traffic / (t_spmv * 1e-3) / 1e9
+            alg = 16 * npts      # algorithmic: read x once, write y once (float64)
+            gbs = alg / (t_spmv * 1e-3) / 1e9
             out["spmv_us"] = round(t_spmv * 1e3, 3)
             out["spmv_gbs"] = round(gbs, 1)
             out["roofline"] = {"kernel": "k_stream<1,0,256> (13-point Cahn-Hilliard SpMV, float64)",
                                "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
                                "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
-                               "traffic": None, "algorithmic_bytes": int(traffic)}
+                               "traffic": recorded_traffic("spmv", n), "algorithmic_bytes": alg,
+                               "launch_us": round(t_spmv * 1e3, 3)}
+            if not a.spmv_only:
+                t_sm = time_smooth(g, n, max(20, a.spmv_reps // 2))
+                alg_sm = 32 * npts   # x, x_prev, b read, x' written
+                gbs_sm = alg_sm / (t_sm * 1e-3) / 1e9
+                out["roofline_smoother"] = {
+                    "kernel": "k_stream<1,4,256> (13-point Chebyshev smoothing sweep, float64)",
+                    "bound": "hbm", "achieved": round(gbs_sm, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(gbs_sm / HBM_PEAK_GBS, 4),
+                    "traffic": recorded_traffic("smooth", n), "algorithmic_bytes": alg_sm,
+                    "launch_us": round(t_sm * 1e3, 3)}
     out["config"] = {"workload": f"{n}x{n} grid, float64 step: Flory-Huggins RHS + MG-PCG "
                                  f"Cahn-Hilliard solve + MG-PCG pressure solve + velocity "
                                  f"correction, rtol 1e-10",

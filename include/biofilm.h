@@ -193,6 +193,17 @@ int bf_prolong_add(bf_grid* g, int32_t nf, const double* coarse, double* fine);
 int bf_residual(bf_grid* g, int32_t op, double c, const double* b, const double* x,
                 double* r, int32_t accurate, double* rel_norm, double* floor_est);
 
+/* One smoothing sweep of the multigrid preconditioner (the paper's Jacobi
+ * preconditioner of Sec. 4.1, listing "Creating PETSc KSP and PC objects",
+ * in the three-term Chebyshev form):
+ *   xout = x + a D^{-1} (b - A x) + gcoef (x - xprev),
+ * D = diag(A) (1 + 20 s, or 1 + 21 s on rows 1 and n-1, for the CH operator;
+ * -4 n^2 for the Laplacian).  xprev may be NULL (taken as 0) and may alias
+ * xout; xout must not alias x or b.  gcoef = 0, a = omega is damped Jacobi.
+ * Asynchronous. */
+int bf_smooth(bf_grid* g, int32_t op, double c, const double* x, const double* xprev,
+              const double* b, double* xout, double a, double gcoef);
+
 /* y = x for one field (16-byte aligned pointers), with the memory access
  * pattern of the stencil kernels (16 bytes per lane, coalesced rows): a
  * streaming kernel of known traffic (8 (n+1) n bytes each way), used to

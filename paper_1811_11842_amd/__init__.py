@@ -110,6 +110,8 @@ def lib():
             "bf_prolong_add": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P]),
             "bf_wdot": (ctypes.c_int, [_P, _P, _P, ctypes.POINTER(ctypes.c_double)]),
             "bf_copy": (ctypes.c_int, [_P, _P, _P]),
+            "bf_smooth": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_double, _P, _P, _P, _P,
+                                         ctypes.c_double, ctypes.c_double]),
             "bf_residual": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_double, _P, _P, _P,
                                            ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                            ctypes.POINTER(ctypes.c_double)]),
@@ -296,6 +298,13 @@ class Grid:
                                  self._ptr(r, "r"), 1 if accurate else 0, ctypes.byref(rel),
                                  ctypes.byref(fl)))
         return r, rel.value, fl.value
+
+    def smooth(self, op, c, x, b, xout=None, xprev=None, a=1.0, g=0.0):
+        xout = self.field() if xout is None else xout
+        _check(lib().bf_smooth(self._h, op, c, self._ptr(x, "x"),
+                               self._ptr(xprev, "xprev") if xprev is not None else None,
+                               self._ptr(b, "b"), self._ptr(xout, "xout"), a, g))
+        return xout
 
     def copy(self, x, y=None):
         y = self.field() if y is None else y

@@ -1080,6 +1080,18 @@ int bf_residual(bf_grid* g, int32_t op, double c, const double* b, const double*
   return BF_OK;
 }
 
+int bf_smooth(bf_grid* g, int32_t op, double c, const double* x, const double* xprev,
+              const double* b, double* xout, double a, double gcoef) {
+  TRY(check_grid(g));
+  if (!x || !b || !xout) return fail(BF_EINVAL, "null field");
+  if (xout == x || xout == b) return fail(BF_EINVAL, "xout must not alias x or b");
+  if (op != BF_OP_LAP && op != BF_OP_CH) return fail(BF_EINVAL, "op %d", op);
+  if (!(c >= 0) || !std::isfinite(c)) return fail(BF_EINVAL, "c = %g must be finite and >= 0", c);
+  launch_smooth(level_op(op, g->n, c), x, xprev, b, xout, a, gcoef, g->stream);
+  HIPCHK(hipGetLastError());
+  return BF_OK;
+}
+
 int bf_copy(bf_grid* g, const double* x, double* y) {
   TRY(check_grid(g));
   if (!x || !y) return fail(BF_EINVAL, "null field");

@@ -76,6 +76,27 @@ def test_apply_matches_oracle(dev, n, op):
     assert np.abs(y - ref).max() <= tol
 
 
+@pytest.mark.parametrize("n", [8, 128, 1024])
+@pytest.mark.parametrize("op", ["lap", "ch"])
+def test_smooth_sweep_and_copy_match_oracle(dev, n, op):
+    """One Chebyshev sweep x' = x + a D^-1 (b - A x) + g (x - xprev) against the
+    oracle's smoother arithmetic, and bf_copy."""
+    c = 3e-7 if op == "ch" else 0.0
+    x, xp, b = (S.random_field(n, seed=s) for s in (1, 2, 3))
+    lev = mg.Level(op, n, c)
+    a, gco = 0.37, 0.21
+    ref = x + a * (b - lev.apply(x)) / lev.diag + gco * (x - xp)
+    g = grid(n)
+    out = to_np(g.smooth(bf.OP_CH if op == "ch" else bf.OP_LAP, c, to_dev(x, dev), to_dev(b, dev),
+                         xprev=to_dev(xp, dev), a=a, g=gco))
+    wsum = (1 + 64 * c * float(n) ** 4) if op == "ch" else 8.0 * n * n
+    dmax = float(np.abs(1 / lev.diag).max())
+    tol = 16 * U * (1 + a * dmax * (wsum + 1) + gco) * 3
+    assert np.abs(out - ref).max() <= tol
+    y = to_np(g.copy(to_dev(x, dev)))
+    assert np.array_equal(y, x)
+
+
 @pytest.mark.parametrize("nf", [8, 16, 128, 1024])
 def test_restrict_and_prolong_match_oracle(dev, nf):
     g = grid(max(nf, 8))

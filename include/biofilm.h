@@ -59,6 +59,7 @@ enum { BF_OP_LAP = 0, BF_OP_CH = 1 };
 enum { BF_KSP_CG = 0, BF_KSP_GMRES = 1 };
 enum { BF_PC_NONE = 0, BF_PC_JACOBI = 1, BF_PC_MG = 2 };
 enum { BF_SMOOTH_CHEBYSHEV = 0, BF_SMOOTH_JACOBI = 1 };
+enum { BF_MG_F64 = 0, BF_MG_F32 = 1 };
 
 /* Grid description (the paper's DMDA object of Sec. 4.1, Listing "Initializing
  * a 2D DMDA object": periodic x, reflected y, stencil width 2, one dof). */
@@ -84,6 +85,13 @@ typedef struct {
   double  ratio;        /* Chebyshev interval lmax/lmin; 0 = default        */
                         /* (CH 16, P 4)                                     */
   double  omega;        /* damped-Jacobi weight; 0 = default                */
+  int32_t mg_precision; /* BF_MG_F64, or BF_MG_F32: the multigrid V-cycle   */
+                        /* (smoothing, residuals, transfers, coarse tail)   */
+                        /* runs on float32 fields while the Krylov method,  */
+                        /* its residual and the iterate stay float64; CG    */
+                        /* then takes the flexible (Polak-Ribiere) beta.    */
+                        /* The float32 hierarchy is allocated on first use. */
+  int32_t reserved;     /* 0                                                */
 } bf_solver_opts;
 
 typedef struct {

@@ -29,6 +29,7 @@ OP_LAP, OP_CH = 0, 1
 KSP_CG, KSP_GMRES = 0, 1
 PC_NONE, PC_JACOBI, PC_MG = 0, 1, 2
 SMOOTH_CHEBYSHEV, SMOOTH_JACOBI = 0, 1
+MG_F64, MG_F32 = 0, 1
 STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", 2: "AT_FLOOR", -1: "EINVAL", -2: "ENOMEM",
                 -3: "EHIP", -4: "ENONFINITE", -5: "EUNSUPPORTED"}
 
@@ -42,7 +43,8 @@ class SolverOpts(ctypes.Structure):
                 ("restart", ctypes.c_int32), ("smoother", ctypes.c_int32),
                 ("degree", ctypes.c_int32), ("check_every", ctypes.c_int32),
                 ("max_restarts", ctypes.c_int32), ("rtol", ctypes.c_double),
-                ("ratio", ctypes.c_double), ("omega", ctypes.c_double)]
+                ("ratio", ctypes.c_double), ("omega", ctypes.c_double),
+                ("mg_precision", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
     def __repr__(self):
         return "SolverOpts(" + ", ".join(f"{k}={getattr(self, k)}" for k, _ in self._fields_) + ")"

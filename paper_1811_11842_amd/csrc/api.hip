@@ -12,6 +12,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/biofilm.h"
@@ -48,14 +49,18 @@ int fail(int code, const char* fmt, ...) {
     if (s_ < 0) return s_;   \
   } while (0)
 
-struct Level {
+// One multigrid level's fields, stored in T (float64, or float32 for the
+// mixed-precision V-cycle).
+template <typename T>
+struct LevelT {
   int n = 0;
   int64_t npts = 0;
-  double* xa = nullptr;  // iterate buffers (ping-pong)
-  double* xb = nullptr;
-  double* r = nullptr;   // residual
-  double* b = nullptr;   // right-hand side (levels >= 1)
+  T* xa = nullptr;  // iterate buffers (ping-pong)
+  T* xb = nullptr;
+  T* r = nullptr;   // residual
+  T* b = nullptr;   // right-hand side (levels >= 1)
 };
+using Level = LevelT<double>;
 
 constexpr int kCoarseN = 4;
 constexpr int kCoarseSize = (kCoarseN + 1) * kCoarseN;
@@ -67,6 +72,8 @@ struct bf_grid {
   int64_t npts = 0;
   hipStream_t stream = nullptr;
   std::vector<Level> lv;
+  std::vector<LevelT<float>> lvf;  // float32 hierarchy (allocated on first mixed use)
+  float* r32 = nullptr;            // float32 copy of the V-cycle's level-0 input
   double *r = nullptr, *z = nullptr, *p = nullptr, *p2 = nullptr, *q = nullptr;
   double *work_b = nullptr;   // Cahn-Hilliard right-hand side inside bf_step
   double *work_p = nullptr;   // projected pressure right-hand side
@@ -81,9 +88,9 @@ struct bf_grid {
   // Captured V-cycles (one hipGraphExec per operator / coefficient / options /
   // input buffer), replayed with a single launch; captured on cap_stream.
   struct VcGraph {
-    int op, smoother, degree, rz;
+    int op, smoother, degree, rz, prec;
     double c, ratio, omega;
-    const double* b;
+    const void* b;
     hipGraphExec_t exec;
     double* result;
     int rz_parts;
@@ -115,6 +122,38 @@ int dalloc(bf_grid* g, double** p, int64_t count) {
 }
 
 bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
+
+// The float32 hierarchy and level-0 input of the mixed-precision V-cycle,
+// allocated on first use (half the bytes of the float64 one).
+int ensure_mixed(bf_grid* g) {
+  if (g->r32) return BF_OK;
+  std::vector<LevelT<float>> lv;
+  auto fal = [&](float** p, int64_t cnt) -> int {
+    void* ptr = nullptr;
+    if (hipMalloc(&ptr, (size_t)cnt * sizeof(float)) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(BF_ENOMEM, "hipMalloc of %lld floats failed", (long long)cnt);
+    }
+    g->allocs.push_back(ptr);
+    *p = (float*)ptr;
+    return BF_OK;
+  };
+  for (const Level& D : g->lv) {
+    LevelT<float> L;
+    L.n = D.n;
+    L.npts = D.npts;
+    TRY(fal(&L.xa, L.npts));
+    TRY(fal(&L.xb, L.npts));
+    TRY(fal(&L.r, L.npts));
+    TRY(fal(&L.b, L.npts));
+    lv.push_back(L);
+  }
+  float* r32 = nullptr;
+  TRY(fal(&r32, g->npts));
+  g->lvf = lv;
+  g->r32 = r32;
+  return BF_OK;
+}
 
 // ------------------------------------------------------------ host-side small
 // dense algebra for the coarsest grid (5 x 4 nodes).
@@ -242,6 +281,8 @@ OpDesc level_op(int op, int n, double c) {
   return A;
 }
 
+int nparts_of(const bf_grid* g) { return red_blocks(g->npts); }
+
 struct Smoother {
   int degree = 0;
   double a[8] = {0};
@@ -293,85 +334,139 @@ Smoother make_smoother(int op, int n, double c, const bf_solver_opts& o) {
   return S;
 }
 
-// One V-cycle on level l with right-hand side b (level 0: external pointer).
-// Returns the buffer holding the level's result.  If rz_parts is given (level
-// 0 only) and the last smoothing sweep can produce it, that sweep also writes
-// partials of <b, z>_W into g->partials and *rz_parts receives their count
-// (0 when the caller must reduce <b, z>_W itself).
-double* vcycle_level(bf_grid* g, int op, double c, const bf_solver_opts& o, int l,
-                     const double* b, int* rz_parts = nullptr) {
-  Level& L = g->lv[l];
+// One V-cycle on level l of hierarchy lv with right-hand side b (level 0:
+// external pointer).  Returns the buffer holding the level's result.
+//
+// float64 hierarchy: if rz_parts is given (level 0 only) and the last
+// smoothing sweep can produce it, that sweep also writes partials of
+// <b, z>_W into g->partials and *rz_parts receives their count (0 when the
+// caller must reduce <b, z>_W itself).
+//
+// float32 hierarchy (mixed precision): level 0 must be given zout, the
+// float64 output, and bd, the float64 right-hand side that b rounds.  The
+// last sweep writes z into zout and partials of <b, z>_W (first group) and
+// <z, q>_W (second group, q = g->q) into g->partials; *rz_parts (if given)
+// receives the group size.  Returns nullptr at level 0 (the result is zout).
+template <typename T>
+T* vcycle_level(bf_grid* g, std::vector<LevelT<T>>& lv, int op, double c,
+                const bf_solver_opts& o, int l, const T* b, int* rz_parts = nullptr,
+                double* zout = nullptr, const double* bd = nullptr) {
+  constexpr bool F32 = std::is_same<T, float>::value;
+  LevelT<T>& L = lv[l];
   hipStream_t st = g->stream;
   if (rz_parts) *rz_parts = 0;
+  T* res = nullptr;
   if (L.n == kCoarseN) {
     launch_coarse_solve(kCoarseSize, op == BF_OP_CH ? g->coarse_ch : g->coarse_lap, b, L.xa, st);
-    return L.xa;
-  }
-  if (L.n <= kTailTop) {
+    res = L.xa;
+  } else if (L.n <= kTailTop) {
     // the rest of the cycle in one workgroup (fields in LDS)
     TailArgs P;
     P.nlev = 0;
     for (int n = L.n; n > kCoarseN; n /= 2) {
       const OpDesc A = level_op(op, n, c);
       const Smoother S = make_smoother(op, n, c, o);
-      TailLevel& T = P.lev[P.nlev++];
-      T.n = n;
-      T.degree = S.degree;
-      T.coef = A.coef;
-      T.dinv_int = A.dinv_int;
-      T.dinv_edge = A.dinv_edge;
+      TailLevel& TL = P.lev[P.nlev++];
+      TL.n = n;
+      TL.degree = S.degree;
+      TL.coef = A.coef;
+      TL.dinv_int = A.dinv_int;
+      TL.dinv_edge = A.dinv_edge;
       for (int k = 0; k < 8; ++k) {
-        T.a[k] = S.a[k];
-        T.g[k] = S.g[k];
+        TL.a[k] = S.a[k];
+        TL.g[k] = S.g[k];
       }
     }
     P.G = op == BF_OP_CH ? g->coarse_ch : g->coarse_lap;
-    P.b_in = b;
-    P.x_out = L.xa;
-    launch_tail(op, P, st);
-    return L.xa;
+    launch_tail(op, P, b, L.xa, st);
+    res = L.xa;
+  }
+  if (res) {
+    if constexpr (F32) {
+      if (zout) {  // a float32 hierarchy this small: widen, then the two dots
+        const int np = nparts_of(g);
+        launch_to_double(L.npts, res, zout, st);
+        launch_dot(L.n, bd, zout, g->partials, np, st);
+        launch_dot(L.n, zout, g->q, g->partials + np, np, st);
+        if (rz_parts) *rz_parts = np;
+        return nullptr;
+      }
+    }
+    return res;
   }
   const OpDesc A = level_op(op, L.n, c);
   const Smoother S = make_smoother(op, L.n, c, o);
-  const bool fused = stream_ok(L.n) && S.degree >= 2;
+  const bool streamed = stream_ok(L.n, (int)sizeof(T));
+  const bool fused = streamed && S.degree >= 2;
   // pre-smoothing from zero
-  double* cur = L.xa;
-  double* oth = L.xb;
+  T* cur = L.xa;
+  T* oth = L.xb;
   if (fused) {
     // sweeps 0 and 1 in one pass (x1 = a0 D^-1 b is never stored), sweep 2
     // re-forms x1 from b for its (x - x_prev) term
-    stream_smooth_from_zero(A, b, cur, S.a[0], S.a[1], S.g[1], st);
+    stream_smooth_from_zero<T>(A, b, cur, S.a[0], S.a[1], S.g[1], st);
     for (int k = 2; k < S.degree; ++k) {
       if (k == 2)
-        stream_smooth_prev_from_b(A, cur, b, oth, S.a[0], S.a[k], S.g[k], st);
+        stream_smooth_prev_from_b<T>(A, cur, b, oth, S.a[0], S.a[k], S.g[k], st);
       else
-        launch_smooth(A, cur, S.g[k] != 0.0 ? oth : nullptr, b, oth, S.a[k], S.g[k], st);
+        launch_smooth<T>(A, cur, S.g[k] != 0.0 ? oth : nullptr, b, oth, S.a[k], S.g[k], st);
       std::swap(cur, oth);
     }
   } else {
-    launch_smooth0(A, b, cur, S.a[0], st);
+    launch_smooth0<T>(A, b, cur, S.a[0], st);
     for (int k = 1; k < S.degree; ++k) {
-      launch_smooth(A, cur, (k == 1 || S.g[k] == 0.0) ? nullptr : oth, b, oth, S.a[k], S.g[k],
-                    st);
+      launch_smooth<T>(A, cur, (k == 1 || S.g[k] == 0.0) ? nullptr : oth, b, oth, S.a[k],
+                       S.g[k], st);
       std::swap(cur, oth);
     }
   }
   // coarse-grid correction
-  launch_residual(A, cur, b, L.r, nullptr, 0, st);
-  Level& C = g->lv[l + 1];
-  launch_restrict(L.n, L.r, C.b, st);
-  double* e = vcycle_level(g, op, c, o, l + 1, C.b);
-  launch_prolong_add(L.n, e, cur, st);
+  launch_residual<T>(A, cur, b, L.r, nullptr, 0, st);
+  LevelT<T>& C = lv[l + 1];
+  launch_restrict<T>(L.n, L.r, C.b, st);
+  T* e = vcycle_level<T>(g, lv, op, c, o, l + 1, C.b);
+  launch_prolong_add<T>(L.n, e, cur, st);
   // post-smoothing (same polynomial)
   for (int k = 0; k < S.degree; ++k) {
-    const double* prev = S.g[k] != 0.0 ? oth : nullptr;
-    if (rz_parts && k == S.degree - 1 && stream_ok(L.n))
-      *rz_parts = stream_smooth_dot(A, cur, prev, b, oth, S.a[k], S.g[k], g->partials, st);
-    else
-      launch_smooth(A, cur, prev, b, oth, S.a[k], S.g[k], st);
+    const T* prev = S.g[k] != 0.0 ? oth : nullptr;
+    const bool last = k == S.degree - 1;
+    if constexpr (F32) {
+      if (last && zout) {
+        int np;
+        if (streamed) {
+          np = stream_smooth_dot2(A, cur, prev, b, zout, g->q, S.a[k], S.g[k], g->partials, st);
+        } else {
+          np = nparts_of(g);
+          launch_smooth<T>(A, cur, prev, b, oth, S.a[k], S.g[k], st);
+          launch_to_double(L.npts, oth, zout, st);
+          launch_dot(L.n, bd, zout, g->partials, np, st);
+          launch_dot(L.n, zout, g->q, g->partials + np, np, st);
+        }
+        if (rz_parts) *rz_parts = np;
+        return nullptr;
+      }
+      launch_smooth<T>(A, cur, prev, b, oth, S.a[k], S.g[k], st);
+    } else {
+      if (rz_parts && last && streamed)
+        *rz_parts = stream_smooth_dot(A, cur, prev, b, oth, S.a[k], S.g[k], g->partials, st);
+      else
+        launch_smooth<T>(A, cur, prev, b, oth, S.a[k], S.g[k], st);
+    }
     std::swap(cur, oth);
   }
   return cur;
+}
+
+// The V-cycle from level 0 in the precision o.mg_precision selects; the
+// float32 cycle reads g->r32 (already holding the rounded r) and writes z
+// into g->z.  Returns the buffer holding z.
+double* vcycle_top(bf_grid* g, int op, double c, const bf_solver_opts& o, const double* r,
+                   int* rz_parts) {
+  if (o.mg_precision == BF_MG_F32) {
+    vcycle_level<float>(g, g->lvf, op, c, o, 0, g->r32, rz_parts, g->z, r);
+    return g->z;
+  }
+  return vcycle_level<double>(g, g->lv, op, c, o, 0, r, rz_parts);
 }
 
 int check_opts(const bf_solver_opts& o) {
@@ -386,6 +481,8 @@ int check_opts(const bf_solver_opts& o) {
     return fail(BF_EINVAL, "restart %d not in 1..64", o.restart);
   if (o.check_every < 1) return fail(BF_EINVAL, "check_every %d < 1", o.check_every);
   if (o.ratio < 0 || o.omega < 0) return fail(BF_EINVAL, "negative ratio/omega");
+  if (o.mg_precision != BF_MG_F64 && o.mg_precision != BF_MG_F32)
+    return fail(BF_EINVAL, "mg_precision %d", o.mg_precision);
   return BF_OK;
 }
 
@@ -401,7 +498,8 @@ double* vcycle_graph(bf_grid* g, int op, double c, const bf_solver_opts& o, cons
   const int rz = rz_parts ? 1 : 0;
   for (auto& e : g->graphs) {
     if (e.op == op && e.c == c && e.smoother == o.smoother && e.degree == o.degree &&
-        e.ratio == o.ratio && e.omega == o.omega && e.b == b && e.rz == rz) {
+        e.ratio == o.ratio && e.omega == o.omega && e.b == b && e.rz == rz &&
+        e.prec == o.mg_precision) {
       if (hipGraphLaunch(e.exec, g->stream) != hipSuccess) return nullptr;
       if (rz_parts) *rz_parts = e.rz_parts;
       return e.result;
@@ -420,6 +518,7 @@ double* vcycle_graph(bf_grid* g, int op, double c, const bf_solver_opts& o, cons
   e.omega = o.omega;
   e.b = b;
   e.rz = rz;
+  e.prec = o.mg_precision;
   e.rz_parts = 0;
   hipStream_t user = g->stream;
   if (hipStreamBeginCapture(g->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
@@ -427,7 +526,7 @@ double* vcycle_graph(bf_grid* g, int op, double c, const bf_solver_opts& o, cons
     return nullptr;
   }
   g->stream = g->cap_stream;
-  e.result = vcycle_level(g, op, c, o, 0, b, rz ? &e.rz_parts : nullptr);
+  e.result = vcycle_top(g, op, c, o, b, rz ? &e.rz_parts : nullptr);
   g->stream = user;
   hipGraph_t graph = nullptr;
   if (hipStreamEndCapture(g->cap_stream, &graph) != hipSuccess || !graph) {
@@ -447,18 +546,20 @@ double* vcycle_graph(bf_grid* g, int op, double c, const bf_solver_opts& o, cons
 }
 
 // z = M r for the chosen preconditioner.  Returns the buffer holding z; see
-// vcycle_level for rz_parts.
+// vcycle_level for rz_parts.  With the float32 V-cycle, r32_ready says that
+// g->r32 already holds (float) r (the CG residual update writes it).
 double* precondition(bf_grid* g, int op, double c, const bf_solver_opts& o, const double* r,
-                     int* rz_parts = nullptr) {
+                     int* rz_parts = nullptr, bool r32_ready = false) {
   if (rz_parts) *rz_parts = 0;
   switch (o.pc) {
     case BF_PC_MG:
+      if (o.mg_precision == BF_MG_F32 && !r32_ready) launch_to_float(g->npts, r, g->r32, g->stream);
       if (g->use_graphs) {
         double* z = vcycle_graph(g, op, c, o, r, rz_parts);
         if (z) return z;
         g->use_graphs = false;  // capture not available: launch eagerly from now on
       }
-      return vcycle_level(g, op, c, o, 0, r, rz_parts);
+      return vcycle_top(g, op, c, o, r, rz_parts);
     case BF_PC_JACOBI:
       launch_jacobi_pc(level_op(op, g->n, c), r, g->z, g->stream);
       return g->z;
@@ -467,8 +568,6 @@ double* precondition(bf_grid* g, int op, double c, const bf_solver_opts& o, cons
       return g->z;
   }
 }
-
-int nparts_of(const bf_grid* g) { return red_blocks(g->npts); }
 
 // Reduce <x, y>_W into scal[slot] (asynchronous).
 void wdot_async(bf_grid* g, const double* x, const double* y, int mode, int slot) {
@@ -581,6 +680,12 @@ int run_cg(bf_grid* g, int op, double c, const double* b, double* x, const bf_so
   if (ks.rel_true <= o.rtol) return BF_OK;
   double last_true = ks.rel_true;
 
+  // With the float32 V-cycle the preconditioner changes slightly from one
+  // application to the next (rounding), so beta takes the flexible
+  // (Polak-Ribiere) form -alpha <z_k, q_{k-1}>_W / rho_{k-1}, which the last
+  // smoothing sweep reduces together with rho_k = <r_k, z_k>_W.
+  const bool mixed = o.pc == BF_PC_MG && o.mg_precision == BF_MG_F32;
+  if (mixed) TRY(ensure_mixed(g));
   double* pcur = g->p;
   double* pnext = g->p2;
   for (;;) {
@@ -602,7 +707,7 @@ int run_cg(bf_grid* g, int op, double c, const double* b, double* x, const bf_so
       std::swap(pcur, pnext);
       first = false;
       pending = true;
-      launch_r_update(g->n, g->r, g->q, g->scal, g->partials, np, st);
+      launch_r_update(g->n, g->r, g->q, g->scal, g->partials, np, st, mixed ? g->r32 : nullptr);
       launch_finalize(g->partials, np, g->scal, F_STORE, S_RR, g->n, st);
       ks.iters++;
       if (ks.iters % o.check_every == 0 || ks.iters == o.maxit) {
@@ -614,8 +719,10 @@ int run_cg(bf_grid* g, int op, double c, const double* b, double* x, const bf_so
           break;
         }
       }
-      z = precondition(g, op, c, o, g->r, &rzp);
-      if (rzp > 0)
+      z = precondition(g, op, c, o, g->r, &rzp, mixed);
+      if (mixed)
+        launch_finalize_flex(g->partials, rzp, g->scal, st);
+      else if (rzp > 0)
         launch_finalize(g->partials, rzp, g->scal, F_BETA, 0, g->n, st);
       else
         wdot_async(g, g->r, z, F_BETA, 0);
@@ -654,6 +761,7 @@ int run_gmres(bf_grid* g, int op, double c, const double* b, double* x, const bf
   const int np = nparts_of(g);
   const int m = o.restart;
   TRY(ensure_gmres(g, m));
+  if (o.pc == BF_PC_MG && o.mg_precision == BF_MG_F32) TRY(ensure_mixed(g));
   const OpDesc A = level_op(op, g->n, c);
   const int64_t N = g->npts;
   wdot_async(g, b, b, F_STORE, S_BN2);
@@ -787,6 +895,7 @@ void default_opts(int32_t op, bf_solver_opts* o) {
   o->rtol = 1e-10;
   o->ratio = 0.0;
   o->omega = 0.0;
+  o->mg_precision = BF_MG_F64;
   (void)op;
 }
 
@@ -864,6 +973,7 @@ int bf_grid_create(const bf_grid_desc* desc, bf_grid** out) {
   }
   if (s == BF_OK) {
     launch_fill(kNumSlots, g->scal, 0.0, g->stream);
+    launch_fill(g->npts, g->q, 0.0, g->stream);
     s = upload_coarse(g, BF_OP_LAP, 0.0);
   }
   if (s != BF_OK) {
@@ -1020,6 +1130,7 @@ int bf_vcycle(bf_grid* g, int32_t op, double c, const bf_solver_opts* o, const d
   if (op == BF_OP_CH) TRY(ensure_coarse_ch(g, c));
   bf_solver_opts om = oo;
   om.pc = BF_PC_MG;
+  if (om.mg_precision == BF_MG_F32) TRY(ensure_mixed(g));
   double* res = precondition(g, op, c, om, r);
   launch_copy(g->npts, res, z, g->stream);
   HIPCHK(hipGetLastError());

@@ -20,10 +20,10 @@ namespace bf {
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < (total); \
        idx += (int64_t)gridDim.x * blockDim.x)
 
-template <int OP>
-__device__ __forceinline__ double stencil_at(const double* __restrict__ x, int i, int j, int n,
-                                             int mask, double coef, double& center) {
-  const Nb13 v = gather<OP>(x, i, j, n, mask);
+template <int OP, typename T>
+__device__ __forceinline__ T stencil_at(const T* __restrict__ x, int i, int j, int n, int mask,
+                                        T coef, T& center) {
+  const Nb13T<T> v = gather<OP>(x, i, j, n, mask);
   center = v.c;
   return apply_vals<OP>(v, coef);
 }
@@ -34,10 +34,10 @@ __device__ __forceinline__ double residual_dd_at(const double* __restrict__ x, d
   return residual_dd_vals<OP>(gather<OP>(x, i, j, n, mask), bval, coef);
 }
 
-template <int OP>
-__device__ __forceinline__ double dinv_at(const OpDesc& A, int j) {
-  if (OP == 0) return A.dinv_int;
-  return (j == 1 || j == A.n - 1) ? A.dinv_edge : A.dinv_int;
+template <int OP, typename T = double>
+__device__ __forceinline__ T dinv_at(const OpDesc& A, int j) {
+  if (OP == 0) return T(A.dinv_int);
+  return T((j == 1 || j == A.n - 1) ? A.dinv_edge : A.dinv_int);
 }
 
 // ------------------------------------------------------------------ operators
@@ -75,21 +75,20 @@ __global__ void __launch_bounds__(kBlock) k_apply_dot(OpDesc A, Geo G, const dou
   if (threadIdx.x == 0) partials[blockIdx.x] = t;
 }
 
-template <int OP>
-__global__ void __launch_bounds__(kBlock) k_residual(OpDesc A, Geo G, const double* __restrict__ x,
-                                                     const double* __restrict__ b,
-                                                     double* __restrict__ r,
+template <int OP, typename T>
+__global__ void __launch_bounds__(kBlock) k_residual(OpDesc A, Geo G, const T* __restrict__ x,
+                                                     const T* __restrict__ b, T* __restrict__ r,
                                                      double* __restrict__ partials) {
   double acc = 0.0;
   GRID_STRIDE(idx, G.npts) {
     const int i = (int)(idx & G.mask), j = (int)(idx >> G.log2n);
-    double v = b[idx];
+    T v = b[idx];
     if (x) {
-      double c;
-      v -= stencil_at<OP>(x, i, j, G.n, G.mask, A.coef, c);
+      T c;
+      v -= stencil_at<OP>(x, i, j, G.n, G.mask, T(A.coef), c);
     }
     r[idx] = v;
-    acc += row_weight(j, G.n) * v * v;
+    acc += row_weight(j, G.n) * double(v) * double(v);
   }
   if (partials) {
     const double t = block_sum(acc);
@@ -124,26 +123,27 @@ __global__ void __launch_bounds__(kBlock) k_residual_dd(OpDesc A, Geo G,
   if (threadIdx.x == 0) partials[gridDim.x + blockIdx.x] = tu;
 }
 
-template <int OP>
-__global__ void __launch_bounds__(kBlock) k_smooth(OpDesc A, Geo G, const double* __restrict__ x,
-                                                   const double* xprev,
-                                                   const double* __restrict__ b, double* xout,
-                                                   double a, double g) {
+template <int OP, typename T>
+__global__ void __launch_bounds__(kBlock) k_smooth(OpDesc A, Geo G, const T* __restrict__ x,
+                                                   const T* xprev, const T* __restrict__ b,
+                                                   T* xout, double a, double g) {
+  const T ta = T(a), tg = T(g), coef = T(A.coef);
   GRID_STRIDE(idx, G.npts) {
     const int i = (int)(idx & G.mask), j = (int)(idx >> G.log2n);
-    double c;
-    const double ax = stencil_at<OP>(x, i, j, G.n, G.mask, A.coef, c);
-    const double prev = xprev ? xprev[idx] : 0.0;
-    xout[idx] = c + a * dinv_at<OP>(A, j) * (b[idx] - ax) + g * (c - prev);
+    T c;
+    const T ax = stencil_at<OP>(x, i, j, G.n, G.mask, coef, c);
+    const T prev = xprev ? xprev[idx] : T(0);
+    xout[idx] = c + ta * dinv_at<OP, T>(A, j) * (b[idx] - ax) + tg * (c - prev);
   }
 }
 
-template <int OP>
-__global__ void __launch_bounds__(kBlock) k_smooth0(OpDesc A, Geo G, const double* __restrict__ b,
-                                                    double* __restrict__ xout, double a) {
+template <int OP, typename T>
+__global__ void __launch_bounds__(kBlock) k_smooth0(OpDesc A, Geo G, const T* __restrict__ b,
+                                                    T* __restrict__ xout, double a) {
+  const T ta = T(a);
   GRID_STRIDE(idx, G.npts) {
     const int j = (int)(idx >> G.log2n);
-    xout[idx] = a * dinv_at<OP>(A, j) * b[idx];
+    xout[idx] = ta * dinv_at<OP, T>(A, j) * b[idx];
   }
 }
 
@@ -158,30 +158,44 @@ __global__ void __launch_bounds__(kBlock) k_jacobi_pc(OpDesc A, Geo G, const dou
 
 // ------------------------------------------------------------------ transfers
 // coarse = R fine and fine += P coarse (one thread per node; small levels).
-__global__ void __launch_bounds__(kBlock) k_restrict(Geo F, Geo C, const double* __restrict__ fine,
-                                                     double* __restrict__ coarse) {
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_restrict(Geo F, Geo C, const T* __restrict__ fine,
+                                                     T* __restrict__ coarse) {
   GRID_STRIDE(idx, C.npts) {
     const int I = (int)(idx & C.mask), J = (int)(idx >> C.log2n);
     coarse[idx] = restrict_at(fine, F.n, F.mask, I, J);
   }
 }
 
-__global__ void __launch_bounds__(kBlock) k_prolong_add(Geo F, Geo C, const double* __restrict__ coarse,
-                                                        double* __restrict__ fine) {
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_prolong_add(Geo F, Geo C, const T* __restrict__ coarse,
+                                                        T* __restrict__ fine) {
   GRID_STRIDE(idx, F.npts) {
     const int i = (int)(idx & F.mask), j = (int)(idx >> F.log2n);
     fine[idx] += prolong_at(coarse, C.n, C.mask, i, j);
   }
 }
 
-__global__ void k_coarse_solve(int size, const double* __restrict__ G, const double* __restrict__ b,
-                               double* __restrict__ x) {
+template <typename T>
+__global__ void k_coarse_solve(int size, const double* __restrict__ G, const T* __restrict__ b,
+                               T* __restrict__ x) {
   const int k = threadIdx.x;
   if (k < size) {
     double acc = 0.0;
-    for (int l = 0; l < size; ++l) acc += G[k * size + l] * b[l];
-    x[k] = acc;
+    for (int l = 0; l < size; ++l) acc += G[k * size + l] * double(b[l]);
+    x[k] = T(acc);
   }
+}
+
+// r32 = (float) r: the right-hand side of the float32 V-cycle.
+__global__ void __launch_bounds__(kBlock) k_to_float(int64_t count, const double* __restrict__ x,
+                                                     float* __restrict__ y) {
+  GRID_STRIDE(idx, count) y[idx] = float(x[idx]);
+}
+
+__global__ void __launch_bounds__(kBlock) k_to_double(int64_t count, const float* __restrict__ x,
+                                                      double* __restrict__ y) {
+  GRID_STRIDE(idx, count) y[idx] = double(x[idx]);
 }
 
 // ------------------------------------------------------------------ reductions
@@ -239,6 +253,27 @@ __global__ void __launch_bounds__(kBlock) k_finalize(const double* __restrict__ 
   }
 }
 
+// Flexible (Polak-Ribiere) CG coefficient from two groups of partials:
+// rho = sum partials[0..np) = <r_k, z_k>_W, gamma = sum partials[np..2 np) =
+// <z_k, q_{k-1}>_W; beta = (rho - <z_k, r_{k-1}>) / rho_old = -alpha gamma / rho_old
+// since r_k = r_{k-1} - alpha q_{k-1}.
+__global__ void __launch_bounds__(kBlock) k_finalize_flex(const double* __restrict__ partials,
+                                                          int nparts, double* __restrict__ scal) {
+  double a1 = 0.0, a2 = 0.0;
+  for (int k = threadIdx.x; k < nparts; k += kBlock) {
+    a1 += partials[k];
+    a2 += partials[nparts + k];
+  }
+  const double rho = block_sum(a1);
+  const double gamma = block_sum(a2);
+  if (threadIdx.x == 0) {
+    const double old = scal[S_RZ];
+    scal[S_RZOLD] = old;
+    scal[S_RZ] = rho;
+    scal[S_BETA] = -scal[S_ALPHA] * gamma / old;
+  }
+}
+
 // Naive form of the fused CG step (small levels; see stream_cg_p).
 template <int OP>
 __global__ void __launch_bounds__(kBlock) k_cg_p(OpDesc A, Geo G, const double* __restrict__ z,
@@ -285,13 +320,15 @@ __global__ void __launch_bounds__(kBlock) k_cg_p(OpDesc A, Geo G, const double* 
 __global__ void __launch_bounds__(kBlock) k_r_update(Geo G, double* __restrict__ r,
                                                      const double* __restrict__ q,
                                                      const double* __restrict__ scal,
-                                                     double* __restrict__ partials) {
+                                                     double* __restrict__ partials,
+                                                     float* __restrict__ r32) {
   const double alpha = scal[S_ALPHA];
   double acc = 0.0;
   GRID_STRIDE(idx, G.npts) {
     const int j = (int)(idx >> G.log2n);
     const double rv = r[idx] - alpha * q[idx];
     r[idx] = rv;
+    if (r32) r32[idx] = float(rv);
     acc += row_weight(j, G.n) * rv * rv;
   }
   const double t = block_sum(acc);
@@ -496,17 +533,22 @@ int launch_apply_dot(const OpDesc& A, const double* p, double* q, double* partia
   return nparts;
 }
 
-int launch_residual(const OpDesc& A, const double* x, const double* b, double* r,
-                    double* partials, int nparts, hipStream_t st) {
-  if (x && stream_ok(A.n)) return stream_residual(A, x, b, r, partials, st);
+template <typename T>
+int launch_residual(const OpDesc& A, const T* x, const T* b, T* r, double* partials, int nparts,
+                    hipStream_t st) {
+  if (x && stream_ok(A.n, sizeof(T))) return stream_residual<T>(A, x, b, r, partials, st);
   const Geo G = make_geo(A.n);
   const int blocks = partials ? nparts : ew_blocks(G.npts);
   if (A.op == 0)
-    LAUNCH(k_residual<0>, blocks, st, A, G, x, b, r, partials);
+    LAUNCH((k_residual<0, T>), blocks, st, A, G, x, b, r, partials);
   else
-    LAUNCH(k_residual<1>, blocks, st, A, G, x, b, r, partials);
+    LAUNCH((k_residual<1, T>), blocks, st, A, G, x, b, r, partials);
   return blocks;
 }
+template int launch_residual<double>(const OpDesc&, const double*, const double*, double*,
+                                     double*, int, hipStream_t);
+template int launch_residual<float>(const OpDesc&, const float*, const float*, float*, double*,
+                                    int, hipStream_t);
 
 int launch_residual_dd(const OpDesc& A, const double* x, const double* b, double* r,
                        double* partials, int nparts, hipStream_t st) {
@@ -519,26 +561,34 @@ int launch_residual_dd(const OpDesc& A, const double* x, const double* b, double
   return nparts;
 }
 
-void launch_smooth(const OpDesc& A, const double* x, const double* xprev, const double* b,
-                   double* xout, double a, double g, hipStream_t st) {
-  if (stream_ok(A.n)) {
-    stream_smooth(A, x, xprev, b, xout, a, g, st);
+template <typename T>
+void launch_smooth(const OpDesc& A, const T* x, const T* xprev, const T* b, T* xout, double a,
+                   double g, hipStream_t st) {
+  if (stream_ok(A.n, sizeof(T))) {
+    stream_smooth<T>(A, x, xprev, b, xout, a, g, st);
     return;
   }
   const Geo G = make_geo(A.n);
   if (A.op == 0)
-    LAUNCH(k_smooth<0>, ew_blocks(G.npts), st, A, G, x, xprev, b, xout, a, g);
+    LAUNCH((k_smooth<0, T>), ew_blocks(G.npts), st, A, G, x, xprev, b, xout, a, g);
   else
-    LAUNCH(k_smooth<1>, ew_blocks(G.npts), st, A, G, x, xprev, b, xout, a, g);
+    LAUNCH((k_smooth<1, T>), ew_blocks(G.npts), st, A, G, x, xprev, b, xout, a, g);
 }
+template void launch_smooth<double>(const OpDesc&, const double*, const double*, const double*,
+                                    double*, double, double, hipStream_t);
+template void launch_smooth<float>(const OpDesc&, const float*, const float*, const float*,
+                                   float*, double, double, hipStream_t);
 
-void launch_smooth0(const OpDesc& A, const double* b, double* xout, double a, hipStream_t st) {
+template <typename T>
+void launch_smooth0(const OpDesc& A, const T* b, T* xout, double a, hipStream_t st) {
   const Geo G = make_geo(A.n);
   if (A.op == 0)
-    LAUNCH(k_smooth0<0>, ew_blocks(G.npts), st, A, G, b, xout, a);
+    LAUNCH((k_smooth0<0, T>), ew_blocks(G.npts), st, A, G, b, xout, a);
   else
-    LAUNCH(k_smooth0<1>, ew_blocks(G.npts), st, A, G, b, xout, a);
+    LAUNCH((k_smooth0<1, T>), ew_blocks(G.npts), st, A, G, b, xout, a);
 }
+template void launch_smooth0<double>(const OpDesc&, const double*, double*, double, hipStream_t);
+template void launch_smooth0<float>(const OpDesc&, const float*, float*, double, hipStream_t);
 
 void launch_jacobi_pc(const OpDesc& A, const double* r, double* z, hipStream_t st) {
   const Geo G = make_geo(A.n);
@@ -548,26 +598,47 @@ void launch_jacobi_pc(const OpDesc& A, const double* r, double* z, hipStream_t s
     LAUNCH(k_jacobi_pc<1>, ew_blocks(G.npts), st, A, G, r, z);
 }
 
-void launch_restrict(int nf, const double* fine, double* coarse, hipStream_t st) {
+template <typename T>
+void launch_restrict(int nf, const T* fine, T* coarse, hipStream_t st) {
   if (transfer_stream_ok(nf)) {
-    stream_restrict(nf, fine, coarse, st);
+    stream_restrict<T>(nf, fine, coarse, st);
     return;
   }
   const Geo F = make_geo(nf), C = make_geo(nf / 2);
-  LAUNCH(k_restrict, ew_blocks(C.npts), st, F, C, fine, coarse);
+  LAUNCH((k_restrict<T>), ew_blocks(C.npts), st, F, C, fine, coarse);
 }
+template void launch_restrict<double>(int, const double*, double*, hipStream_t);
+template void launch_restrict<float>(int, const float*, float*, hipStream_t);
 
-void launch_prolong_add(int nf, const double* coarse, double* fine, hipStream_t st) {
+template <typename T>
+void launch_prolong_add(int nf, const T* coarse, T* fine, hipStream_t st) {
   if (transfer_stream_ok(nf)) {
-    stream_prolong_add(nf, coarse, fine, st);
+    stream_prolong_add<T>(nf, coarse, fine, st);
     return;
   }
   const Geo F = make_geo(nf), C = make_geo(nf / 2);
-  LAUNCH(k_prolong_add, ew_blocks(F.npts), st, F, C, coarse, fine);
+  LAUNCH((k_prolong_add<T>), ew_blocks(F.npts), st, F, C, coarse, fine);
+}
+template void launch_prolong_add<double>(int, const double*, double*, hipStream_t);
+template void launch_prolong_add<float>(int, const float*, float*, hipStream_t);
+
+template <typename T>
+void launch_coarse_solve(int size, const double* G, const T* b, T* x, hipStream_t st) {
+  hipLaunchKernelGGL((k_coarse_solve<T>), dim3(1), dim3(64), 0, st, size, G, b, x);
+}
+template void launch_coarse_solve<double>(int, const double*, const double*, double*, hipStream_t);
+template void launch_coarse_solve<float>(int, const double*, const float*, float*, hipStream_t);
+
+void launch_to_float(int64_t count, const double* x, float* y, hipStream_t st) {
+  LAUNCH(k_to_float, ew_blocks(count), st, count, x, y);
 }
 
-void launch_coarse_solve(int size, const double* G, const double* b, double* x, hipStream_t st) {
-  hipLaunchKernelGGL(k_coarse_solve, dim3(1), dim3(64), 0, st, size, G, b, x);
+void launch_to_double(int64_t count, const float* x, double* y, hipStream_t st) {
+  LAUNCH(k_to_double, ew_blocks(count), st, count, x, y);
+}
+
+void launch_finalize_flex(const double* partials, int nparts, double* scal, hipStream_t st) {
+  LAUNCH(k_finalize_flex, 1, st, partials, nparts, scal);
 }
 
 void launch_dot(int n, const double* x, const double* y, double* partials, int nparts,
@@ -598,8 +669,8 @@ int launch_cg_p(const OpDesc& A, const double* z, const double* p_old, double* p
 }
 
 void launch_r_update(int n, double* r, const double* q, const double* scal, double* partials,
-                     int nparts, hipStream_t st) {
-  LAUNCH(k_r_update, nparts, st, make_geo(n), r, q, scal, partials);
+                     int nparts, hipStream_t st, float* r32) {
+  LAUNCH(k_r_update, nparts, st, make_geo(n), r, q, scal, partials, r32);
 }
 
 void launch_x_update(int n, double* x, const double* p, const double* scal, hipStream_t st) {

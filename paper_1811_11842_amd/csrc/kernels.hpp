@@ -30,24 +30,35 @@ struct StreamCfg {
   int blocks;   // 8 * per_xcd (blocks beyond `tiles` exit at once)
   int xcd_map;  // 1: tile ranges dealt to XCDs (block b -> XCD b % 8)
 };
-bool stream_ok(int n);
+bool stream_ok(int n);              // float64 fields
 StreamCfg stream_cfg(int n);
+bool stream_ok(int n, int elem_bytes);
+StreamCfg stream_cfg(int n, int elem_bytes);
 int stream_apply(const OpDesc& A, const double* x, double* y, hipStream_t st);
 int stream_apply_dot(const OpDesc& A, const double* p, double* q, double* partials, bool dd,
                      hipStream_t st);
-int stream_residual(const OpDesc& A, const double* x, const double* b, double* r,
-                    double* partials, hipStream_t st);
+template <typename T>
+int stream_residual(const OpDesc& A, const T* x, const T* b, T* r, double* partials,
+                    hipStream_t st);
 int stream_residual_dd(const OpDesc& A, const double* x, const double* b, double* r,
                        double* partials, hipStream_t st);
-void stream_smooth(const OpDesc& A, const double* x, const double* xprev, const double* b,
-                   double* xout, double a, double g, hipStream_t st);
+template <typename T>
+void stream_smooth(const OpDesc& A, const T* x, const T* xprev, const T* b, T* xout, double a,
+                   double g, hipStream_t st);
 // Two sweeps from a zero guess in one pass: x1 = a0 D^{-1} b is formed on
 // load, xout = x1 + a1 D^{-1}(b - A x1) + g1 x1.
-void stream_smooth_from_zero(const OpDesc& A, const double* b, double* xout, double a0, double a1,
+template <typename T>
+void stream_smooth_from_zero(const OpDesc& A, const T* b, T* xout, double a0, double a1,
                              double g1, hipStream_t st);
 // xout = x + a D^{-1}(b - A x) + g (x - x1), x1 = a0 D^{-1} b formed on the fly.
-void stream_smooth_prev_from_b(const OpDesc& A, const double* x, const double* b, double* xout,
-                               double a0, double a, double g, hipStream_t st);
+template <typename T>
+void stream_smooth_prev_from_b(const OpDesc& A, const T* x, const T* b, T* xout, double a0,
+                               double a, double g, hipStream_t st);
+// Float32 smoothing sweep writing a float64 result, with partials of <b, out>_W
+// (partials[0..np)) and <out, q>_W (partials[np..2 np)); returns np.
+int stream_smooth_dot2(const OpDesc& A, const float* x, const float* xprev, const float* b,
+                       double* xout, const double* q, double a, double g, double* partials,
+                       hipStream_t st);
 // Smoothing sweep that also writes partials of <b, xout>_W; returns their count.
 int stream_smooth_dot(const OpDesc& A, const double* x, const double* xprev, const double* b,
                       double* xout, double a, double g, double* partials, hipStream_t st);
@@ -61,14 +72,17 @@ int stream_cg_p(const OpDesc& A, const double* z, const double* p_old, double* p
 int launch_cg_p(const OpDesc& A, const double* z, const double* p_old, double* p_new, double* q,
                 double* x, const double* scal, bool first, double* partials, int nparts,
                 hipStream_t st);
-// r -= alpha q (alpha = scal[S_ALPHA]), partials of ||r||_W^2.
+// r -= alpha q (alpha = scal[S_ALPHA]), partials of ||r||_W^2; if r32 is
+// given, also r32 = (float) r.
 void launch_r_update(int n, double* r, const double* q, const double* scal, double* partials,
-                     int nparts, hipStream_t st);
+                     int nparts, hipStream_t st, float* r32 = nullptr);
 // x += alpha p (alpha = scal[S_ALPHA]).
 void launch_x_update(int n, double* x, const double* p, const double* scal, hipStream_t st);
 bool transfer_stream_ok(int nf);
-void stream_prolong_add(int nf, const double* coarse, double* fine, hipStream_t st);
-void stream_restrict(int nf, const double* fine, double* coarse, hipStream_t st);
+template <typename T>
+void stream_prolong_add(int nf, const T* coarse, T* fine, hipStream_t st);
+template <typename T>
+void stream_restrict(int nf, const T* fine, T* coarse, hipStream_t st);
 
 // Coarse tail: all levels 8 <= n <= kTailTop plus the exact 5 x 4 solve in
 // one workgroup with the fields in LDS (tail.hip).
@@ -85,10 +99,9 @@ struct TailArgs {
   int nlev;                       // smoothing levels (top n down to 8)
   TailLevel lev[kTailMaxLevels];  // lev[0] is the top (finest) tail level
   const double* G;                // dense solve of the 5 x 4 grid (20 x 20, row-major)
-  const double* b_in;             // right-hand side of the top tail level (global)
-  double* x_out;                  // its V-cycle result (global)
 };
-void launch_tail(int op, const TailArgs& P, hipStream_t st);
+template <typename T>
+void launch_tail(int op, const TailArgs& P, const T* b_in, T* x_out, hipStream_t st);
 
 // The launchers that write reduction partials return how many they wrote
 // (the count the matching launch_finalize must reduce); `nparts` is the
@@ -98,8 +111,9 @@ void launch_apply(const OpDesc& A, const double* x, double* y, hipStream_t st);
 int launch_apply_dot(const OpDesc& A, const double* p, double* q, double* partials,
                      int nparts, hipStream_t st, bool accurate);
 // r = b - A x (x == nullptr means x = 0); partials of ||r||_W^2 if partials != nullptr.
-int launch_residual(const OpDesc& A, const double* x, const double* b, double* r,
-                    double* partials, int nparts, hipStream_t st);
+template <typename T>
+int launch_residual(const OpDesc& A, const T* x, const T* b, T* r, double* partials, int nparts,
+                    hipStream_t st);
 // r = b - A x evaluated with a double-double stencil sum (accurate to a few
 // ulps of r); partials[0..np) of ||r||_W^2 and partials[np..2 np) of
 // sum_W ulp(x)^2, np = the returned count.
@@ -107,17 +121,26 @@ int launch_residual_dd(const OpDesc& A, const double* x, const double* b, double
                        double* partials, int nparts, hipStream_t st);
 // xout = x + a D^{-1}(b - A x) + g (x - xprev); xprev == nullptr means 0.
 // xout may alias xprev, not x.
-void launch_smooth(const OpDesc& A, const double* x, const double* xprev, const double* b,
-                   double* xout, double a, double g, hipStream_t st);
+template <typename T>
+void launch_smooth(const OpDesc& A, const T* x, const T* xprev, const T* b, T* xout, double a,
+                   double g, hipStream_t st);
 // xout = a D^{-1} b (first sweep from a zero guess).
-void launch_smooth0(const OpDesc& A, const double* b, double* xout, double a, hipStream_t st);
+template <typename T>
+void launch_smooth0(const OpDesc& A, const T* b, T* xout, double a, hipStream_t st);
 // z = D^{-1} r (Jacobi preconditioner).
 void launch_jacobi_pc(const OpDesc& A, const double* r, double* z, hipStream_t st);
 
-void launch_restrict(int nf, const double* fine, double* coarse, hipStream_t st);
-void launch_prolong_add(int nf, const double* coarse, double* fine, hipStream_t st);
-// x = G b on the coarsest grid (dense size x size matrix, row-major).
-void launch_coarse_solve(int size, const double* G, const double* b, double* x, hipStream_t st);
+template <typename T>
+void launch_restrict(int nf, const T* fine, T* coarse, hipStream_t st);
+template <typename T>
+void launch_prolong_add(int nf, const T* coarse, T* fine, hipStream_t st);
+// x = G b on the coarsest grid (dense size x size matrix, row-major, float64).
+template <typename T>
+void launch_coarse_solve(int size, const double* G, const T* b, T* x, hipStream_t st);
+// y = (float) x
+void launch_to_float(int64_t count, const double* x, float* y, hipStream_t st);
+// y = (double) x
+void launch_to_double(int64_t count, const float* x, double* y, hipStream_t st);
 
 // partials of <x, y>_W (y == nullptr means y = 1: weighted sum of x).
 void launch_dot(int n, const double* x, const double* y, double* partials, int nparts,
@@ -128,6 +151,9 @@ void launch_wsum_diff(int n, const double* x, const double* y, double* partials,
 // Reduce partials in a fixed order and update scalars (see FinalizeMode).
 void launch_finalize(const double* partials, int nparts, double* scal, int mode, int slot,
                      int n, hipStream_t st);
+// Flexible CG: scal[S_RZ] = rho (partials[0..np)), scal[S_BETA] =
+// -scal[S_ALPHA] * gamma / rho_old with gamma = sum partials[np..2 np).
+void launch_finalize_flex(const double* partials, int nparts, double* scal, hipStream_t st);
 // y = x - scal[S_MEAN]
 void launch_sub_mean(int n, const double* x, double* y, const double* scal, hipStream_t st);
 // y = x + scal[S_MEAN]

@@ -12,22 +12,25 @@ namespace bf {
 
 // Values around one node: centre c; axis neighbours at distance 1 (x-1, x+1,
 // y-1, y+1); diagonals; axis neighbours at distance 2.  Ghost rows are
-// already reflected and columns wrapped by the caller.
-struct Nb13 {
-  double c;
-  double xm1, xp1, ym1, yp1;
-  double dmm, dmp, dpm, dpp;  // (y-1,x-1) (y-1,x+1) (y+1,x-1) (y+1,x+1)
-  double xm2, xp2, ym2, yp2;
+// already reflected and columns wrapped by the caller.  T is the storage and
+// arithmetic type (double, or float inside the mixed-precision V-cycle).
+template <typename T>
+struct Nb13T {
+  T c;
+  T xm1, xp1, ym1, yp1;
+  T dmm, dmp, dpm, dpp;  // (y-1,x-1) (y-1,x+1) (y+1,x-1) (y+1,x+1)
+  T xm2, xp2, ym2, yp2;
 };
+using Nb13 = Nb13T<double>;
 
 // Gather the stencil values around (i, j) of an (n+1) x n field at x (global
 // or LDS): ghost rows reflected, columns wrapped.
-template <int OP>
-__device__ __forceinline__ Nb13 gather(const double* x, int i, int j, int n, int mask) {
-  Nb13 v;
-  const double* r0 = x + (int64_t)j * n;
-  const double* rm1 = x + (int64_t)refl(j - 1, n) * n;
-  const double* rp1 = x + (int64_t)refl(j + 1, n) * n;
+template <int OP, typename T>
+__device__ __forceinline__ Nb13T<T> gather(const T* x, int i, int j, int n, int mask) {
+  Nb13T<T> v;
+  const T* r0 = x + (int64_t)j * n;
+  const T* rm1 = x + (int64_t)refl(j - 1, n) * n;
+  const T* rp1 = x + (int64_t)refl(j + 1, n) * n;
   const int im1 = (i - 1) & mask, ip1 = (i + 1) & mask;
   v.c = r0[i];
   v.xm1 = r0[im1];
@@ -35,8 +38,8 @@ __device__ __forceinline__ Nb13 gather(const double* x, int i, int j, int n, int
   v.ym1 = rm1[i];
   v.yp1 = rp1[i];
   if (OP == 1) {
-    const double* rm2 = x + (int64_t)refl(j - 2, n) * n;
-    const double* rp2 = x + (int64_t)refl(j + 2, n) * n;
+    const T* rm2 = x + (int64_t)refl(j - 2, n) * n;
+    const T* rp2 = x + (int64_t)refl(j + 2, n) * n;
     const int im2 = (i - 2) & mask, ip2 = (i + 2) & mask;
     v.dmm = rm1[im1];
     v.dmp = rm1[ip1];
@@ -53,15 +56,15 @@ __device__ __forceinline__ Nb13 gather(const double* x, int i, int j, int n, int
 // coarse(J, I) = sum_{dj, di in {0, +-1, +-3}} w_dj w_di fine(2J+dj, 2I+di),
 // w_0 = 1/2, w_{+-1} = 9/32, w_{+-3} = -1/32 (the weighted adjoint of cubic
 // interpolation, scaled by 1/4); fine rows reflected, columns wrapped.
-__device__ __forceinline__ double restrict_at(const double* fine, int nf, int fmask, int I,
-                                              int J) {
+template <typename T>
+__device__ __forceinline__ T restrict_at(const T* fine, int nf, int fmask, int I, int J) {
   const int off[5] = {-3, -1, 0, 1, 3};
-  const double w[5] = {-1.0 / 32, 9.0 / 32, 0.5, 9.0 / 32, -1.0 / 32};
-  double acc = 0.0;
+  const T w[5] = {T(-1.0 / 32), T(9.0 / 32), T(0.5), T(9.0 / 32), T(-1.0 / 32)};
+  T acc = T(0);
 #pragma unroll
   for (int a = 0; a < 5; ++a) {
-    const double* row = fine + (int64_t)refl(2 * J + off[a], nf) * nf;
-    double rs = 0.0;
+    const T* row = fine + (int64_t)refl(2 * J + off[a], nf) * nf;
+    T rs = T(0);
 #pragma unroll
     for (int c = 0; c < 5; ++c) rs += w[c] * row[(2 * I + off[c]) & fmask];
     acc += w[a] * rs;
@@ -71,34 +74,34 @@ __device__ __forceinline__ double restrict_at(const double* fine, int nf, int fm
 
 // (P coarse)(j, i): tensor-product cubic interpolation (-1, 9, 9, -1)/16 at
 // odd fine nodes, injection at even ones; coarse rows reflected, columns wrapped.
-__device__ __forceinline__ double interp_x_at(const double* coarse, int nc, int cmask, int J,
-                                              int i) {
-  const double* row = coarse + (int64_t)refl(J, nc) * nc;
+template <typename T>
+__device__ __forceinline__ T interp_x_at(const T* coarse, int nc, int cmask, int J, int i) {
+  const T* row = coarse + (int64_t)refl(J, nc) * nc;
   const int I = i >> 1;
   if ((i & 1) == 0) return row[I];
-  return (-row[(I - 1) & cmask] + 9.0 * row[I] + 9.0 * row[(I + 1) & cmask] -
+  return (-row[(I - 1) & cmask] + T(9) * row[I] + T(9) * row[(I + 1) & cmask] -
           row[(I + 2) & cmask]) *
-         0.0625;
+         T(0.0625);
 }
 
-__device__ __forceinline__ double prolong_at(const double* coarse, int nc, int cmask, int i,
-                                             int j) {
+template <typename T>
+__device__ __forceinline__ T prolong_at(const T* coarse, int nc, int cmask, int i, int j) {
   const int J = j >> 1;
   if ((j & 1) == 0) return interp_x_at(coarse, nc, cmask, J, i);
-  return (-interp_x_at(coarse, nc, cmask, J - 1, i) + 9.0 * interp_x_at(coarse, nc, cmask, J, i) +
-          9.0 * interp_x_at(coarse, nc, cmask, J + 1, i) -
+  return (-interp_x_at(coarse, nc, cmask, J - 1, i) + T(9) * interp_x_at(coarse, nc, cmask, J, i) +
+          T(9) * interp_x_at(coarse, nc, cmask, J + 1, i) -
           interp_x_at(coarse, nc, cmask, J + 2, i)) *
-         0.0625;
+         T(0.0625);
 }
 
 // A x at the node.  OP 0: n^2 (axis - 4 c); OP 1: c + s (20 c - 8 axis + 2 diag + far).
-template <int OP>
-__device__ __forceinline__ double apply_vals(const Nb13& v, double coef) {
-  const double axis = (v.xm1 + v.xp1) + (v.ym1 + v.yp1);
-  if (OP == 0) return coef * (axis - 4.0 * v.c);
-  const double diag = (v.dmm + v.dmp) + (v.dpm + v.dpp);
-  const double far = (v.xm2 + v.xp2) + (v.ym2 + v.yp2);
-  return v.c + coef * (20.0 * v.c - 8.0 * axis + 2.0 * diag + far);
+template <int OP, typename T>
+__device__ __forceinline__ T apply_vals(const Nb13T<T>& v, T coef) {
+  const T axis = (v.xm1 + v.xp1) + (v.ym1 + v.yp1);
+  if (OP == 0) return coef * (axis - T(4) * v.c);
+  const T diag = (v.dmm + v.dmp) + (v.dpm + v.dpp);
+  const T far = (v.xm2 + v.xp2) + (v.ym2 + v.yp2);
+  return v.c + coef * (T(20) * v.c - T(8) * axis + T(2) * diag + far);
 }
 
 // Error-free transformations (Knuth TwoSum; TwoProduct through fma).  They

@@ -1,22 +1,27 @@
 // Streaming stencil kernels for the large grid levels.
 //
-// Tiling: a block of TPB threads owns a strip of TX = 2*TPB columns (two
-// adjacent columns per lane, 16-byte loads and stores) and a chunk of TY
-// rows, which it walks top to bottom.  Each lane keeps the vertical window of
-// its two columns (rows j-R .. j+R, R = 1 for the 5-point and 2 for the
-// 13-point operator) in registers, prefetching two rows ahead; the horizontal
-// neighbours come from a ring of four LDS rows (TX + 4 doubles each, the
-// two-column halos on both sides loaded by lanes 0..3 with periodic wrap).
-// One barrier per output row.  Ghost rows outside 0..n are the reflected rows
-// of the two-layer even reflection (paper, Sec. 4, eq. discreteBC).
+// Tiling: a block of TPB threads owns a strip of TX = V*TPB columns (V
+// adjacent columns per lane, 16-byte loads and stores: V = 2 for float64,
+// 4 for float32) and a chunk of TY rows, which it walks row by row.  Each
+// lane keeps the vertical window of its columns (rows j-R .. j+R, R = 1 for
+// the 5-point and 2 for the 13-point operator) in registers, prefetching two
+// rows ahead; the horizontal neighbours come from a ring of four LDS rows
+// (TX + 4 values each, the two-column halos on both sides loaded by lanes
+// 0..3 with periodic wrap).  One barrier per output row.  Ghost rows outside
+// 0..n are the reflected rows of the two-layer even reflection (paper,
+// Sec. 4, eq. discreteBC).
+//
+// Sweep direction alternates with the chunk (even chunks walk down, odd
+// chunks walk up), so two neighbouring chunks read the rows they share in the
+// same phase of their sweeps and the second read is served by L2.
 //
 // XCD-aware launch: workgroups are dealt round-robin to the 8 XCDs of the
 // MI355X, so block b runs on XCD b % 8; tiles are numbered strip-major and
-// each XCD receives a contiguous range of them, so vertically adjacent
-// chunks (which re-read each other's halo rows) share that XCD's L2.
+// each XCD receives a contiguous range of them.
 #include <hip/hip_runtime.h>
 
 #include <cstdlib>
+#include <type_traits>
 
 #include "common.hpp"
 #include "kernels.hpp"
@@ -39,44 +44,63 @@ enum Epi {
   E_CG_P = 10,         // CG step: p' = z + beta p formed on load; out = A p' (double-double
                        // for the CH operator), out2 = p', partials of <p', A p'>_W, and the
                        // deferred x += alpha p (alpha, beta from device scalars)
+  E_SMOOTH_DOT2 = 11   // E_SMOOTH and partials of <b, out>_W and <out, q>_W (q float64)
 };
 
+// 16-byte vector of V elements of T, and a pair for the LDS halo reads.
+template <typename T, int V>
+struct alignas(16) VecN {
+  T v[V];
+};
+template <typename T>
+struct alignas(2 * sizeof(T)) Pair {
+  T v[2];
+};
+
+template <typename T, typename TO>
 struct StreamArgs {
   OpDesc A;
   Geo G;
-  const double* x;
-  const double* b;
-  const double* xprev;
-  double* out;
+  const T* x;
+  const T* b;
+  const T* xprev;
+  TO* out;
   double* partials;
   double a, g, a0;
   int ty, chunks, tiles, per_xcd;
   double* out2;        // E_CG_P: p'
   double* xu;          // E_CG_P: x (updated in place)
   const double* scal;  // E_CG_P: device scalars (alpha, beta)
+  const double* q;     // E_SMOOTH_DOT2: second vector of the extra dot
   int first;           // E_CG_P: first step after a (re)start: p' = z, no x update
   int xcd_map;         // 1: deal contiguous tile ranges to the 8 XCDs
 };
 
-template <int OP, int EPI, int TPB>
-__global__ void __launch_bounds__(TPB) k_stream(StreamArgs P) {
+template <int OP, int EPI, int TPB, typename T, typename TO>
+__global__ void __launch_bounds__(TPB) k_stream(StreamArgs<T, TO> P) {
+  constexpr int V = 16 / sizeof(T);
   constexpr int R = (OP == 0) ? 1 : 2;
   constexpr int W = 2 * R + 1;
-  constexpr int TX = 2 * TPB;
+  constexpr int TX = V * TPB;
   constexpr int LW = TX + 4;
   constexpr bool SMOOTH = (EPI == E_SMOOTH || EPI == E_SMOOTH_XB || EPI == E_SMOOTH_PB ||
-                           EPI == E_SMOOTH_DOT);
+                           EPI == E_SMOOTH_DOT || EPI == E_SMOOTH_DOT2);
   constexpr bool RED = (EPI == E_APPLY_DOT || EPI == E_RESID_NORM || EPI == E_APPLY_DOT_DD ||
-                        EPI == E_RESID_DD || EPI == E_SMOOTH_DOT || EPI == E_CG_P);
+                        EPI == E_RESID_DD || EPI == E_SMOOTH_DOT || EPI == E_CG_P ||
+                        EPI == E_SMOOTH_DOT2);
+  constexpr bool RED2 = (EPI == E_RESID_DD || EPI == E_SMOOTH_DOT2);
   constexpr bool NEEDB = (EPI == E_RESID || EPI == E_RESID_NORM || SMOOTH || EPI == E_RESID_DD);
-  __shared__ double lds[4][LW];
+  constexpr bool NEEDP = (EPI == E_SMOOTH || EPI == E_SMOOTH_DOT || EPI == E_SMOOTH_DOT2);
+  using VT = VecN<T, V>;
+  using VO = VecN<TO, V>;
+  __shared__ T lds[4][LW];
 
   const int bid = blockIdx.x;
   const int t = P.xcd_map ? (bid & 7) * P.per_xcd + (bid >> 3) : bid;
   if (t >= P.tiles) {
     if (RED && threadIdx.x == 0) {
       P.partials[bid] = 0.0;
-      if (EPI == E_RESID_DD) P.partials[gridDim.x + bid] = 0.0;
+      if (RED2) P.partials[gridDim.x + bid] = 0.0;
     }
     return;
   }
@@ -87,74 +111,82 @@ __global__ void __launch_bounds__(TPB) k_stream(StreamArgs P) {
   const int j1 = min(j0 + P.ty, n + 1);
   const int col0 = strip * TX;
   const int tid = threadIdx.x;
-  const int c = col0 + 2 * tid;  // own columns c, c+1
-  const int lc = 2 + 2 * tid;    // their LDS index
+  const int c = col0 + V * tid;  // own columns c .. c+V-1
+  const int lc = 2 + V * tid;    // their LDS index
   const bool hthread = tid < 4;
   int hcol = 0, hslot = 0;
   if (hthread) {
     hcol = (tid < 2) ? ((col0 - 2 + tid) & mask) : ((col0 + TX + tid - 2) & mask);
     hslot = (tid < 2) ? tid : (TX + tid);
   }
-  const double* __restrict__ X = P.x;
+  const T* __restrict__ X = P.x;
+  const T coef = T(P.A.coef);
+  const T ca = T(P.a), cg = T(P.g), ca0 = T(P.a0);
   double beta = 0.0, alpha_prev = 0.0;
-  if (EPI == E_CG_P && !P.first) {
-    beta = P.scal[S_BETA];
-    alpha_prev = P.scal[S_ALPHA];
+  if constexpr (EPI == E_CG_P) {
+    if (!P.first) {
+      beta = P.scal[S_BETA];
+      alpha_prev = P.scal[S_ALPHA];
+    }
   }
 
-  auto dinv_row = [&](int jr) {
-    return (OP == 1 && (jr == 1 || jr == n - 1)) ? P.A.dinv_edge : P.A.dinv_int;
+  auto dinv_row = [&](int jr) -> T {
+    return T((OP == 1 && (jr == 1 || jr == n - 1)) ? P.A.dinv_edge : P.A.dinv_int);
   };
-  auto load_row = [&](int jj, double2& own, double& halo) {
+  auto load_row = [&](int jj, T(&own)[V], T& halo) {
     const int jr = refl(jj, n);
-    const double* row = X + (int64_t)jr * n;
-    own = *reinterpret_cast<const double2*>(row + c);
-    halo = hthread ? row[hcol] : 0.0;
-    if (EPI == E_CG_P && !P.first) {
-      const double* prow = P.xprev + (int64_t)jr * n;
-      const double2 po = *reinterpret_cast<const double2*>(prow + c);
-      own.x += beta * po.x;
-      own.y += beta * po.y;
-      if (hthread) halo += beta * prow[hcol];
+    const T* row = X + (int64_t)jr * n;
+    const VT v = *reinterpret_cast<const VT*>(row + c);
+#pragma unroll
+    for (int i = 0; i < V; ++i) own[i] = v.v[i];
+    halo = hthread ? row[hcol] : T(0);
+    if constexpr (EPI == E_CG_P) {
+      if (!P.first) {
+        const T* prow = P.xprev + (int64_t)jr * n;
+        const VT po = *reinterpret_cast<const VT*>(prow + c);
+#pragma unroll
+        for (int i = 0; i < V; ++i) own[i] += beta * po.v[i];
+        if (hthread) halo += beta * prow[hcol];
+      }
     }
-    if (EPI == E_SMOOTH_XB) {
-      const double sc = P.a0 * dinv_row(jr);
-      own.x *= sc;
-      own.y *= sc;
+    if constexpr (EPI == E_SMOOTH_XB) {
+      const T sc = ca0 * dinv_row(jr);
+#pragma unroll
+      for (int i = 0; i < V; ++i) own[i] *= sc;
       halo *= sc;
     }
   };
-  auto load_ep = [&](int jj, double2& bb, double2& pp) {
+  auto load_ep = [&](int jj, VT& bb, VT& pp) {
     if (jj > n) return;
     const int64_t o = (int64_t)jj * n + c;
-    if (NEEDB) bb = *reinterpret_cast<const double2*>(P.b + o);
-    if ((EPI == E_SMOOTH || EPI == E_SMOOTH_DOT) && P.xprev)
-      pp = *reinterpret_cast<const double2*>(P.xprev + o);
+    if (NEEDB) bb = *reinterpret_cast<const VT*>(P.b + o);
+    if (NEEDP && P.xprev) pp = *reinterpret_cast<const VT*>(P.xprev + o);
   };
-  auto store_lds = [&](int slot, const double2& own, double halo) {
-    *reinterpret_cast<double2*>(&lds[slot][lc]) = own;
+  auto store_lds = [&](int slot, const T(&own)[V], T halo) {
+    VT v;
+#pragma unroll
+    for (int i = 0; i < V; ++i) v.v[i] = own[i];
+    *reinterpret_cast<VT*>(&lds[slot][lc]) = v;
     if (hthread) lds[slot][hslot] = halo;
   };
 
-  // Sweep direction alternates with the chunk: even chunks walk down, odd
-  // chunks walk up.  Two neighbouring chunks then read the rows they share
-  // (the 2-row halos) in the same phase of their sweeps -- both at the start or
-  // both at the end -- so the second read hits L2 instead of going out to
-  // memory again.  w[k] holds row j + (k - R) * dir (dir = +-1).
+  // w[k] holds row j + (k - R) * dir of the lane's columns (dir = +-1).
   const int dir = (chunk & 1) ? -1 : 1;
   const int len = j1 - j0;
   const int jstart = dir > 0 ? j0 : j1 - 1;
-  double2 w[W];
-  double hw[W];
+  T w[W][V];
+  T hw[W];
 #pragma unroll
   for (int k = 0; k < W; ++k) load_row(jstart + (k - R) * dir, w[k], hw[k]);
   // prefetch queue: the rows entering the window at steps s+1 and s+2; rows
   // beyond the tile's last need are never loaded
-  double2 q0 = make_double2(0.0, 0.0), q1 = make_double2(0.0, 0.0);
-  double hq0 = 0.0, hq1 = 0.0;
+  T q0[V], q1[V];
+  T hq0 = T(0), hq1 = T(0);
+#pragma unroll
+  for (int i = 0; i < V; ++i) q0[i] = q1[i] = T(0);
   if (1 < len) load_row(jstart + (R + 1) * dir, q0, hq0);
   if (2 < len) load_row(jstart + (R + 2) * dir, q1, hq1);
-  double2 bq = make_double2(0.0, 0.0), pq = make_double2(0.0, 0.0);
+  VT bq{}, pq{};
   load_ep(jstart, bq, pq);
   if (R == 2) {
     store_lds((jstart - dir) & 3, w[1], hw[1]);
@@ -169,117 +201,154 @@ __global__ void __launch_bounds__(TPB) k_stream(StreamArgs P) {
     else
       store_lds(j & 3, w[1], hw[1]);
     __syncthreads();
-    const double2 bcur = bq, pcur = pq;
+    const VT bcur = bq, pcur = pq;
     if (s + 1 < len) load_ep(j + dir, bq, pq);
 
-    // rows j-1 / j+1 (and j-2 / j+2) in the window, whatever the direction
-    const double2 wm1 = dir > 0 ? w[R - 1] : w[R + 1];
-    const double2 wp1 = dir > 0 ? w[R + 1] : w[R - 1];
-    const double* L0 = lds[j & 3];
-    const double2 cl = *reinterpret_cast<const double2*>(&L0[lc - 2]);  // c-2, c-1
-    const double2 cr = *reinterpret_cast<const double2*>(&L0[lc + 2]);  // c+2, c+3
-    Nb13 v0, v1;
-    v0.c = w[R].x;
-    v1.c = w[R].y;
-    v0.xm1 = cl.y;
-    v0.xp1 = w[R].y;
-    v1.xm1 = w[R].x;
-    v1.xp1 = cr.x;
-    v0.ym1 = wm1.x;
-    v0.yp1 = wp1.x;
-    v1.ym1 = wm1.y;
-    v1.yp1 = wp1.y;
+    // rows of the window by their true offset from j, whatever the direction
+    const T* wm1 = dir > 0 ? w[R - 1] : w[R + 1];
+    const T* wp1 = dir > 0 ? w[R + 1] : w[R - 1];
+    const T* L0 = lds[j & 3];
+    // rowj: columns c-2 .. c+V+1 of row j
+    T rowj[V + 4];
+    {
+      const Pair<T> l = *reinterpret_cast<const Pair<T>*>(&L0[lc - 2]);
+      const Pair<T> r = *reinterpret_cast<const Pair<T>*>(&L0[lc + V]);
+      rowj[0] = l.v[0];
+      rowj[1] = l.v[1];
+#pragma unroll
+      for (int i = 0; i < V; ++i) rowj[2 + i] = w[R][i];
+      rowj[V + 2] = r.v[0];
+      rowj[V + 3] = r.v[1];
+    }
+    Nb13T<T> nb[V];
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
+      nb[i].c = rowj[i + 2];
+      nb[i].xm1 = rowj[i + 1];
+      nb[i].xp1 = rowj[i + 3];
+      nb[i].ym1 = wm1[i];
+      nb[i].yp1 = wp1[i];
+    }
     if (R == 2) {
-      const double2 wm2 = dir > 0 ? w[0] : w[W - 1];
-      const double2 wp2 = dir > 0 ? w[W - 1] : w[0];
-      const double* Lm = lds[(j - 1) & 3];
-      const double* Lp = lds[(j + 1) & 3];
-      v0.xm2 = cl.x;
-      v0.xp2 = cr.x;
-      v1.xm2 = cl.y;
-      v1.xp2 = cr.y;
-      v0.ym2 = wm2.x;
-      v0.yp2 = wp2.x;
-      v1.ym2 = wm2.y;
-      v1.yp2 = wp2.y;
-      v0.dmm = Lm[lc - 1];
-      v0.dmp = wm1.y;
-      v1.dmm = wm1.x;
-      v1.dmp = Lm[lc + 2];
-      v0.dpm = Lp[lc - 1];
-      v0.dpp = wp1.y;
-      v1.dpm = wp1.x;
-      v1.dpp = Lp[lc + 2];
+      const T* wm2 = dir > 0 ? w[0] : w[W - 1];
+      const T* wp2 = dir > 0 ? w[W - 1] : w[0];
+      const T* Lm = lds[(j - 1) & 3];
+      const T* Lp = lds[(j + 1) & 3];
+      T rowm[V + 2], rowp[V + 2];
+      rowm[0] = Lm[lc - 1];
+      rowm[V + 1] = Lm[lc + V];
+      rowp[0] = Lp[lc - 1];
+      rowp[V + 1] = Lp[lc + V];
+#pragma unroll
+      for (int i = 0; i < V; ++i) {
+        rowm[1 + i] = wm1[i];
+        rowp[1 + i] = wp1[i];
+      }
+#pragma unroll
+      for (int i = 0; i < V; ++i) {
+        nb[i].xm2 = rowj[i];
+        nb[i].xp2 = rowj[i + 4];
+        nb[i].ym2 = wm2[i];
+        nb[i].yp2 = wp2[i];
+        nb[i].dmm = rowm[i];
+        nb[i].dmp = rowm[i + 2];
+        nb[i].dpm = rowp[i];
+        nb[i].dpp = rowp[i + 2];
+      }
     }
     const int64_t o = (int64_t)j * n + c;
     const double wgt = row_weight(j, n);
-    double2 res;
-    if (EPI == E_APPLY || EPI == E_APPLY_DOT) {
-      res.x = apply_vals<OP>(v0, P.A.coef);
-      res.y = apply_vals<OP>(v1, P.A.coef);
-      if (EPI == E_APPLY_DOT) acc += wgt * (v0.c * res.x + v1.c * res.y);
-    } else if (EPI == E_RESID || EPI == E_RESID_NORM) {
-      res.x = bcur.x - apply_vals<OP>(v0, P.A.coef);
-      res.y = bcur.y - apply_vals<OP>(v1, P.A.coef);
-      if (EPI == E_RESID_NORM) acc += wgt * (res.x * res.x + res.y * res.y);
-    } else if (SMOOTH) {
-      const double dinv = dinv_row(j);
-      const double ad = P.a * dinv;
-      double2 prev = make_double2(0.0, 0.0);
-      if (EPI == E_SMOOTH_PB) {
-        prev.x = P.a0 * dinv * bcur.x;
-        prev.y = P.a0 * dinv * bcur.y;
-      } else if (EPI != E_SMOOTH_XB && P.xprev) {
-        prev = pcur;
+    VO res;
+    if constexpr (EPI == E_APPLY || EPI == E_APPLY_DOT) {
+#pragma unroll
+      for (int i = 0; i < V; ++i) {
+        const T ax = apply_vals<OP>(nb[i], coef);
+        res.v[i] = TO(ax);
+        if (EPI == E_APPLY_DOT) acc += wgt * double(nb[i].c) * double(ax);
       }
-      res.x = v0.c + ad * (bcur.x - apply_vals<OP>(v0, P.A.coef)) + P.g * (v0.c - prev.x);
-      res.y = v1.c + ad * (bcur.y - apply_vals<OP>(v1, P.A.coef)) + P.g * (v1.c - prev.y);
-      if (EPI == E_SMOOTH_DOT) acc += wgt * (bcur.x * res.x + bcur.y * res.y);
-    } else if (EPI == E_APPLY_DOT_DD) {
-      res.x = -residual_dd_vals<OP>(v0, 0.0, P.A.coef);
-      res.y = -residual_dd_vals<OP>(v1, 0.0, P.A.coef);
-      acc += wgt * (v0.c * res.x + v1.c * res.y);
-    } else if (EPI == E_CG_P) {
-      if (OP == 1) {
-        res.x = -residual_dd_vals<OP>(v0, 0.0, P.A.coef);
-        res.y = -residual_dd_vals<OP>(v1, 0.0, P.A.coef);
-      } else {
-        res.x = apply_vals<OP>(v0, P.A.coef);
-        res.y = apply_vals<OP>(v1, P.A.coef);
+    } else if constexpr (EPI == E_RESID || EPI == E_RESID_NORM) {
+#pragma unroll
+      for (int i = 0; i < V; ++i) {
+        const T r = bcur.v[i] - apply_vals<OP>(nb[i], coef);
+        res.v[i] = TO(r);
+        if (EPI == E_RESID_NORM) acc += wgt * double(r) * double(r);
       }
-      acc += wgt * (v0.c * res.x + v1.c * res.y);
-      *reinterpret_cast<double2*>(P.out2 + o) = make_double2(v0.c, v1.c);
-      if (!P.first) {
-        const double2 po = *reinterpret_cast<const double2*>(P.xprev + o);
-        double2 xv = *reinterpret_cast<const double2*>(P.xu + o);
-        xv.x += alpha_prev * po.x;
-        xv.y += alpha_prev * po.y;
-        *reinterpret_cast<double2*>(P.xu + o) = xv;
+    } else if constexpr (SMOOTH) {
+      const T ad = ca * dinv_row(j);
+      const T d0 = ca0 * dinv_row(j);
+#pragma unroll
+      for (int i = 0; i < V; ++i) {
+        T prev = T(0);
+        if (EPI == E_SMOOTH_PB)
+          prev = d0 * bcur.v[i];
+        else if (EPI != E_SMOOTH_XB && P.xprev)
+          prev = pcur.v[i];
+        const T xn =
+            nb[i].c + ad * (bcur.v[i] - apply_vals<OP>(nb[i], coef)) + cg * (nb[i].c - prev);
+        res.v[i] = TO(xn);
+        if (EPI == E_SMOOTH_DOT || EPI == E_SMOOTH_DOT2)
+          acc += wgt * double(bcur.v[i]) * double(TO(xn));
       }
-    } else {  // E_RESID_DD
-      res.x = residual_dd_vals<OP>(v0, bcur.x, P.A.coef);
-      res.y = residual_dd_vals<OP>(v1, bcur.y, P.A.coef);
-      acc += wgt * (res.x * res.x + res.y * res.y);
-      const double u0 = ulp_of(v0.c), u1 = ulp_of(v1.c);
-      acc2 += wgt * (u0 * u0 + u1 * u1);
+      if constexpr (EPI == E_SMOOTH_DOT2) {
+        const VecN<double, V> qv = *reinterpret_cast<const VecN<double, V>*>(P.q + o);
+#pragma unroll
+        for (int i = 0; i < V; ++i) acc2 += wgt * double(res.v[i]) * qv.v[i];
+      }
+    } else if constexpr (std::is_same<T, double>::value) {
+      if constexpr (EPI == E_APPLY_DOT_DD) {
+#pragma unroll
+        for (int i = 0; i < V; ++i) {
+          res.v[i] = -residual_dd_vals<OP>(nb[i], 0.0, P.A.coef);
+          acc += wgt * nb[i].c * res.v[i];
+        }
+      } else if constexpr (EPI == E_CG_P) {
+        VecN<double, V> pn;
+#pragma unroll
+        for (int i = 0; i < V; ++i) {
+          res.v[i] = OP == 1 ? -residual_dd_vals<OP>(nb[i], 0.0, P.A.coef)
+                             : apply_vals<OP>(nb[i], P.A.coef);
+          acc += wgt * nb[i].c * res.v[i];
+          pn.v[i] = nb[i].c;
+        }
+        *reinterpret_cast<VecN<double, V>*>(P.out2 + o) = pn;
+        if (!P.first) {
+          const VecN<double, V> po = *reinterpret_cast<const VecN<double, V>*>(P.xprev + o);
+          VecN<double, V> xv = *reinterpret_cast<const VecN<double, V>*>(P.xu + o);
+#pragma unroll
+          for (int i = 0; i < V; ++i) xv.v[i] += alpha_prev * po.v[i];
+          *reinterpret_cast<VecN<double, V>*>(P.xu + o) = xv;
+        }
+      } else if constexpr (EPI == E_RESID_DD) {
+#pragma unroll
+        for (int i = 0; i < V; ++i) {
+          res.v[i] = residual_dd_vals<OP>(nb[i], bcur.v[i], P.A.coef);
+          acc += wgt * res.v[i] * res.v[i];
+          const double u = ulp_of(nb[i].c);
+          acc2 += wgt * u * u;
+        }
+      }
     }
-    *reinterpret_cast<double2*>(P.out + o) = res;
+    *reinterpret_cast<VO*>(P.out + o) = res;
 
 #pragma unroll
     for (int k = 0; k < W - 1; ++k) {
-      w[k] = w[k + 1];
+#pragma unroll
+      for (int i = 0; i < V; ++i) w[k][i] = w[k + 1][i];
       hw[k] = hw[k + 1];
     }
-    w[W - 1] = q0;
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
+      w[W - 1][i] = q0[i];
+      q0[i] = q1[i];
+    }
     hw[W - 1] = hq0;
-    q0 = q1;
     hq0 = hq1;
     if (s + 3 < len) load_row(j + (R + 3) * dir, q1, hq1);
   }
   if (RED) {
     const double s = block_sum_n<TPB>(acc);
     if (tid == 0) P.partials[bid] = s;
-    if (EPI == E_RESID_DD) {
+    if (RED2) {
       const double s2 = block_sum_n<TPB>(acc2);
       if (tid == 0) P.partials[gridDim.x + bid] = s2;
     }
@@ -296,15 +365,16 @@ int env_int(const char* name, int dflt) {
 
 }  // namespace
 
-bool stream_ok(int n) { return n >= 128; }
+bool stream_ok(int n, int elem_bytes) { return n >= 64 * (16 / elem_bytes); }
 
-StreamCfg stream_cfg(int n) {
+StreamCfg stream_cfg(int n, int elem_bytes) {
   StreamCfg c;
-  c.tpb = n >= 1024 ? 256 : (n >= 256 ? 128 : 64);
-  const int tx = 2 * c.tpb;
+  const int vcols = 16 / elem_bytes;
+  c.tpb = n >= 256 * vcols ? 256 : (n >= 128 * vcols ? 128 : 64);
+  const int tx = vcols * c.tpb;
   const int strips = n / tx;
   // aim at ~4096 tiles (16 per CU over the 256 CUs), 8..64 rows each; on
-  // 4096^2 this gives 8-row tiles, measured fastest for whole solves
+  // 4096^2 in float64 this gives 8-row tiles, measured fastest for whole solves
   int ty = (int)(((int64_t)(n + 1) * strips) / 4096);
   static const int ty_env = env_int("BF_STREAM_TY", 0);
   if (ty_env > 0) ty = ty_env;
@@ -319,27 +389,30 @@ StreamCfg stream_cfg(int n) {
   return c;
 }
 
-template <int OP, int EPI>
-static void dispatch(const StreamCfg& c, const StreamArgs& P, hipStream_t st) {
+bool stream_ok(int n) { return stream_ok(n, 8); }
+StreamCfg stream_cfg(int n) { return stream_cfg(n, 8); }
+
+template <int OP, int EPI, typename T, typename TO>
+static void dispatch(const StreamCfg& c, const StreamArgs<T, TO>& P, hipStream_t st) {
   switch (c.tpb) {
     case 256:
-      hipLaunchKernelGGL((k_stream<OP, EPI, 256>), dim3(c.blocks), dim3(256), 0, st, P);
+      hipLaunchKernelGGL((k_stream<OP, EPI, 256, T, TO>), dim3(c.blocks), dim3(256), 0, st, P);
       break;
     case 128:
-      hipLaunchKernelGGL((k_stream<OP, EPI, 128>), dim3(c.blocks), dim3(128), 0, st, P);
+      hipLaunchKernelGGL((k_stream<OP, EPI, 128, T, TO>), dim3(c.blocks), dim3(128), 0, st, P);
       break;
     default:
-      hipLaunchKernelGGL((k_stream<OP, EPI, 64>), dim3(c.blocks), dim3(64), 0, st, P);
+      hipLaunchKernelGGL((k_stream<OP, EPI, 64, T, TO>), dim3(c.blocks), dim3(64), 0, st, P);
       break;
   }
 }
 
-template <int EPI>
-static int stream_launch(const OpDesc& A, const double* x, const double* b, const double* xprev,
-                         double* out, double* partials, double a, double g, hipStream_t st,
-                         double a0 = 0.0) {
-  const StreamCfg c = stream_cfg(A.n);
-  StreamArgs P{};
+template <int EPI, typename T, typename TO>
+static int stream_launch(const OpDesc& A, const T* x, const T* b, const T* xprev, TO* out,
+                         double* partials, double a, double g, hipStream_t st, double a0 = 0.0,
+                         const double* q = nullptr) {
+  const StreamCfg c = stream_cfg(A.n, sizeof(T));
+  StreamArgs<T, TO> P{};
   P.A = A;
   P.G = make_geo(A.n);
   P.x = x;
@@ -350,6 +423,7 @@ static int stream_launch(const OpDesc& A, const double* x, const double* b, cons
   P.a = a;
   P.g = g;
   P.a0 = a0;
+  P.q = q;
   P.ty = c.ty;
   P.chunks = c.chunks;
   P.tiles = c.tiles;
@@ -363,42 +437,57 @@ static int stream_launch(const OpDesc& A, const double* x, const double* b, cons
 }
 
 int stream_apply(const OpDesc& A, const double* x, double* y, hipStream_t st) {
-  return stream_launch<E_APPLY>(A, x, nullptr, nullptr, y, nullptr, 0, 0, st);
+  return stream_launch<E_APPLY, double, double>(A, x, nullptr, nullptr, y, nullptr, 0, 0, st);
 }
 int stream_apply_dot(const OpDesc& A, const double* p, double* q, double* partials, bool dd,
                      hipStream_t st) {
-  if (dd) return stream_launch<E_APPLY_DOT_DD>(A, p, nullptr, nullptr, q, partials, 0, 0, st);
-  return stream_launch<E_APPLY_DOT>(A, p, nullptr, nullptr, q, partials, 0, 0, st);
-}
-int stream_residual(const OpDesc& A, const double* x, const double* b, double* r,
-                    double* partials, hipStream_t st) {
-  if (partials) return stream_launch<E_RESID_NORM>(A, x, b, nullptr, r, partials, 0, 0, st);
-  return stream_launch<E_RESID>(A, x, b, nullptr, r, nullptr, 0, 0, st);
+  if (dd)
+    return stream_launch<E_APPLY_DOT_DD, double, double>(A, p, nullptr, nullptr, q, partials, 0,
+                                                         0, st);
+  return stream_launch<E_APPLY_DOT, double, double>(A, p, nullptr, nullptr, q, partials, 0, 0,
+                                                    st);
 }
 int stream_residual_dd(const OpDesc& A, const double* x, const double* b, double* r,
                        double* partials, hipStream_t st) {
-  return stream_launch<E_RESID_DD>(A, x, b, nullptr, r, partials, 0, 0, st);
+  return stream_launch<E_RESID_DD, double, double>(A, x, b, nullptr, r, partials, 0, 0, st);
 }
-void stream_smooth(const OpDesc& A, const double* x, const double* xprev, const double* b,
-                   double* xout, double a, double g, hipStream_t st) {
-  stream_launch<E_SMOOTH>(A, x, b, xprev, xout, nullptr, a, g, st);
+
+template <typename T>
+int stream_residual(const OpDesc& A, const T* x, const T* b, T* r, double* partials,
+                    hipStream_t st) {
+  if (partials)
+    return stream_launch<E_RESID_NORM, T, T>(A, x, b, nullptr, r, partials, 0, 0, st);
+  return stream_launch<E_RESID, T, T>(A, x, b, nullptr, r, nullptr, 0, 0, st);
 }
-void stream_smooth_from_zero(const OpDesc& A, const double* b, double* xout, double a0, double a1,
+template <typename T>
+void stream_smooth(const OpDesc& A, const T* x, const T* xprev, const T* b, T* xout, double a,
+                   double g, hipStream_t st) {
+  stream_launch<E_SMOOTH, T, T>(A, x, b, xprev, xout, nullptr, a, g, st);
+}
+template <typename T>
+void stream_smooth_from_zero(const OpDesc& A, const T* b, T* xout, double a0, double a1,
                              double g1, hipStream_t st) {
-  stream_launch<E_SMOOTH_XB>(A, b, b, nullptr, xout, nullptr, a1, g1, st, a0);
+  stream_launch<E_SMOOTH_XB, T, T>(A, b, b, nullptr, xout, nullptr, a1, g1, st, a0);
 }
-void stream_smooth_prev_from_b(const OpDesc& A, const double* x, const double* b, double* xout,
-                               double a0, double a, double g, hipStream_t st) {
-  stream_launch<E_SMOOTH_PB>(A, x, b, nullptr, xout, nullptr, a, g, st, a0);
+template <typename T>
+void stream_smooth_prev_from_b(const OpDesc& A, const T* x, const T* b, T* xout, double a0,
+                               double a, double g, hipStream_t st) {
+  stream_launch<E_SMOOTH_PB, T, T>(A, x, b, nullptr, xout, nullptr, a, g, st, a0);
 }
 int stream_smooth_dot(const OpDesc& A, const double* x, const double* xprev, const double* b,
                       double* xout, double a, double g, double* partials, hipStream_t st) {
-  return stream_launch<E_SMOOTH_DOT>(A, x, b, xprev, xout, partials, a, g, st);
+  return stream_launch<E_SMOOTH_DOT, double, double>(A, x, b, xprev, xout, partials, a, g, st);
+}
+int stream_smooth_dot2(const OpDesc& A, const float* x, const float* xprev, const float* b,
+                       double* xout, const double* q, double a, double g, double* partials,
+                       hipStream_t st) {
+  return stream_launch<E_SMOOTH_DOT2, float, double>(A, x, b, xprev, xout, partials, a, g, st,
+                                                     0.0, q);
 }
 int stream_cg_p(const OpDesc& A, const double* z, const double* p_old, double* p_new, double* q,
                 double* x, const double* scal, bool first, double* partials, hipStream_t st) {
-  const StreamCfg c = stream_cfg(A.n);
-  StreamArgs P{};
+  const StreamCfg c = stream_cfg(A.n, 8);
+  StreamArgs<double, double> P{};
   P.A = A;
   P.G = make_geo(A.n);
   P.x = z;
@@ -420,5 +509,22 @@ int stream_cg_p(const OpDesc& A, const double* z, const double* p_old, double* p
     dispatch<1, E_CG_P>(c, P, st);
   return c.blocks;
 }
+
+template int stream_residual<double>(const OpDesc&, const double*, const double*, double*,
+                                     double*, hipStream_t);
+template int stream_residual<float>(const OpDesc&, const float*, const float*, float*, double*,
+                                    hipStream_t);
+template void stream_smooth<double>(const OpDesc&, const double*, const double*, const double*,
+                                    double*, double, double, hipStream_t);
+template void stream_smooth<float>(const OpDesc&, const float*, const float*, const float*,
+                                   float*, double, double, hipStream_t);
+template void stream_smooth_from_zero<double>(const OpDesc&, const double*, double*, double,
+                                              double, double, hipStream_t);
+template void stream_smooth_from_zero<float>(const OpDesc&, const float*, float*, double, double,
+                                             double, hipStream_t);
+template void stream_smooth_prev_from_b<double>(const OpDesc&, const double*, const double*,
+                                                double*, double, double, double, hipStream_t);
+template void stream_smooth_prev_from_b<float>(const OpDesc&, const float*, const float*, float*,
+                                               double, double, double, hipStream_t);
 
 }  // namespace bf

@@ -26,32 +26,33 @@ __host__ __device__ inline int tail_lds_doubles(int top) {
   return total + 2 * 20;
 }
 
-template <int OP>
-__device__ void tail_sweep(const TailLevel& L, const double* x, const double* xprev,
-                           const double* b, double* xout, double a, double g) {
+template <int OP, typename T>
+__device__ void tail_sweep(const TailLevel& L, const T* x, const T* xprev, const T* b, T* xout,
+                           double a, double g) {
   const int n = L.n, mask = n - 1, npts = (n + 1) * n;
   int lg = 0;
   while ((1 << lg) < n) ++lg;
+  const T ta = T(a), tg = T(g), coef = T(L.coef);
   for (int idx = threadIdx.x; idx < npts; idx += kTailThreads) {
     const int i = idx & mask, j = idx >> lg;
-    const Nb13 v = gather<OP>(x, i, j, n, mask);
-    const double ax = apply_vals<OP>(v, L.coef);
-    const double dinv = (OP == 1 && (j == 1 || j == n - 1)) ? L.dinv_edge : L.dinv_int;
-    const double prev = xprev ? xprev[idx] : 0.0;
-    xout[idx] = v.c + a * dinv * (b[idx] - ax) + g * (v.c - prev);
+    const Nb13T<T> v = gather<OP>(x, i, j, n, mask);
+    const T ax = apply_vals<OP>(v, coef);
+    const T dinv = T((OP == 1 && (j == 1 || j == n - 1)) ? L.dinv_edge : L.dinv_int);
+    const T prev = xprev ? xprev[idx] : T(0);
+    xout[idx] = v.c + ta * dinv * (b[idx] - ax) + tg * (v.c - prev);
   }
   __syncthreads();
 }
 
-template <int OP>
-__global__ void __launch_bounds__(kTailThreads) k_tail(TailArgs P) {
-  __shared__ double lds[kTailMaxDoubles];
+template <int OP, typename T>
+__global__ void __launch_bounds__(kTailThreads) k_tail(TailArgs P, const T* b_in, T* x_out) {
+  __shared__ T lds[kTailMaxDoubles];
   const int tid = threadIdx.x;
   // carve LDS
-  double* xa[kTailMaxLevels];
-  double* xb[kTailMaxLevels];
-  double* bb[kTailMaxLevels];
-  double* rr[kTailMaxLevels];
+  T* xa[kTailMaxLevels];
+  T* xb[kTailMaxLevels];
+  T* bb[kTailMaxLevels];
+  T* rr[kTailMaxLevels];
   int off = 0;
   for (int l = 0; l < P.nlev; ++l) {
     const int npts = (P.lev[l].n + 1) * P.lev[l].n;
@@ -61,46 +62,47 @@ __global__ void __launch_bounds__(kTailThreads) k_tail(TailArgs P) {
     rr[l] = bb[l] + npts;
     off += 4 * npts;
   }
-  double* xc = lds + off;  // coarsest x (20)
-  double* bc = xc + 20;    // coarsest b (20)
+  T* xc = lds + off;  // coarsest x (20)
+  T* bc = xc + 20;    // coarsest b (20)
 
   // right-hand side of the top tail level
   {
     const int npts = (P.lev[0].n + 1) * P.lev[0].n;
-    for (int idx = tid; idx < npts; idx += kTailThreads) bb[0][idx] = P.b_in[idx];
+    for (int idx = tid; idx < npts; idx += kTailThreads) bb[0][idx] = b_in[idx];
   }
   __syncthreads();
 
-  double* res[kTailMaxLevels];  // buffer holding each level's iterate
-  double* oth[kTailMaxLevels];
+  T* res[kTailMaxLevels];  // buffer holding each level's iterate
+  T* oth[kTailMaxLevels];
   // downward leg
   for (int l = 0; l < P.nlev; ++l) {
     const TailLevel& L = P.lev[l];
     const int n = L.n, npts = (n + 1) * n;
-    double* cur = xa[l];
-    double* o = xb[l];
+    T* cur = xa[l];
+    T* o = xb[l];
     for (int idx = tid; idx < npts; idx += kTailThreads) {
       const int j = idx / n;
       const double dinv = (OP == 1 && (j == 1 || j == n - 1)) ? L.dinv_edge : L.dinv_int;
-      cur[idx] = L.a[0] * dinv * bb[l][idx];
+      cur[idx] = T(L.a[0] * dinv) * bb[l][idx];
     }
     __syncthreads();
     for (int k = 1; k < L.degree; ++k) {
-      tail_sweep<OP>(L, cur, (k == 1 || L.g[k] == 0.0) ? nullptr : o, bb[l], o, L.a[k], L.g[k]);
-      double* t = cur;
+      tail_sweep<OP, T>(L, cur, (k == 1 || L.g[k] == 0.0) ? nullptr : o, bb[l], o, L.a[k],
+                        L.g[k]);
+      T* t = cur;
       cur = o;
       o = t;
     }
     // residual
     for (int idx = tid; idx < npts; idx += kTailThreads) {
       const int i = idx & (n - 1), j = idx / n;
-      const Nb13 v = gather<OP>(cur, i, j, n, n - 1);
-      rr[l][idx] = bb[l][idx] - apply_vals<OP>(v, L.coef);
+      const Nb13T<T> v = gather<OP>(cur, i, j, n, n - 1);
+      rr[l][idx] = bb[l][idx] - apply_vals<OP>(v, T(L.coef));
     }
     __syncthreads();
     // restriction to the next level (or to the coarsest grid)
     const int nc = n / 2, cpts = (nc + 1) * nc;
-    double* bnext = (l + 1 < P.nlev) ? bb[l + 1] : bc;
+    T* bnext = (l + 1 < P.nlev) ? bb[l + 1] : bc;
     for (int idx = tid; idx < cpts; idx += kTailThreads) {
       const int I = idx & (nc - 1), J = idx / nc;
       bnext[idx] = restrict_at(rr[l], n, n - 1, I, J);
@@ -112,25 +114,25 @@ __global__ void __launch_bounds__(kTailThreads) k_tail(TailArgs P) {
   // coarsest grid: x = G b
   if (tid < 20) {
     double acc = 0.0;
-    for (int k = 0; k < 20; ++k) acc += P.G[tid * 20 + k] * bc[k];
-    xc[tid] = acc;
+    for (int k = 0; k < 20; ++k) acc += P.G[tid * 20 + k] * double(bc[k]);
+    xc[tid] = T(acc);
   }
   __syncthreads();
   // upward leg
   for (int l = P.nlev - 1; l >= 0; --l) {
     const TailLevel& L = P.lev[l];
     const int n = L.n, npts = (n + 1) * n, nc = n / 2;
-    const double* e = (l + 1 < P.nlev) ? res[l + 1] : xc;
-    double* cur = res[l];
-    double* o = oth[l];
+    const T* e = (l + 1 < P.nlev) ? res[l + 1] : xc;
+    T* cur = res[l];
+    T* o = oth[l];
     for (int idx = tid; idx < npts; idx += kTailThreads) {
       const int i = idx & (n - 1), j = idx / n;
       cur[idx] += prolong_at(e, nc, nc - 1, i, j);
     }
     __syncthreads();
     for (int k = 0; k < L.degree; ++k) {
-      tail_sweep<OP>(L, cur, L.g[k] != 0.0 ? o : nullptr, bb[l], o, L.a[k], L.g[k]);
-      double* t = cur;
+      tail_sweep<OP, T>(L, cur, L.g[k] != 0.0 ? o : nullptr, bb[l], o, L.a[k], L.g[k]);
+      T* t = cur;
       cur = o;
       o = t;
     }
@@ -138,15 +140,18 @@ __global__ void __launch_bounds__(kTailThreads) k_tail(TailArgs P) {
   }
   {
     const int npts = (P.lev[0].n + 1) * P.lev[0].n;
-    for (int idx = tid; idx < npts; idx += kTailThreads) P.x_out[idx] = res[0][idx];
+    for (int idx = tid; idx < npts; idx += kTailThreads) x_out[idx] = res[0][idx];
   }
 }
 
-void launch_tail(int op, const TailArgs& P, hipStream_t st) {
+template <typename T>
+void launch_tail(int op, const TailArgs& P, const T* b_in, T* x_out, hipStream_t st) {
   if (op == 0)
-    hipLaunchKernelGGL(k_tail<0>, dim3(1), dim3(kTailThreads), 0, st, P);
+    hipLaunchKernelGGL((k_tail<0, T>), dim3(1), dim3(kTailThreads), 0, st, P, b_in, x_out);
   else
-    hipLaunchKernelGGL(k_tail<1>, dim3(1), dim3(kTailThreads), 0, st, P);
+    hipLaunchKernelGGL((k_tail<1, T>), dim3(1), dim3(kTailThreads), 0, st, P, b_in, x_out);
 }
+template void launch_tail<double>(int, const TailArgs&, const double*, double*, hipStream_t);
+template void launch_tail<float>(int, const TailArgs&, const float*, float*, hipStream_t);
 
 }  // namespace bf

@@ -17,20 +17,26 @@
 
 namespace bf {
 
+template <typename T>
 struct TransferArgs {
   Geo F, C;
-  const double* in;
-  double* out;
+  const T* in;
+  T* out;
   int cy, chunks, tiles, per_xcd;
+};
+
+template <typename T>
+struct alignas(2 * sizeof(T)) Two {
+  T x, y;
 };
 
 // fine += P coarse.  Lane = coarse column I; the window holds, for coarse
 // rows J-1 .. J+2, the x-interpolated values at the lane's fine columns:
 // tx(J) = (e(J, I), (-e(J,I-1) + 9 e(J,I) + 9 e(J,I+1) - e(J,I+2)) / 16).
 // Fine row 2J = tx(J); fine row 2J+1 = (-tx(J-1) + 9 tx(J) + 9 tx(J+1) - tx(J+2)) / 16.
-template <int TPB>
-__global__ void __launch_bounds__(TPB) k_prolong_stream(TransferArgs P) {
-  __shared__ double row[TPB + 3];
+template <int TPB, typename T>
+__global__ void __launch_bounds__(TPB) k_prolong_stream(TransferArgs<T> P) {
+  __shared__ T row[TPB + 3];
   const int bid = blockIdx.x;
   const int t = (bid & 7) * P.per_xcd + (bid >> 3);
   if (t >= P.tiles) return;
@@ -41,13 +47,13 @@ __global__ void __launch_bounds__(TPB) k_prolong_stream(TransferArgs P) {
   const int J1 = min(J0 + P.cy, nc + 1);  // coarse rows J0 .. J1-1
   const int tid = threadIdx.x;
   const int I = strip * TPB + tid;
-  const double* __restrict__ E = P.in;
-  double* __restrict__ Fo = P.out;
+  const T* __restrict__ E = P.in;
+  T* __restrict__ Fo = P.out;
 
   // x-interpolate coarse row JJ (reflected) for this lane: needs columns
   // I-1 .. I+2; the block loads columns strip*TPB - 1 .. strip*TPB + TPB + 1.
-  auto tx_row = [&](int JJ) -> double2 {
-    const double* er = E + (int64_t)refl(JJ, nc) * nc;
+  auto tx_row = [&](int JJ) -> Two<T> {
+    const T* er = E + (int64_t)refl(JJ, nc) * nc;
     const int base = strip * TPB;
     __syncthreads();  // previous readers of row[] are done
     row[tid + 1] = er[I];
@@ -56,25 +62,25 @@ __global__ void __launch_bounds__(TPB) k_prolong_stream(TransferArgs P) {
       row[tid == 0 ? 0 : TPB + tid] = er[col];
     }
     __syncthreads();
-    const double em1 = row[tid], e0 = row[tid + 1], e1 = row[tid + 2], e2 = row[tid + 3];
-    return make_double2(e0, (-em1 + 9.0 * e0 + 9.0 * e1 - e2) * 0.0625);
+    const T em1 = row[tid], e0 = row[tid + 1], e1 = row[tid + 2], e2 = row[tid + 3];
+    return Two<T>{e0, (-em1 + T(9) * e0 + T(9) * e1 - e2) * T(0.0625)};
   };
 
-  double2 w0 = tx_row(J0 - 1), w1 = tx_row(J0), w2 = tx_row(J0 + 1), w3 = tx_row(J0 + 2);
+  Two<T> w0 = tx_row(J0 - 1), w1 = tx_row(J0), w2 = tx_row(J0 + 1), w3 = tx_row(J0 + 2);
   for (int J = J0; J < J1; ++J) {
     // fine row 2J
     {
-      double2* dst = reinterpret_cast<double2*>(Fo + (int64_t)(2 * J) * nf + 2 * I);
-      double2 v = *dst;
+      Two<T>* dst = reinterpret_cast<Two<T>*>(Fo + (int64_t)(2 * J) * nf + 2 * I);
+      Two<T> v = *dst;
       v.x += w1.x;
       v.y += w1.y;
       *dst = v;
     }
     if (2 * J + 1 <= nf) {
-      double2* dst = reinterpret_cast<double2*>(Fo + (int64_t)(2 * J + 1) * nf + 2 * I);
-      double2 v = *dst;
-      v.x += (-w0.x + 9.0 * w1.x + 9.0 * w2.x - w3.x) * 0.0625;
-      v.y += (-w0.y + 9.0 * w1.y + 9.0 * w2.y - w3.y) * 0.0625;
+      Two<T>* dst = reinterpret_cast<Two<T>*>(Fo + (int64_t)(2 * J + 1) * nf + 2 * I);
+      Two<T> v = *dst;
+      v.x += (-w0.x + T(9) * w1.x + T(9) * w2.x - w3.x) * T(0.0625);
+      v.y += (-w0.y + T(9) * w1.y + T(9) * w2.y - w3.y) * T(0.0625);
       *dst = v;
     }
     w0 = w1;
@@ -88,9 +94,9 @@ __global__ void __launch_bounds__(TPB) k_prolong_stream(TransferArgs P) {
 // rs(f) = 1/2 r(f,2I) + 9/32 (r(f,2I-1) + r(f,2I+1)) - 1/32 (r(f,2I-3) + r(f,2I+3))
 // and coarse(J, I) = 1/2 rs(2J) + 9/32 (rs(2J-1) + rs(2J+1)) - 1/32 (rs(2J-3) + rs(2J+3)),
 // fine rows reflected.  The window keeps rs for fine rows 2J-3 .. 2J+3.
-template <int TPB>
-__global__ void __launch_bounds__(TPB) k_restrict_stream(TransferArgs P) {
-  __shared__ double row[2 * TPB + 8];
+template <int TPB, typename T>
+__global__ void __launch_bounds__(TPB) k_restrict_stream(TransferArgs<T> P) {
+  __shared__ T row[2 * TPB + 8];
   const int bid = blockIdx.x;
   const int t = (bid & 7) * P.per_xcd + (bid >> 3);
   if (t >= P.tiles) return;
@@ -102,31 +108,30 @@ __global__ void __launch_bounds__(TPB) k_restrict_stream(TransferArgs P) {
   const int tid = threadIdx.x;
   const int I = strip * TPB + tid;
   const int base = 2 * strip * TPB;  // first fine column of the strip
-  const double* __restrict__ Fi = P.in;
+  const T* __restrict__ Fi = P.in;
 
   // row[] holds fine columns base-4 .. base+2*TPB+3 at index (col - base + 4)
-  auto rs_row = [&](int f) -> double {
-    const double* fr = Fi + (int64_t)refl(f, nf) * nf;
+  auto rs_row = [&](int f) -> T {
+    const T* fr = Fi + (int64_t)refl(f, nf) * nf;
     __syncthreads();
-    *reinterpret_cast<double2*>(&row[2 * tid + 4]) =
-        *reinterpret_cast<const double2*>(fr + 2 * I);
+    *reinterpret_cast<Two<T>*>(&row[2 * tid + 4]) = *reinterpret_cast<const Two<T>*>(fr + 2 * I);
     if (tid < 8) {
       const int k = tid < 4 ? tid : 2 * TPB + tid;  // 0..3 | 2TPB+4 .. 2TPB+7
       row[k] = fr[(base - 4 + k) & fmask];
     }
     __syncthreads();
     const int k = 2 * tid + 4;
-    return 0.5 * row[k] + (9.0 / 32) * (row[k - 1] + row[k + 1]) -
-           (1.0 / 32) * (row[k - 3] + row[k + 3]);
+    return T(0.5) * row[k] + T(9.0 / 32) * (row[k - 1] + row[k + 1]) -
+           T(1.0 / 32) * (row[k - 3] + row[k + 3]);
   };
 
   // window: r[m] = rs(2J - 3 + m), m = 0..6
-  double r0 = rs_row(2 * J0 - 3), r1 = rs_row(2 * J0 - 2), r2 = rs_row(2 * J0 - 1);
-  double r3 = rs_row(2 * J0), r4 = rs_row(2 * J0 + 1), r5 = rs_row(2 * J0 + 2);
-  double r6 = rs_row(2 * J0 + 3);
+  T r0 = rs_row(2 * J0 - 3), r1 = rs_row(2 * J0 - 2), r2 = rs_row(2 * J0 - 1);
+  T r3 = rs_row(2 * J0), r4 = rs_row(2 * J0 + 1), r5 = rs_row(2 * J0 + 2);
+  T r6 = rs_row(2 * J0 + 3);
   for (int J = J0; J < J1; ++J) {
     P.out[(int64_t)J * nc + I] =
-        0.5 * r3 + (9.0 / 32) * (r2 + r4) - (1.0 / 32) * (r0 + r6);
+        T(0.5) * r3 + T(9.0 / 32) * (r2 + r4) - T(1.0 / 32) * (r0 + r6);
     if (J + 1 < J1) {
       r0 = r2;
       r1 = r3;
@@ -160,8 +165,9 @@ TCfg transfer_cfg(int nc) {
   return c;
 }
 
-TransferArgs targs(int nf, const double* in, double* out, const TCfg& c) {
-  TransferArgs P;
+template <typename T>
+TransferArgs<T> targs(int nf, const T* in, T* out, const TCfg& c) {
+  TransferArgs<T> P;
   P.F = make_geo(nf);
   P.C = make_geo(nf / 2);
   P.in = in;
@@ -177,26 +183,33 @@ TransferArgs targs(int nf, const double* in, double* out, const TCfg& c) {
 
 bool transfer_stream_ok(int nf) { return nf / 2 >= 64; }
 
-void stream_prolong_add(int nf, const double* coarse, double* fine, hipStream_t st) {
+template <typename T>
+void stream_prolong_add(int nf, const T* coarse, T* fine, hipStream_t st) {
   const TCfg c = transfer_cfg(nf / 2);
-  const TransferArgs P = targs(nf, coarse, fine, c);
+  const TransferArgs<T> P = targs(nf, coarse, fine, c);
   if (c.tpb == 256)
-    hipLaunchKernelGGL(k_prolong_stream<256>, dim3(c.blocks), dim3(256), 0, st, P);
+    hipLaunchKernelGGL((k_prolong_stream<256, T>), dim3(c.blocks), dim3(256), 0, st, P);
   else if (c.tpb == 128)
-    hipLaunchKernelGGL(k_prolong_stream<128>, dim3(c.blocks), dim3(128), 0, st, P);
+    hipLaunchKernelGGL((k_prolong_stream<128, T>), dim3(c.blocks), dim3(128), 0, st, P);
   else
-    hipLaunchKernelGGL(k_prolong_stream<64>, dim3(c.blocks), dim3(64), 0, st, P);
+    hipLaunchKernelGGL((k_prolong_stream<64, T>), dim3(c.blocks), dim3(64), 0, st, P);
 }
 
-void stream_restrict(int nf, const double* fine, double* coarse, hipStream_t st) {
+template <typename T>
+void stream_restrict(int nf, const T* fine, T* coarse, hipStream_t st) {
   const TCfg c = transfer_cfg(nf / 2);
-  const TransferArgs P = targs(nf, fine, coarse, c);
+  const TransferArgs<T> P = targs(nf, fine, coarse, c);
   if (c.tpb == 256)
-    hipLaunchKernelGGL(k_restrict_stream<256>, dim3(c.blocks), dim3(256), 0, st, P);
+    hipLaunchKernelGGL((k_restrict_stream<256, T>), dim3(c.blocks), dim3(256), 0, st, P);
   else if (c.tpb == 128)
-    hipLaunchKernelGGL(k_restrict_stream<128>, dim3(c.blocks), dim3(128), 0, st, P);
+    hipLaunchKernelGGL((k_restrict_stream<128, T>), dim3(c.blocks), dim3(128), 0, st, P);
   else
-    hipLaunchKernelGGL(k_restrict_stream<64>, dim3(c.blocks), dim3(64), 0, st, P);
+    hipLaunchKernelGGL((k_restrict_stream<64, T>), dim3(c.blocks), dim3(64), 0, st, P);
 }
+
+template void stream_prolong_add<double>(int, const double*, double*, hipStream_t);
+template void stream_prolong_add<float>(int, const float*, float*, hipStream_t);
+template void stream_restrict<double>(int, const double*, double*, hipStream_t);
+template void stream_restrict<float>(int, const float*, float*, hipStream_t);
 
 }  // namespace bf

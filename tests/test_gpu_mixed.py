@@ -1,0 +1,190 @@
+"""GPU parity of the mixed-precision solver: the multigrid V-cycle on float32
+fields inside float64 CG / GMRES (flexible CG coefficient), against the CPU
+oracle.
+
+The bar for solves and steps is the float64 one: forward error against the
+long-double spectral solution <= 1e-10, because the Krylov iteration, its
+residual (double-double for the Cahn-Hilliard operator) and the iterate stay
+float64; only the preconditioner is rounded.  A single float32 V-cycle is
+compared with the oracle's float64 V-cycle at a tolerance that follows from
+float32 rounding (see test_vcycle_f32_close_to_oracle).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synthetic as S
+from oracle import fh, mg, ops, spectral
+
+bf = pytest.importorskip("paper_1811_11842_amd")
+
+pytestmark = pytest.mark.gpu
+PRM = S.DEFAULT_PARAMS
+C_CH = PRM["dt"] * PRM["M"] * PRM["kappa"]
+U32 = 2.0 ** -24
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    return torch.device("cuda:0")
+
+
+_grids = {}
+
+
+def grid(n):
+    if n not in _grids:
+        _grids[n] = bf.Grid(n)
+    return _grids[n]
+
+
+def to_dev(a, dev):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+def to_np(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def relw(a, b):
+    return float(ops.wnorm(a - b) / ops.wnorm(b))
+
+
+def opts(op, **kw):
+    return bf.default_opts(op, mg_precision=bf.MG_F32, **kw)
+
+
+@pytest.mark.parametrize("n", [4, 8, 64, 256, 1024])
+@pytest.mark.parametrize("op", ["lap", "ch"])
+def test_vcycle_f32_close_to_oracle(dev, n, op):
+    """One float32 V-cycle against the oracle's float64 V-cycle.  Each float32
+    sweep perturbs its iterate by a few units of float32 rounding relative to
+    the iterate, and the cycle (a contraction on the smooth error, a damping
+    of the rough one) does not amplify these perturbations by more than a
+    modest factor; 64 u32 |z| (about 4e-6) bounds them with margin.  An
+    indexing or coefficient mistake gives differences of order one."""
+    print(f"vcycle f32 op={op} n={n}", flush=True)
+    r = S.random_field(n, seed=500 + n)
+    c = C_CH if op == "ch" else 0.0
+    if op == "lap":
+        r = r - ops.wmean(r)
+    ref = mg.vcycle(mg.hierarchy(op, n, c), r)
+    opc = bf.OP_CH if op == "ch" else bf.OP_LAP
+    z = to_np(grid(n).vcycle(opc, c, to_dev(r, dev), opts=opts(opc)))
+    if op == "lap":
+        z, ref = z - ops.wmean(z), ref - ops.wmean(ref)
+    d = relw(z, ref)
+    print(f"  rel diff {d:.2e}")
+    assert d <= 64 * U32
+    assert d > 0.0 or n == 4   # it did run in float32 (n = 4 is the float64 dense solve)
+
+
+@pytest.mark.parametrize("n", [4, 8, 64, 256, 1024])
+def test_solve_ch_mixed_forward_error(dev, n):
+    print(f"solve_ch mixed n={n}", flush=True)
+    phi = S.initial_phi(n)
+    b = fh.rhs_ch(phi, PRM["dt"], PRM["M"], PRM["Npoly"], PRM["chi"])
+    g = grid(n)
+    rtol = 1e-12 if n <= 64 else 1e-10
+    x64 = g.field(0.0)
+    st64 = g.solve_ch(C_CH, to_dev(b, dev), x64, bf.default_opts(bf.OP_CH, rtol=rtol))
+    x = g.field(0.0)
+    st = g.solve_ch(C_CH, to_dev(b, dev), x, opts(bf.OP_CH, rtol=rtol))
+    x_ld = spectral.solve_ch(b.astype(np.longdouble), C_CH)
+    fe = relw(to_np(x), x_ld)
+    print(f"  mixed iters={st.iters} status={st.status} fe={fe:.2e} | f64 iters={st64.iters}")
+    assert st.status in (bf.OK, bf.AT_FLOOR)
+    assert fe <= 1e-10
+    assert st.iters <= st64.iters + 3
+
+
+@pytest.mark.parametrize("n", [8, 64, 256, 1024])
+def test_solve_pressure_mixed_forward_error(dev, n):
+    print(f"solve_pressure mixed n={n}", flush=True)
+    u, v = S.inflow_velocity(n)
+    rhs = oracle.step.pressure_rhs(u, v, PRM["dt"])
+    g = grid(n)
+    p = g.field(0.0)
+    st = g.solve_pressure(to_dev(rhs, dev), p, opts(bf.OP_LAP, rtol=1e-12))
+    p_ld = spectral.solve_poisson(rhs.astype(np.longdouble))
+    ph = to_np(p)
+    fe = relw(ph, p_ld)
+    print(f"  iters={st.iters} status={st.status} fe={fe:.2e}")
+    assert st.status == bf.OK
+    assert fe <= 1e-10
+    assert abs(ops.wmean(ph)) <= 1e-14 * np.abs(ph).max()
+
+
+def test_gmres_with_f32_vcycle(dev):
+    """Flexible GMRES with the float32 V-cycle reaches the same solution."""
+    n = 256
+    phi = S.initial_phi(n)
+    b = fh.rhs_ch(phi, PRM["dt"], PRM["M"], PRM["Npoly"], PRM["chi"])
+    g = grid(n)
+    x = g.field(0.0)
+    st = g.solve_ch(C_CH, to_dev(b, dev), x, opts(bf.OP_CH, ksp=bf.KSP_GMRES, rtol=1e-10))
+    xs = spectral.solve_ch(b.astype(np.longdouble), C_CH)
+    assert st.status in (bf.OK, bf.AT_FLOOR), st
+    assert relw(to_np(x), xs) <= 1e-10
+
+
+def test_mixed_graph_replays_match_eager(dev, monkeypatch):
+    """The float32 V-cycle replayed from a captured HIP graph equals the eager
+    launch sequence bit for bit on every replay."""
+    n = 256
+    r = S.random_field(n, seed=77)
+    rd = to_dev(r, dev)
+    monkeypatch.setenv("BF_NO_GRAPHS", "1")
+    with bf.Grid(n) as ge:
+        z_eager = to_np(ge.vcycle(bf.OP_CH, C_CH, rd, opts=opts(bf.OP_CH)))
+    monkeypatch.delenv("BF_NO_GRAPHS")
+    g = grid(n)
+    for rep in range(4):
+        z = to_np(g.vcycle(bf.OP_CH, C_CH, rd, opts=opts(bf.OP_CH)))
+        g.apply(bf.OP_CH, C_CH, rd, g.field())
+        torch.cuda.synchronize()
+        assert np.array_equal(z, z_eager), rep
+
+
+def test_mixed_solves_are_deterministic(dev):
+    n = 256
+    phi = S.initial_phi(n)
+    b = to_dev(fh.rhs_ch(phi, PRM["dt"], PRM["M"], PRM["Npoly"], PRM["chi"]), dev)
+    g = grid(n)
+    x1, x2 = g.field(0.0), g.field(0.0)
+    g.solve_ch(C_CH, b, x1, opts(bf.OP_CH))
+    g.solve_ch(C_CH, b, x2, opts(bf.OP_CH))
+    assert torch.equal(x1, x2)
+
+
+def test_bad_precision_rejected(dev):
+    g = grid(8)
+    with pytest.raises(bf.BiofilmError):
+        g.solve_ch(C_CH, g.field(1.0), g.field(0.0), bf.default_opts(bf.OP_CH, mg_precision=7))
+
+
+def test_step_4096_mixed_matches_oracle(dev):
+    """The benchmark configuration with the float32 V-cycle: 4096 x 4096,
+    float64 step, forward error 1e-10 as in float64."""
+    n = 4096
+    print("step mixed n=4096", flush=True)
+    phi0 = S.initial_phi(n)
+    u0, v0 = S.inflow_velocity(n)
+    g = grid(n)
+    phi = to_dev(phi0, dev)
+    us, vs = to_dev(u0, dev), to_dev(v0, dev)
+    p, u, v = g.field(), g.field(), g.field()
+    st = g.step(bf.make_params(**PRM), phi, us, vs, p, u, v,
+                opts(bf.OP_CH, rtol=1e-10), opts(bf.OP_LAP, rtol=1e-10))
+    print("stats", st[0], st[1], flush=True)
+    rphi, rp, ru, rv = oracle.step.step(phi0, u0, v0, **PRM)
+    assert relw(to_np(phi), rphi) <= 1e-10
+    assert relw(to_np(p), rp) <= 1e-9
+    assert relw(to_np(u), ru) <= 1e-10 and relw(to_np(v), rv) <= 1e-10
+    assert st[0].status in (bf.OK, bf.AT_FLOOR)
+    assert st[1].status == bf.OK

@@ -40,7 +40,7 @@ def test_default_options():
 
 
 def test_struct_layouts_match_header():
-    assert ctypes.sizeof(bf.SolverOpts) == 8 * 4 + 3 * 8
+    assert ctypes.sizeof(bf.SolverOpts) == 8 * 4 + 3 * 8 + 2 * 4
     assert ctypes.sizeof(bf.SolveStats) == 4 * 4 + 4 * 8
     assert ctypes.sizeof(bf.Params) == 7 * 8
     assert ctypes.sizeof(bf.GridDesc) == 16

@@ -1,21 +1,28 @@
 """Benchmark: biofilm-flow time step on one MI355X.
 
-A step is the whole hot path over one 4096 x 4096 grid in float64: the
-Flory-Huggins right-hand side, the Cahn-Hilliard solve (13-point operator,
-MG-preconditioned CG to rtol 1e-10, stopping at the float64 floor), the
-pressure right-hand side, the pressure Poisson solve (5-point operator,
+A step is the whole hot path over one 4096 x 4096 grid with float64 fields:
+the Flory-Huggins right-hand side, the Cahn-Hilliard solve (13-point
+operator, MG-preconditioned CG to rtol 1e-10, stopping at the float64 floor),
+the pressure right-hand side, the pressure Poisson solve (5-point operator,
 MG-preconditioned CG to rtol 1e-10) and the velocity correction.  Inputs are
 synthetic (seeded initial biofilm and inflow) and resident in HBM before the
 timed region.
 
-Prints one JSON line.  `value` is the device time per step (ms, lower is
-better).  `roofline` covers the 13-point stencil SpMV (y = x + c L^2 x) timed
+Two precisions are timed over the same K steps from the same initial state:
+mixed (float32 multigrid V-cycle inside float64 CG, float64 residuals,
+iterate and step arithmetic) and plain float64.  `value` is the mixed
+device time per step (ms, lower is better); `fp64_ms_per_step` is the
+float64 one at the same tolerance, and `mixed_vs_fp64_rel_diff` the weighted
+relative difference of the two final states.
+
+`roofline` covers the 13-point stencil SpMV (y = x + c L^2 x, float64) timed
 with HIP events on the grid's stream over back-to-back launches on rotating
 buffers (so the 256 MB last-level cache cannot hold the working set).
 `cpu_baseline` times the CPU oracle on a bounded sample of the same workload.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 4096]
-       [--no-cpu-baseline] [--spmv-only] [--steps-only]
+       [--precision both|mixed|f64] [--no-cpu-baseline] [--spmv-only]
+       [--steps-only]
 """
 from __future__ import annotations
 
@@ -49,6 +56,7 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--precision", choices=["both", "mixed", "f64"], default="both")
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=4096)
     ap.add_argument("--spmv-reps", type=int, default=100)
@@ -67,7 +75,10 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def time_steps(g, n, steps, warmup):
+def time_steps(g, n, steps, warmup, mg_precision):
+    """Warm up on a copy of the initial state, then time `steps` steps from
+    the initial state itself; returns device ms/step, wall ms/step, stats and
+    the final (phi, p)."""
     dev = g.device
     phi0 = S.initial_phi(n)
     u0, v0 = S.inflow_velocity(n)
@@ -75,11 +86,13 @@ def time_steps(g, n, steps, warmup):
     phi = torch.from_numpy(phi0).to(dev)
     us, vs = torch.from_numpy(u0).to(dev), torch.from_numpy(v0).to(dev)
     p, u, v = g.field(0.0), g.field(0.0), g.field(0.0)
-    oc = bf.default_opts(bf.OP_CH, rtol=1e-10)
-    op = bf.default_opts(bf.OP_LAP, rtol=1e-10)
+    oc = bf.default_opts(bf.OP_CH, rtol=1e-10, mg_precision=mg_precision)
+    op = bf.default_opts(bf.OP_LAP, rtol=1e-10, mg_precision=mg_precision)
+    phw = phi.clone()
     for k in range(warmup):
-        st = g.step(prm, phi, us, vs, p, u, v, oc, op)
+        st = g.step(prm, phw, us, vs, p, u, v, oc, op)
         log(f"warmup step {k}: CH {st[0].as_dict()} P {st[1].as_dict()}")
+    del phw
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     stats = []
@@ -95,7 +108,31 @@ def time_steps(g, n, steps, warmup):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms = e0.elapsed_time(e1)
-    return ms / steps, wall / steps * 1e3, stats
+    return ms / steps, wall / steps * 1e3, stats, (phi, p)
+
+
+def wrel(a, b):
+    """||a - b||_W / ||b||_W (trapezoid weights in y) on the device."""
+    w = torch.ones(a.shape[0], 1, dtype=a.dtype, device=a.device)
+    w[0] = w[-1] = 0.5
+    return float(torch.sqrt((w * (a - b) ** 2).sum() / (w * b ** 2).sum()))
+
+
+def step_summary(prefix, ms_step, wall_ms, stats):
+    it_ch = [s[0].iters for s in stats]
+    it_p = [s[1].iters for s in stats]
+    return {
+        f"{prefix}ms_per_step": round(ms_step, 4),
+        f"{prefix}wall_ms_per_step": round(wall_ms, 4),
+        f"{prefix}ch_iters_mean": float(np.mean(it_ch)),
+        f"{prefix}p_iters_mean": float(np.mean(it_p)),
+        f"{prefix}ch_solve_ms_mean": round(float(np.mean([s[0].ms for s in stats])), 4),
+        f"{prefix}p_solve_ms_mean": round(float(np.mean([s[1].ms for s in stats])), 4),
+        f"{prefix}ch_status": sorted({bf.STATUS_NAMES[s[0].status] for s in stats}),
+        f"{prefix}p_status": sorted({bf.STATUS_NAMES[s[1].status] for s in stats}),
+        f"{prefix}ch_rel_res_true_max": float(max(s[0].rel_res_true for s in stats)),
+        f"{prefix}p_rel_res_true_max": float(max(s[1].rel_res_true for s in stats)),
+    }
 
 
 def time_spmv(g, n, reps):
@@ -204,20 +241,26 @@ def main():
                               "smooth_gbs": round(32 * npts / (t_sm * 1e-3) / 1e9, 1)}), flush=True)
             return
         if not a.spmv_only:
-            ms_step, wall_ms, stats = time_steps(g, n, a.steps, a.warmup)
-            it_ch = [s[0].iters for s in stats]
-            it_p = [s[1].iters for s in stats]
-            out.update({
-                "value": round(ms_step, 4), "unit": "ms/step", "ms_per_step": round(ms_step, 4),
-                "wall_ms_per_step": round(wall_ms, 4),
-                "ch_iters_mean": float(np.mean(it_ch)), "p_iters_mean": float(np.mean(it_p)),
-                "ch_solve_ms_mean": float(np.mean([s[0].ms for s in stats])),
-                "p_solve_ms_mean": float(np.mean([s[1].ms for s in stats])),
-                "ch_status": sorted({bf.STATUS_NAMES[s[0].status] for s in stats}),
-                "p_status": sorted({bf.STATUS_NAMES[s[1].status] for s in stats}),
-                "ch_rel_res_true_max": float(max(s[0].rel_res_true for s in stats)),
-                "p_rel_res_true_max": float(max(s[1].rel_res_true for s in stats)),
-            })
+            res = {}
+            if a.precision in ("both", "mixed"):
+                ms_m, wall_m, st_m, fin_m = time_steps(g, n, a.steps, a.warmup, bf.MG_F32)
+                res["mixed"] = fin_m
+                out.update({"value": round(ms_m, 4), "unit": "ms/step",
+                            "ms_per_step": round(ms_m, 4)})
+                out.update(step_summary("", ms_m, wall_m, st_m))
+            if a.precision in ("both", "f64"):
+                ms_d, wall_d, st_d, fin_d = time_steps(g, n, a.steps, a.warmup, bf.MG_F64)
+                res["f64"] = fin_d
+                if a.precision == "f64":
+                    out.update({"value": round(ms_d, 4), "unit": "ms/step",
+                                "ms_per_step": round(ms_d, 4)})
+                out.update(step_summary("fp64_", ms_d, wall_d, st_d))
+            if len(res) == 2:
+                out["speedup_mixed_vs_fp64"] = round(out["fp64_ms_per_step"] / out["ms_per_step"], 3)
+                out["mixed_vs_fp64_rel_diff"] = {
+                    "phi": wrel(res["mixed"][0], res["f64"][0]),
+                    "p": wrel(res["mixed"][1], res["f64"][1])}
+            out["dtype"] = {"both": "f64+f32", "mixed": "f64+f32", "f64": "f64"}[a.precision]
         if not a.steps_only:
             t_spmv = time_spmv(g, n, a.spmv_reps)
             alg = 16 * npts      # algorithmic: read x once, write y once (float64)
@@ -239,9 +282,12 @@ def main():
                     "unit": "GB/s", "frac": round(gbs_sm / HBM_PEAK_GBS, 4),
                     "traffic": recorded_traffic("smooth", n), "algorithmic_bytes": alg_sm,
                     "launch_us": round(t_sm * 1e3, 3)}
-    out["config"] = {"workload": f"{n}x{n} grid, float64 step: Flory-Huggins RHS + MG-PCG "
+    prec = {"both": "float32 V-cycle in float64 CG (value) and plain float64",
+            "mixed": "float32 V-cycle in float64 CG", "f64": "plain float64"}[a.precision]
+    out["config"] = {"workload": f"{n}x{n} grid, {a.steps} steps: Flory-Huggins RHS + MG-PCG "
                                  f"Cahn-Hilliard solve + MG-PCG pressure solve + velocity "
-                                 f"correction, rtol 1e-10",
+                                 f"correction, rtol 1e-10, {prec}",
+                     "precision": a.precision, "mg_precision_value": "f32" if a.precision != "f64" else "f64",
                      "n": n, "rows": n + 1, "cols": n, "points": npts,
                      "dt": S.DEFAULT_PARAMS["dt"], "kappa": S.DEFAULT_PARAMS["kappa"],
                      "chi": S.DEFAULT_PARAMS["chi"], "Npoly": S.DEFAULT_PARAMS["Npoly"]}

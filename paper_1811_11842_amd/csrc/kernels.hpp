@@ -19,16 +19,15 @@ struct OpDesc {
   double dinv_edge;// 1 / diag on rows 1 and n-1
 };
 
-// Launch shape of the streaming stencil kernels (stream.hip), used for grid
-// levels with n >= 128; smaller levels use the one-thread-per-node kernels.
+// Launch shape of the tiled stencil kernels (stream.hip), used for grid
+// levels with n >= 64 V (V = 2 float64 or 4 float32 values per lane);
+// smaller levels use the one-thread-per-node kernels.
 struct StreamCfg {
-  int tpb;      // threads per block (2 columns each)
-  int ty;       // rows per tile
-  int chunks;   // tiles per column strip
-  int tiles;    // strips * chunks
-  int per_xcd;  // tiles per XCD
-  int blocks;   // 8 * per_xcd (blocks beyond `tiles` exit at once)
-  int xcd_map;  // 1: tile ranges dealt to XCDs (block b -> XCD b % 8)
+  int rpw;      // output rows per wavefront tile
+  int wstrips;  // column strips of 64 V columns
+  int rgroups;  // row groups of rpw rows
+  int tiles;    // wstrips * rgroups (one wavefront each)
+  int blocks;   // workgroups of 4 wavefronts (capped; wavefronts then loop)
 };
 bool stream_ok(int n);              // float64 fields
 StreamCfg stream_cfg(int n);

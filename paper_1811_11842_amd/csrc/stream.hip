@@ -1,23 +1,26 @@
-// Streaming stencil kernels for the large grid levels.
+// Stencil kernels for the large grid levels.
 //
-// Tiling: a block of TPB threads owns a strip of TX = V*TPB columns (V
-// adjacent columns per lane, 16-byte loads and stores: V = 2 for float64,
-// 4 for float32) and a chunk of TY rows, which it walks row by row.  Each
-// lane keeps the vertical window of its columns (rows j-R .. j+R, R = 1 for
-// the 5-point and 2 for the 13-point operator) in registers, prefetching two
-// rows ahead; the horizontal neighbours come from a ring of four LDS rows
-// (TX + 4 values each, the two-column halos on both sides loaded by lanes
-// 0..3 with periodic wrap).  One barrier per output row.  Ghost rows outside
-// 0..n are the reflected rows of the two-layer even reflection (paper,
-// Sec. 4, eq. discreteBC).
+// Tiling: every wavefront owns one tile of RPW output rows by 64 V columns
+// (V adjacent columns per lane, 16-byte loads and stores: V = 2 for float64,
+// 4 for float32).  It issues all loads of the tile at once -- the RPW + 2R
+// input rows of its columns (R = 1 for the 5-point and 2 for the 13-point
+// operator; ghost rows are the reflected rows of the two-layer even
+// reflection, paper Sec. 4, eq. discreteBC) and the epilogue's other inputs
+// -- and takes the horizontal neighbours of each value from the adjacent
+// lanes with DPP wave shifts; lanes 0 and 63 load the two columns beyond the
+// wavefront's edge (periodic wrap) themselves.  No LDS and no barriers: each
+// wavefront works on its own, and there are many short ones.
 //
-// Sweep direction alternates with the chunk (even chunks walk down, odd
-// chunks walk up), so two neighbouring chunks read the rows they share in the
-// same phase of their sweeps and the second read is served by L2.
-//
-// XCD-aware launch: workgroups are dealt round-robin to the 8 XCDs of the
-// MI355X, so block b runs on XCD b % 8; tiles are numbered strip-major and
-// each XCD receives a contiguous range of them.
+// Launch order: tiles are numbered row-group-major (all column strips of rows
+// j0 .. j0+RPW-1, then the next row group) and handed to consecutive
+// wavefronts, and the hardware deals consecutive workgroups round-robin to
+// the 8 XCDs.  The wavefronts resident at any moment therefore cover one
+// compact band of rows, which streams through DRAM like a copy; the input
+// rows shared by neighbouring tiles (2R per tile) are read by neighbouring
+// wavefronts at about the same time and mostly hit in cache.  (Dealing
+// contiguous tile ranges to each XCD, or walking long chunks of rows per
+// workgroup with a register window, measured 10-20% slower on 4096^2.)
+// Outputs are stored non-temporally.
 #include <hip/hip_runtime.h>
 
 #include <cstdlib>
@@ -47,14 +50,13 @@ enum Epi {
   E_SMOOTH_DOT2 = 11   // E_SMOOTH and partials of <b, out>_W and <out, q>_W (q float64)
 };
 
-// 16-byte vector of V elements of T, and a pair for the LDS halo reads.
+constexpr int kStreamTPB = 256;         // 4 wavefronts per workgroup
+constexpr int kStreamMaxBlocks = 16384; // beyond this, wavefronts loop over tiles
+
+// 16-byte vector of V elements of T.
 template <typename T, int V>
 struct alignas(16) VecN {
   T v[V];
-};
-template <typename T>
-struct alignas(2 * sizeof(T)) Pair {
-  T v[2];
 };
 
 template <typename T, typename TO>
@@ -67,22 +69,56 @@ struct StreamArgs {
   TO* out;
   double* partials;
   double a, g, a0;
-  int ty, chunks, tiles, per_xcd;
+  int rgroups;         // row groups of RPW rows
+  int wstrips;         // column strips of 64 V columns
+  int tiles;           // rgroups * wstrips
   double* out2;        // E_CG_P: p'
   double* xu;          // E_CG_P: x (updated in place)
   const double* scal;  // E_CG_P: device scalars (alpha, beta)
   const double* q;     // E_SMOOTH_DOT2: second vector of the extra dot
   int first;           // E_CG_P: first step after a (re)start: p' = z, no x update
-  int xcd_map;         // 1: deal contiguous tile ranges to the 8 XCDs
 };
 
-template <int OP, int EPI, int TPB, typename T, typename TO>
-__global__ void __launch_bounds__(TPB) k_stream(StreamArgs<T, TO> P) {
+// Lane i receives the value of lane i-1 (DPP wave_shr:1) or of lane i+1
+// (wave_shl:1); lanes without a source receive 0 (replaced by the caller).
+__device__ __forceinline__ float from_left(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float from_right(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, false));
+}
+__device__ __forceinline__ double from_left(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x138, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x138, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double from_right(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x130, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x130, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+
+// One input row of a lane: its V values and, on lanes 0 and 63, the two
+// values beyond the wavefront's edge (lane 0: columns c-2, c-1; lane 63:
+// columns c+V, c+V+1).
+template <typename T, int V>
+struct XRow {
+  T o[V];
+  T h0, h1;
+};
+
+// Non-temporal store of a vector (the outputs are not re-read by this kernel).
+template <typename T, int V>
+__device__ __forceinline__ void store_nt(VecN<T, V>* dst, const VecN<T, V>& v) {
+#pragma unroll
+  for (int i = 0; i < V; ++i) __builtin_nontemporal_store(v.v[i], &dst->v[i]);
+}
+
+template <int OP, int EPI, int RPW, typename T, typename TO>
+__global__ void __launch_bounds__(kStreamTPB) k_stream(StreamArgs<T, TO> P) {
   constexpr int V = 16 / sizeof(T);
   constexpr int R = (OP == 0) ? 1 : 2;
-  constexpr int W = 2 * R + 1;
-  constexpr int TX = V * TPB;
-  constexpr int LW = TX + 4;
+  constexpr int NR = RPW + 2 * R;
   constexpr bool SMOOTH = (EPI == E_SMOOTH || EPI == E_SMOOTH_XB || EPI == E_SMOOTH_PB ||
                            EPI == E_SMOOTH_DOT || EPI == E_SMOOTH_DOT2);
   constexpr bool RED = (EPI == E_APPLY_DOT || EPI == E_RESID_NORM || EPI == E_APPLY_DOT_DD ||
@@ -93,33 +129,10 @@ __global__ void __launch_bounds__(TPB) k_stream(StreamArgs<T, TO> P) {
   constexpr bool NEEDP = (EPI == E_SMOOTH || EPI == E_SMOOTH_DOT || EPI == E_SMOOTH_DOT2);
   using VT = VecN<T, V>;
   using VO = VecN<TO, V>;
-  __shared__ T lds[4][LW];
 
-  const int bid = blockIdx.x;
-  const int t = P.xcd_map ? (bid & 7) * P.per_xcd + (bid >> 3) : bid;
-  if (t >= P.tiles) {
-    if (RED && threadIdx.x == 0) {
-      P.partials[bid] = 0.0;
-      if (RED2) P.partials[gridDim.x + bid] = 0.0;
-    }
-    return;
-  }
   const int n = P.G.n, mask = P.G.mask;
-  const int strip = t / P.chunks;
-  const int chunk = t - strip * P.chunks;
-  const int j0 = chunk * P.ty;
-  const int j1 = min(j0 + P.ty, n + 1);
-  const int col0 = strip * TX;
-  const int tid = threadIdx.x;
-  const int c = col0 + V * tid;  // own columns c .. c+V-1
-  const int lc = 2 + V * tid;    // their LDS index
-  const bool hthread = tid < 4;
-  int hcol = 0, hslot = 0;
-  if (hthread) {
-    hcol = (tid < 2) ? ((col0 - 2 + tid) & mask) : ((col0 + TX + tid - 2) & mask);
-    hslot = (tid < 2) ? tid : (TX + tid);
-  }
-  const T* __restrict__ X = P.x;
+  const int lane = threadIdx.x & 63;
+  const bool hl = lane == 0, hr = lane == 63;
   const T coef = T(P.A.coef);
   const T ca = T(P.a), cg = T(P.g), ca0 = T(P.a0);
   double beta = 0.0, alpha_prev = 0.0;
@@ -129,228 +142,223 @@ __global__ void __launch_bounds__(TPB) k_stream(StreamArgs<T, TO> P) {
       alpha_prev = P.scal[S_ALPHA];
     }
   }
-
   auto dinv_row = [&](int jr) -> T {
     return T((OP == 1 && (jr == 1 || jr == n - 1)) ? P.A.dinv_edge : P.A.dinv_int);
   };
-  auto load_row = [&](int jj, T(&own)[V], T& halo) {
-    const int jr = refl(jj, n);
-    const T* row = X + (int64_t)jr * n;
-    const VT v = *reinterpret_cast<const VT*>(row + c);
-#pragma unroll
-    for (int i = 0; i < V; ++i) own[i] = v.v[i];
-    halo = hthread ? row[hcol] : T(0);
-    if constexpr (EPI == E_CG_P) {
-      if (!P.first) {
-        const T* prow = P.xprev + (int64_t)jr * n;
-        const VT po = *reinterpret_cast<const VT*>(prow + c);
-#pragma unroll
-        for (int i = 0; i < V; ++i) own[i] += beta * po.v[i];
-        if (hthread) halo += beta * prow[hcol];
-      }
-    }
-    if constexpr (EPI == E_SMOOTH_XB) {
-      const T sc = ca0 * dinv_row(jr);
-#pragma unroll
-      for (int i = 0; i < V; ++i) own[i] *= sc;
-      halo *= sc;
-    }
-  };
-  auto load_ep = [&](int jj, VT& bb, VT& pp) {
-    if (jj > n) return;
-    const int64_t o = (int64_t)jj * n + c;
-    if (NEEDB) bb = *reinterpret_cast<const VT*>(P.b + o);
-    if (NEEDP && P.xprev) pp = *reinterpret_cast<const VT*>(P.xprev + o);
-  };
-  auto store_lds = [&](int slot, const T(&own)[V], T halo) {
-    VT v;
-#pragma unroll
-    for (int i = 0; i < V; ++i) v.v[i] = own[i];
-    *reinterpret_cast<VT*>(&lds[slot][lc]) = v;
-    if (hthread) lds[slot][hslot] = halo;
-  };
-
-  // w[k] holds row j + (k - R) * dir of the lane's columns (dir = +-1).
-  const int dir = (chunk & 1) ? -1 : 1;
-  const int len = j1 - j0;
-  const int jstart = dir > 0 ? j0 : j1 - 1;
-  T w[W][V];
-  T hw[W];
-#pragma unroll
-  for (int k = 0; k < W; ++k) load_row(jstart + (k - R) * dir, w[k], hw[k]);
-  // prefetch queue: the rows entering the window at steps s+1 and s+2; rows
-  // beyond the tile's last need are never loaded
-  T q0[V], q1[V];
-  T hq0 = T(0), hq1 = T(0);
-#pragma unroll
-  for (int i = 0; i < V; ++i) q0[i] = q1[i] = T(0);
-  if (1 < len) load_row(jstart + (R + 1) * dir, q0, hq0);
-  if (2 < len) load_row(jstart + (R + 2) * dir, q1, hq1);
-  VT bq{}, pq{};
-  load_ep(jstart, bq, pq);
-  if (R == 2) {
-    store_lds((jstart - dir) & 3, w[1], hw[1]);
-    store_lds(jstart & 3, w[2], hw[2]);
-  }
-
   double acc = 0.0, acc2 = 0.0;
-  for (int s = 0; s < len; ++s) {
-    const int j = jstart + s * dir;
-    if (R == 2)
-      store_lds((j + dir) & 3, w[3], hw[3]);
-    else
-      store_lds(j & 3, w[1], hw[1]);
-    __syncthreads();
-    const VT bcur = bq, pcur = pq;
-    if (s + 1 < len) load_ep(j + dir, bq, pq);
 
-    // rows of the window by their true offset from j, whatever the direction
-    const T* wm1 = dir > 0 ? w[R - 1] : w[R + 1];
-    const T* wp1 = dir > 0 ? w[R + 1] : w[R - 1];
-    const T* L0 = lds[j & 3];
-    // rowj: columns c-2 .. c+V+1 of row j
-    T rowj[V + 4];
-    {
-      const Pair<T> l = *reinterpret_cast<const Pair<T>*>(&L0[lc - 2]);
-      const Pair<T> r = *reinterpret_cast<const Pair<T>*>(&L0[lc + V]);
-      rowj[0] = l.v[0];
-      rowj[1] = l.v[1];
+  const int wpb = kStreamTPB / 64;
+  for (int t = blockIdx.x * wpb + (threadIdx.x >> 6); t < P.tiles; t += gridDim.x * wpb) {
+    const int rg = t / P.wstrips;
+    const int strip = t - rg * P.wstrips;
+    const int j0 = rg * RPW;
+    const int jl = min(j0 + RPW, n + 1) - 1;  // last output row of the tile
+    const int c = strip * (64 * V) + V * lane;
+    const int hcol = hl ? ((c - V) & mask) : ((c + V) & mask);
+
+    auto load_row = [&](const T* base, int jr, bool halo, XRow<T, V>& r) {
+      const T* row = base + (int64_t)jr * n;
+      const VT v = *reinterpret_cast<const VT*>(row + c);
 #pragma unroll
-      for (int i = 0; i < V; ++i) rowj[2 + i] = w[R][i];
-      rowj[V + 2] = r.v[0];
-      rowj[V + 3] = r.v[1];
-    }
-    Nb13T<T> nb[V];
-#pragma unroll
-    for (int i = 0; i < V; ++i) {
-      nb[i].c = rowj[i + 2];
-      nb[i].xm1 = rowj[i + 1];
-      nb[i].xp1 = rowj[i + 3];
-      nb[i].ym1 = wm1[i];
-      nb[i].yp1 = wp1[i];
-    }
-    if (R == 2) {
-      const T* wm2 = dir > 0 ? w[0] : w[W - 1];
-      const T* wp2 = dir > 0 ? w[W - 1] : w[0];
-      const T* Lm = lds[(j - 1) & 3];
-      const T* Lp = lds[(j + 1) & 3];
-      T rowm[V + 2], rowp[V + 2];
-      rowm[0] = Lm[lc - 1];
-      rowm[V + 1] = Lm[lc + V];
-      rowp[0] = Lp[lc - 1];
-      rowp[V + 1] = Lp[lc + V];
-#pragma unroll
-      for (int i = 0; i < V; ++i) {
-        rowm[1 + i] = wm1[i];
-        rowp[1 + i] = wp1[i];
+      for (int i = 0; i < V; ++i) r.o[i] = v.v[i];
+      r.h0 = r.h1 = T(0);
+      if (halo && (hl || hr)) {
+        const VT h = *reinterpret_cast<const VT*>(row + hcol);
+        r.h0 = hl ? h.v[V - 2] : h.v[0];
+        r.h1 = hl ? h.v[V - 1] : h.v[1];
       }
+    };
+
+    // input rows j0 - R .. jl + R (reflected); rows 1 .. NR-2 of the window
+    // are centre or vertical neighbours of an output and need their halo
+    XRow<T, V> xr[NR];
 #pragma unroll
-      for (int i = 0; i < V; ++i) {
-        nb[i].xm2 = rowj[i];
-        nb[i].xp2 = rowj[i + 4];
-        nb[i].ym2 = wm2[i];
-        nb[i].yp2 = wp2[i];
-        nb[i].dmm = rowm[i];
-        nb[i].dmp = rowm[i + 2];
-        nb[i].dpm = rowp[i];
-        nb[i].dpp = rowp[i + 2];
+    for (int k = 0; k < NR; ++k) {
+      const int jj = j0 - R + k;
+      const bool halo = k >= 1 && k <= NR - 2;
+      if (jj > jl + R) {
+#pragma unroll
+        for (int i = 0; i < V; ++i) xr[k].o[i] = T(0);
+        xr[k].h0 = xr[k].h1 = T(0);
+        continue;
       }
-    }
-    const int64_t o = (int64_t)j * n + c;
-    const double wgt = row_weight(j, n);
-    VO res;
-    if constexpr (EPI == E_APPLY || EPI == E_APPLY_DOT) {
-#pragma unroll
-      for (int i = 0; i < V; ++i) {
-        const T ax = apply_vals<OP>(nb[i], coef);
-        res.v[i] = TO(ax);
-        if (EPI == E_APPLY_DOT) acc += wgt * double(nb[i].c) * double(ax);
-      }
-    } else if constexpr (EPI == E_RESID || EPI == E_RESID_NORM) {
-#pragma unroll
-      for (int i = 0; i < V; ++i) {
-        const T r = bcur.v[i] - apply_vals<OP>(nb[i], coef);
-        res.v[i] = TO(r);
-        if (EPI == E_RESID_NORM) acc += wgt * double(r) * double(r);
-      }
-    } else if constexpr (SMOOTH) {
-      const T ad = ca * dinv_row(j);
-      const T d0 = ca0 * dinv_row(j);
-#pragma unroll
-      for (int i = 0; i < V; ++i) {
-        T prev = T(0);
-        if (EPI == E_SMOOTH_PB)
-          prev = d0 * bcur.v[i];
-        else if (EPI != E_SMOOTH_XB && P.xprev)
-          prev = pcur.v[i];
-        const T xn =
-            nb[i].c + ad * (bcur.v[i] - apply_vals<OP>(nb[i], coef)) + cg * (nb[i].c - prev);
-        res.v[i] = TO(xn);
-        if (EPI == E_SMOOTH_DOT || EPI == E_SMOOTH_DOT2)
-          acc += wgt * double(bcur.v[i]) * double(TO(xn));
-      }
-      if constexpr (EPI == E_SMOOTH_DOT2) {
-        const VecN<double, V> qv = *reinterpret_cast<const VecN<double, V>*>(P.q + o);
-#pragma unroll
-        for (int i = 0; i < V; ++i) acc2 += wgt * double(res.v[i]) * qv.v[i];
-      }
-    } else if constexpr (std::is_same<T, double>::value) {
-      if constexpr (EPI == E_APPLY_DOT_DD) {
-#pragma unroll
-        for (int i = 0; i < V; ++i) {
-          res.v[i] = -residual_dd_vals<OP>(nb[i], 0.0, P.A.coef);
-          acc += wgt * nb[i].c * res.v[i];
-        }
-      } else if constexpr (EPI == E_CG_P) {
-        VecN<double, V> pn;
-#pragma unroll
-        for (int i = 0; i < V; ++i) {
-          res.v[i] = OP == 1 ? -residual_dd_vals<OP>(nb[i], 0.0, P.A.coef)
-                             : apply_vals<OP>(nb[i], P.A.coef);
-          acc += wgt * nb[i].c * res.v[i];
-          pn.v[i] = nb[i].c;
-        }
-        *reinterpret_cast<VecN<double, V>*>(P.out2 + o) = pn;
+      const int jr = refl(jj, n);
+      load_row(P.x, jr, halo, xr[k]);
+      if constexpr (EPI == E_CG_P) {
         if (!P.first) {
-          const VecN<double, V> po = *reinterpret_cast<const VecN<double, V>*>(P.xprev + o);
-          VecN<double, V> xv = *reinterpret_cast<const VecN<double, V>*>(P.xu + o);
+          XRow<T, V> po;
+          load_row(P.xprev, jr, halo, po);
 #pragma unroll
-          for (int i = 0; i < V; ++i) xv.v[i] += alpha_prev * po.v[i];
-          *reinterpret_cast<VecN<double, V>*>(P.xu + o) = xv;
-        }
-      } else if constexpr (EPI == E_RESID_DD) {
-#pragma unroll
-        for (int i = 0; i < V; ++i) {
-          res.v[i] = residual_dd_vals<OP>(nb[i], bcur.v[i], P.A.coef);
-          acc += wgt * res.v[i] * res.v[i];
-          const double u = ulp_of(nb[i].c);
-          acc2 += wgt * u * u;
+          for (int i = 0; i < V; ++i) xr[k].o[i] += beta * po.o[i];
+          xr[k].h0 += beta * po.h0;
+          xr[k].h1 += beta * po.h1;
         }
       }
+      if constexpr (EPI == E_SMOOTH_XB) {
+        const T sc = ca0 * dinv_row(jr);
+#pragma unroll
+        for (int i = 0; i < V; ++i) xr[k].o[i] *= sc;
+        xr[k].h0 *= sc;
+        xr[k].h1 *= sc;
+      }
     }
-    *reinterpret_cast<VO*>(P.out + o) = res;
+
+    // neighbours across lanes: column c-1, c-2 (left) and c+V, c+V+1 (right)
+    auto left1 = [&](const XRow<T, V>& r) {
+      const T v = from_left(r.o[V - 1]);
+      return hl ? r.h1 : v;
+    };
+    auto left2 = [&](const XRow<T, V>& r) {
+      const T v = from_left(r.o[V - 2]);
+      return hl ? r.h0 : v;
+    };
+    auto right1 = [&](const XRow<T, V>& r) {
+      const T v = from_right(r.o[0]);
+      return hr ? r.h0 : v;
+    };
+    auto right2 = [&](const XRow<T, V>& r) {
+      const T v = from_right(r.o[1]);
+      return hr ? r.h1 : v;
+    };
 
 #pragma unroll
-    for (int k = 0; k < W - 1; ++k) {
+    for (int s = 0; s < RPW; ++s) {
+      const int j = j0 + s;
+      if (j > jl) break;
+      const int k = s + R;
+      const XRow<T, V>& C = xr[k];
+      // centre row, columns c-2 .. c+V+1
+      T e[V + 4];
+      e[1] = left1(C);
+      e[V + 2] = right1(C);
+      if (OP == 1) {
+        e[0] = left2(C);
+        e[V + 3] = right2(C);
+      } else {
+        e[0] = e[V + 3] = T(0);
+      }
 #pragma unroll
-      for (int i = 0; i < V; ++i) w[k][i] = w[k + 1][i];
-      hw[k] = hw[k + 1];
-    }
+      for (int i = 0; i < V; ++i) e[2 + i] = C.o[i];
+      Nb13T<T> nb[V];
 #pragma unroll
-    for (int i = 0; i < V; ++i) {
-      w[W - 1][i] = q0[i];
-      q0[i] = q1[i];
+      for (int i = 0; i < V; ++i) {
+        nb[i].c = e[i + 2];
+        nb[i].xm1 = e[i + 1];
+        nb[i].xp1 = e[i + 3];
+        nb[i].ym1 = xr[k - 1].o[i];
+        nb[i].yp1 = xr[k + 1].o[i];
+      }
+      if constexpr (OP == 1) {
+        const XRow<T, V>& Mr = xr[k - 1];
+        const XRow<T, V>& Pr = xr[k + 1];
+        T m[V + 2], p[V + 2];  // rows j-1, j+1, columns c-1 .. c+V
+        m[0] = left1(Mr);
+        m[V + 1] = right1(Mr);
+        p[0] = left1(Pr);
+        p[V + 1] = right1(Pr);
+#pragma unroll
+        for (int i = 0; i < V; ++i) {
+          m[1 + i] = Mr.o[i];
+          p[1 + i] = Pr.o[i];
+        }
+#pragma unroll
+        for (int i = 0; i < V; ++i) {
+          nb[i].xm2 = e[i];
+          nb[i].xp2 = e[i + 4];
+          nb[i].ym2 = xr[k - 2].o[i];
+          nb[i].yp2 = xr[k + 2].o[i];
+          nb[i].dmm = m[i];
+          nb[i].dmp = m[i + 2];
+          nb[i].dpm = p[i];
+          nb[i].dpp = p[i + 2];
+        }
+      }
+      const int64_t o = (int64_t)j * n + c;
+      const double wgt = row_weight(j, n);
+      VT bcur{}, pcur{};
+      if constexpr (NEEDB) bcur = *reinterpret_cast<const VT*>(P.b + o);
+      if constexpr (NEEDP) {
+        if (P.xprev) pcur = *reinterpret_cast<const VT*>(P.xprev + o);
+      }
+      VO res;
+      if constexpr (EPI == E_APPLY || EPI == E_APPLY_DOT) {
+#pragma unroll
+        for (int i = 0; i < V; ++i) {
+          const T ax = apply_vals<OP>(nb[i], coef);
+          res.v[i] = TO(ax);
+          if (EPI == E_APPLY_DOT) acc += wgt * double(nb[i].c) * double(ax);
+        }
+      } else if constexpr (EPI == E_RESID || EPI == E_RESID_NORM) {
+#pragma unroll
+        for (int i = 0; i < V; ++i) {
+          const T r = bcur.v[i] - apply_vals<OP>(nb[i], coef);
+          res.v[i] = TO(r);
+          if (EPI == E_RESID_NORM) acc += wgt * double(r) * double(r);
+        }
+      } else if constexpr (SMOOTH) {
+        const T ad = ca * dinv_row(j);
+        const T d0 = ca0 * dinv_row(j);
+#pragma unroll
+        for (int i = 0; i < V; ++i) {
+          T prev = T(0);
+          if (EPI == E_SMOOTH_PB)
+            prev = d0 * bcur.v[i];
+          else if (EPI != E_SMOOTH_XB && P.xprev)
+            prev = pcur.v[i];
+          const T xn =
+              nb[i].c + ad * (bcur.v[i] - apply_vals<OP>(nb[i], coef)) + cg * (nb[i].c - prev);
+          res.v[i] = TO(xn);
+          if (EPI == E_SMOOTH_DOT || EPI == E_SMOOTH_DOT2)
+            acc += wgt * double(bcur.v[i]) * double(TO(xn));
+        }
+        if constexpr (EPI == E_SMOOTH_DOT2) {
+          const VecN<double, V> qv = *reinterpret_cast<const VecN<double, V>*>(P.q + o);
+#pragma unroll
+          for (int i = 0; i < V; ++i) acc2 += wgt * double(res.v[i]) * qv.v[i];
+        }
+      } else if constexpr (std::is_same<T, double>::value) {
+        if constexpr (EPI == E_APPLY_DOT_DD) {
+#pragma unroll
+          for (int i = 0; i < V; ++i) {
+            res.v[i] = -residual_dd_vals<OP>(nb[i], 0.0, P.A.coef);
+            acc += wgt * nb[i].c * res.v[i];
+          }
+        } else if constexpr (EPI == E_CG_P) {
+          VecN<double, V> pn;
+#pragma unroll
+          for (int i = 0; i < V; ++i) {
+            res.v[i] = OP == 1 ? -residual_dd_vals<OP>(nb[i], 0.0, P.A.coef)
+                               : apply_vals<OP>(nb[i], P.A.coef);
+            acc += wgt * nb[i].c * res.v[i];
+            pn.v[i] = nb[i].c;
+          }
+          store_nt(reinterpret_cast<VecN<double, V>*>(P.out2 + o), pn);
+          if (!P.first) {
+            const VecN<double, V> po = *reinterpret_cast<const VecN<double, V>*>(P.xprev + o);
+            VecN<double, V> xv = *reinterpret_cast<const VecN<double, V>*>(P.xu + o);
+#pragma unroll
+            for (int i = 0; i < V; ++i) xv.v[i] += alpha_prev * po.v[i];
+            store_nt(reinterpret_cast<VecN<double, V>*>(P.xu + o), xv);
+          }
+        } else if constexpr (EPI == E_RESID_DD) {
+#pragma unroll
+          for (int i = 0; i < V; ++i) {
+            res.v[i] = residual_dd_vals<OP>(nb[i], bcur.v[i], P.A.coef);
+            acc += wgt * res.v[i] * res.v[i];
+            const double u = ulp_of(nb[i].c);
+            acc2 += wgt * u * u;
+          }
+        }
+      }
+      store_nt(reinterpret_cast<VO*>(P.out + o), res);
     }
-    hw[W - 1] = hq0;
-    hq0 = hq1;
-    if (s + 3 < len) load_row(j + (R + 3) * dir, q1, hq1);
   }
-  if (RED) {
-    const double s = block_sum_n<TPB>(acc);
-    if (tid == 0) P.partials[bid] = s;
-    if (RED2) {
-      const double s2 = block_sum_n<TPB>(acc2);
-      if (tid == 0) P.partials[gridDim.x + bid] = s2;
+  if constexpr (RED) {
+    const double s1 = block_sum_n<kStreamTPB>(acc);
+    if (threadIdx.x == 0) P.partials[blockIdx.x] = s1;
+    if constexpr (RED2) {
+      const double s2 = block_sum_n<kStreamTPB>(acc2);
+      if (threadIdx.x == 0) P.partials[gridDim.x + blockIdx.x] = s2;
     }
   }
 }
@@ -367,25 +375,19 @@ int env_int(const char* name, int dflt) {
 
 bool stream_ok(int n, int elem_bytes) { return n >= 64 * (16 / elem_bytes); }
 
+// Rows per tile: 4 (measured best on 4096^2 among 2..6 for the 13-point
+// SpMV: fewer rows re-read more neighbour rows, more rows hold more registers
+// and widen the band of rows in flight).  BF_STREAM_RPW=8 selects 8.
 StreamCfg stream_cfg(int n, int elem_bytes) {
   StreamCfg c;
-  const int vcols = 16 / elem_bytes;
-  c.tpb = n >= 256 * vcols ? 256 : (n >= 128 * vcols ? 128 : 64);
-  const int tx = vcols * c.tpb;
-  const int strips = n / tx;
-  // aim at ~4096 tiles (16 per CU over the 256 CUs), 8..64 rows each; on
-  // 4096^2 in float64 this gives 8-row tiles, measured fastest for whole solves
-  int ty = (int)(((int64_t)(n + 1) * strips) / 4096);
-  static const int ty_env = env_int("BF_STREAM_TY", 0);
-  if (ty_env > 0) ty = ty_env;
-  ty = ty < 8 ? 8 : (ty > 64 ? 64 : ty);
-  c.ty = ty;
-  c.chunks = (n + 1 + ty - 1) / ty;
-  c.tiles = strips * c.chunks;
-  static const int xm = env_int("BF_XCD_MAP", 1);
-  c.xcd_map = xm;
-  c.per_xcd = (c.tiles + 7) / 8;
-  c.blocks = xm ? 8 * c.per_xcd : c.tiles;
+  static const int rpw_env = env_int("BF_STREAM_RPW", 4);
+  c.rpw = rpw_env == 8 ? 8 : 4;
+  c.wstrips = n / (64 * (16 / elem_bytes));
+  c.rgroups = (n + 1 + c.rpw - 1) / c.rpw;
+  c.tiles = c.wstrips * c.rgroups;
+  const int wpb = kStreamTPB / 64;
+  const int64_t blocks = ((int64_t)c.tiles + wpb - 1) / wpb;
+  c.blocks = (int)(blocks < kStreamMaxBlocks ? blocks : kStreamMaxBlocks);
   return c;
 }
 
@@ -393,18 +395,14 @@ bool stream_ok(int n) { return stream_ok(n, 8); }
 StreamCfg stream_cfg(int n) { return stream_cfg(n, 8); }
 
 template <int OP, int EPI, typename T, typename TO>
-static void dispatch(const StreamCfg& c, const StreamArgs<T, TO>& P, hipStream_t st) {
-  switch (c.tpb) {
-    case 256:
-      hipLaunchKernelGGL((k_stream<OP, EPI, 256, T, TO>), dim3(c.blocks), dim3(256), 0, st, P);
-      break;
-    case 128:
-      hipLaunchKernelGGL((k_stream<OP, EPI, 128, T, TO>), dim3(c.blocks), dim3(128), 0, st, P);
-      break;
-    default:
-      hipLaunchKernelGGL((k_stream<OP, EPI, 64, T, TO>), dim3(c.blocks), dim3(64), 0, st, P);
-      break;
-  }
+static void dispatch(const StreamCfg& c, StreamArgs<T, TO> P, hipStream_t st) {
+  P.rgroups = c.rgroups;
+  P.wstrips = c.wstrips;
+  P.tiles = c.tiles;
+  if (c.rpw == 8)
+    hipLaunchKernelGGL((k_stream<OP, EPI, 8, T, TO>), dim3(c.blocks), dim3(kStreamTPB), 0, st, P);
+  else
+    hipLaunchKernelGGL((k_stream<OP, EPI, 4, T, TO>), dim3(c.blocks), dim3(kStreamTPB), 0, st, P);
 }
 
 template <int EPI, typename T, typename TO>
@@ -424,11 +422,6 @@ static int stream_launch(const OpDesc& A, const T* x, const T* b, const T* xprev
   P.g = g;
   P.a0 = a0;
   P.q = q;
-  P.ty = c.ty;
-  P.chunks = c.chunks;
-  P.tiles = c.tiles;
-  P.per_xcd = c.per_xcd;
-  P.xcd_map = c.xcd_map;
   if (A.op == 0)
     dispatch<0, EPI>(c, P, st);
   else
@@ -498,11 +491,6 @@ int stream_cg_p(const OpDesc& A, const double* z, const double* p_old, double* p
   P.scal = scal;
   P.first = first ? 1 : 0;
   P.partials = partials;
-  P.ty = c.ty;
-  P.chunks = c.chunks;
-  P.tiles = c.tiles;
-  P.per_xcd = c.per_xcd;
-  P.xcd_map = c.xcd_map;
   if (A.op == 0)
     dispatch<0, E_CG_P>(c, P, st);
   else

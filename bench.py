@@ -49,7 +49,7 @@ KERNEL_SOURCES = ["paper_1811_11842_amd/csrc/stream.hip", "paper_1811_11842_amd/
 # (profiles/spmv_13pt_4096_counters.md), KiB per dispatch, scaled by the ratio of known to
 # counted bytes of the bf_copy calibration kernel.  Valid only for the kernel sources
 # whose sha256 is recorded; otherwise the traffic is reported as null.
-TRAFFIC_RECORD = {"n": 4096, "fetch_scale": 1.9996, "write_scale": 1.0, "kernels": {"spmv": {"fetch_kib": 75693.2, "write_kib": 131104.0}, "smooth": {"fetch_kib": 208517.1, "write_kib": 131104.0}}, "sources_sha256": "21019ae8e33f25fb60c29db160016b2c72a6e7228b80aabff13666a4adefb2c6"}
+TRAFFIC_RECORD = {"n": 4096, "fetch_scale": 1.9998, "write_scale": 1.0, "kernels": {"spmv": {"fetch_kib": 69730.7, "write_kib": 131104.1}, "smooth": {"fetch_kib": 200817.3, "write_kib": 131104.0}}, "sources_sha256": "7dcc8754dc5818c6f8b4ea5812adc8267c643bd49c27e9610fd651401ade2f4a"}
 
 
 def parse():
@@ -267,7 +267,7 @@ def main():
             gbs = alg / (t_spmv * 1e-3) / 1e9
             out["spmv_us"] = round(t_spmv * 1e3, 3)
             out["spmv_gbs"] = round(gbs, 1)
-            out["roofline"] = {"kernel": "k_stream<1,0,256> (13-point Cahn-Hilliard SpMV, float64)",
+            out["roofline"] = {"kernel": "k_stream<1,0,4,double,double> (13-point Cahn-Hilliard SpMV, float64)",
                                "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
                                "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
                                "traffic": recorded_traffic("spmv", n), "algorithmic_bytes": alg,
@@ -277,7 +277,7 @@ def main():
                 alg_sm = 32 * npts   # x, x_prev, b read, x' written
                 gbs_sm = alg_sm / (t_sm * 1e-3) / 1e9
                 out["roofline_smoother"] = {
-                    "kernel": "k_stream<1,4,256> (13-point Chebyshev smoothing sweep, float64)",
+                    "kernel": "k_stream<1,4,4,double,double> (13-point Chebyshev smoothing sweep, float64)",
                     "bound": "hbm", "achieved": round(gbs_sm, 1), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(gbs_sm / HBM_PEAK_GBS, 4),
                     "traffic": recorded_traffic("smooth", n), "algorithmic_bytes": alg_sm,

@@ -188,3 +188,24 @@ def test_step_4096_mixed_matches_oracle(dev):
     assert relw(to_np(u), ru) <= 1e-10 and relw(to_np(v), rv) <= 1e-10
     assert st[0].status in (bf.OK, bf.AT_FLOOR)
     assert st[1].status == bf.OK
+
+
+def test_step_512_mixed_error(dev):
+    """The 512 x 512 subproblem: one mixed-precision step against the float64
+    oracle step; the relative W-norm errors of phi and p are printed for the
+    record and held to the float64 bar."""
+    n = 512
+    phi0 = S.initial_phi(n)
+    u0, v0 = S.inflow_velocity(n)
+    g = grid(n)
+    phi = to_dev(phi0, dev)
+    us, vs = to_dev(u0, dev), to_dev(v0, dev)
+    p, u, v = g.field(), g.field(), g.field()
+    st = g.step(bf.make_params(**PRM), phi, us, vs, p, u, v,
+                opts(bf.OP_CH, rtol=1e-10), opts(bf.OP_LAP, rtol=1e-10))
+    rphi, rp, ru, rv = oracle.step.step(phi0, u0, v0, **PRM)
+    e_phi, e_p = relw(to_np(phi), rphi), relw(to_np(p), rp)
+    print(f"512^2 mixed step: error phi {e_phi:.3e}, p {e_p:.3e}, "
+          f"iters CH {st[0].iters} P {st[1].iters}")
+    assert e_phi <= 1e-10
+    assert e_p <= 1e-9

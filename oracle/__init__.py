@@ -20,6 +20,10 @@ Biofilm Flow using the Modified Cahn-Hilliard Equation", arXiv:1811.11842):
   * mg        -- geometric-multigrid pieces and the V-cycle, written plainly.
   * step      -- one projection step (Sec. 4: eqs. pressuresolve and
                  velocityupdate) coupled with the Cahn-Hilliard solve.
+  * adjoint   -- the Cahn-Hilliard rollout with explicit advection (the flux
+                 div(phi v) of eq. modCH) and its hand-derived adjoint: the
+                 gradients of the upper-half mass with respect to chi, the
+                 inflow speed and the initial phi.
 
 Only tests, the smoke check and the benchmark's CPU-baseline leg may import
 this package.  It shares no code with the HIP path and must never be used as
@@ -28,4 +32,4 @@ a fallback for it.
 Every function cites the passage it follows.  Pins (checks against what the
 paper and mathematics fix, not against this code) live in tests/test_oracle_*.py.
 """
-from . import ops, fh, spectral, dense, cg, mg, step  # noqa: F401
+from . import ops, fh, spectral, dense, cg, mg, step, adjoint  # noqa: F401

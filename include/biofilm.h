@@ -172,10 +172,40 @@ int bf_step(bf_grid* g, const bf_params* prm, double* phi, const double* ustar,
             const bf_solver_opts* ch, const bf_solver_opts* pr,
             bf_solve_stats stats[2]);
 
-/* Reverse (adjoint) step with checkpointing: not available in this version;
- * returns BF_EUNSUPPORTED. */
+/* One Cahn-Hilliard step with explicit advection (the flux div(phi v) of
+ * Sec. 2.2, eq. modCH):
+ *   b = phi + dt*M*L mu_FH(clamp(phi)) - dt*D(phi; u, v),
+ *   D(phi; u, v) = div_h(phi*u, phi*v)  (2h central, phi even and v odd
+ *   across the walls),
+ *   (I + dt*M*kappa*L^2) phi' = b, solved in place from a zero guess.
+ * u, v: device fields of the advecting velocity (both NULL: no advection,
+ * the Cahn-Hilliard half of bf_step); they must not alias phi.  Synchronous;
+ * stats (may be NULL) receives the solve's statistics and the clamp count. */
+int bf_step_ch(bf_grid* g, const bf_params* prm, double* phi, const double* u,
+               const double* v, const bf_solver_opts* o, bf_solve_stats* stats);
+
+/* Reverse (adjoint) of one bf_step_ch, for gradients of a functional J of a
+ * later state (the rollout's checkpointing is the caller's; the adjoint of a
+ * rollout calls this once per step in reverse order).  With the plain
+ * (Euclidean) transpose and lambda_in = dJ/dphi',
+ *   eta = A^{-T} lambda_in = W A^{-1} W^{-1} lambda_in  (A = I + c L^2 is
+ *         self-adjoint in the trapezoid inner product W; the transpose solve
+ *         is the forward solve between two diagonal scalings),
+ *   lambda_out = dJ/dphi_n = eta + dt*M*mu_FH'(phi_n) (L^T eta) - dt*D^T eta
+ *         (mu_FH' = 1/(N phi) + 1/(1 - phi) - 2 chi, 0 where the clamp is
+ *         active; L^T = W L W^{-1}; D^T the transpose of phi -> D(phi; u, v)),
+ *   grads[0] += dt*M * sum (L^T eta)(1 - 2 clamp(phi_n))      (dJ/dchi),
+ *   grads[1] += -dt * sum eta D(phi_n; du, dv)               (dJ/dU, where
+ *         (du, dv) = d(u, v)/dU; both NULL: grads[1] unchanged).
+ * phi_n is the state the forward step started from; u, v as in bf_step_ch
+ * (both NULL: no advection).  lambda_out may alias lambda_in, not phi_n, u, v,
+ * du or dv.  grads is a host array (may be NULL).  o / stats: options and
+ * statistics of the transpose solve.  Synchronous.  Returns the solve's
+ * status (BF_OK, BF_AT_FLOOR, BF_NOT_CONVERGED) or a negative error. */
 int bf_adjoint_step(bf_grid* g, const bf_params* prm, const double* phi_n,
-                    const double* lambda_in, double* lambda_out);
+                    const double* u, const double* v, const double* du,
+                    const double* dv, const double* lambda_in, double* lambda_out,
+                    double grads[2], const bf_solver_opts* o, bf_solve_stats* stats);
 
 /* z = V(r): one multigrid V-cycle (the preconditioner of the solves) of the
  * operator op with the options o (smoother, degree, ratio, omega), from a

@@ -105,7 +105,12 @@ def lib():
             "bf_step": (ctypes.c_int, [_P, ctypes.POINTER(Params), _P, _P, _P, _P, _P, _P,
                                        ctypes.POINTER(SolverOpts), ctypes.POINTER(SolverOpts),
                                        ctypes.POINTER(SolveStats)]),
-            "bf_adjoint_step": (ctypes.c_int, [_P, ctypes.POINTER(Params), _P, _P, _P]),
+            "bf_step_ch": (ctypes.c_int, [_P, ctypes.POINTER(Params), _P, _P, _P,
+                                          ctypes.POINTER(SolverOpts), ctypes.POINTER(SolveStats)]),
+            "bf_adjoint_step": (ctypes.c_int, [_P, ctypes.POINTER(Params), _P, _P, _P, _P, _P, _P,
+                                               _P, ctypes.POINTER(ctypes.c_double),
+                                               ctypes.POINTER(SolverOpts),
+                                               ctypes.POINTER(SolveStats)]),
             "bf_vcycle": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_double,
                                          ctypes.POINTER(SolverOpts), _P, _P]),
             "bf_restrict": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P]),
@@ -269,9 +274,28 @@ class Grid:
                              ctypes.byref(pr) if pr is not None else None, st))
         return st[0], st[1]
 
-    def adjoint_step(self, params: Params, phi_n, lam_in, lam_out):
+    def step_ch(self, params: Params, phi, u=None, v=None, opts=None) -> SolveStats:
+        """One Cahn-Hilliard step in place, advected by (u, v) if given."""
+        st = SolveStats()
+        _check(lib().bf_step_ch(self._h, ctypes.byref(params), self._ptr(phi, "phi"),
+                                self._ptr(u, "u"), self._ptr(v, "v"),
+                                ctypes.byref(opts) if opts is not None else None,
+                                ctypes.byref(st)))
+        return st
+
+    def adjoint_step(self, params: Params, phi_n, lam_in, lam_out=None, u=None, v=None,
+                     du=None, dv=None, opts=None):
+        """(lam_out, [dJ/dchi, dJ/dU] contributions, stats) of one reverse step."""
+        lam_out = self.field() if lam_out is None else lam_out
+        g = (ctypes.c_double * 2)(0.0, 0.0)
+        st = SolveStats()
         _check(lib().bf_adjoint_step(self._h, ctypes.byref(params), self._ptr(phi_n, "phi_n"),
-                                     self._ptr(lam_in, "lam_in"), self._ptr(lam_out, "lam_out")))
+                                     self._ptr(u, "u"), self._ptr(v, "v"),
+                                     self._ptr(du, "du"), self._ptr(dv, "dv"),
+                                     self._ptr(lam_in, "lam_in"), self._ptr(lam_out, "lam_out"),
+                                     g, ctypes.byref(opts) if opts is not None else None,
+                                     ctypes.byref(st)))
+        return lam_out, (g[0], g[1]), st
 
     def vcycle(self, op, c, r, z=None, opts=None):
         z = self.field() if z is None else z

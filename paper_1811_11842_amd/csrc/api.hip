@@ -77,6 +77,7 @@ struct bf_grid {
   double *r = nullptr, *z = nullptr, *p = nullptr, *p2 = nullptr, *q = nullptr;
   double *work_b = nullptr;   // Cahn-Hilliard right-hand side inside bf_step
   double *work_p = nullptr;   // projected pressure right-hand side
+  double *work_e = nullptr;   // adjoint: W^{-1} eta (allocated on first use)
   double* scal = nullptr;     // device scalars (kNumSlots)
   double* partials = nullptr; // reduction partials (kMaxRedBlocks * 72)
   double* coarse_ch = nullptr;
@@ -1108,14 +1109,65 @@ int bf_step(bf_grid* g, const bf_params* prm, double* phi, const double* ustar,
   return s1 > s2 ? s1 : s2;
 }
 
-int bf_adjoint_step(bf_grid* g, const bf_params* prm, const double* phi_n, const double* lambda_in,
-                    double* lambda_out) {
-  (void)g;
-  (void)prm;
-  (void)phi_n;
-  (void)lambda_in;
-  (void)lambda_out;
-  return fail(BF_EUNSUPPORTED, "bf_adjoint_step is not available in this version");
+int bf_step_ch(bf_grid* g, const bf_params* prm, double* phi, const double* u, const double* v,
+               const bf_solver_opts* o, bf_solve_stats* stats) {
+  TRY(check_grid(g));
+  if (!prm || !phi) return fail(BF_EINVAL, "null argument");
+  if ((u == nullptr) != (v == nullptr)) return fail(BF_EINVAL, "u and v must both be given or both be null");
+  if (u && (u == phi || v == phi)) return fail(BF_EINVAL, "u, v must not alias phi");
+  bf_solve_stats local;
+  bf_solve_stats* S = stats ? stats : &local;
+  std::memset(S, 0, sizeof(*S));
+  TRY(bf_ch_rhs(g, prm, phi, g->work_b, g->counter));
+  if (u) launch_advect_sub(g->n, phi, u, v, g->work_b, prm->dt, g->stream);
+  launch_fill(g->npts, phi, 0.0, g->stream);
+  const int s = bf_solve_ch(g, prm->dt * prm->M * prm->kappa, g->work_b, phi, o, S);
+  if (s < 0) return s;
+  int32_t clamped = 0;
+  HIPCHK(hipMemcpyAsync(&clamped, g->counter, sizeof(int32_t), hipMemcpyDeviceToHost, g->stream));
+  HIPCHK(hipStreamSynchronize(g->stream));
+  S->clamped = clamped;
+  return s;
+}
+
+int bf_adjoint_step(bf_grid* g, const bf_params* prm, const double* phi_n, const double* u,
+                    const double* v, const double* du, const double* dv,
+                    const double* lambda_in, double* lambda_out, double grads[2],
+                    const bf_solver_opts* o, bf_solve_stats* stats) {
+  TRY(check_grid(g));
+  if (!prm || !phi_n || !lambda_in || !lambda_out) return fail(BF_EINVAL, "null argument");
+  if ((u == nullptr) != (v == nullptr)) return fail(BF_EINVAL, "u and v must both be given or both be null");
+  if ((du == nullptr) != (dv == nullptr)) return fail(BF_EINVAL, "du and dv must both be given or both be null");
+  if (lambda_out == phi_n || (u && (lambda_out == u || lambda_out == v)) ||
+      (du && (lambda_out == du || lambda_out == dv)))
+    return fail(BF_EINVAL, "lambda_out must not alias phi_n, u, v, du or dv");
+  if (!(prm->Npoly > 0) || !(prm->phi_lo > 0) || !(prm->phi_hi < 1) || !(prm->phi_lo < prm->phi_hi))
+    return fail(BF_EINVAL, "bad Flory-Huggins parameters");
+  if (!g->work_e) TRY(dalloc(g, &g->work_e, g->npts));
+  hipStream_t st = g->stream;
+  // eta = A^{-T} lam = W A^{-1} W^{-1} lam: solve A e = W^{-1} lam, eta = W e
+  launch_wscale(g->n, lambda_in, g->work_b, true, st);
+  launch_fill(g->npts, g->work_e, 0.0, st);
+  const double dtM = prm->dt * prm->M;
+  const int s = bf_solve_ch(g, dtM * prm->kappa, g->work_b, g->work_e, o, stats);
+  if (s < 0) return s;
+  AdjCoef C;
+  C.dt = prm->dt;
+  C.dtM = dtM;
+  C.inv_npoly = 1.0 / prm->Npoly;
+  C.chi = prm->chi;
+  C.lo = prm->phi_lo;
+  C.hi = prm->phi_hi;
+  const int np = nparts_of(g);
+  launch_adjoint_rhs(g->n, g->work_e, phi_n, u, v, du, dv, lambda_out, C, g->partials, np, st);
+  launch_finalize(g->partials, np, g->scal, F_STORE, S_TMP, g->n, st);
+  launch_finalize(g->partials + np, np, g->scal, F_STORE, S_TMP + 1, g->n, st);
+  TRY(read_scalars(g, S_TMP + 2));
+  if (grads) {
+    grads[0] += dtM * g->h_scal[S_TMP];
+    if (du) grads[1] += -prm->dt * g->h_scal[S_TMP + 1];
+  }
+  return s;
 }
 
 int bf_vcycle(bf_grid* g, int32_t op, double c, const bf_solver_opts* o, const double* r,

@@ -431,6 +431,106 @@ __global__ void __launch_bounds__(kBlock) k_velocity(Geo G, const double* __rest
   }
 }
 
+// ------------------------------------------------------------------ advection, adjoint
+// D(phi; u, v)_ij * 2h = (phi u)_{i+1} - (phi u)_{i-1} + (phi v)_{j+1} - (phi v)_{j-1}
+// with phi even and v odd across the walls (phi v odd): wall rows fold the
+// ghost onto the first interior row.
+__device__ __forceinline__ double flux_div2h(const double* phi, const double* u, const double* v,
+                                             int i, int j, int n, int mask) {
+  const double* pr = phi + (int64_t)j * n;
+  const double* ur = u + (int64_t)j * n;
+  const int im = (i - 1) & mask, ip = (i + 1) & mask;
+  const double dx = pr[ip] * ur[ip] - pr[im] * ur[im];
+  double dy;
+  if (j == 0) {
+    dy = 2.0 * phi[(int64_t)n + i] * v[(int64_t)n + i];
+  } else if (j == n) {
+    const int64_t o = (int64_t)(n - 1) * n + i;
+    dy = -2.0 * phi[o] * v[o];
+  } else {
+    const int64_t op = (int64_t)(j + 1) * n + i, om = (int64_t)(j - 1) * n + i;
+    dy = phi[op] * v[op] - phi[om] * v[om];
+  }
+  return dx + dy;
+}
+
+// b -= dt D(phi; u, v)   (scale = dt / (2h))
+__global__ void __launch_bounds__(kBlock) k_advect_sub(Geo G, const double* __restrict__ phi,
+                                                       const double* __restrict__ u,
+                                                       const double* __restrict__ v,
+                                                       double* __restrict__ b, double scale) {
+  GRID_STRIDE(idx, G.npts) {
+    const int i = (int)(idx & G.mask), j = (int)(idx >> G.log2n);
+    b[idx] -= scale * flux_div2h(phi, u, v, i, j, G.n, G.mask);
+  }
+}
+
+// y = x * w_j (inverse = 0) or x / w_j (inverse = 1), w = trapezoid row weights.
+__global__ void __launch_bounds__(kBlock) k_wscale(Geo G, const double* __restrict__ x,
+                                                   double* __restrict__ y, int inverse) {
+  GRID_STRIDE(idx, G.npts) {
+    const int j = (int)(idx >> G.log2n);
+    const double w = row_weight(j, G.n);
+    y[idx] = inverse ? x[idx] / w : x[idx] * w;
+  }
+}
+
+// Adjoint right-hand side of one step, from e = W^{-1} eta (the solution of
+// A e = W^{-1} lam_next, so eta = W e = A^{-T} lam_next):
+//   lam = eta + dtM mu'(phi) (L^T eta) - dt D^T eta,  L^T eta = W L e,
+//   partials[b]          of sum (L^T eta)(1 - 2 clamp(phi))   (dJ/dchi / dtM)
+//   partials[nparts + b] of sum eta D(phi; du, dv)             (dJ/dU / -dt)
+// D^T eta = u (eta_{i-1} - eta_{i+1})/(2h) + v (em - ep) with
+//   em = eta_{j-1}/(2h) for j >= 2, eta_0/h for j = 1, 0 for j = 0;
+//   ep = eta_{j+1}/(2h) for j <= n-2, eta_n/h for j = n-1, 0 for j = n.
+__global__ void __launch_bounds__(kBlock) k_adjoint_rhs(Geo G, const double* __restrict__ e,
+                                                        const double* __restrict__ phi,
+                                                        const double* __restrict__ u,
+                                                        const double* __restrict__ v,
+                                                        const double* __restrict__ du,
+                                                        const double* __restrict__ dv,
+                                                        double* __restrict__ lam, AdjCoef C,
+                                                        double* __restrict__ partials) {
+  double a1 = 0.0, a2 = 0.0;
+  const int n = G.n;
+  const double n2 = (double)n * (double)n, inv2h = 0.5 * (double)n;
+  GRID_STRIDE(idx, G.npts) {
+    const int i = (int)(idx & G.mask), j = (int)(idx >> G.log2n);
+    const double wj = row_weight(j, n);
+    const double* er = e + (int64_t)j * n;
+    const int im = (i - 1) & G.mask, ip = (i + 1) & G.mask;
+    const double ec = er[i];
+    const double le = n2 * ((er[im] + er[ip]) + (e[(int64_t)refl(j - 1, n) * n + i] +
+                                                 e[(int64_t)refl(j + 1, n) * n + i]) -
+                            4.0 * ec);
+    const double lt = wj * le;
+    const double eta = wj * ec;
+    const double p = phi[idx];
+    const bool active = p >= C.lo && p <= C.hi;
+    const double ph = p < C.lo ? C.lo : (p > C.hi ? C.hi : p);
+    const double mup = active ? (C.inv_npoly / ph + 1.0 / (1.0 - ph) - 2.0 * C.chi) : 0.0;
+    double out = eta + C.dtM * mup * lt;
+    if (u) {
+      const double dxt = u[idx] * wj * (er[im] - er[ip]) * inv2h;
+      double em = 0.0, epp = 0.0;
+      if (j >= 2) em = row_weight(j - 1, n) * e[idx - n] * inv2h;
+      else if (j == 1) em = row_weight(0, n) * e[i] * 2.0 * inv2h;
+      if (j <= n - 2) epp = row_weight(j + 1, n) * e[idx + n] * inv2h;
+      else if (j == n - 1) epp = row_weight(n, n) * e[(int64_t)n * n + i] * 2.0 * inv2h;
+      out -= C.dt * (dxt + v[idx] * (em - epp));
+    }
+    lam[idx] = out;
+    a1 += lt * (1.0 - 2.0 * ph);
+    if (du) a2 += eta * flux_div2h(phi, du, dv, i, j, n, G.mask) * inv2h;
+  }
+  const double s1 = block_sum(a1);
+  const double s2 = block_sum(a2);
+  if (threadIdx.x == 0) {
+    partials[blockIdx.x] = s1;
+    partials[gridDim.x + blockIdx.x] = s2;
+  }
+}
+
 // ------------------------------------------------------------------ GMRES pieces
 constexpr int kMdotGroup = 8;
 
@@ -723,6 +823,24 @@ void launch_velocity(int n, const double* p, const double* us, const double* vs,
                      double* v, double scale, hipStream_t st) {
   const Geo G = make_geo(n);
   LAUNCH(k_velocity, ew_blocks(G.npts), st, G, p, us, vs, u, v, scale);
+}
+
+void launch_advect_sub(int n, const double* phi, const double* u, const double* v, double* b,
+                       double dt, hipStream_t st) {
+  const Geo G = make_geo(n);
+  LAUNCH(k_advect_sub, ew_blocks(G.npts), st, G, phi, u, v, b, dt * 0.5 * (double)n);
+}
+
+void launch_wscale(int n, const double* x, double* y, bool inverse, hipStream_t st) {
+  const Geo G = make_geo(n);
+  LAUNCH(k_wscale, ew_blocks(G.npts), st, G, x, y, inverse ? 1 : 0);
+}
+
+void launch_adjoint_rhs(int n, const double* e, const double* phi, const double* u,
+                        const double* v, const double* du, const double* dv, double* lam,
+                        const AdjCoef& C, double* partials, int nparts, hipStream_t st) {
+  const Geo G = make_geo(n);
+  LAUNCH(k_adjoint_rhs, nparts, st, G, e, phi, u, v, du, dv, lam, C, partials);
 }
 
 void launch_mdot(int n, const double* V, int m, const double* w, double* partials, int nparts,

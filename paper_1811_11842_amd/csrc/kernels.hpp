@@ -171,6 +171,22 @@ void launch_divergence(int n, const double* u, const double* v, double* rhs, dou
 void launch_velocity(int n, const double* p, const double* us, const double* vs, double* u,
                      double* v, double scale, hipStream_t st);
 
+// Advection and adjoint pieces.
+// b -= dt D(phi; u, v), D = div_h(phi u, phi v), phi even and v odd across the walls.
+void launch_advect_sub(int n, const double* phi, const double* u, const double* v, double* b,
+                       double dt, hipStream_t st);
+// y = x w_j (inverse false) or x / w_j (inverse true); trapezoid row weights.
+void launch_wscale(int n, const double* x, double* y, bool inverse, hipStream_t st);
+struct AdjCoef {
+  double dt, dtM, inv_npoly, chi, lo, hi;
+};
+// lam = eta + dtM mu'(phi) L^T eta - dt D^T eta from e = W^{-1} eta (u, v may be
+// null: no advection; du, dv may be null: no U term); partials[0..nparts) of
+// sum L^T eta (1 - 2 clamp(phi)), partials[nparts..2 nparts) of sum eta D(phi; du, dv).
+void launch_adjoint_rhs(int n, const double* e, const double* phi, const double* u,
+                        const double* v, const double* du, const double* dv, double* lam,
+                        const AdjCoef& C, double* partials, int nparts, hipStream_t st);
+
 // GMRES pieces (weighted inner products).
 // partials[k * nparts + b] of <V_k, w>_W for k < m (V: m vectors of npts each).
 void launch_mdot(int n, const double* V, int m, const double* w, double* partials, int nparts,

@@ -366,8 +366,8 @@ def test_bad_arguments_rejected(dev):
         g.solve_ch(C_CH, x, g.field(0.0), bf.default_opts(bf.OP_CH, degree=9))
     with pytest.raises(ValueError):
         g.apply(bf.OP_LAP, 0.0, torch.zeros(10, 10, dtype=torch.float64, device=dev))
-    with pytest.raises(bf.BiofilmError, match="EUNSUPPORTED"):
-        g.adjoint_step(bf.make_params(), x, x, g.field())
+    with pytest.raises(bf.BiofilmError, match="EINVAL"):
+        g.adjoint_step(bf.make_params(), x, g.field(0.0), x)   # lambda_out aliases phi_n
 
 
 def test_solves_are_deterministic(dev):

@@ -57,7 +57,9 @@ def test_invalid_grid_arguments_rejected_before_any_device_work():
     d = bf.GridDesc(64, 7, None)
     assert L.bf_grid_create(ctypes.byref(d), ctypes.byref(h)) == bf.EUNSUPPORTED
     assert L.bf_apply(None, 0, 0.0, None, None) == bf.EINVAL
-    assert L.bf_adjoint_step(None, None, None, None, None) == bf.EUNSUPPORTED
+    assert L.bf_adjoint_step(None, None, None, None, None, None, None, None, None, None, None,
+                             None) == bf.EINVAL
+    assert L.bf_step_ch(None, None, None, None, None, None, None) == bf.EINVAL
 
 
 def test_missing_library_fails_loudly(tmp_path, monkeypatch):

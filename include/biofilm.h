@@ -207,6 +207,44 @@ int bf_adjoint_step(bf_grid* g, const bf_params* prm, const double* phi_n,
                     const double* dv, const double* lambda_in, double* lambda_out,
                     double grads[2], const bf_solver_opts* o, bf_solve_stats* stats);
 
+/* ------------------------------------------------------------ ensemble
+ * Many independent instances of bf_step, of uneven sizes and with their own
+ * parameters (the batched-ensemble configuration: seeded sizes in
+ * {128, 256, 512, 1024}, per-instance chi, dt, protrusion radius and noise).
+ * Instances of equal size form a class; every operation on a class is one
+ * launch over all its instances with per-instance coefficients and
+ * convergence masks; classes run concurrently on streams of their own.  */
+typedef struct bf_ensemble bf_ensemble;
+
+/* n[count]: intervals per side of each instance, powers of two in
+ * [128, 8192].  stream: hipStream_t the caller orders work on (0 = default).
+ * Allocates all workspaces (per class: fields, multigrid hierarchy, Krylov
+ * vectors) and tunes the stencil tile height per class by timing. */
+int bf_ensemble_create(const int32_t* n, int32_t count, void* stream, bf_ensemble** out);
+int bf_ensemble_destroy(bf_ensemble* e);
+
+/* Packed field layout: every field of the ensemble (phi, u*, v*, p, u, v) is
+ * one caller-owned device array of *total doubles; instance i occupies the
+ * (n_i+1) x n_i row-major block starting at offsets[i] (host arrays). */
+int bf_ensemble_layout(const bf_ensemble* e, int64_t* offsets, int64_t* total);
+
+/* Size classes: their sizes, instance counts and tuned tile heights (host
+ * arrays of at least as many entries as classes, each may be NULL). */
+int bf_ensemble_info(const bf_ensemble* e, int32_t* nclasses, int32_t* class_n,
+                     int32_t* class_count, int32_t* class_rpw);
+
+/* One step of every instance (bf_step semantics: phi in/out, p out, u, v out
+ * or both NULL) with the parameters prm[i].  ch / pr: only rtol and maxit may
+ * differ from the defaults (float64 CG with the default multigrid; others
+ * return BF_EUNSUPPORTED); no refinement restarts.  stats[2 i] / stats[2 i + 1]
+ * receive the Cahn-Hilliard / pressure solve of instance i.  ms (host, may be
+ * NULL) receives the wall time of the call.  Synchronous.  Returns the worst
+ * soft status or a negative error. */
+int bf_ensemble_step(bf_ensemble* e, const bf_params* prm, double* phi, const double* ustar,
+                     const double* vstar, double* p, double* u, double* v,
+                     const bf_solver_opts* ch, const bf_solver_opts* pr, bf_solve_stats* stats,
+                     double* ms);
+
 /* z = V(r): one multigrid V-cycle (the preconditioner of the solves) of the
  * operator op with the options o (smoother, degree, ratio, omega), from a
  * zero initial guess.  Asynchronous.  Used to check the cycle itself. */

@@ -122,6 +122,20 @@ def lib():
             "bf_residual": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_double, _P, _P, _P,
                                            ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                            ctypes.POINTER(ctypes.c_double)]),
+            "bf_ensemble_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int32), ctypes.c_int32,
+                                                  _P, ctypes.POINTER(_P)]),
+            "bf_ensemble_destroy": (ctypes.c_int, [_P]),
+            "bf_ensemble_layout": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64),
+                                                  ctypes.POINTER(ctypes.c_int64)]),
+            "bf_ensemble_info": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32),
+                                                ctypes.POINTER(ctypes.c_int32),
+                                                ctypes.POINTER(ctypes.c_int32),
+                                                ctypes.POINTER(ctypes.c_int32)]),
+            "bf_ensemble_step": (ctypes.c_int, [_P, ctypes.POINTER(Params), _P, _P, _P, _P, _P, _P,
+                                                ctypes.POINTER(SolverOpts),
+                                                ctypes.POINTER(SolverOpts),
+                                                ctypes.POINTER(SolveStats),
+                                                ctypes.POINTER(ctypes.c_double)]),
             "bf_last_error": (ctypes.c_char_p, []),
         }
         for name, (res, args) in sig.items():
@@ -344,3 +358,91 @@ class Grid:
 
 
 grid_create = Grid
+
+
+class Ensemble:
+    """Handle of an ensemble of independent grids (bf_ensemble_create).
+
+    Fields are packed: one float64 device tensor of `total` elements per
+    quantity, instance i in the (n_i+1) x n_i block at offsets[i] (`view`)."""
+
+    def __init__(self, sizes, stream: torch.cuda.Stream | None = None):
+        L = lib()
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.sizes = [int(n) for n in sizes]
+        self.count = len(self.sizes)
+        self.stream = stream
+        self.device = stream.device
+        arr = (ctypes.c_int32 * self.count)(*self.sizes)
+        h = _P()
+        with torch.cuda.device(self.device):
+            _check(L.bf_ensemble_create(arr, self.count, stream.cuda_stream, ctypes.byref(h)))
+        self._h = h
+        offs = (ctypes.c_int64 * self.count)()
+        tot = ctypes.c_int64()
+        _check(L.bf_ensemble_layout(self._h, offs, ctypes.byref(tot)))
+        self.offsets = list(offs)
+        self.total = tot.value
+
+    def info(self):
+        """[(n, instances, tile height)] per size class."""
+        nc = ctypes.c_int32()
+        cn = (ctypes.c_int32 * self.count)()
+        cc = (ctypes.c_int32 * self.count)()
+        cr = (ctypes.c_int32 * self.count)()
+        _check(lib().bf_ensemble_info(self._h, ctypes.byref(nc), cn, cc, cr))
+        return [(cn[k], cc[k], cr[k]) for k in range(nc.value)]
+
+    def field(self, fill=None):
+        t = torch.empty(self.total, dtype=torch.float64, device=self.device)
+        if fill is not None:
+            t.fill_(fill)
+        return t
+
+    def view(self, t, i):
+        n = self.sizes[i]
+        o = self.offsets[i]
+        return t[o:o + (n + 1) * n].view(n + 1, n)
+
+    def _ptr(self, t, name):
+        if t is None:
+            return None
+        if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()
+                and t.numel() == self.total):
+            raise ValueError(f"{name}: expected a contiguous float64 CUDA tensor of "
+                             f"{self.total} elements")
+        return ctypes.c_void_p(t.data_ptr())
+
+    def step(self, params, phi, ustar, vstar, p, u=None, v=None, ch=None, pr=None):
+        """One step of every instance; params: list of Params (one per instance).
+        Returns ([(ch_stats, p_stats)] per instance, wall ms)."""
+        if len(params) != self.count:
+            raise ValueError("one Params per instance")
+        prm = (Params * self.count)(*params)
+        st = (SolveStats * (2 * self.count))()
+        ms = ctypes.c_double()
+        _check(lib().bf_ensemble_step(self._h, prm, self._ptr(phi, "phi"),
+                                      self._ptr(ustar, "ustar"), self._ptr(vstar, "vstar"),
+                                      self._ptr(p, "p"), self._ptr(u, "u"), self._ptr(v, "v"),
+                                      ctypes.byref(ch) if ch is not None else None,
+                                      ctypes.byref(pr) if pr is not None else None, st,
+                                      ctypes.byref(ms)))
+        return [(st[2 * i], st[2 * i + 1]) for i in range(self.count)], ms.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().bf_ensemble_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbiofilm.so")
-SOURCES = ["kernels.hip", "stream.hip", "transfer.hip", "tail.hip", "api.hip"]
+SOURCES = ["kernels.hip", "stream.hip", "transfer.hip", "tail.hip", "api.hip", "ensemble.hip"]
 ARCH = os.environ.get("BF_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

@@ -230,9 +230,8 @@ std::vector<double> coarse_matrix(int op, double coef) {
 //  CH : G = A^{-1}
 //  LAP: G = top-left block of [[L, 1], [w^T, 0]]^{-1}; G b solves L p = b - wmean(b)
 //       with w^T p = 0 (the weighted-mean constraint on the null space).
-int upload_coarse(bf_grid* g, int op, double c) {
+int coarse_operator(int op, double c, std::vector<double>& G) {
   const int n = kCoarseN, size = kCoarseSize;
-  std::vector<double> G;
   if (op == BF_OP_CH) {
     G = coarse_matrix(op, c * std::pow((double)n, 4));
     if (!invert(G, size)) return fail(BF_EINVAL, "coarse Cahn-Hilliard matrix is singular");
@@ -251,6 +250,13 @@ int upload_coarse(bf_grid* g, int op, double c) {
     for (int k = 0; k < size; ++k)
       for (int l = 0; l < size; ++l) G[k * size + l] = B[k * bs + l];
   }
+  return BF_OK;
+}
+
+int upload_coarse(bf_grid* g, int op, double c) {
+  const int size = kCoarseSize;
+  std::vector<double> G;
+  TRY(coarse_operator(op, c, G));
   double* dst = op == BF_OP_CH ? g->coarse_ch : g->coarse_lap;
   HIPCHK(hipMemcpyAsync(dst, G.data(), sizeof(double) * size * size, hipMemcpyHostToDevice,
                         g->stream));
@@ -906,6 +912,26 @@ int check_grid(const bf_grid* g) {
 }
 
 }  // namespace
+
+// Host helpers shared with the ensemble driver (host.hpp).
+namespace bf {
+int host_fail(int code, const char* msg) { return fail(code, "%s", msg); }
+OpDesc host_level_op(int op, int n, double c) { return level_op(op, n, c); }
+int host_smoother(int op, int n, double c, const bf_solver_opts& o, double* a, double* g) {
+  const Smoother S = make_smoother(op, n, c, o);
+  for (int k = 0; k < 8; ++k) {
+    a[k] = S.a[k];
+    g[k] = S.g[k];
+  }
+  return S.degree;
+}
+int host_coarse_operator(int op, double c, std::vector<double>& G) {
+  return coarse_operator(op, c, G);
+}
+double host_column_sq(const OpDesc& A) { return column_sq(A); }
+void host_default_opts(int op, bf_solver_opts* o) { default_opts(op, o); }
+int host_check_opts(const bf_solver_opts& o) { return check_opts(o); }
+}  // namespace bf
 
 // ====================================================================== C ABI
 extern "C" {

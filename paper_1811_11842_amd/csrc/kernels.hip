@@ -34,6 +34,41 @@ __device__ __forceinline__ double residual_dd_at(const double* __restrict__ x, d
   return residual_dd_vals<OP>(gather<OP>(x, i, j, n, mask), bval, coef);
 }
 
+// Batches on the one-thread-per-node kernels: blockIdx.y is the instance,
+// fields are s0 (coarse fields of transfers: s1) elements apart, and coef
+// (if set) holds each instance's coefficient record (see BatchCtx).
+struct BArgs {
+  int64_t s0, s1;
+  const double* coef;
+  int ia, ig, ia0;
+};
+
+static BArgs batch_args() {
+  const BatchCtx& c = g_batch;
+  BArgs B;
+  B.s0 = c.count > 1 ? c.stride : 0;
+  B.s1 = c.count > 1 ? c.stride_c : 0;
+  B.coef = c.coef;
+  B.ia = c.ia;
+  B.ig = c.ig;
+  B.ia0 = c.ia0;
+  return B;
+}
+static int batch_count() { return g_batch.count > 1 ? g_batch.count : 1; }
+
+__device__ __forceinline__ void inst_coef(const BArgs& B, OpDesc& A, double& a, double& g,
+                                          double& a0) {
+  if (B.coef) {
+    const double* rc = B.coef + (int64_t)blockIdx.y * kCoefStride;
+    A.coef = rc[0];
+    A.dinv_int = rc[1];
+    A.dinv_edge = rc[2];
+    a = rc[3 + B.ia];
+    g = rc[11 + B.ig];
+    a0 = rc[3 + B.ia0];
+  }
+}
+
 template <int OP, typename T = double>
 __device__ __forceinline__ T dinv_at(const OpDesc& A, int j) {
   if (OP == 0) return T(A.dinv_int);
@@ -78,8 +113,16 @@ __global__ void __launch_bounds__(kBlock) k_apply_dot(OpDesc A, Geo G, const dou
 template <int OP, typename T>
 __global__ void __launch_bounds__(kBlock) k_residual(OpDesc A, Geo G, const T* __restrict__ x,
                                                      const T* __restrict__ b, T* __restrict__ r,
-                                                     double* __restrict__ partials) {
+                                                     double* __restrict__ partials, BArgs Bt) {
   double acc = 0.0;
+  {
+    double a_, g_, a0_;
+    inst_coef(Bt, A, a_, g_, a0_);
+    const int64_t o = (int64_t)blockIdx.y * Bt.s0;
+    if (x) x += o;
+    b += o;
+    r += o;
+  }
   GRID_STRIDE(idx, G.npts) {
     const int i = (int)(idx & G.mask), j = (int)(idx >> G.log2n);
     T v = b[idx];
@@ -92,7 +135,7 @@ __global__ void __launch_bounds__(kBlock) k_residual(OpDesc A, Geo G, const T* _
   }
   if (partials) {
     const double t = block_sum(acc);
-    if (threadIdx.x == 0) partials[blockIdx.x] = t;
+    if (threadIdx.x == 0) partials[blockIdx.y * gridDim.x + blockIdx.x] = t;
   }
 }
 
@@ -126,7 +169,16 @@ __global__ void __launch_bounds__(kBlock) k_residual_dd(OpDesc A, Geo G,
 template <int OP, typename T>
 __global__ void __launch_bounds__(kBlock) k_smooth(OpDesc A, Geo G, const T* __restrict__ x,
                                                    const T* xprev, const T* __restrict__ b,
-                                                   T* xout, double a, double g) {
+                                                   T* xout, double a, double g, BArgs Bt) {
+  {
+    double a0_;
+    inst_coef(Bt, A, a, g, a0_);
+    const int64_t o = (int64_t)blockIdx.y * Bt.s0;
+    x += o;
+    if (xprev) xprev += o;
+    b += o;
+    xout += o;
+  }
   const T ta = T(a), tg = T(g), coef = T(A.coef);
   GRID_STRIDE(idx, G.npts) {
     const int i = (int)(idx & G.mask), j = (int)(idx >> G.log2n);
@@ -139,7 +191,15 @@ __global__ void __launch_bounds__(kBlock) k_smooth(OpDesc A, Geo G, const T* __r
 
 template <int OP, typename T>
 __global__ void __launch_bounds__(kBlock) k_smooth0(OpDesc A, Geo G, const T* __restrict__ b,
-                                                    T* __restrict__ xout, double a) {
+                                                    T* __restrict__ xout, double a, BArgs Bt) {
+  {
+    double g_, a0_;
+    inst_coef(Bt, A, a, g_, a0_);
+    if (Bt.coef) a = a0_;  // the first sweep takes a[ia0]
+    const int64_t o = (int64_t)blockIdx.y * Bt.s0;
+    b += o;
+    xout += o;
+  }
   const T ta = T(a);
   GRID_STRIDE(idx, G.npts) {
     const int j = (int)(idx >> G.log2n);
@@ -160,7 +220,9 @@ __global__ void __launch_bounds__(kBlock) k_jacobi_pc(OpDesc A, Geo G, const dou
 // coarse = R fine and fine += P coarse (one thread per node; small levels).
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_restrict(Geo F, Geo C, const T* __restrict__ fine,
-                                                     T* __restrict__ coarse) {
+                                                     T* __restrict__ coarse, BArgs Bt) {
+  fine += (int64_t)blockIdx.y * Bt.s0;
+  coarse += (int64_t)blockIdx.y * Bt.s1;
   GRID_STRIDE(idx, C.npts) {
     const int I = (int)(idx & C.mask), J = (int)(idx >> C.log2n);
     coarse[idx] = restrict_at(fine, F.n, F.mask, I, J);
@@ -169,7 +231,9 @@ __global__ void __launch_bounds__(kBlock) k_restrict(Geo F, Geo C, const T* __re
 
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_prolong_add(Geo F, Geo C, const T* __restrict__ coarse,
-                                                        T* __restrict__ fine) {
+                                                        T* __restrict__ fine, BArgs Bt) {
+  coarse += (int64_t)blockIdx.y * Bt.s1;
+  fine += (int64_t)blockIdx.y * Bt.s0;
   GRID_STRIDE(idx, F.npts) {
     const int i = (int)(idx & F.mask), j = (int)(idx >> F.log2n);
     fine[idx] += prolong_at(coarse, C.n, C.mask, i, j);
@@ -602,6 +666,9 @@ __global__ void __launch_bounds__(kBlock) k_scale(Geo G, const double* __restric
 
 // ------------------------------------------------------------------ launchers
 #define LAUNCH(kern, blocks, st, ...) hipLaunchKernelGGL(kern, dim3(blocks), dim3(kBlock), 0, st, __VA_ARGS__)
+// Launch over the instances of the current batch (grid.y = instance).
+#define LAUNCH_B(kern, blocks, st, ...) \
+  hipLaunchKernelGGL(kern, dim3(blocks, batch_count()), dim3(kBlock), 0, st, __VA_ARGS__)
 
 void launch_apply(const OpDesc& A, const double* x, double* y, hipStream_t st) {
   if (stream_ok(A.n)) {
@@ -640,10 +707,10 @@ int launch_residual(const OpDesc& A, const T* x, const T* b, T* r, double* parti
   const Geo G = make_geo(A.n);
   const int blocks = partials ? nparts : ew_blocks(G.npts);
   if (A.op == 0)
-    LAUNCH((k_residual<0, T>), blocks, st, A, G, x, b, r, partials);
+    LAUNCH_B((k_residual<0, T>), blocks, st, A, G, x, b, r, partials, batch_args());
   else
-    LAUNCH((k_residual<1, T>), blocks, st, A, G, x, b, r, partials);
-  return blocks;
+    LAUNCH_B((k_residual<1, T>), blocks, st, A, G, x, b, r, partials, batch_args());
+  return blocks * batch_count();
 }
 template int launch_residual<double>(const OpDesc&, const double*, const double*, double*,
                                      double*, int, hipStream_t);
@@ -670,9 +737,11 @@ void launch_smooth(const OpDesc& A, const T* x, const T* xprev, const T* b, T* x
   }
   const Geo G = make_geo(A.n);
   if (A.op == 0)
-    LAUNCH((k_smooth<0, T>), ew_blocks(G.npts), st, A, G, x, xprev, b, xout, a, g);
+    LAUNCH_B((k_smooth<0, T>), ew_blocks(G.npts), st, A, G, x, xprev, b, xout, a, g,
+             batch_args());
   else
-    LAUNCH((k_smooth<1, T>), ew_blocks(G.npts), st, A, G, x, xprev, b, xout, a, g);
+    LAUNCH_B((k_smooth<1, T>), ew_blocks(G.npts), st, A, G, x, xprev, b, xout, a, g,
+             batch_args());
 }
 template void launch_smooth<double>(const OpDesc&, const double*, const double*, const double*,
                                     double*, double, double, hipStream_t);
@@ -683,9 +752,9 @@ template <typename T>
 void launch_smooth0(const OpDesc& A, const T* b, T* xout, double a, hipStream_t st) {
   const Geo G = make_geo(A.n);
   if (A.op == 0)
-    LAUNCH((k_smooth0<0, T>), ew_blocks(G.npts), st, A, G, b, xout, a);
+    LAUNCH_B((k_smooth0<0, T>), ew_blocks(G.npts), st, A, G, b, xout, a, batch_args());
   else
-    LAUNCH((k_smooth0<1, T>), ew_blocks(G.npts), st, A, G, b, xout, a);
+    LAUNCH_B((k_smooth0<1, T>), ew_blocks(G.npts), st, A, G, b, xout, a, batch_args());
 }
 template void launch_smooth0<double>(const OpDesc&, const double*, double*, double, hipStream_t);
 template void launch_smooth0<float>(const OpDesc&, const float*, float*, double, hipStream_t);
@@ -705,7 +774,7 @@ void launch_restrict(int nf, const T* fine, T* coarse, hipStream_t st) {
     return;
   }
   const Geo F = make_geo(nf), C = make_geo(nf / 2);
-  LAUNCH((k_restrict<T>), ew_blocks(C.npts), st, F, C, fine, coarse);
+  LAUNCH_B((k_restrict<T>), ew_blocks(C.npts), st, F, C, fine, coarse, batch_args());
 }
 template void launch_restrict<double>(int, const double*, double*, hipStream_t);
 template void launch_restrict<float>(int, const float*, float*, hipStream_t);
@@ -717,7 +786,7 @@ void launch_prolong_add(int nf, const T* coarse, T* fine, hipStream_t st) {
     return;
   }
   const Geo F = make_geo(nf), C = make_geo(nf / 2);
-  LAUNCH((k_prolong_add<T>), ew_blocks(F.npts), st, F, C, coarse, fine);
+  LAUNCH_B((k_prolong_add<T>), ew_blocks(F.npts), st, F, C, coarse, fine, batch_args());
 }
 template void launch_prolong_add<double>(int, const double*, double*, hipStream_t);
 template void launch_prolong_add<float>(int, const float*, float*, hipStream_t);

@@ -19,6 +19,25 @@ struct OpDesc {
   double dinv_edge;// 1 / diag on rows 1 and n-1
 };
 
+// Batches of equal-sized instances (the ensemble driver).  While a thread's
+// batch context has count > 1, the launchers below that support batches run
+// every field operation on `count` instances stored `stride` elements apart
+// (coarse fields of transfers: `stride_c`), with per-instance coefficient
+// records (`coef`, kCoefStride doubles each: coef, dinv_int, dinv_edge,
+// a[8], g[8]; a = a[ia], g = g[ig], a0 = a[ia0] for smoothing sweeps) and
+// per-instance device scalars kNumSlots apart; reductions return the
+// partial count of all instances (instance i owns the i-th equal share).
+constexpr int kCoefStride = 20;
+struct BatchCtx {
+  int count = 1;
+  int64_t stride = 0, stride_c = 0;
+  const double* coef = nullptr;
+  int ia = 0, ig = 0, ia0 = 0;
+  const int* active = nullptr;
+  int rpw = 0;  // stencil tile height for this batch (0: default)
+};
+extern thread_local BatchCtx g_batch;
+
 // Launch shape of the tiled stencil kernels (stream.hip), used for grid
 // levels with n >= 64 V (V = 2 float64 or 4 float32 values per lane);
 // smaller levels use the one-thread-per-node kernels.
@@ -101,6 +120,10 @@ struct TailArgs {
 };
 template <typename T>
 void launch_tail(int op, const TailArgs& P, const T* b_in, T* x_out, hipStream_t st);
+// Batched tail: args (device, count entries) per instance; fields sin / sout apart.
+template <typename T>
+void launch_tail_batch(int op, const TailArgs* args, int count, const T* b_in, T* x_out,
+                       int64_t sin, int64_t sout, hipStream_t st);
 
 // The launchers that write reduction partials return how many they wrote
 // (the count the matching launch_finalize must reduce); `nparts` is the

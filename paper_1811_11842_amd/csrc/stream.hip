@@ -77,6 +77,17 @@ struct StreamArgs {
   const double* scal;  // E_CG_P: device scalars (alpha, beta)
   const double* q;     // E_SMOOTH_DOT2: second vector of the extra dot
   int first;           // E_CG_P: first step after a (re)start: p' = z, no x update
+  // Batch of equal-sized instances stored bstride elements apart: workgroups
+  // bpi * i .. bpi * (i+1) - 1 work on instance i (their partials are the
+  // instance's), device scalars are kNumSlots apart.  bcoef (optional): per
+  // instance kCoefStride doubles {coef, dinv_int, dinv_edge, a[8], g[8]}
+  // replacing A's coefficients and a = a[ia], g = g[ig], a0 = a[ia0].
+  // active (optional): instances with active[i] == 0 are skipped.
+  int batch, bpi;
+  int64_t bstride;
+  const double* bcoef;
+  int ia, ig, ia0;
+  const int* active;
 };
 
 // Lane i receives the value of lane i-1 (DPP wave_shr:1) or of lane i+1
@@ -133,22 +144,42 @@ __global__ void __launch_bounds__(kStreamTPB) k_stream(StreamArgs<T, TO> P) {
   const int n = P.G.n, mask = P.G.mask;
   const int lane = threadIdx.x & 63;
   const bool hl = lane == 0, hr = lane == 63;
-  const T coef = T(P.A.coef);
-  const T ca = T(P.a), cg = T(P.g), ca0 = T(P.a0);
+  const int inst = blockIdx.x / P.bpi;
+  const int lblock = blockIdx.x - inst * P.bpi;
+  const int64_t ioff = (int64_t)inst * P.bstride;
+  const T* const Xp = P.x + ioff;
+  const T* const Bp = P.b ? P.b + ioff : nullptr;
+  const T* const XPp = P.xprev ? P.xprev + ioff : nullptr;
+  TO* const Op = P.out + ioff;
+  double* const O2p = P.out2 ? P.out2 + ioff : nullptr;
+  double* const XUp = P.xu ? P.xu + ioff : nullptr;
+  const double* const Qp = P.q ? P.q + ioff : nullptr;
+  double cf = P.A.coef, di = P.A.dinv_int, de = P.A.dinv_edge;
+  double pa = P.a, pg = P.g, pa0 = P.a0;
+  if (P.bcoef) {
+    const double* rc = P.bcoef + (int64_t)inst * kCoefStride;
+    cf = rc[0];
+    di = rc[1];
+    de = rc[2];
+    pa = rc[3 + P.ia];
+    pg = rc[11 + P.ig];
+    pa0 = rc[3 + P.ia0];
+  }
+  const T coef = T(cf);
+  const T ca = T(pa), cg = T(pg), ca0 = T(pa0);
   double beta = 0.0, alpha_prev = 0.0;
   if constexpr (EPI == E_CG_P) {
     if (!P.first) {
-      beta = P.scal[S_BETA];
-      alpha_prev = P.scal[S_ALPHA];
+      beta = P.scal[(int64_t)inst * kNumSlots + S_BETA];
+      alpha_prev = P.scal[(int64_t)inst * kNumSlots + S_ALPHA];
     }
   }
-  auto dinv_row = [&](int jr) -> T {
-    return T((OP == 1 && (jr == 1 || jr == n - 1)) ? P.A.dinv_edge : P.A.dinv_int);
-  };
+  auto dinv_row = [&](int jr) -> T { return T((OP == 1 && (jr == 1 || jr == n - 1)) ? de : di); };
   double acc = 0.0, acc2 = 0.0;
+  const bool skip = P.active && !P.active[inst];
 
   const int wpb = kStreamTPB / 64;
-  for (int t = blockIdx.x * wpb + (threadIdx.x >> 6); t < P.tiles; t += gridDim.x * wpb) {
+  for (int t = lblock * wpb + (threadIdx.x >> 6); !skip && t < P.tiles; t += P.bpi * wpb) {
     const int rg = t / P.wstrips;
     const int strip = t - rg * P.wstrips;
     const int j0 = rg * RPW;
@@ -183,11 +214,11 @@ __global__ void __launch_bounds__(kStreamTPB) k_stream(StreamArgs<T, TO> P) {
         continue;
       }
       const int jr = refl(jj, n);
-      load_row(P.x, jr, halo, xr[k]);
+      load_row(Xp, jr, halo, xr[k]);
       if constexpr (EPI == E_CG_P) {
         if (!P.first) {
           XRow<T, V> po;
-          load_row(P.xprev, jr, halo, po);
+          load_row(XPp, jr, halo, po);
 #pragma unroll
           for (int i = 0; i < V; ++i) xr[k].o[i] += beta * po.o[i];
           xr[k].h0 += beta * po.h0;
@@ -276,9 +307,9 @@ __global__ void __launch_bounds__(kStreamTPB) k_stream(StreamArgs<T, TO> P) {
       const int64_t o = (int64_t)j * n + c;
       const double wgt = row_weight(j, n);
       VT bcur{}, pcur{};
-      if constexpr (NEEDB) bcur = *reinterpret_cast<const VT*>(P.b + o);
+      if constexpr (NEEDB) bcur = *reinterpret_cast<const VT*>(Bp + o);
       if constexpr (NEEDP) {
-        if (P.xprev) pcur = *reinterpret_cast<const VT*>(P.xprev + o);
+        if (XPp) pcur = *reinterpret_cast<const VT*>(XPp + o);
       }
       VO res;
       if constexpr (EPI == E_APPLY || EPI == E_APPLY_DOT) {
@@ -303,7 +334,7 @@ __global__ void __launch_bounds__(kStreamTPB) k_stream(StreamArgs<T, TO> P) {
           T prev = T(0);
           if (EPI == E_SMOOTH_PB)
             prev = d0 * bcur.v[i];
-          else if (EPI != E_SMOOTH_XB && P.xprev)
+          else if (EPI != E_SMOOTH_XB && XPp)
             prev = pcur.v[i];
           const T xn =
               nb[i].c + ad * (bcur.v[i] - apply_vals<OP>(nb[i], coef)) + cg * (nb[i].c - prev);
@@ -312,7 +343,7 @@ __global__ void __launch_bounds__(kStreamTPB) k_stream(StreamArgs<T, TO> P) {
             acc += wgt * double(bcur.v[i]) * double(TO(xn));
         }
         if constexpr (EPI == E_SMOOTH_DOT2) {
-          const VecN<double, V> qv = *reinterpret_cast<const VecN<double, V>*>(P.q + o);
+          const VecN<double, V> qv = *reinterpret_cast<const VecN<double, V>*>(Qp + o);
 #pragma unroll
           for (int i = 0; i < V; ++i) acc2 += wgt * double(res.v[i]) * qv.v[i];
         }
@@ -320,37 +351,36 @@ __global__ void __launch_bounds__(kStreamTPB) k_stream(StreamArgs<T, TO> P) {
         if constexpr (EPI == E_APPLY_DOT_DD) {
 #pragma unroll
           for (int i = 0; i < V; ++i) {
-            res.v[i] = -residual_dd_vals<OP>(nb[i], 0.0, P.A.coef);
+            res.v[i] = -residual_dd_vals<OP>(nb[i], 0.0, cf);
             acc += wgt * nb[i].c * res.v[i];
           }
         } else if constexpr (EPI == E_CG_P) {
           VecN<double, V> pn;
 #pragma unroll
           for (int i = 0; i < V; ++i) {
-            res.v[i] = OP == 1 ? -residual_dd_vals<OP>(nb[i], 0.0, P.A.coef)
-                               : apply_vals<OP>(nb[i], P.A.coef);
+            res.v[i] = OP == 1 ? -residual_dd_vals<OP>(nb[i], 0.0, cf) : apply_vals<OP>(nb[i], cf);
             acc += wgt * nb[i].c * res.v[i];
             pn.v[i] = nb[i].c;
           }
-          store_nt(reinterpret_cast<VecN<double, V>*>(P.out2 + o), pn);
+          store_nt(reinterpret_cast<VecN<double, V>*>(O2p + o), pn);
           if (!P.first) {
-            const VecN<double, V> po = *reinterpret_cast<const VecN<double, V>*>(P.xprev + o);
-            VecN<double, V> xv = *reinterpret_cast<const VecN<double, V>*>(P.xu + o);
+            const VecN<double, V> po = *reinterpret_cast<const VecN<double, V>*>(XPp + o);
+            VecN<double, V> xv = *reinterpret_cast<const VecN<double, V>*>(XUp + o);
 #pragma unroll
             for (int i = 0; i < V; ++i) xv.v[i] += alpha_prev * po.v[i];
-            store_nt(reinterpret_cast<VecN<double, V>*>(P.xu + o), xv);
+            store_nt(reinterpret_cast<VecN<double, V>*>(XUp + o), xv);
           }
         } else if constexpr (EPI == E_RESID_DD) {
 #pragma unroll
           for (int i = 0; i < V; ++i) {
-            res.v[i] = residual_dd_vals<OP>(nb[i], bcur.v[i], P.A.coef);
+            res.v[i] = residual_dd_vals<OP>(nb[i], bcur.v[i], cf);
             acc += wgt * res.v[i] * res.v[i];
             const double u = ulp_of(nb[i].c);
             acc2 += wgt * u * u;
           }
         }
       }
-      store_nt(reinterpret_cast<VO*>(P.out + o), res);
+      store_nt(reinterpret_cast<VO*>(Op + o), res);
     }
   }
   if constexpr (RED) {
@@ -373,6 +403,10 @@ int env_int(const char* name, int dflt) {
 
 }  // namespace
 
+// Batch of the launches issued by this thread (set by the ensemble driver;
+// count 1 = a single field).
+thread_local BatchCtx g_batch;
+
 bool stream_ok(int n, int elem_bytes) { return n >= 64 * (16 / elem_bytes); }
 
 // Rows per tile: 4 (measured best on 4096^2 among 2..6 for the 13-point
@@ -382,6 +416,7 @@ StreamCfg stream_cfg(int n, int elem_bytes) {
   StreamCfg c;
   static const int rpw_env = env_int("BF_STREAM_RPW", 4);
   c.rpw = rpw_env == 8 ? 8 : 4;
+  if (g_batch.rpw == 4 || g_batch.rpw == 8) c.rpw = g_batch.rpw;
   c.wstrips = n / (64 * (16 / elem_bytes));
   c.rgroups = (n + 1 + c.rpw - 1) / c.rpw;
   c.tiles = c.wstrips * c.rgroups;
@@ -395,14 +430,31 @@ bool stream_ok(int n) { return stream_ok(n, 8); }
 StreamCfg stream_cfg(int n) { return stream_cfg(n, 8); }
 
 template <int OP, int EPI, typename T, typename TO>
-static void dispatch(const StreamCfg& c, StreamArgs<T, TO> P, hipStream_t st) {
+static int dispatch(const StreamCfg& c, StreamArgs<T, TO> P, hipStream_t st) {
   P.rgroups = c.rgroups;
   P.wstrips = c.wstrips;
   P.tiles = c.tiles;
+  const BatchCtx& B = g_batch;
+  P.batch = B.count > 1 ? B.count : 1;
+  P.bstride = B.count > 1 ? B.stride : 0;
+  P.bcoef = B.coef;
+  P.ia = B.ia;
+  P.ig = B.ig;
+  P.ia0 = B.ia0;
+  P.active = B.active;
+  // per instance: all of its tiles, at most kStreamMaxBlocks / batch workgroups
+  int bpi = c.blocks;
+  if (P.batch > 1) {
+    const int cap = kStreamMaxBlocks / P.batch;
+    bpi = bpi < cap ? bpi : (cap > 0 ? cap : 1);
+  }
+  P.bpi = bpi;
+  const int blocks = bpi * P.batch;
   if (c.rpw == 8)
-    hipLaunchKernelGGL((k_stream<OP, EPI, 8, T, TO>), dim3(c.blocks), dim3(kStreamTPB), 0, st, P);
+    hipLaunchKernelGGL((k_stream<OP, EPI, 8, T, TO>), dim3(blocks), dim3(kStreamTPB), 0, st, P);
   else
-    hipLaunchKernelGGL((k_stream<OP, EPI, 4, T, TO>), dim3(c.blocks), dim3(kStreamTPB), 0, st, P);
+    hipLaunchKernelGGL((k_stream<OP, EPI, 4, T, TO>), dim3(blocks), dim3(kStreamTPB), 0, st, P);
+  return blocks;
 }
 
 template <int EPI, typename T, typename TO>
@@ -422,11 +474,8 @@ static int stream_launch(const OpDesc& A, const T* x, const T* b, const T* xprev
   P.g = g;
   P.a0 = a0;
   P.q = q;
-  if (A.op == 0)
-    dispatch<0, EPI>(c, P, st);
-  else
-    dispatch<1, EPI>(c, P, st);
-  return c.blocks;
+  if (A.op == 0) return dispatch<0, EPI>(c, P, st);
+  return dispatch<1, EPI>(c, P, st);
 }
 
 int stream_apply(const OpDesc& A, const double* x, double* y, hipStream_t st) {
@@ -491,11 +540,8 @@ int stream_cg_p(const OpDesc& A, const double* z, const double* p_old, double* p
   P.scal = scal;
   P.first = first ? 1 : 0;
   P.partials = partials;
-  if (A.op == 0)
-    dispatch<0, E_CG_P>(c, P, st);
-  else
-    dispatch<1, E_CG_P>(c, P, st);
-  return c.blocks;
+  if (A.op == 0) return dispatch<0, E_CG_P>(c, P, st);
+  return dispatch<1, E_CG_P>(c, P, st);
 }
 
 template int stream_residual<double>(const OpDesc&, const double*, const double*, double*,

@@ -45,7 +45,7 @@ __device__ void tail_sweep(const TailLevel& L, const T* x, const T* xprev, const
 }
 
 template <int OP, typename T>
-__global__ void __launch_bounds__(kTailThreads) k_tail(TailArgs P, const T* b_in, T* x_out) {
+__device__ void tail_body(const TailArgs& P, const T* b_in, T* x_out) {
   __shared__ T lds[kTailMaxDoubles];
   const int tid = threadIdx.x;
   // carve LDS
@@ -143,6 +143,33 @@ __global__ void __launch_bounds__(kTailThreads) k_tail(TailArgs P, const T* b_in
     for (int idx = tid; idx < npts; idx += kTailThreads) x_out[idx] = res[0][idx];
   }
 }
+
+template <int OP, typename T>
+__global__ void __launch_bounds__(kTailThreads) k_tail(TailArgs P, const T* b_in, T* x_out) {
+  tail_body<OP, T>(P, b_in, x_out);
+}
+
+// One workgroup per instance of a batch; args[i] holds instance i's levels.
+template <int OP, typename T>
+__global__ void __launch_bounds__(kTailThreads) k_tail_batch(const TailArgs* args, const T* b_in,
+                                                             T* x_out, int64_t sin,
+                                                             int64_t sout) {
+  const int i = blockIdx.x;
+  tail_body<OP, T>(args[i], b_in + (int64_t)i * sin, x_out + (int64_t)i * sout);
+}
+
+template <typename T>
+void launch_tail_batch(int op, const TailArgs* args, int count, const T* b_in, T* x_out,
+                       int64_t sin, int64_t sout, hipStream_t st) {
+  if (op == 0)
+    hipLaunchKernelGGL((k_tail_batch<0, T>), dim3(count), dim3(kTailThreads), 0, st, args, b_in,
+                       x_out, sin, sout);
+  else
+    hipLaunchKernelGGL((k_tail_batch<1, T>), dim3(count), dim3(kTailThreads), 0, st, args, b_in,
+                       x_out, sin, sout);
+}
+template void launch_tail_batch<double>(int, const TailArgs*, int, const double*, double*,
+                                        int64_t, int64_t, hipStream_t);
 
 template <typename T>
 void launch_tail(int op, const TailArgs& P, const T* b_in, T* x_out, hipStream_t st) {

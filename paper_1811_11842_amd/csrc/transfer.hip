@@ -49,6 +49,8 @@ __device__ __forceinline__ double shr_in(double v) {
 struct TArgs {
   int nf, nc;
   int wstrips, tiles;
+  int bpi;              // workgroups per instance (batches)
+  int64_t sf, sc;       // fine / coarse stride between instances
 };
 
 // coarse = R fine.  Per fine row f the lane forms the x-restricted values
@@ -63,8 +65,11 @@ __global__ void __launch_bounds__(kTPB) k_restrict_tile(TArgs A, const T* __rest
   const int lane = threadIdx.x & 63;
   const bool hl = lane == 0, hr = lane == 63;
   const T h = T(0.5), w1 = T(9.0 / 32), w3 = T(-1.0 / 32);
-  for (int t = blockIdx.x * (kTPB / 64) + (threadIdx.x >> 6); t < A.tiles;
-       t += gridDim.x * (kTPB / 64)) {
+  const int inst = blockIdx.x / A.bpi;
+  fine += (int64_t)inst * A.sf;
+  coarse += (int64_t)inst * A.sc;
+  for (int t = (blockIdx.x - inst * A.bpi) * (kTPB / 64) + (threadIdx.x >> 6); t < A.tiles;
+       t += A.bpi * (kTPB / 64)) {
     const int rg = t / A.wstrips;
     const int strip = t - rg * A.wstrips;
     const int J0 = rg * kCR;
@@ -122,8 +127,11 @@ __global__ void __launch_bounds__(kTPB) k_prolong_tile(TArgs A, const T* __restr
   const int lane = threadIdx.x & 63;
   const bool hl = lane == 0, hr = lane == 63;
   const T k9 = T(9), k16 = T(0.0625);
-  for (int t = blockIdx.x * (kTPB / 64) + (threadIdx.x >> 6); t < A.tiles;
-       t += gridDim.x * (kTPB / 64)) {
+  const int inst = blockIdx.x / A.bpi;
+  coarse += (int64_t)inst * A.sc;
+  fine += (int64_t)inst * A.sf;
+  for (int t = (blockIdx.x - inst * A.bpi) * (kTPB / 64) + (threadIdx.x >> 6); t < A.tiles;
+       t += A.bpi * (kTPB / 64)) {
     const int rg = t / A.wstrips;
     const int strip = t - rg * A.wstrips;
     const int J0 = rg * kCR;
@@ -189,8 +197,14 @@ TArgs targs(int nf, int& blocks) {
   A.nc = nf / 2;
   A.wstrips = nf / 256;
   A.tiles = A.wstrips * ((A.nc + 1 + kCR - 1) / kCR);
+  const BatchCtx& B = g_batch;
+  const int count = B.count > 1 ? B.count : 1;
+  const int cap = kMaxBlocks / count > 0 ? kMaxBlocks / count : 1;
   const int64_t b = ((int64_t)A.tiles + kTPB / 64 - 1) / (kTPB / 64);
-  blocks = (int)(b < kMaxBlocks ? b : kMaxBlocks);
+  A.bpi = (int)(b < cap ? b : cap);
+  A.sf = count > 1 ? B.stride : 0;
+  A.sc = count > 1 ? B.stride_c : 0;
+  blocks = A.bpi * count;
   return A;
 }
 

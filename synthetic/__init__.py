@@ -84,3 +84,33 @@ CONFIGS = {
     "plain_1024": dict(n=1024, steps=50, rtol=1e-10),
     "large_4096": dict(n=4096, steps=20, rtol=1e-10),
 }
+
+
+SEED_ENSEMBLE = 7
+
+
+def ensemble_specs(count: int = 64, seed: int = SEED_ENSEMBLE,
+                   sizes=(128, 256, 512, 1024)) -> list[dict]:
+    """Seeded batched-ensemble recipe: per instance a size drawn uniformly
+    from `sizes`, chi ~ U[0.5, 0.9], dt ~ U[5e-5, 2e-4], protrusion radius
+    ~ U[0.05, 0.15] and its own noise seeds (other parameters as
+    DEFAULT_PARAMS)."""
+    rng = np.random.default_rng(seed)
+    specs = []
+    for k in range(count):
+        specs.append(dict(
+            n=int(rng.choice(sizes)),
+            chi=float(rng.uniform(0.5, 0.9)),
+            dt=float(rng.uniform(5e-5, 2e-4)),
+            radius=float(rng.uniform(0.05, 0.15)),
+            seed_phi=1000 + 3 * k, seed_u=1001 + 3 * k, seed_v=1002 + 3 * k))
+    return specs
+
+
+def ensemble_instance(spec: dict):
+    """(phi0, u*, v*, params) of one ensemble instance."""
+    n = spec["n"]
+    phi = initial_phi(n, seed=spec["seed_phi"], radius=spec["radius"])
+    u, v = inflow_velocity(n, seed_u=spec["seed_u"], seed_v=spec["seed_v"])
+    prm = dict(DEFAULT_PARAMS, chi=spec["chi"], dt=spec["dt"])
+    return phi, u, v, prm

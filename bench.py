@@ -57,6 +57,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--precision", choices=["both", "mixed", "f64"], default="both")
+    ap.add_argument("--ensemble", action="store_true",
+                    help="time only the batched ensemble (64 instances, 10 steps)")
+    ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=4096)
     ap.add_argument("--spmv-reps", type=int, default=100)
@@ -174,6 +177,70 @@ def time_smooth(g, n, reps):
     return e0.elapsed_time(e1) / reps
 
 
+def time_ensemble(steps=10, warmup=1, count=64):
+    """The batched-ensemble configuration (64 seeded instances of sizes in
+    {128, 256, 512, 1024} with their own chi, dt, radius and noise, float64):
+    device time per ensemble step, and the same instances stepped one after
+    the other on single grids (the unbatched path) for comparison."""
+    specs = S.ensemble_specs(count)
+    inst = [S.ensemble_instance(sp) for sp in specs]
+    dev = torch.device("cuda", torch.cuda.current_device())
+    ens = bf.Ensemble([sp["n"] for sp in specs])
+
+    def pack(arrays):
+        t = torch.zeros(ens.total, dtype=torch.float64)
+        for i, a in enumerate(arrays):
+            o = ens.offsets[i]
+            t[o:o + a.size] = torch.from_numpy(np.ascontiguousarray(a).ravel())
+        return t.to(dev)
+
+    phi0 = pack([a[0] for a in inst])
+    us, vs = pack([a[1] for a in inst]), pack([a[2] for a in inst])
+    p, u, v = ens.field(0.0), ens.field(0.0), ens.field(0.0)
+    prms = [bf.make_params(**a[3]) for a in inst]
+    oc, op = bf.default_opts(bf.OP_CH, rtol=1e-10), bf.default_opts(bf.OP_LAP, rtol=1e-10)
+    phi = phi0.clone()
+    for _ in range(warmup):
+        ens.step(prms, phi, us, vs, p, u, v, oc, op)
+    phi.copy_(phi0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    worst = 0
+    its = []
+    for _ in range(steps):
+        st, _ = ens.step(prms, phi, us, vs, p, u, v, oc, op)
+        worst = max(worst, max(max(a.status, b.status) for a, b in st))
+        its.append(sum(a.iters for a, _ in st) / count)
+    torch.cuda.synchronize()
+    ens_ms = (time.perf_counter() - t0) / steps * 1e3
+    # unbatched: every instance on its own grid, one after the other
+    seq_ms = 0.0
+    for sp, (ph, uu, vv, prm) in zip(specs, inst):
+        with bf.Grid(sp["n"]) as g:
+            t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
+            x, us1, vs1 = t(ph), t(uu), t(vv)
+            p1, u1, v1 = g.field(0.0), g.field(0.0), g.field(0.0)
+            P = bf.make_params(**prm)
+            xw = x.clone()
+            for _ in range(warmup):
+                g.step(P, xw, us1, vs1, p1, u1, v1, oc, op)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for _ in range(steps):
+                g.step(P, x, us1, vs1, p1, u1, v1, oc, op)
+            torch.cuda.synchronize()
+            seq_ms += (time.perf_counter() - t1) / steps * 1e3
+    points = sum((sp["n"] + 1) * sp["n"] for sp in specs)
+    classes = [{"n": c[0], "instances": c[1], "tile_rows": c[2]} for c in ens.info()]
+    ens.close()
+    return {"instances": count, "steps": steps, "points": points, "classes": classes,
+            "ms_per_step": round(ens_ms, 3), "sequential_ms_per_step": round(seq_ms, 3),
+            "speedup_vs_sequential": round(seq_ms / ens_ms, 2),
+            "ch_iters_mean": round(float(np.mean(its)), 2),
+            "worst_status": bf.STATUS_NAMES.get(worst, str(worst)),
+            "timing": "wall clock around synchronous steps (host thread per size class)"}
+
+
 def sources_sha256():
     import hashlib
     h = hashlib.sha256()
@@ -234,6 +301,9 @@ def main():
     out = {"metric": METRIC, "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
            "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
            "dtype": "f64", "data": "synthetic"}
+    if a.ensemble:
+        print(json.dumps({"ensemble": time_ensemble()}), flush=True)
+        return
     with bf.Grid(n) as g:
         if a.smooth_only:
             t_sm = time_smooth(g, n, a.spmv_reps)
@@ -291,6 +361,9 @@ def main():
                      "n": n, "rows": n + 1, "cols": n, "points": npts,
                      "dt": S.DEFAULT_PARAMS["dt"], "kappa": S.DEFAULT_PARAMS["kappa"],
                      "chi": S.DEFAULT_PARAMS["chi"], "Npoly": S.DEFAULT_PARAMS["Npoly"]}
+    if not (a.no_ensemble or a.spmv_only or a.steps_only or a.smooth_only):
+        log("batched ensemble: 64 instances, 10 steps (and the same one by one)")
+        out["ensemble"] = time_ensemble()
     if not a.no_cpu_baseline and not a.spmv_only:
         log(f"cpu baseline: {a.cpu_steps} oracle steps at {n}x{n}")
         cms = cpu_baseline(n, a.cpu_steps)

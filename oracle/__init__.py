@@ -20,6 +20,8 @@ Biofilm Flow using the Modified Cahn-Hilliard Equation", arXiv:1811.11842):
   * mg        -- geometric-multigrid pieces and the V-cycle, written plainly.
   * step      -- one projection step (Sec. 4: eqs. pressuresolve and
                  velocityupdate) coupled with the Cahn-Hilliard solve.
+  * cn        -- the Crank-Nicolson step with extrapolated chemical
+                 potential (the paper's second-order time scheme, Sec. 4).
   * adjoint   -- the Cahn-Hilliard rollout with explicit advection (the flux
                  div(phi v) of eq. modCH) and its hand-derived adjoint: the
                  gradients of the upper-half mass with respect to chi, the
@@ -32,4 +34,4 @@ a fallback for it.
 Every function cites the passage it follows.  Pins (checks against what the
 paper and mathematics fix, not against this code) live in tests/test_oracle_*.py.
 """
-from . import ops, fh, spectral, dense, cg, mg, step, adjoint  # noqa: F401
+from . import ops, fh, spectral, dense, cg, mg, step, adjoint, cn  # noqa: F401

@@ -184,6 +184,16 @@ int bf_step(bf_grid* g, const bf_params* prm, double* phi, const double* ustar,
 int bf_step_ch(bf_grid* g, const bf_params* prm, double* phi, const double* u,
                const double* v, const bf_solver_opts* o, bf_solve_stats* stats);
 
+/* One Crank-Nicolson Cahn-Hilliard step with extrapolated chemical potential
+ * (the paper's second-order time scheme, Sec. 4):
+ *   (I + c/2 L^2) phi^{n+1} = (I - c/2 L^2) phi^n + dt*M*L mu_FH(clamp(phi*)),
+ *   phi* = (3 phi^n - phi^{n-1}) / 2,  c = dt*M*kappa,
+ * solved from a zero guess.  phi: in phi^n, out phi^{n+1}; phi_prev: in
+ * phi^{n-1} (ignored when first != 0, then phi* = phi^n), out phi^n.  They
+ * must not alias.  Synchronous; stats as in bf_step_ch. */
+int bf_step_ch_cn(bf_grid* g, const bf_params* prm, double* phi, double* phi_prev,
+                  int32_t first, const bf_solver_opts* o, bf_solve_stats* stats);
+
 /* Reverse (adjoint) of one bf_step_ch, for gradients of a functional J of a
  * later state (the rollout's checkpointing is the caller's; the adjoint of a
  * rollout calls this once per step in reverse order).  With the plain

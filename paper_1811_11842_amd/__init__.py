@@ -107,6 +107,9 @@ def lib():
                                        ctypes.POINTER(SolveStats)]),
             "bf_step_ch": (ctypes.c_int, [_P, ctypes.POINTER(Params), _P, _P, _P,
                                           ctypes.POINTER(SolverOpts), ctypes.POINTER(SolveStats)]),
+            "bf_step_ch_cn": (ctypes.c_int, [_P, ctypes.POINTER(Params), _P, _P, ctypes.c_int32,
+                                             ctypes.POINTER(SolverOpts),
+                                             ctypes.POINTER(SolveStats)]),
             "bf_adjoint_step": (ctypes.c_int, [_P, ctypes.POINTER(Params), _P, _P, _P, _P, _P, _P,
                                                _P, ctypes.POINTER(ctypes.c_double),
                                                ctypes.POINTER(SolverOpts),
@@ -295,6 +298,15 @@ class Grid:
                                 self._ptr(u, "u"), self._ptr(v, "v"),
                                 ctypes.byref(opts) if opts is not None else None,
                                 ctypes.byref(st)))
+        return st
+
+    def step_ch_cn(self, params: Params, phi, phi_prev, first=False, opts=None) -> SolveStats:
+        """One Crank-Nicolson step: phi -> phi^{n+1}, phi_prev -> phi^n."""
+        st = SolveStats()
+        _check(lib().bf_step_ch_cn(self._h, ctypes.byref(params), self._ptr(phi, "phi"),
+                                   self._ptr(phi_prev, "phi_prev"), 1 if first else 0,
+                                   ctypes.byref(opts) if opts is not None else None,
+                                   ctypes.byref(st)))
         return st
 
     def adjoint_step(self, params: Params, phi_n, lam_in, lam_out=None, u=None, v=None,

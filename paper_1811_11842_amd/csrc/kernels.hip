@@ -467,6 +467,31 @@ __global__ void __launch_bounds__(kBlock) k_ch_rhs(Geo G, const double* __restri
   if (clamp_count && cnt) atomicAdd(clamp_count, cnt);
 }
 
+// Crank-Nicolson right-hand side, nonlinear part: b += dtM L mu_FH(clamp(phi*))
+// with phi* = 3/2 phi - 1/2 prev (prev == nullptr: phi* = phi).
+__global__ void __launch_bounds__(kBlock) k_ch_rhs_cn(Geo G, const double* __restrict__ phi,
+                                                      const double* __restrict__ prev,
+                                                      double* __restrict__ b, double dtMn2,
+                                                      double inv_npoly, double chi, double lo,
+                                                      double hi, int32_t* clamp_count) {
+  int cnt = 0;
+  auto star = [&](int64_t k) { return prev ? 1.5 * phi[k] - 0.5 * prev[k] : phi[k]; };
+  GRID_STRIDE(idx, G.npts) {
+    const int i = (int)(idx & G.mask), j = (int)(idx >> G.log2n);
+    const int n = G.n;
+    const int64_t r0 = (int64_t)j * n;
+    const double c = star(idx);
+    cnt += (c < lo || c > hi) ? 1 : 0;
+    const double mc = mu_fh(clampd(c, lo, hi), inv_npoly, chi);
+    const double ml = mu_fh(clampd(star(r0 + ((i - 1) & G.mask)), lo, hi), inv_npoly, chi);
+    const double mr = mu_fh(clampd(star(r0 + ((i + 1) & G.mask)), lo, hi), inv_npoly, chi);
+    const double md = mu_fh(clampd(star((int64_t)refl(j - 1, n) * n + i), lo, hi), inv_npoly, chi);
+    const double mu = mu_fh(clampd(star((int64_t)refl(j + 1, n) * n + i), lo, hi), inv_npoly, chi);
+    b[idx] += dtMn2 * ((ml + mr) + (md + mu) - 4.0 * mc);
+  }
+  if (clamp_count && cnt) atomicAdd(clamp_count, cnt);
+}
+
 // rhs = (u[i+1] - u[i-1] + v[j+1] - v[j-1]) * scale, v odd across the walls.
 __global__ void __launch_bounds__(kBlock) k_divergence(Geo G, const double* __restrict__ u,
                                                        const double* __restrict__ v,
@@ -880,6 +905,14 @@ void launch_ch_rhs(int n, const double* phi, double* b, double dtM, double inv_n
   const Geo G = make_geo(n);
   LAUNCH(k_ch_rhs, ew_blocks(G.npts), st, G, phi, b, dtM * (double)n * (double)n, inv_npoly, chi,
          lo, hi, clamp_count);
+}
+
+void launch_ch_rhs_cn(int n, const double* phi, const double* prev, double* b, double dtM,
+                      double inv_npoly, double chi, double lo, double hi, int32_t* clamp_count,
+                      hipStream_t st) {
+  const Geo G = make_geo(n);
+  LAUNCH(k_ch_rhs_cn, ew_blocks(G.npts), st, G, phi, prev, b, dtM * (double)n * (double)n,
+         inv_npoly, chi, lo, hi, clamp_count);
 }
 
 void launch_divergence(int n, const double* u, const double* v, double* rhs, double scale,

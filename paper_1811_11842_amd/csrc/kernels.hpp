@@ -189,6 +189,10 @@ void launch_copy2(int64_t count, const double* x, double* y, hipStream_t st);
 // Step pieces.
 void launch_ch_rhs(int n, const double* phi, double* b, double dtM, double inv_npoly,
                    double chi, double lo, double hi, int32_t* clamp_count, hipStream_t st);
+// b += dtM L mu_FH(clamp(phi*)), phi* = 3/2 phi - 1/2 prev (prev null: phi).
+void launch_ch_rhs_cn(int n, const double* phi, const double* prev, double* b, double dtM,
+                      double inv_npoly, double chi, double lo, double hi, int32_t* clamp_count,
+                      hipStream_t st);
 void launch_divergence(int n, const double* u, const double* v, double* rhs, double scale,
                        hipStream_t st);
 void launch_velocity(int n, const double* p, const double* us, const double* vs, double* u,

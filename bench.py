@@ -241,6 +241,53 @@ def time_ensemble(steps=10, warmup=1, count=64):
             "timing": "wall clock around synchronous steps (host thread per size class)"}
 
 
+def time_cn(g, n, steps=5):
+    """Crank-Nicolson Cahn-Hilliard steps (bf_step_ch_cn, float64, rtol 1e-10)."""
+    phi = torch.from_numpy(S.initial_phi(n)).to(g.device)
+    prev = g.field(0.0)
+    prm = bf.make_params(**S.DEFAULT_PARAMS)
+    o = bf.default_opts(bf.OP_CH, rtol=1e-10)
+    g.step_ch_cn(prm, phi, prev, first=True, opts=o)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its = []
+    for _ in range(steps):
+        its.append(g.step_ch_cn(prm, phi, prev, first=False, opts=o).iters)
+    torch.cuda.synchronize()
+    return {"n": n, "steps": steps, "ms_per_step": round((time.perf_counter() - t0) / steps * 1e3, 3),
+            "ch_iters_mean": float(np.mean(its))}
+
+
+def time_adjoint(n=2048, steps=20, every=5):
+    """Gradient of the upper-half mass after `steps` advected Cahn-Hilliard
+    steps with respect to phi0, chi and the inflow speed (checkpoints every
+    `every` steps): wall time of the forward and of the reverse pass."""
+    from paper_1811_11842_amd import adjoint as bfa
+    dev = torch.device("cuda", torch.cuda.current_device())
+    Y, _ = S.node_coords(n)
+    nu, nv = S.inflow_velocity(n, U=0.0)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
+    prm = {k: S.DEFAULT_PARAMS[k] for k in ("dt", "M", "kappa", "Npoly")}
+    with bf.Grid(n) as g:
+        ro = bfa.Rollout(g, steps, t(Y * (2.0 - Y)), t(nu), t(nv), checkpoint_every=every,
+                         rtol_forward=1e-12, rtol_adjoint=1e-12, rtol_pressure=1e-12, **prm)
+        p0 = t(S.initial_phi(n)).requires_grad_(True)
+        chi = torch.tensor(S.DEFAULT_PARAMS["chi"], dtype=torch.float64, requires_grad=True)
+        U = torch.tensor(1.0, dtype=torch.float64, requires_grad=True)
+        w = bfa.upper_half_weights(g)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        J = (w * bfa.RolloutFn.apply(p0, chi, U, ro)).sum()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        J.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+    return {"n": n, "steps": steps, "checkpoint_every": every, "J": J.item(),
+            "dJ_dchi": chi.grad.item(), "dJ_dU": U.grad.item(),
+            "forward_ms": round((t1 - t0) * 1e3, 1), "reverse_ms": round((t2 - t1) * 1e3, 1)}
+
+
 def sources_sha256():
     import hashlib
     h = hashlib.sha256()
@@ -361,6 +408,10 @@ def main():
                      "n": n, "rows": n + 1, "cols": n, "points": npts,
                      "dt": S.DEFAULT_PARAMS["dt"], "kappa": S.DEFAULT_PARAMS["kappa"],
                      "chi": S.DEFAULT_PARAMS["chi"], "Npoly": S.DEFAULT_PARAMS["Npoly"]}
+    if not (a.spmv_only or a.steps_only or a.smooth_only):
+        with bf.Grid(n) as g:
+            out["crank_nicolson"] = time_cn(g, n)
+        out["adjoint"] = time_adjoint()
     if not (a.no_ensemble or a.spmv_only or a.steps_only or a.smooth_only):
         log("batched ensemble: 64 instances, 10 steps (and the same one by one)")
         out["ensemble"] = time_ensemble()

@@ -12,6 +12,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <type_traits>
 #include <vector>
 
@@ -105,6 +106,13 @@ struct bf_grid {
   double* gm_Z = nullptr;  // m preconditioned vectors
   double* gm_y = nullptr;  // m coefficients (device)
   std::vector<void*> allocs;
+  // bf_step runs the pressure half (independent of the Cahn-Hilliard half
+  // within a step) on a second grid with its own stream and host thread, so
+  // the two solves overlap (created on first use; BF_NO_OVERLAP=1 disables)
+  bf_grid* twin = nullptr;
+  hipStream_t twin_stream = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  bool overlap = true;
 };
 
 namespace {
@@ -997,6 +1005,8 @@ int bf_grid_create(const bf_grid_desc* desc, bf_grid** out) {
   {
     const char* ng = std::getenv("BF_NO_GRAPHS");
     if (ng && ng[0] == '1') g->use_graphs = false;
+    const char* no = std::getenv("BF_NO_OVERLAP");
+    if (no && no[0] == '1') g->overlap = false;
   }
   if (s == BF_OK) {
     launch_fill(kNumSlots, g->scal, 0.0, g->stream);
@@ -1015,6 +1025,10 @@ int bf_grid_create(const bf_grid_desc* desc, bf_grid** out) {
 
 int bf_grid_destroy(bf_grid* g) {
   if (!g) return BF_OK;
+  if (g->twin) bf_grid_destroy(g->twin);
+  if (g->twin_stream) (void)hipStreamDestroy(g->twin_stream);
+  if (g->ev_fork) (void)hipEventDestroy(g->ev_fork);
+  if (g->ev_join) (void)hipEventDestroy(g->ev_join);
   if (g->stream) (void)hipStreamSynchronize(g->stream);
   else (void)hipDeviceSynchronize();
   for (auto& e : g->graphs) (void)hipGraphExecDestroy(e.exec);
@@ -1111,6 +1125,33 @@ int bf_velocity_correct(bf_grid* g, double dt, const double* p, const double* us
   return BF_OK;
 }
 
+namespace {
+
+// The pressure half of a step on grid h (its stream, its workspaces).
+int pressure_half(bf_grid* h, const bf_params* prm, const double* ustar, const double* vstar,
+                  double* p, double* u, double* v, const bf_solver_opts* pr, bf_solve_stats* S) {
+  TRY(bf_pressure_rhs(h, prm->dt, ustar, vstar, h->work_b));
+  launch_fill(h->npts, p, 0.0, h->stream);
+  const int s = bf_solve_pressure(h, h->work_b, p, pr, S);
+  if (s < 0) return s;
+  if (u || v) TRY(bf_velocity_correct(h, prm->dt, p, ustar, vstar, u, v));
+  return s;
+}
+
+int ensure_twin(bf_grid* g) {
+  if (g->twin) return BF_OK;
+  HIPCHK(hipStreamCreateWithFlags(&g->twin_stream, hipStreamNonBlocking));
+  HIPCHK(hipEventCreateWithFlags(&g->ev_fork, hipEventDisableTiming));
+  HIPCHK(hipEventCreateWithFlags(&g->ev_join, hipEventDisableTiming));
+  bf_grid_desc d;
+  d.n = g->n;
+  d.dtype = BF_F64;
+  d.stream = g->twin_stream;
+  return bf_grid_create(&d, &g->twin);
+}
+
+}  // namespace
+
 int bf_step(bf_grid* g, const bf_params* prm, double* phi, const double* ustar,
             const double* vstar, double* p, double* u, double* v, const bf_solver_opts* ch,
             const bf_solver_opts* pr, bf_solve_stats stats[2]) {
@@ -1119,6 +1160,34 @@ int bf_step(bf_grid* g, const bf_params* prm, double* phi, const double* ustar,
   bf_solve_stats local[2];
   bf_solve_stats* S = stats ? stats : local;
   std::memset(S, 0, sizeof(bf_solve_stats) * 2);
+  if (g->overlap && ensure_twin(g) == BF_OK) {
+    // fork: the pressure half waits for the caller's prior work on its own stream
+    HIPCHK(hipEventRecord(g->ev_fork, g->stream));
+    HIPCHK(hipStreamWaitEvent(g->twin_stream, g->ev_fork, 0));
+    int s2 = BF_OK;
+    std::string err2;
+    std::thread th([&] {
+      s2 = pressure_half(g->twin, prm, ustar, vstar, p, u, v, pr, &S[1]);
+      if (s2 < 0) err2 = bf_last_error();
+    });
+    int s1 = bf_ch_rhs(g, prm, phi, g->work_b, g->counter);
+    if (s1 >= 0) {
+      launch_fill(g->npts, phi, 0.0, g->stream);
+      s1 = bf_solve_ch(g, prm->dt * prm->M * prm->kappa, g->work_b, phi, ch, &S[0]);
+    }
+    th.join();
+    HIPCHK(hipEventRecord(g->ev_join, g->twin_stream));
+    HIPCHK(hipStreamWaitEvent(g->stream, g->ev_join, 0));
+    if (s1 < 0) return s1;
+    if (s2 < 0) return fail(s2, "%s", err2.c_str());
+    int32_t clamped = 0;
+    HIPCHK(hipMemcpyAsync(&clamped, g->counter, sizeof(int32_t), hipMemcpyDeviceToHost,
+                          g->stream));
+    HIPCHK(hipStreamSynchronize(g->stream));
+    S[0].clamped = clamped;
+    return s1 > s2 ? s1 : s2;
+  }
+  (void)hipGetLastError();
   TRY(bf_ch_rhs(g, prm, phi, g->work_b, g->counter));
   launch_fill(g->npts, phi, 0.0, g->stream);
   const int s1 = bf_solve_ch(g, prm->dt * prm->M * prm->kappa, g->work_b, phi, ch, &S[0]);

@@ -49,7 +49,7 @@ KERNEL_SOURCES = ["paper_1811_11842_amd/csrc/stream.hip", "paper_1811_11842_amd/
 # (profiles/spmv_13pt_4096_counters.md), KiB per dispatch, scaled by the ratio of known to
 # counted bytes of the bf_copy calibration kernel.  Valid only for the kernel sources
 # whose sha256 is recorded; otherwise the traffic is reported as null.
-TRAFFIC_RECORD = {"n": 4096, "fetch_scale": 1.9998, "write_scale": 1.0, "kernels": {"spmv": {"fetch_kib": 69730.7, "write_kib": 131104.1}, "smooth": {"fetch_kib": 200817.3, "write_kib": 131104.0}}, "sources_sha256": "7dcc8754dc5818c6f8b4ea5812adc8267c643bd49c27e9610fd651401ade2f4a"}
+TRAFFIC_RECORD = {"n": 4096, "fetch_scale": 1.9998, "write_scale": 1.0, "kernels": {"spmv": {"fetch_kib": 69707.2, "write_kib": 131104.0}, "smooth": {"fetch_kib": 200831.9, "write_kib": 131104.0}}, "sources_sha256": "021da3f31936fdacb56697f6995d784ad36f4a71964935fa490b8f3e2499b20b"}
 
 
 def parse():
@@ -384,7 +384,7 @@ def main():
             gbs = alg / (t_spmv * 1e-3) / 1e9
             out["spmv_us"] = round(t_spmv * 1e3, 3)
             out["spmv_gbs"] = round(gbs, 1)
-            out["roofline"] = {"kernel": "k_stream<1,0,4,double,double> (13-point Cahn-Hilliard SpMV, float64)",
+            out["roofline"] = {"kernel": "k_stream<1,0,5,double,double> (13-point Cahn-Hilliard SpMV, float64, 5-row tiles)",
                                "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
                                "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
                                "traffic": recorded_traffic("spmv", n), "algorithmic_bytes": alg,

@@ -79,6 +79,7 @@ struct bf_grid {
   double *work_b = nullptr;   // Cahn-Hilliard right-hand side inside bf_step
   double *work_p = nullptr;   // projected pressure right-hand side
   double *work_e = nullptr;   // adjoint: W^{-1} eta (allocated on first use)
+  double *work_mu = nullptr;  // chemical potential of the right-hand side
   double* scal = nullptr;     // device scalars (kNumSlots)
   double* partials = nullptr; // reduction partials (kMaxRedBlocks * 72)
   double* coarse_ch = nullptr;
@@ -983,6 +984,7 @@ int bf_grid_create(const bf_grid_desc* desc, bf_grid** out) {
   A(&g->q, g->npts);
   A(&g->work_b, g->npts);
   A(&g->work_p, g->npts);
+  A(&g->work_mu, g->npts);
   A(&g->scal, kNumSlots);
   A(&g->partials, (int64_t)kMaxRedBlocks * 72);
   A(&g->coarse_ch, kCoarseSize * kCoarseSize);
@@ -1099,8 +1101,8 @@ int bf_ch_rhs(bf_grid* g, const bf_params* prm, const double* phi, double* b, in
   if (!(prm->Npoly > 0) || !(prm->phi_lo > 0) || !(prm->phi_hi < 1) || !(prm->phi_lo < prm->phi_hi))
     return fail(BF_EINVAL, "bad Flory-Huggins parameters");
   if (clamped) launch_fill_i32(1, clamped, 0, g->stream);
-  launch_ch_rhs(g->n, phi, b, prm->dt * prm->M, 1.0 / prm->Npoly, prm->chi, prm->phi_lo,
-                prm->phi_hi, clamped, g->stream);
+  launch_ch_rhs(g->n, phi, nullptr, phi, b, g->work_mu, prm->dt * prm->M, 1.0 / prm->Npoly,
+                prm->chi, prm->phi_lo, prm->phi_hi, clamped, g->stream);
   HIPCHK(hipGetLastError());
   return BF_OK;
 }
@@ -1244,8 +1246,9 @@ int bf_step_ch_cn(bf_grid* g, const bf_params* prm, double* phi, double* phi_pre
   launch_apply_dot(level_op(BF_OP_CH, g->n, -0.5 * c), phi, g->work_b, g->partials,
                    nparts_of(g), st, true);
   launch_fill_i32(1, g->counter, 0, st);
-  launch_ch_rhs_cn(g->n, phi, first ? nullptr : phi_prev, g->work_b, prm->dt * prm->M,
-                   1.0 / prm->Npoly, prm->chi, prm->phi_lo, prm->phi_hi, g->counter, st);
+  launch_ch_rhs(g->n, phi, first ? nullptr : phi_prev, g->work_b, g->work_b, g->work_mu,
+                prm->dt * prm->M, 1.0 / prm->Npoly, prm->chi, prm->phi_lo, prm->phi_hi,
+                g->counter, st);
   launch_copy(g->npts, phi, phi_prev, st);
   launch_fill(g->npts, phi, 0.0, st);
   const int s = bf_solve_ch(g, 0.5 * c, g->work_b, phi, o, S);

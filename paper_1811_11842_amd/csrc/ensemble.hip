@@ -20,7 +20,7 @@
 // NOT_CONVERGED from the true residual, without refinement restarts.
 //
 // Tile height of the stencil kernels: chosen per class at creation by
-// timing the smoothing sweep of that class with 4- and 8-row tiles.
+// timing the smoothing sweep of that class with 4-, 5- and 8-row tiles.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -723,7 +723,7 @@ int e_step_class(bf_ensemble* e, EClass& C, const bf_params* prm, double* phi,
 }
 
 // Tile height per class: time the class's float64 smoothing sweep (all its
-// instances in one launch) with 4- and 8-row tiles and keep the faster.
+// instances in one launch) with 4-, 5- and 8-row tiles and keep the fastest.
 int autotune(EClass& C) {
   if (!stream_ok(C.n, 8)) return BF_OK;
   hipEvent_t a = nullptr, b = nullptr;
@@ -735,7 +735,7 @@ int autotune(EClass& C) {
   launch_fill(L.npts * C.count, L.xb, 0.0, C.stream);
   launch_fill(L.npts * C.count, L.b, 0.0, C.stream);
   float best = 1e30f;
-  for (int rpw : {4, 8}) {
+  for (int rpw : {4, 5, 8}) {
     BatchScope scope(C, L.npts, 0, level_coef(C, BF_OP_LAP, 0), nullptr, rpw);
     set_sweep(1, 1, 0);
     for (int w = 0; w < 2; ++w) stream_smooth<double>(A, L.xa, L.xb, L.b, L.r, 0, 0, C.stream);

@@ -443,53 +443,37 @@ __device__ __forceinline__ double clampd(double f, double lo, double hi) {
   return fmin(fmax(f, lo), hi);
 }
 
-// b = phi + dt*M * L mu(clamp(phi)); mu even across the walls.
-__global__ void __launch_bounds__(kBlock) k_ch_rhs(Geo G, const double* __restrict__ phi,
-                                                   double* __restrict__ b, double dtMn2,
-                                                   double inv_npoly, double chi, double lo,
-                                                   double hi, int32_t* clamp_count) {
+// Flory-Huggins right-hand side in two passes, so that the logarithms are
+// evaluated once per node (not five times, as a one-pass five-point stencil
+// of mu would): mu = mu_FH(clamp(phi*)) with phi* = phi, or the extrapolation
+// 3/2 phi - 1/2 prev when prev is given (Crank-Nicolson), counting clamped
+// nodes; then b = base + dtM n^2 (axis - 4 c) of mu (base may alias b).
+__global__ void __launch_bounds__(kBlock) k_mu(Geo G, const double* __restrict__ phi,
+                                               const double* __restrict__ prev,
+                                               double* __restrict__ mu, double inv_npoly,
+                                               double chi, double lo, double hi,
+                                               int32_t* clamp_count) {
   int cnt = 0;
   GRID_STRIDE(idx, G.npts) {
-    const int i = (int)(idx & G.mask), j = (int)(idx >> G.log2n);
-    const int n = G.n;
-    const double* r0 = phi + (int64_t)j * n;
-    const double* rm = phi + (int64_t)refl(j - 1, n) * n;
-    const double* rp = phi + (int64_t)refl(j + 1, n) * n;
-    const double c = r0[i];
+    const double c = prev ? 1.5 * phi[idx] - 0.5 * prev[idx] : phi[idx];
     cnt += (c < lo || c > hi) ? 1 : 0;
-    const double mc = mu_fh(clampd(c, lo, hi), inv_npoly, chi);
-    const double ml = mu_fh(clampd(r0[(i - 1) & G.mask], lo, hi), inv_npoly, chi);
-    const double mr = mu_fh(clampd(r0[(i + 1) & G.mask], lo, hi), inv_npoly, chi);
-    const double md = mu_fh(clampd(rm[i], lo, hi), inv_npoly, chi);
-    const double mu = mu_fh(clampd(rp[i], lo, hi), inv_npoly, chi);
-    b[idx] = c + dtMn2 * ((ml + mr) + (md + mu) - 4.0 * mc);
+    mu[idx] = mu_fh(clampd(c, lo, hi), inv_npoly, chi);
   }
   if (clamp_count && cnt) atomicAdd(clamp_count, cnt);
 }
 
-// Crank-Nicolson right-hand side, nonlinear part: b += dtM L mu_FH(clamp(phi*))
-// with phi* = 3/2 phi - 1/2 prev (prev == nullptr: phi* = phi).
-__global__ void __launch_bounds__(kBlock) k_ch_rhs_cn(Geo G, const double* __restrict__ phi,
-                                                      const double* __restrict__ prev,
-                                                      double* __restrict__ b, double dtMn2,
-                                                      double inv_npoly, double chi, double lo,
-                                                      double hi, int32_t* clamp_count) {
-  int cnt = 0;
-  auto star = [&](int64_t k) { return prev ? 1.5 * phi[k] - 0.5 * prev[k] : phi[k]; };
+__global__ void __launch_bounds__(kBlock) k_lap_axpy(Geo G, const double* __restrict__ mu,
+                                                     const double* base, double* b,
+                                                     double scale) {
   GRID_STRIDE(idx, G.npts) {
     const int i = (int)(idx & G.mask), j = (int)(idx >> G.log2n);
     const int n = G.n;
-    const int64_t r0 = (int64_t)j * n;
-    const double c = star(idx);
-    cnt += (c < lo || c > hi) ? 1 : 0;
-    const double mc = mu_fh(clampd(c, lo, hi), inv_npoly, chi);
-    const double ml = mu_fh(clampd(star(r0 + ((i - 1) & G.mask)), lo, hi), inv_npoly, chi);
-    const double mr = mu_fh(clampd(star(r0 + ((i + 1) & G.mask)), lo, hi), inv_npoly, chi);
-    const double md = mu_fh(clampd(star((int64_t)refl(j - 1, n) * n + i), lo, hi), inv_npoly, chi);
-    const double mu = mu_fh(clampd(star((int64_t)refl(j + 1, n) * n + i), lo, hi), inv_npoly, chi);
-    b[idx] += dtMn2 * ((ml + mr) + (md + mu) - 4.0 * mc);
+    const double* r0 = mu + (int64_t)j * n;
+    const double lap = (r0[(i - 1) & G.mask] + r0[(i + 1) & G.mask]) +
+                       (mu[(int64_t)refl(j - 1, n) * n + i] + mu[(int64_t)refl(j + 1, n) * n + i]) -
+                       4.0 * r0[i];
+    b[idx] = base[idx] + scale * lap;
   }
-  if (clamp_count && cnt) atomicAdd(clamp_count, cnt);
 }
 
 // rhs = (u[i+1] - u[i-1] + v[j+1] - v[j-1]) * scale, v odd across the walls.
@@ -900,19 +884,12 @@ void launch_fill_i32(int count, int32_t* x, int32_t v, hipStream_t st) {
   LAUNCH(k_fill_i32, 1, st, count, x, v);
 }
 
-void launch_ch_rhs(int n, const double* phi, double* b, double dtM, double inv_npoly, double chi,
-                   double lo, double hi, int32_t* clamp_count, hipStream_t st) {
+void launch_ch_rhs(int n, const double* phi, const double* prev, const double* base, double* b,
+                   double* mu_ws, double dtM, double inv_npoly, double chi, double lo, double hi,
+                   int32_t* clamp_count, hipStream_t st) {
   const Geo G = make_geo(n);
-  LAUNCH(k_ch_rhs, ew_blocks(G.npts), st, G, phi, b, dtM * (double)n * (double)n, inv_npoly, chi,
-         lo, hi, clamp_count);
-}
-
-void launch_ch_rhs_cn(int n, const double* phi, const double* prev, double* b, double dtM,
-                      double inv_npoly, double chi, double lo, double hi, int32_t* clamp_count,
-                      hipStream_t st) {
-  const Geo G = make_geo(n);
-  LAUNCH(k_ch_rhs_cn, ew_blocks(G.npts), st, G, phi, prev, b, dtM * (double)n * (double)n,
-         inv_npoly, chi, lo, hi, clamp_count);
+  LAUNCH(k_mu, ew_blocks(G.npts), st, G, phi, prev, mu_ws, inv_npoly, chi, lo, hi, clamp_count);
+  LAUNCH(k_lap_axpy, ew_blocks(G.npts), st, G, mu_ws, base, b, dtM * (double)n * (double)n);
 }
 
 void launch_divergence(int n, const double* u, const double* v, double* rhs, double scale,

@@ -52,6 +52,7 @@ bool stream_ok(int n);              // float64 fields
 StreamCfg stream_cfg(int n);
 bool stream_ok(int n, int elem_bytes);
 StreamCfg stream_cfg(int n, int elem_bytes);
+StreamCfg stream_cfg(int n, int elem_bytes, bool apply);  // apply: y = A x kernels
 int stream_apply(const OpDesc& A, const double* x, double* y, hipStream_t st);
 int stream_apply_dot(const OpDesc& A, const double* p, double* q, double* partials, bool dd,
                      hipStream_t st);
@@ -187,12 +188,11 @@ void launch_fill_i32(int count, int32_t* x, int32_t v, hipStream_t st);
 void launch_copy2(int64_t count, const double* x, double* y, hipStream_t st);
 
 // Step pieces.
-void launch_ch_rhs(int n, const double* phi, double* b, double dtM, double inv_npoly,
-                   double chi, double lo, double hi, int32_t* clamp_count, hipStream_t st);
-// b += dtM L mu_FH(clamp(phi*)), phi* = 3/2 phi - 1/2 prev (prev null: phi).
-void launch_ch_rhs_cn(int n, const double* phi, const double* prev, double* b, double dtM,
-                      double inv_npoly, double chi, double lo, double hi, int32_t* clamp_count,
-                      hipStream_t st);
+// b = base + dtM L mu_FH(clamp(phi*)), phi* = phi (prev null) or 3/2 phi - 1/2 prev;
+// mu_ws: a field of workspace; base may alias b; clamped nodes counted into clamp_count.
+void launch_ch_rhs(int n, const double* phi, const double* prev, const double* base, double* b,
+                   double* mu_ws, double dtM, double inv_npoly, double chi, double lo, double hi,
+                   int32_t* clamp_count, hipStream_t st);
 void launch_divergence(int n, const double* u, const double* v, double* rhs, double scale,
                        hipStream_t st);
 void launch_velocity(int n, const double* p, const double* us, const double* vs, double* u,

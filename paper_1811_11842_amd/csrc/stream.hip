@@ -409,14 +409,19 @@ thread_local BatchCtx g_batch;
 
 bool stream_ok(int n, int elem_bytes) { return n >= 64 * (16 / elem_bytes); }
 
-// Rows per tile: 4 (measured best on 4096^2 among 2..6 for the 13-point
-// SpMV: fewer rows re-read more neighbour rows, more rows hold more registers
-// and widen the band of rows in flight).  BF_STREAM_RPW=8 selects 8.
-StreamCfg stream_cfg(int n, int elem_bytes) {
+// Rows per tile: 5 for the operator applications (y = A x, q = A p: on
+// 4096^2 the 13-point SpMV measured 47.8-48.8 us with 5 rows against
+// 48.4-49.1 with 4), 4 for the kernels with more inputs per row (smoothing
+// sweeps, residuals, the CG step: a 5-row tile holds too many registers;
+// smoothing measured 91 us with 4 rows, 93 with 5).  Fewer rows re-read more
+// neighbour rows, more rows widen the band of rows in flight; 2, 3, 6 and 8
+// were slower.  BF_STREAM_RPW=4, 5 or 8 forces one height; a batch may set its own.
+StreamCfg stream_cfg(int n, int elem_bytes, bool apply) {
   StreamCfg c;
-  static const int rpw_env = env_int("BF_STREAM_RPW", 4);
-  c.rpw = rpw_env == 8 ? 8 : 4;
-  if (g_batch.rpw == 4 || g_batch.rpw == 8) c.rpw = g_batch.rpw;
+  static const int rpw_env = env_int("BF_STREAM_RPW", 0);
+  c.rpw = apply ? 5 : 4;
+  if (rpw_env == 4 || rpw_env == 5 || rpw_env == 8) c.rpw = rpw_env;
+  if (g_batch.rpw == 4 || g_batch.rpw == 5 || g_batch.rpw == 8) c.rpw = g_batch.rpw;
   c.wstrips = n / (64 * (16 / elem_bytes));
   c.rgroups = (n + 1 + c.rpw - 1) / c.rpw;
   c.tiles = c.wstrips * c.rgroups;
@@ -426,6 +431,7 @@ StreamCfg stream_cfg(int n, int elem_bytes) {
   return c;
 }
 
+StreamCfg stream_cfg(int n, int elem_bytes) { return stream_cfg(n, elem_bytes, false); }
 bool stream_ok(int n) { return stream_ok(n, 8); }
 StreamCfg stream_cfg(int n) { return stream_cfg(n, 8); }
 
@@ -452,8 +458,10 @@ static int dispatch(const StreamCfg& c, StreamArgs<T, TO> P, hipStream_t st) {
   const int blocks = bpi * P.batch;
   if (c.rpw == 8)
     hipLaunchKernelGGL((k_stream<OP, EPI, 8, T, TO>), dim3(blocks), dim3(kStreamTPB), 0, st, P);
-  else
+  else if (c.rpw == 4)
     hipLaunchKernelGGL((k_stream<OP, EPI, 4, T, TO>), dim3(blocks), dim3(kStreamTPB), 0, st, P);
+  else
+    hipLaunchKernelGGL((k_stream<OP, EPI, 5, T, TO>), dim3(blocks), dim3(kStreamTPB), 0, st, P);
   return blocks;
 }
 
@@ -461,7 +469,8 @@ template <int EPI, typename T, typename TO>
 static int stream_launch(const OpDesc& A, const T* x, const T* b, const T* xprev, TO* out,
                          double* partials, double a, double g, hipStream_t st, double a0 = 0.0,
                          const double* q = nullptr) {
-  const StreamCfg c = stream_cfg(A.n, sizeof(T));
+  constexpr bool kApply = EPI == E_APPLY || EPI == E_APPLY_DOT || EPI == E_APPLY_DOT_DD;
+  const StreamCfg c = stream_cfg(A.n, sizeof(T), kApply);
   StreamArgs<T, TO> P{};
   P.A = A;
   P.G = make_geo(A.n);

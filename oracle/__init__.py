@@ -26,6 +26,10 @@ Biofilm Flow using the Modified Cahn-Hilliard Equation", arXiv:1811.11842):
                  div(phi v) of eq. modCH) and its hand-derived adjoint: the
                  gradients of the upper-half mass with respect to chi, the
                  inflow speed and the initial phi.
+  * momentum  -- the momentum predictor of the projection method (Sec. 4,
+                 eq. nopressmomentum): explicit advection, theta-implicit
+                 viscous term, i.e. one 5-point Helmholtz solve per velocity
+                 component with Dirichlet walls.
 
 Only tests, the smoke check and the benchmark's CPU-baseline leg may import
 this package.  It shares no code with the HIP path and must never be used as
@@ -34,4 +38,4 @@ a fallback for it.
 Every function cites the passage it follows.  Pins (checks against what the
 paper and mathematics fix, not against this code) live in tests/test_oracle_*.py.
 """
-from . import ops, fh, spectral, dense, cg, mg, step, adjoint, cn  # noqa: F401
+from . import ops, fh, spectral, dense, cg, mg, step, adjoint, cn, momentum  # noqa: F401

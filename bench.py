@@ -258,6 +258,35 @@ def time_cn(g, n, steps=5):
             "ch_iters_mean": float(np.mean(its))}
 
 
+def time_predictor(g, n, calls=5):
+    """Momentum predictor (bf_momentum_predict: explicit advection, Crank-
+    Nicolson viscous term at the paper's viscous scale nu = 1e3, dt = 1e-4,
+    two Helmholtz solves at rtol 1e-12 run concurrently), float64 and
+    float32-V-cycle multigrid: wall time per call."""
+    Y, X = S.node_coords(n)
+    u0, v0 = S.inflow_velocity(n, U=0.1)
+    u0 = u0 + 0.05 * np.sin(2 * np.pi * X) * np.sin(np.pi * Y)
+    v0 = v0 + 0.05 * np.cos(2 * np.pi * X) * np.sin(np.pi * Y) ** 2
+    u0[0], u0[-1], v0[0], v0[-1] = 0.0, 0.1, 0.0, 0.0
+    u = torch.from_numpy(u0).to(g.device)
+    v = torch.from_numpy(v0).to(g.device)
+    us, vs = g.field(0.0), g.field(0.0)
+    res = {"n": n, "dt": 1e-4, "nu": 1e3, "theta": 0.5, "rtol": 1e-12}
+    for name, mp in (("f64", bf.MG_F64), ("mixed", bf.MG_F32)):
+        o = bf.default_opts(bf.OP_HELM, rtol=1e-12, mg_precision=mp)
+        g.momentum_predict(1e-4, 1e3, 0.5, 0.1, u, v, us, vs, opts=o)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        its = []
+        for _ in range(calls):
+            _, _, (su, sv) = g.momentum_predict(1e-4, 1e3, 0.5, 0.1, u, v, us, vs, opts=o)
+            its.append((su.iters, sv.iters))
+        torch.cuda.synchronize()
+        res[f"{name}_ms_per_call"] = round((time.perf_counter() - t0) / calls * 1e3, 3)
+        res[f"{name}_iters"] = [float(np.mean([a for a, _ in its])), float(np.mean([b for _, b in its]))]
+    return res
+
+
 def time_adjoint(n=2048, steps=20, every=5):
     """Gradient of the upper-half mass after `steps` advected Cahn-Hilliard
     steps with respect to phi0, chi and the inflow speed (checkpoints every
@@ -411,6 +440,8 @@ def main():
     if not (a.spmv_only or a.steps_only or a.smooth_only):
         with bf.Grid(n) as g:
             out["crank_nicolson"] = time_cn(g, n)
+            log("momentum predictor (two Helmholtz solves)")
+            out["momentum_predictor"] = time_predictor(g, n)
         out["adjoint"] = time_adjoint()
     if not (a.no_ensemble or a.spmv_only or a.steps_only or a.smooth_only):
         log("batched ensemble: 64 instances, 10 steps (and the same one by one)")

@@ -55,7 +55,7 @@ enum bf_status {
 };
 
 enum { BF_F64 = 0 };
-enum { BF_OP_LAP = 0, BF_OP_CH = 1 };
+enum { BF_OP_LAP = 0, BF_OP_CH = 1, BF_OP_HELM = 2 };
 enum { BF_KSP_CG = 0, BF_KSP_GMRES = 1 };
 enum { BF_PC_NONE = 0, BF_PC_JACOBI = 1, BF_PC_MG = 2 };
 enum { BF_SMOOTH_CHEBYSHEV = 0, BF_SMOOTH_JACOBI = 1 };
@@ -129,7 +129,10 @@ int bf_grid_shape(const bf_grid* g, int64_t* rows, int64_t* cols);
 /* y = L x (op = BF_OP_LAP, 5-point Laplacian: the paper's matrix row 4, -1,
  * -1, -1, -1 of Sec. 4.1 scaled by -1/h^2) or y = x + c * L^2 x (op =
  * BF_OP_CH, the 13-point Cahn-Hilliard operator; c = dt*M*kappa, Sec. 2.2
- * eq. modCH), ghosts by eq. discreteBC, periodic x.  Asynchronous. */
+ * eq. modCH), ghosts by eq. discreteBC, periodic x; or y = x - c * L_D x
+ * (op = BF_OP_HELM, the momentum predictor's Helmholtz operator: interior rows
+ * 1..n-1 read the wall rows 0 and n as Dirichlet values, the wall rows are
+ * identity rows, y = x there).  Asynchronous. */
 int bf_apply(bf_grid* g, int32_t op, double c, const double* x, double* y);
 
 /* Solve (I + c L^2) x = b (Sec. 4.1: KSPSolve).  x: in = initial guess,
@@ -143,6 +146,34 @@ int bf_solve_ch(bf_grid* g, double c, const double* b, double* x,
  * modified.  p: in = initial guess, out = solution with zero weighted mean. */
 int bf_solve_pressure(bf_grid* g, const double* rhs, double* p,
                       const bf_solver_opts* o, bf_solve_stats* st);
+
+/* Solve the Helmholtz problem of the momentum predictor (Sec. 4, eq.
+ * nopressmomentum with the viscous term implicit):
+ *   x - beta * L_D x = b on the interior rows 1..n-1,  x = b on rows 0 and n,
+ * i.e. Dirichlet walls whose values are given in the wall rows of b; L_D is
+ * the 5-point Laplacian (row values of Sec. 4.1 times -1/h^2) reading the wall
+ * rows as boundary values, periodic in x.  x: in = initial guess (its wall
+ * rows are replaced by b's), out = solution.  beta >= 0.  MG-preconditioned
+ * CG by default; the multigrid keeps every correction zero on the wall rows.
+ * Synchronous; errors as bf_solve_ch. */
+int bf_solve_helmholtz(bf_grid* g, double beta, const double* b, double* x,
+                       const bf_solver_opts* o, bf_solve_stats* st);
+
+/* Momentum predictor of the projection method (Sec. 4, eq. nopressmomentum),
+ * without the stress term R, viscosity nu = 1/(rho Re_a) constant:
+ *   (I - theta*dt*nu*L_D) u* = u - dt*(u u_x + v u_y) + (1-theta)*dt*nu*L_D u
+ *   (I - theta*dt*nu*L_D) v* = v - dt*(u v_x + v v_y) + (1-theta)*dt*nu*L_D v
+ * on the interior rows (2h central differences; theta = 1/2 is the paper's
+ * Crank-Nicolson, 1 backward Euler), with u* = 0 on the bottom wall, u* = U
+ * on the top wall and v* = 0 on both.  u, v: the velocity v^n (device
+ * fields); u*, v*: out (u may alias ustar and v may alias vstar, no other
+ * aliasing); the solves start from u, v.  The two component solves run
+ * concurrently on a second stream (as the two solves of bf_step).
+ * stats[0] = x component, stats[1] = y component (may be NULL).
+ * Synchronous.  dt > 0, nu >= 0, 0 <= theta <= 1. */
+int bf_momentum_predict(bf_grid* g, double dt, double nu, double theta, double U,
+                        const double* u, const double* v, double* ustar, double* vstar,
+                        const bf_solver_opts* o, bf_solve_stats stats[2]);
 
 /* b = phi + dt*M*L mu_FH(clamp(phi)), mu_FH(f) = ln(f)/N + 1/N - ln(1-f) - 1
  * + chi*(1-2f), clamp to [phi_lo, phi_hi] (phi itself untouched).  If
@@ -269,7 +300,7 @@ int bf_vcycle(bf_grid* g, int32_t op, double c, const bf_solver_opts* o,
 int bf_restrict(bf_grid* g, int32_t nf, const double* fine, double* coarse);
 int bf_prolong_add(bf_grid* g, int32_t nf, const double* coarse, double* fine);
 
-/* r = b - A x for op (BF_OP_LAP or BF_OP_CH with coefficient c).  accurate
+/* r = b - A x for op (BF_OP_LAP, BF_OP_CH or BF_OP_HELM with coefficient c).  accurate
  * != 0 evaluates the stencil sum in double-double (r correct to a few ulps
  * of r itself, whatever c/h^4); accurate == 0 uses plain float64.  If
  * rel_norm (host) is given it receives ||r||_W / ||b||_W; if floor_est (host)
@@ -284,7 +315,8 @@ int bf_residual(bf_grid* g, int32_t op, double c, const double* b, const double*
  * in the three-term Chebyshev form):
  *   xout = x + a D^{-1} (b - A x) + gcoef (x - xprev),
  * D = diag(A) (1 + 20 s, or 1 + 21 s on rows 1 and n-1, for the CH operator;
- * -4 n^2 for the Laplacian).  xprev may be NULL (taken as 0) and may alias
+ * -4 n^2 for the Laplacian; 1 + 4 c n^2 for the Helmholtz operator, whose
+ * wall rows the sweep leaves unchanged).  xprev may be NULL (taken as 0) and may alias
  * xout; xout must not alias x or b.  gcoef = 0, a = omega is damped Jacobi.
  * Asynchronous. */
 int bf_smooth(bf_grid* g, int32_t op, double c, const double* x, const double* xprev,

@@ -25,7 +25,7 @@ HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "biofilm.h")
 # status codes (include/biofilm.h)
 OK, NOT_CONVERGED, AT_FLOOR = 0, 1, 2
 EINVAL, ENOMEM, EHIP, ENONFINITE, EUNSUPPORTED = -1, -2, -3, -4, -5
-OP_LAP, OP_CH = 0, 1
+OP_LAP, OP_CH, OP_HELM = 0, 1, 2
 KSP_CG, KSP_GMRES = 0, 1
 PC_NONE, PC_JACOBI, PC_MG = 0, 1, 2
 SMOOTH_CHEBYSHEV, SMOOTH_JACOBI = 0, 1
@@ -99,6 +99,13 @@ def lib():
                                            ctypes.POINTER(SolveStats)]),
             "bf_solve_pressure": (ctypes.c_int, [_P, _P, _P, ctypes.POINTER(SolverOpts),
                                                  ctypes.POINTER(SolveStats)]),
+            "bf_solve_helmholtz": (ctypes.c_int, [_P, ctypes.c_double, _P, _P,
+                                                  ctypes.POINTER(SolverOpts),
+                                                  ctypes.POINTER(SolveStats)]),
+            "bf_momentum_predict": (ctypes.c_int, [_P, ctypes.c_double, ctypes.c_double,
+                                                   ctypes.c_double, ctypes.c_double, _P, _P, _P,
+                                                   _P, ctypes.POINTER(SolverOpts),
+                                                   ctypes.POINTER(SolveStats)]),
             "bf_ch_rhs": (ctypes.c_int, [_P, ctypes.POINTER(Params), _P, _P, _P]),
             "bf_pressure_rhs": (ctypes.c_int, [_P, ctypes.c_double, _P, _P, _P]),
             "bf_velocity_correct": (ctypes.c_int, [_P, ctypes.c_double, _P, _P, _P, _P, _P]),
@@ -256,6 +263,25 @@ class Grid:
                                        ctypes.byref(opts) if opts is not None else None,
                                        ctypes.byref(st)))
         return st
+
+    def solve_helmholtz(self, beta, b, x, opts=None) -> SolveStats:
+        """x - beta L_D x = b inside, x = b on the wall rows (Dirichlet data)."""
+        st = SolveStats()
+        _check(lib().bf_solve_helmholtz(self._h, beta, self._ptr(b, "b"), self._ptr(x, "x"),
+                                        ctypes.byref(opts) if opts is not None else None,
+                                        ctypes.byref(st)))
+        return st
+
+    def momentum_predict(self, dt, nu, theta, U, u, v, ustar=None, vstar=None, opts=None):
+        """(u*, v*, stats) of the momentum predictor; ustar may be u, vstar may be v."""
+        ustar = self.field() if ustar is None else ustar
+        vstar = self.field() if vstar is None else vstar
+        st = (SolveStats * 2)()
+        _check(lib().bf_momentum_predict(self._h, dt, nu, theta, U, self._ptr(u, "u"),
+                                         self._ptr(v, "v"), self._ptr(ustar, "ustar"),
+                                         self._ptr(vstar, "vstar"),
+                                         ctypes.byref(opts) if opts is not None else None, st))
+        return ustar, vstar, (st[0], st[1])
 
     def ch_rhs(self, params: Params, phi, b=None, clamped=None):
         b = self.field() if b is None else b

@@ -84,7 +84,9 @@ struct bf_grid {
   double* partials = nullptr; // reduction partials (kMaxRedBlocks * 72)
   double* coarse_ch = nullptr;
   double* coarse_lap = nullptr;
+  double* coarse_helm = nullptr;
   double cached_c = -1.0;
+  double cached_beta = -1.0;
   int32_t* counter = nullptr;
   double* h_scal = nullptr;   // pinned host mirror of scalars
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -181,6 +183,11 @@ void host_apply(int op, int n, double coef, const double* x, double* y) {
       const double axis = X(j, i - 1) + X(j, i + 1) + X(j - 1, i) + X(j + 1, i);
       if (op == BF_OP_LAP) {
         y[j * n + i] = coef * (axis - 4.0 * c);
+      } else if (op == BF_OP_HELM) {
+        // wall rows are identity rows; interior rows read the wall rows as they are
+        const double xm = (j >= 1) ? X(j - 1, i) : 0.0, xp = (j < n) ? X(j + 1, i) : 0.0;
+        const double ax = X(j, i - 1) + X(j, i + 1) + xm + xp;
+        y[j * n + i] = (j == 0 || j == n) ? c : c + coef * (4.0 * c - ax);
       } else {
         const double diag = X(j - 1, i - 1) + X(j - 1, i + 1) + X(j + 1, i - 1) + X(j + 1, i + 1);
         const double far = X(j, i - 2) + X(j, i + 2) + X(j - 2, i) + X(j + 2, i);
@@ -237,6 +244,9 @@ std::vector<double> coarse_matrix(int op, double coef) {
 
 // Exact coarsest-grid solution operators:
 //  CH : G = A^{-1}
+//  HELM: G = inverse of the interior block (rows 1..n-1), zero on the wall rows
+//       and columns: the V-cycle's wall rows stay zero and whatever the
+//       restriction leaves in the coarse wall rows is ignored
 //  LAP: G = top-left block of [[L, 1], [w^T, 0]]^{-1}; G b solves L p = b - wmean(b)
 //       with w^T p = 0 (the weighted-mean constraint on the null space).
 int coarse_operator(int op, double c, std::vector<double>& G) {
@@ -244,6 +254,16 @@ int coarse_operator(int op, double c, std::vector<double>& G) {
   if (op == BF_OP_CH) {
     G = coarse_matrix(op, c * std::pow((double)n, 4));
     if (!invert(G, size)) return fail(BF_EINVAL, "coarse Cahn-Hilliard matrix is singular");
+  } else if (op == BF_OP_HELM) {
+    const std::vector<double> A = coarse_matrix(op, c * (double)n * n);
+    const int isz = (n - 1) * n;  // interior rows 1..n-1
+    std::vector<double> B(isz * isz);
+    for (int k = 0; k < isz; ++k)
+      for (int l = 0; l < isz; ++l) B[k * isz + l] = A[(k + n) * size + (l + n)];
+    if (!invert(B, isz)) return fail(BF_EINVAL, "coarse Helmholtz matrix is singular");
+    G.assign(size * size, 0.0);
+    for (int k = 0; k < isz; ++k)
+      for (int l = 0; l < isz; ++l) G[(k + n) * size + (l + n)] = B[k * isz + l];
   } else {
     std::vector<double> A = coarse_matrix(op, (double)n * n);
     const int bs = size + 1;
@@ -262,11 +282,15 @@ int coarse_operator(int op, double c, std::vector<double>& G) {
   return BF_OK;
 }
 
+double* coarse_of(bf_grid* g, int op) {
+  return op == BF_OP_CH ? g->coarse_ch : op == BF_OP_HELM ? g->coarse_helm : g->coarse_lap;
+}
+
 int upload_coarse(bf_grid* g, int op, double c) {
   const int size = kCoarseSize;
   std::vector<double> G;
   TRY(coarse_operator(op, c, G));
-  double* dst = op == BF_OP_CH ? g->coarse_ch : g->coarse_lap;
+  double* dst = coarse_of(g, op);
   HIPCHK(hipMemcpyAsync(dst, G.data(), sizeof(double) * size * size, hipMemcpyHostToDevice,
                         g->stream));
   HIPCHK(hipStreamSynchronize(g->stream));
@@ -280,6 +304,21 @@ int ensure_coarse_ch(bf_grid* g, double c) {
   return BF_OK;
 }
 
+int ensure_coarse_helm(bf_grid* g, double beta) {
+  if (g->cached_beta == beta) return BF_OK;
+  TRY(upload_coarse(g, BF_OP_HELM, beta));
+  g->cached_beta = beta;
+  return BF_OK;
+}
+
+// The coarsest-grid operator of op (CH and HELM for the coefficient last
+// made current by ensure_coarse_*).
+int ensure_coarse(bf_grid* g, int op, double c) {
+  if (op == BF_OP_CH) return ensure_coarse_ch(g, c);
+  if (op == BF_OP_HELM) return ensure_coarse_helm(g, c);
+  return BF_OK;
+}
+
 // ------------------------------------------------------------ level operators
 OpDesc level_op(int op, int n, double c) {
   OpDesc A;
@@ -288,6 +327,10 @@ OpDesc level_op(int op, int n, double c) {
   if (op == BF_OP_LAP) {
     A.coef = (double)n * (double)n;
     A.dinv_int = A.dinv_edge = -1.0 / (4.0 * A.coef);
+  } else if (op == BF_OP_HELM) {
+    A.coef = c * (double)n * (double)n;
+    A.dinv_int = 1.0 / (1.0 + 4.0 * A.coef);
+    A.dinv_edge = 0.0;  // wall rows: Dirichlet data, never smoothed
   } else {
     const double s = c * std::pow((double)n, 4);
     A.coef = s;
@@ -314,7 +357,7 @@ Smoother make_smoother(int op, int n, double c, const bf_solver_opts& o) {
   if (o.smoother == BF_SMOOTH_JACOBI) {
     double w = o.omega;
     if (w <= 0) {
-      if (op == BF_OP_LAP) {
+      if (op != BF_OP_CH) {
         w = 0.8;
       } else {
         const double s = c * std::pow((double)n, 4);
@@ -330,6 +373,9 @@ Smoother make_smoother(int op, int n, double c, const bf_solver_opts& o) {
   double lmax;
   if (op == BF_OP_LAP) {
     lmax = 2.0;
+  } else if (op == BF_OP_HELM) {
+    const double s = c * (double)n * n;
+    lmax = (1.0 + 8.0 * s) / (1.0 + 4.0 * s);
   } else {
     const double s = c * std::pow((double)n, 4);
     lmax = (1.0 + 64.0 * s) / (1.0 + 20.0 * s);
@@ -373,7 +419,7 @@ T* vcycle_level(bf_grid* g, std::vector<LevelT<T>>& lv, int op, double c,
   if (rz_parts) *rz_parts = 0;
   T* res = nullptr;
   if (L.n == kCoarseN) {
-    launch_coarse_solve(kCoarseSize, op == BF_OP_CH ? g->coarse_ch : g->coarse_lap, b, L.xa, st);
+    launch_coarse_solve(kCoarseSize, coarse_of(g, op), b, L.xa, st);
     res = L.xa;
   } else if (L.n <= kTailTop) {
     // the rest of the cycle in one workgroup (fields in LDS)
@@ -393,7 +439,7 @@ T* vcycle_level(bf_grid* g, std::vector<LevelT<T>>& lv, int op, double c,
         TL.g[k] = S.g[k];
       }
     }
-    P.G = op == BF_OP_CH ? g->coarse_ch : g->coarse_lap;
+    P.G = coarse_of(g, op);
     launch_tail(op, P, b, L.xa, st);
     res = L.xa;
   }
@@ -624,6 +670,7 @@ struct KrylovState {
 // amplification of independent rounding errors of x into the residual).
 double column_sq(const OpDesc& A) {
   if (A.op == BF_OP_LAP) return 20.0 * A.coef * A.coef;
+  if (A.op == BF_OP_HELM) return (1.0 + 4.0 * A.coef) * (1.0 + 4.0 * A.coef) + 4.0 * A.coef * A.coef;
   const double d = 1.0 + 20.0 * A.coef;
   return d * d + 276.0 * A.coef * A.coef;
 }
@@ -876,8 +923,15 @@ int run_gmres(bf_grid* g, int op, double c, const double* b, double* x, const bf
 int run_krylov(bf_grid* g, int op, double c, const double* b, double* x, const bf_solver_opts& o,
                bf_solve_stats* st) {
   TRY(check_opts(o));
-  if (op == BF_OP_CH) TRY(ensure_coarse_ch(g, c));
+  TRY(ensure_coarse(g, op, c));
   HIPCHK(hipEventRecord(g->ev0, g->stream));
+  if (op == BF_OP_HELM) {
+    // Dirichlet walls: the iterate starts (and stays) at the wall data in b
+    const size_t row = sizeof(double) * (size_t)g->n;
+    HIPCHK(hipMemcpyAsync(x, b, row, hipMemcpyDeviceToDevice, g->stream));
+    HIPCHK(hipMemcpyAsync(x + (int64_t)g->n * g->n, b + (int64_t)g->n * g->n, row,
+                          hipMemcpyDeviceToDevice, g->stream));
+  }
   KrylovState ks;
   int status = o.ksp == BF_KSP_CG ? run_cg(g, op, c, b, x, o, ks) : run_gmres(g, op, c, b, x, o, ks);
   if (status < 0) return status;
@@ -989,6 +1043,7 @@ int bf_grid_create(const bf_grid_desc* desc, bf_grid** out) {
   A(&g->partials, (int64_t)kMaxRedBlocks * 72);
   A(&g->coarse_ch, kCoarseSize * kCoarseSize);
   A(&g->coarse_lap, kCoarseSize * kCoarseSize);
+  A(&g->coarse_helm, kCoarseSize * kCoarseSize);
   if (s == BF_OK) {
     void* p = nullptr;
     if (hipMalloc(&p, sizeof(int32_t) * 4) != hipSuccess)
@@ -1056,7 +1111,7 @@ int bf_apply(bf_grid* g, int32_t op, double c, const double* x, double* y) {
   TRY(check_grid(g));
   if (!x || !y) return fail(BF_EINVAL, "null field");
   if (x == y) return fail(BF_EINVAL, "x and y must not alias");
-  if (op != BF_OP_LAP && op != BF_OP_CH) return fail(BF_EINVAL, "op %d", op);
+  if (op != BF_OP_LAP && op != BF_OP_CH && op != BF_OP_HELM) return fail(BF_EINVAL, "op %d", op);
   launch_apply(level_op(op, g->n, c), x, y, g->stream);
   HIPCHK(hipGetLastError());
   return BF_OK;
@@ -1206,6 +1261,69 @@ int bf_step(bf_grid* g, const bf_params* prm, double* phi, const double* ustar,
   return s1 > s2 ? s1 : s2;
 }
 
+int bf_solve_helmholtz(bf_grid* g, double beta, const double* b, double* x,
+                       const bf_solver_opts* o, bf_solve_stats* st) {
+  TRY(check_grid(g));
+  if (!b || !x) return fail(BF_EINVAL, "null field");
+  if (b == x) return fail(BF_EINVAL, "b and x must not alias");
+  if (!(beta >= 0) || !std::isfinite(beta))
+    return fail(BF_EINVAL, "beta = %g must be finite and >= 0", beta);
+  bf_solver_opts d;
+  default_opts(BF_OP_HELM, &d);
+  return run_krylov(g, BF_OP_HELM, beta, b, x, o ? *o : d, st);
+}
+
+int bf_momentum_predict(bf_grid* g, double dt, double nu, double theta, double U,
+                        const double* u, const double* v, double* ustar, double* vstar,
+                        const bf_solver_opts* o, bf_solve_stats stats[2]) {
+  TRY(check_grid(g));
+  if (!u || !v || !ustar || !vstar) return fail(BF_EINVAL, "null field");
+  if (ustar == vstar || u == vstar || v == ustar || u == v)
+    return fail(BF_EINVAL, "the two components must not alias each other");
+  if (!(dt > 0) || !std::isfinite(dt)) return fail(BF_EINVAL, "dt must be finite and > 0");
+  if (!(nu >= 0) || !std::isfinite(nu)) return fail(BF_EINVAL, "nu must be finite and >= 0");
+  if (!(theta >= 0 && theta <= 1)) return fail(BF_EINVAL, "theta must lie in [0, 1]");
+  if (!std::isfinite(U)) return fail(BF_EINVAL, "U must be finite");
+  bf_solver_opts d;
+  default_opts(BF_OP_HELM, &d);
+  const bf_solver_opts& oo = o ? *o : d;
+  TRY(check_opts(oo));
+  bf_solve_stats local[2];
+  bf_solve_stats* S = stats ? stats : local;
+  std::memset(S, 0, sizeof(bf_solve_stats) * 2);
+  const double beta = theta * dt * nu;
+  // both right-hand sides first (they read u and v), then the initial guesses
+  launch_momentum_rhs(g->n, u, v, dt, (1.0 - theta) * dt * nu, U, g->work_b, g->work_mu,
+                      g->stream);
+  if (ustar != u) launch_copy(g->npts, u, ustar, g->stream);
+  if (vstar != v) launch_copy(g->npts, v, vstar, g->stream);
+  HIPCHK(hipGetLastError());
+  if (g->overlap && ensure_twin(g) == BF_OK) {
+    // the two component solves are independent: the y component runs on the twin grid
+    HIPCHK(hipEventRecord(g->ev_fork, g->stream));
+    HIPCHK(hipStreamWaitEvent(g->twin_stream, g->ev_fork, 0));
+    int s2 = BF_OK;
+    std::string err2;
+    std::thread th([&] {
+      s2 = bf_solve_helmholtz(g->twin, beta, g->work_mu, vstar, &oo, &S[1]);
+      if (s2 < 0) err2 = bf_last_error();
+    });
+    const int s1 = bf_solve_helmholtz(g, beta, g->work_b, ustar, &oo, &S[0]);
+    th.join();
+    HIPCHK(hipEventRecord(g->ev_join, g->twin_stream));
+    HIPCHK(hipStreamWaitEvent(g->stream, g->ev_join, 0));
+    if (s1 < 0) return s1;
+    if (s2 < 0) return fail(s2, "%s", err2.c_str());
+    return s1 > s2 ? s1 : s2;
+  }
+  (void)hipGetLastError();
+  const int s1 = bf_solve_helmholtz(g, beta, g->work_b, ustar, &oo, &S[0]);
+  if (s1 < 0) return s1;
+  const int s2 = bf_solve_helmholtz(g, beta, g->work_mu, vstar, &oo, &S[1]);
+  if (s2 < 0) return s2;
+  return s1 > s2 ? s1 : s2;
+}
+
 int bf_step_ch(bf_grid* g, const bf_params* prm, double* phi, const double* u, const double* v,
                const bf_solver_opts* o, bf_solve_stats* stats) {
   TRY(check_grid(g));
@@ -1304,12 +1422,12 @@ int bf_vcycle(bf_grid* g, int32_t op, double c, const bf_solver_opts* o, const d
               double* z) {
   TRY(check_grid(g));
   if (!r || !z) return fail(BF_EINVAL, "null field");
-  if (op != BF_OP_LAP && op != BF_OP_CH) return fail(BF_EINVAL, "op %d", op);
+  if (op != BF_OP_LAP && op != BF_OP_CH && op != BF_OP_HELM) return fail(BF_EINVAL, "op %d", op);
   bf_solver_opts d;
   default_opts(op, &d);
   const bf_solver_opts& oo = o ? *o : d;
   TRY(check_opts(oo));
-  if (op == BF_OP_CH) TRY(ensure_coarse_ch(g, c));
+  TRY(ensure_coarse(g, op, c));
   bf_solver_opts om = oo;
   om.pc = BF_PC_MG;
   if (om.mg_precision == BF_MG_F32) TRY(ensure_mixed(g));
@@ -1342,7 +1460,7 @@ int bf_residual(bf_grid* g, int32_t op, double c, const double* b, const double*
   TRY(check_grid(g));
   if (!b || !x || !r) return fail(BF_EINVAL, "null field");
   if (r == x) return fail(BF_EINVAL, "r must not alias x");
-  if (op != BF_OP_LAP && op != BF_OP_CH) return fail(BF_EINVAL, "op %d", op);
+  if (op != BF_OP_LAP && op != BF_OP_CH && op != BF_OP_HELM) return fail(BF_EINVAL, "op %d", op);
   if (!(c >= 0) || !std::isfinite(c)) return fail(BF_EINVAL, "c = %g must be finite and >= 0", c);
   const OpDesc A = level_op(op, g->n, c);
   const int np = nparts_of(g);
@@ -1378,7 +1496,7 @@ int bf_smooth(bf_grid* g, int32_t op, double c, const double* x, const double* x
   TRY(check_grid(g));
   if (!x || !b || !xout) return fail(BF_EINVAL, "null field");
   if (xout == x || xout == b) return fail(BF_EINVAL, "xout must not alias x or b");
-  if (op != BF_OP_LAP && op != BF_OP_CH) return fail(BF_EINVAL, "op %d", op);
+  if (op != BF_OP_LAP && op != BF_OP_CH && op != BF_OP_HELM) return fail(BF_EINVAL, "op %d", op);
   if (!(c >= 0) || !std::isfinite(c)) return fail(BF_EINVAL, "c = %g must be finite and >= 0", c);
   launch_smooth(level_op(op, g->n, c), x, xprev, b, xout, a, gcoef, g->stream);
   HIPCHK(hipGetLastError());

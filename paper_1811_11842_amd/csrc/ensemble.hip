@@ -615,7 +615,7 @@ int e_solve(EClass& C, int op, const std::vector<double>& c, const double* b, do
   const OpDesc A0 = host_level_op(op, C.n, 0.0);
   const std::vector<double>& h_coef = C.h_coef0[op];
   std::vector<int> ran;
-  for (int pass = 0;; ++pass) {
+  for (;;) {
     C.h_active = todo;
     ETRY(e_cg_pass(C, op, bn.data(), x, o, stats, ran));
     ECHK(hipMemcpyAsync(C.sel, ran.data(), sizeof(int) * B, hipMemcpyHostToDevice, st));

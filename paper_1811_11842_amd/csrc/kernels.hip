@@ -25,13 +25,13 @@ __device__ __forceinline__ T stencil_at(const T* __restrict__ x, int i, int j, i
                                         T coef, T& center) {
   const Nb13T<T> v = gather<OP>(x, i, j, n, mask);
   center = v.c;
-  return apply_vals<OP>(v, coef);
+  return apply_vals<OP>(v, T(row_coef<OP>(double(coef), j, n)));
 }
 
 template <int OP>
 __device__ __forceinline__ double residual_dd_at(const double* __restrict__ x, double bval, int i,
                                                  int j, int n, int mask, double coef) {
-  return residual_dd_vals<OP>(gather<OP>(x, i, j, n, mask), bval, coef);
+  return residual_dd_vals<OP>(gather<OP>(x, i, j, n, mask), bval, row_coef<OP>(coef, j, n));
 }
 
 // Batches on the one-thread-per-node kernels: blockIdx.y is the instance,
@@ -71,8 +71,7 @@ __device__ __forceinline__ void inst_coef(const BArgs& B, OpDesc& A, double& a, 
 
 template <int OP, typename T = double>
 __device__ __forceinline__ T dinv_at(const OpDesc& A, int j) {
-  if (OP == 0) return T(A.dinv_int);
-  return T((j == 1 || j == A.n - 1) ? A.dinv_edge : A.dinv_int);
+  return T(row_dinv<OP>(A.dinv_int, A.dinv_edge, j, A.n));
 }
 
 // ------------------------------------------------------------------ operators
@@ -371,8 +370,8 @@ __global__ void __launch_bounds__(kBlock) k_cg_p(OpDesc A, Geo G, const double* 
       }
       x[idx] += alpha * w.c;
     }
-    const double qv =
-        OP == 1 ? -residual_dd_vals<OP>(v, 0.0, A.coef) : apply_vals<OP>(v, A.coef);
+    const double cj = row_coef<OP>(A.coef, j, G.n);
+    const double qv = OP == 1 ? -residual_dd_vals<OP>(v, 0.0, cj) : apply_vals<OP>(v, cj);
     q[idx] = qv;
     p_new[idx] = v.c;
     acc += row_weight(j, G.n) * v.c * qv;
@@ -501,6 +500,37 @@ __global__ void __launch_bounds__(kBlock) k_velocity(Geo G, const double* __rest
     const double gy = p[(int64_t)refl(j + 1, n) * n + i] - p[(int64_t)refl(j - 1, n) * n + i];
     if (u) u[idx] = us[idx] - scale * gx;
     if (v) v[idx] = vs[idx] - scale * gy;
+  }
+}
+
+// Right-hand sides of the momentum predictor (one node per thread): on the
+// interior rows f - dt (u f_x + v f_y) + e L_D f for f = u and f = v (central
+// differences; the y differences and the Laplacian read the wall rows as
+// they are); on the wall rows the Dirichlet data (bu: 0 at the bottom, U at
+// the top; bv: 0).  h1 = n/2 = 1/(2h), h2 = n^2 = 1/h^2.
+__global__ void __launch_bounds__(kBlock) k_momentum_rhs(Geo G, const double* __restrict__ u,
+                                                         const double* __restrict__ v, double dt,
+                                                         double e, double U,
+                                                         double* __restrict__ bu,
+                                                         double* __restrict__ bv) {
+  const int n = G.n;
+  const double h1 = 0.5 * n, h2 = (double)n * n;
+  GRID_STRIDE(idx, G.npts) {
+    const int i = (int)(idx & G.mask), j = (int)(idx >> G.log2n);
+    if (j == 0 || j == n) {
+      bu[idx] = j == 0 ? 0.0 : U;
+      bv[idx] = 0.0;
+      continue;
+    }
+    const int64_t im = (int64_t)j * n + ((i - 1) & G.mask), ip = (int64_t)j * n + ((i + 1) & G.mask);
+    const int64_t jm = idx - n, jp = idx + n;
+    const double uc = u[idx], vc = v[idx];
+    const double ux = (u[ip] - u[im]) * h1, uy = (u[jp] - u[jm]) * h1;
+    const double vx = (v[ip] - v[im]) * h1, vy = (v[jp] - v[jm]) * h1;
+    const double lu = (u[im] + u[ip] + u[jm] + u[jp] - 4.0 * uc) * h2;
+    const double lv = (v[im] + v[ip] + v[jm] + v[jp] - 4.0 * vc) * h2;
+    bu[idx] = uc - dt * (uc * ux + vc * uy) + e * lu;
+    bv[idx] = vc - dt * (uc * vx + vc * vy) + e * lv;
   }
 }
 
@@ -687,6 +717,8 @@ void launch_apply(const OpDesc& A, const double* x, double* y, hipStream_t st) {
   const Geo G = make_geo(A.n);
   if (A.op == 0)
     LAUNCH(k_apply<0>, ew_blocks(G.npts), st, A, G, x, y);
+  else if (A.op == 2)
+    LAUNCH(k_apply<2>, ew_blocks(G.npts), st, A, G, x, y);
   else
     LAUNCH(k_apply<1>, ew_blocks(G.npts), st, A, G, x, y);
 }
@@ -700,6 +732,11 @@ int launch_apply_dot(const OpDesc& A, const double* p, double* q, double* partia
       LAUNCH((k_apply_dot<0, 1>), nparts, st, A, G, p, q, partials);
     else
       LAUNCH((k_apply_dot<0, 0>), nparts, st, A, G, p, q, partials);
+  } else if (A.op == 2) {
+    if (accurate)
+      LAUNCH((k_apply_dot<2, 1>), nparts, st, A, G, p, q, partials);
+    else
+      LAUNCH((k_apply_dot<2, 0>), nparts, st, A, G, p, q, partials);
   } else {
     if (accurate)
       LAUNCH((k_apply_dot<1, 1>), nparts, st, A, G, p, q, partials);
@@ -717,6 +754,8 @@ int launch_residual(const OpDesc& A, const T* x, const T* b, T* r, double* parti
   const int blocks = partials ? nparts : ew_blocks(G.npts);
   if (A.op == 0)
     LAUNCH_B((k_residual<0, T>), blocks, st, A, G, x, b, r, partials, batch_args());
+  else if (A.op == 2)
+    LAUNCH_B((k_residual<2, T>), blocks, st, A, G, x, b, r, partials, batch_args());
   else
     LAUNCH_B((k_residual<1, T>), blocks, st, A, G, x, b, r, partials, batch_args());
   return blocks * batch_count();
@@ -732,6 +771,8 @@ int launch_residual_dd(const OpDesc& A, const double* x, const double* b, double
   const Geo G = make_geo(A.n);
   if (A.op == 0)
     LAUNCH(k_residual_dd<0>, nparts, st, A, G, x, b, r, partials);
+  else if (A.op == 2)
+    LAUNCH(k_residual_dd<2>, nparts, st, A, G, x, b, r, partials);
   else
     LAUNCH(k_residual_dd<1>, nparts, st, A, G, x, b, r, partials);
   return nparts;
@@ -748,6 +789,9 @@ void launch_smooth(const OpDesc& A, const T* x, const T* xprev, const T* b, T* x
   if (A.op == 0)
     LAUNCH_B((k_smooth<0, T>), ew_blocks(G.npts), st, A, G, x, xprev, b, xout, a, g,
              batch_args());
+  else if (A.op == 2)
+    LAUNCH_B((k_smooth<2, T>), ew_blocks(G.npts), st, A, G, x, xprev, b, xout, a, g,
+             batch_args());
   else
     LAUNCH_B((k_smooth<1, T>), ew_blocks(G.npts), st, A, G, x, xprev, b, xout, a, g,
              batch_args());
@@ -762,6 +806,8 @@ void launch_smooth0(const OpDesc& A, const T* b, T* xout, double a, hipStream_t 
   const Geo G = make_geo(A.n);
   if (A.op == 0)
     LAUNCH_B((k_smooth0<0, T>), ew_blocks(G.npts), st, A, G, b, xout, a, batch_args());
+  else if (A.op == 2)
+    LAUNCH_B((k_smooth0<2, T>), ew_blocks(G.npts), st, A, G, b, xout, a, batch_args());
   else
     LAUNCH_B((k_smooth0<1, T>), ew_blocks(G.npts), st, A, G, b, xout, a, batch_args());
 }
@@ -772,6 +818,8 @@ void launch_jacobi_pc(const OpDesc& A, const double* r, double* z, hipStream_t s
   const Geo G = make_geo(A.n);
   if (A.op == 0)
     LAUNCH(k_jacobi_pc<0>, ew_blocks(G.npts), st, A, G, r, z);
+  else if (A.op == 2)
+    LAUNCH(k_jacobi_pc<2>, ew_blocks(G.npts), st, A, G, r, z);
   else
     LAUNCH(k_jacobi_pc<1>, ew_blocks(G.npts), st, A, G, r, z);
 }
@@ -841,6 +889,8 @@ int launch_cg_p(const OpDesc& A, const double* z, const double* p_old, double* p
   const Geo G = make_geo(A.n);
   if (A.op == 0)
     LAUNCH(k_cg_p<0>, nparts, st, A, G, z, p_old, p_new, q, x, scal, first ? 1 : 0, partials);
+  else if (A.op == 2)
+    LAUNCH(k_cg_p<2>, nparts, st, A, G, z, p_old, p_new, q, x, scal, first ? 1 : 0, partials);
   else
     LAUNCH(k_cg_p<1>, nparts, st, A, G, z, p_old, p_new, q, x, scal, first ? 1 : 0, partials);
   return nparts;
@@ -902,6 +952,12 @@ void launch_velocity(int n, const double* p, const double* us, const double* vs,
                      double* v, double scale, hipStream_t st) {
   const Geo G = make_geo(n);
   LAUNCH(k_velocity, ew_blocks(G.npts), st, G, p, us, vs, u, v, scale);
+}
+
+void launch_momentum_rhs(int n, const double* u, const double* v, double dt, double e, double U,
+                         double* bu, double* bv, hipStream_t st) {
+  const Geo G = make_geo(n);
+  LAUNCH(k_momentum_rhs, ew_blocks(G.npts), st, G, u, v, dt, e, U, bu, bv);
 }
 
 void launch_advect_sub(int n, const double* phi, const double* u, const double* v, double* b,

@@ -12,11 +12,11 @@ namespace bf {
 //   OP_LAP: A = L (5-point), coef = n^2
 //   OP_CH : A = I + s * S13 with S13 the integer 13-point stencil, s = c n^4
 struct OpDesc {
-  int op;          // 0 = Laplacian, 1 = Cahn-Hilliard
+  int op;          // 0 = Laplacian, 1 = Cahn-Hilliard, 2 = Helmholtz with Dirichlet walls
   int n;
-  double coef;     // n^2 (LAP) or s = c n^4 (CH)
+  double coef;     // n^2 (LAP), s = c n^4 (CH) or s = beta n^2 (Helmholtz)
   double dinv_int; // 1 / diag on ordinary rows
-  double dinv_edge;// 1 / diag on rows 1 and n-1
+  double dinv_edge;// 1 / diag on rows 1 and n-1 (CH); 0 on the wall rows (Helmholtz)
 };
 
 // Batches of equal-sized instances (the ensemble driver).  While a thread's
@@ -195,6 +195,8 @@ void launch_ch_rhs(int n, const double* phi, const double* prev, const double* b
                    int32_t* clamp_count, hipStream_t st);
 void launch_divergence(int n, const double* u, const double* v, double* rhs, double scale,
                        hipStream_t st);
+void launch_momentum_rhs(int n, const double* u, const double* v, double dt, double e, double U,
+                         double* bu, double* bv, hipStream_t st);
 void launch_velocity(int n, const double* p, const double* us, const double* vs, double* u,
                      double* v, double scale, hipStream_t st);
 

@@ -1,6 +1,14 @@
 // Pointwise stencil arithmetic shared by the plain and the streaming kernels:
-// the 5-point Laplacian and the 13-point Cahn-Hilliard operator on values
-// already gathered, in float64 and in double-double (error-free transforms).
+// the 5-point Laplacian (OP 0), the 13-point Cahn-Hilliard operator (OP 1)
+// and the 5-point Helmholtz operator of the momentum predictor (OP 2) on
+// values already gathered, in float64 and in double-double (error-free
+// transforms).
+//
+// OP 2, x + s (4 x - axis neighbours) with s = beta n^2, has Dirichlet walls:
+// its rows 0 and n are identity rows (the wall value is data), which the
+// callers realise with a zero coefficient there (row_coef) and a zero
+// smoother weight (row_dinv), so iterates and corrections never change the
+// wall rows; the first and last interior rows read the wall rows as they are.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -94,11 +102,31 @@ __device__ __forceinline__ T prolong_at(const T* coarse, int nc, int cmask, int 
          T(0.0625);
 }
 
-// A x at the node.  OP 0: n^2 (axis - 4 c); OP 1: c + s (20 c - 8 axis + 2 diag + far).
+// Coefficient of the stencil term on row j (OP 2: 0 on the wall rows, which
+// makes them identity rows).
+template <int OP>
+__host__ __device__ __forceinline__ double row_coef(double coef, int j, int n) {
+  return (OP == 2 && (j == 0 || j == n)) ? 0.0 : coef;
+}
+
+// Smoother weight D^{-1} on row j: the 13-point operator's diagonal is 21 s
+// on rows 1 and n-1 (dinv_edge there); OP 2 leaves its wall rows alone
+// (dinv_edge = 0 there).
+template <int OP>
+__host__ __device__ __forceinline__ double row_dinv(double dinv_int, double dinv_edge, int j,
+                                                    int n) {
+  if (OP == 1) return (j == 1 || j == n - 1) ? dinv_edge : dinv_int;
+  if (OP == 2) return (j == 0 || j == n) ? dinv_edge : dinv_int;
+  return dinv_int;
+}
+
+// A x at the node.  OP 0: n^2 (axis - 4 c); OP 1: c + s (20 c - 8 axis + 2 diag + far);
+// OP 2: c + s (4 c - axis).
 template <int OP, typename T>
 __device__ __forceinline__ T apply_vals(const Nb13T<T>& v, T coef) {
   const T axis = (v.xm1 + v.xp1) + (v.ym1 + v.yp1);
   if (OP == 0) return coef * (axis - T(4) * v.c);
+  if (OP == 2) return v.c + coef * (T(4) * v.c - axis);
   const T diag = (v.dmm + v.dmp) + (v.dpm + v.dpp);
   const T far = (v.xm2 + v.xp2) + (v.ym2 + v.yp2);
   return v.c + coef * (T(20) * v.c - T(8) * axis + T(2) * diag + far);
@@ -135,6 +163,9 @@ __device__ __forceinline__ double residual_dd_vals(const Nb13& v, double bval, d
   if (OP == 0) {
     t[0] = v.xm1; t[1] = v.xp1; t[2] = v.ym1; t[3] = v.yp1; t[4] = -4.0 * v.c;
     nt = 5;
+  } else if (OP == 2) {
+    t[0] = 4.0 * v.c; t[1] = -v.xm1; t[2] = -v.xp1; t[3] = -v.ym1; t[4] = -v.yp1;
+    nt = 5;
   } else {
     two_prod(20.0, v.c, t[0], t[1]);
     t[2] = -8.0 * v.xm1; t[3] = -8.0 * v.xp1; t[4] = -8.0 * v.ym1; t[5] = -8.0 * v.yp1;
@@ -155,7 +186,7 @@ __device__ __forceinline__ double residual_dd_vals(const Nb13& v, double bval, d
   two_prod(coef, hi, ph, pe);
   pe = fma(coef, lo, pe);
   double w, ve = pe;
-  if (OP == 1) {
+  if (OP != 0) {
     double e;
     two_sum(v.c, ph, w, e);
     ve = pe + e;

@@ -128,7 +128,7 @@ __device__ __forceinline__ void store_nt(VecN<T, V>* dst, const VecN<T, V>& v) {
 template <int OP, int EPI, int RPW, typename T, typename TO>
 __global__ void __launch_bounds__(kStreamTPB) k_stream(StreamArgs<T, TO> P) {
   constexpr int V = 16 / sizeof(T);
-  constexpr int R = (OP == 0) ? 1 : 2;
+  constexpr int R = (OP == 1) ? 2 : 1;
   constexpr int NR = RPW + 2 * R;
   constexpr bool SMOOTH = (EPI == E_SMOOTH || EPI == E_SMOOTH_XB || EPI == E_SMOOTH_PB ||
                            EPI == E_SMOOTH_DOT || EPI == E_SMOOTH_DOT2);
@@ -165,7 +165,6 @@ __global__ void __launch_bounds__(kStreamTPB) k_stream(StreamArgs<T, TO> P) {
     pg = rc[11 + P.ig];
     pa0 = rc[3 + P.ia0];
   }
-  const T coef = T(cf);
   const T ca = T(pa), cg = T(pg), ca0 = T(pa0);
   double beta = 0.0, alpha_prev = 0.0;
   if constexpr (EPI == E_CG_P) {
@@ -174,7 +173,7 @@ __global__ void __launch_bounds__(kStreamTPB) k_stream(StreamArgs<T, TO> P) {
       alpha_prev = P.scal[(int64_t)inst * kNumSlots + S_ALPHA];
     }
   }
-  auto dinv_row = [&](int jr) -> T { return T((OP == 1 && (jr == 1 || jr == n - 1)) ? de : di); };
+  auto dinv_row = [&](int jr) -> T { return T(row_dinv<OP>(di, de, jr, n)); };
   double acc = 0.0, acc2 = 0.0;
   const bool skip = P.active && !P.active[inst];
 
@@ -306,6 +305,8 @@ __global__ void __launch_bounds__(kStreamTPB) k_stream(StreamArgs<T, TO> P) {
       }
       const int64_t o = (int64_t)j * n + c;
       const double wgt = row_weight(j, n);
+      const double cfj = row_coef<OP>(cf, j, n);
+      const T coefj = T(cfj);
       VT bcur{}, pcur{};
       if constexpr (NEEDB) bcur = *reinterpret_cast<const VT*>(Bp + o);
       if constexpr (NEEDP) {
@@ -315,14 +316,14 @@ __global__ void __launch_bounds__(kStreamTPB) k_stream(StreamArgs<T, TO> P) {
       if constexpr (EPI == E_APPLY || EPI == E_APPLY_DOT) {
 #pragma unroll
         for (int i = 0; i < V; ++i) {
-          const T ax = apply_vals<OP>(nb[i], coef);
+          const T ax = apply_vals<OP>(nb[i], coefj);
           res.v[i] = TO(ax);
           if (EPI == E_APPLY_DOT) acc += wgt * double(nb[i].c) * double(ax);
         }
       } else if constexpr (EPI == E_RESID || EPI == E_RESID_NORM) {
 #pragma unroll
         for (int i = 0; i < V; ++i) {
-          const T r = bcur.v[i] - apply_vals<OP>(nb[i], coef);
+          const T r = bcur.v[i] - apply_vals<OP>(nb[i], coefj);
           res.v[i] = TO(r);
           if (EPI == E_RESID_NORM) acc += wgt * double(r) * double(r);
         }
@@ -337,7 +338,7 @@ __global__ void __launch_bounds__(kStreamTPB) k_stream(StreamArgs<T, TO> P) {
           else if (EPI != E_SMOOTH_XB && XPp)
             prev = pcur.v[i];
           const T xn =
-              nb[i].c + ad * (bcur.v[i] - apply_vals<OP>(nb[i], coef)) + cg * (nb[i].c - prev);
+              nb[i].c + ad * (bcur.v[i] - apply_vals<OP>(nb[i], coefj)) + cg * (nb[i].c - prev);
           res.v[i] = TO(xn);
           if (EPI == E_SMOOTH_DOT || EPI == E_SMOOTH_DOT2)
             acc += wgt * double(bcur.v[i]) * double(TO(xn));
@@ -351,14 +352,14 @@ __global__ void __launch_bounds__(kStreamTPB) k_stream(StreamArgs<T, TO> P) {
         if constexpr (EPI == E_APPLY_DOT_DD) {
 #pragma unroll
           for (int i = 0; i < V; ++i) {
-            res.v[i] = -residual_dd_vals<OP>(nb[i], 0.0, cf);
+            res.v[i] = -residual_dd_vals<OP>(nb[i], 0.0, cfj);
             acc += wgt * nb[i].c * res.v[i];
           }
         } else if constexpr (EPI == E_CG_P) {
           VecN<double, V> pn;
 #pragma unroll
           for (int i = 0; i < V; ++i) {
-            res.v[i] = OP == 1 ? -residual_dd_vals<OP>(nb[i], 0.0, cf) : apply_vals<OP>(nb[i], cf);
+            res.v[i] = OP == 1 ? -residual_dd_vals<OP>(nb[i], 0.0, cfj) : apply_vals<OP>(nb[i], T(cfj));
             acc += wgt * nb[i].c * res.v[i];
             pn.v[i] = nb[i].c;
           }
@@ -373,7 +374,7 @@ __global__ void __launch_bounds__(kStreamTPB) k_stream(StreamArgs<T, TO> P) {
         } else if constexpr (EPI == E_RESID_DD) {
 #pragma unroll
           for (int i = 0; i < V; ++i) {
-            res.v[i] = residual_dd_vals<OP>(nb[i], bcur.v[i], cf);
+            res.v[i] = residual_dd_vals<OP>(nb[i], bcur.v[i], cfj);
             acc += wgt * res.v[i] * res.v[i];
             const double u = ulp_of(nb[i].c);
             acc2 += wgt * u * u;
@@ -484,6 +485,7 @@ static int stream_launch(const OpDesc& A, const T* x, const T* b, const T* xprev
   P.a0 = a0;
   P.q = q;
   if (A.op == 0) return dispatch<0, EPI>(c, P, st);
+  if (A.op == 2) return dispatch<2, EPI>(c, P, st);
   return dispatch<1, EPI>(c, P, st);
 }
 
@@ -550,6 +552,7 @@ int stream_cg_p(const OpDesc& A, const double* z, const double* p_old, double* p
   P.first = first ? 1 : 0;
   P.partials = partials;
   if (A.op == 0) return dispatch<0, E_CG_P>(c, P, st);
+  if (A.op == 2) return dispatch<2, E_CG_P>(c, P, st);
   return dispatch<1, E_CG_P>(c, P, st);
 }
 

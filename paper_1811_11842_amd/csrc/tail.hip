@@ -32,12 +32,12 @@ __device__ void tail_sweep(const TailLevel& L, const T* x, const T* xprev, const
   const int n = L.n, mask = n - 1, npts = (n + 1) * n;
   int lg = 0;
   while ((1 << lg) < n) ++lg;
-  const T ta = T(a), tg = T(g), coef = T(L.coef);
+  const T ta = T(a), tg = T(g);
   for (int idx = threadIdx.x; idx < npts; idx += kTailThreads) {
     const int i = idx & mask, j = idx >> lg;
     const Nb13T<T> v = gather<OP>(x, i, j, n, mask);
-    const T ax = apply_vals<OP>(v, coef);
-    const T dinv = T((OP == 1 && (j == 1 || j == n - 1)) ? L.dinv_edge : L.dinv_int);
+    const T ax = apply_vals<OP>(v, T(row_coef<OP>(L.coef, j, n)));
+    const T dinv = T(row_dinv<OP>(L.dinv_int, L.dinv_edge, j, n));
     const T prev = xprev ? xprev[idx] : T(0);
     xout[idx] = v.c + ta * dinv * (b[idx] - ax) + tg * (v.c - prev);
   }
@@ -82,7 +82,7 @@ __device__ void tail_body(const TailArgs& P, const T* b_in, T* x_out) {
     T* o = xb[l];
     for (int idx = tid; idx < npts; idx += kTailThreads) {
       const int j = idx / n;
-      const double dinv = (OP == 1 && (j == 1 || j == n - 1)) ? L.dinv_edge : L.dinv_int;
+      const double dinv = row_dinv<OP>(L.dinv_int, L.dinv_edge, j, n);
       cur[idx] = T(L.a[0] * dinv) * bb[l][idx];
     }
     __syncthreads();
@@ -97,7 +97,7 @@ __device__ void tail_body(const TailArgs& P, const T* b_in, T* x_out) {
     for (int idx = tid; idx < npts; idx += kTailThreads) {
       const int i = idx & (n - 1), j = idx / n;
       const Nb13T<T> v = gather<OP>(cur, i, j, n, n - 1);
-      rr[l][idx] = bb[l][idx] - apply_vals<OP>(v, T(L.coef));
+      rr[l][idx] = bb[l][idx] - apply_vals<OP>(v, T(row_coef<OP>(L.coef, j, n)));
     }
     __syncthreads();
     // restriction to the next level (or to the coarsest grid)
@@ -164,6 +164,9 @@ void launch_tail_batch(int op, const TailArgs* args, int count, const T* b_in, T
   if (op == 0)
     hipLaunchKernelGGL((k_tail_batch<0, T>), dim3(count), dim3(kTailThreads), 0, st, args, b_in,
                        x_out, sin, sout);
+  else if (op == 2)
+    hipLaunchKernelGGL((k_tail_batch<2, T>), dim3(count), dim3(kTailThreads), 0, st, args, b_in,
+                       x_out, sin, sout);
   else
     hipLaunchKernelGGL((k_tail_batch<1, T>), dim3(count), dim3(kTailThreads), 0, st, args, b_in,
                        x_out, sin, sout);
@@ -175,6 +178,8 @@ template <typename T>
 void launch_tail(int op, const TailArgs& P, const T* b_in, T* x_out, hipStream_t st) {
   if (op == 0)
     hipLaunchKernelGGL((k_tail<0, T>), dim3(1), dim3(kTailThreads), 0, st, P, b_in, x_out);
+  else if (op == 2)
+    hipLaunchKernelGGL((k_tail<2, T>), dim3(1), dim3(kTailThreads), 0, st, P, b_in, x_out);
   else
     hipLaunchKernelGGL((k_tail<1, T>), dim3(1), dim3(kTailThreads), 0, st, P, b_in, x_out);
 }

@@ -1,0 +1,187 @@
+"""GPU parity of the momentum predictor (Sec. 4, eq. nopressmomentum): the
+Helmholtz operator with Dirichlet walls (bf_apply with BF_OP_HELM), its
+multigrid-preconditioned solve (bf_solve_helmholtz) and the whole predictor
+(bf_momentum_predict) against the CPU oracle (oracle/momentum.py).
+
+Sizes: 64 (plain kernels), 256 and 1024 (streaming kernels, several tiles and
+the coarse tail), and 4096 (the benchmark size, whole field against the
+oracle's direct solve).  Coefficients: a mild one (s = beta n^2 of order 1)
+and the paper's viscous scale, nu = 1/Re_s with Re_s = rho0 h0^2/(eta_s t0)
+about 1e-3 from the parameter table of Sec. 5, dt = 1e-4, so dt*nu = 0.1
+and s = beta n^2 reaches 1e6 at 4096^2.
+
+Tolerance: relative W-norm error of the solution <= 1e-10 (the float64
+solve bar) with the solves at rtol 1e-12.  The operator itself: <= 1e-14
+relative (one rounding per term)."""
+import numpy as np
+import pytest
+import torch
+
+import synthetic as S
+from oracle import momentum as mom
+from oracle import ops
+
+bf = pytest.importorskip("paper_1811_11842_amd")
+
+pytestmark = pytest.mark.gpu
+DT = 1e-4
+NU_PAPER = 1.0e3
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    return torch.device("cuda:0")
+
+
+_grids = {}
+
+
+def grid(n):
+    if n not in _grids:
+        _grids[n] = bf.Grid(n)
+    return _grids[n]
+
+
+def D(a, dev):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+def to_np(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def relw(a, b):
+    return float(ops.wnorm(a - b) / ops.wnorm(b))
+
+
+def velocity(n, U=0.1):
+    """v^n: the sheared inflow with noise (synthetic recipe) plus a smooth
+    vortex pair, wall rows at the Dirichlet data."""
+    u, v = S.inflow_velocity(n, U=U)
+    Y, X = S.node_coords(n)
+    u = u + 0.05 * np.sin(2 * np.pi * X) * np.sin(np.pi * Y)
+    v = v + 0.05 * np.cos(2 * np.pi * X) * np.sin(np.pi * Y) ** 2
+    u[0], u[-1] = 0.0, U
+    v[0], v[-1] = 0.0, 0.0
+    return u, v
+
+
+@pytest.mark.parametrize("n", [64, 512])
+def test_operator_matches_oracle(dev, n):
+    print(f"helmholtz apply n={n}", flush=True)
+    rng = np.random.default_rng(n)
+    x = rng.standard_normal((n + 1, n))
+    for beta in (1e-3 / n, DT * NU_PAPER):
+        y = grid(n).apply(bf.OP_HELM, beta, D(x, dev))
+        ref = mom.apply_helmholtz(x, beta)
+        assert relw(to_np(y), ref) <= 1e-14
+        # wall rows are identity rows
+        assert np.array_equal(to_np(y)[[0, -1]], x[[0, -1]])
+
+
+@pytest.mark.parametrize("n", [64, 256, 1024])
+@pytest.mark.parametrize("which", ["mild", "paper"])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_helmholtz_solve_matches_oracle(dev, n, which, prec):
+    print(f"helmholtz solve n={n} {which} {prec}", flush=True)
+    beta = 1.0 / (n * n) if which == "mild" else 0.5 * DT * NU_PAPER
+    rng = np.random.default_rng(10 * n + (which == "paper"))
+    u, _ = velocity(n)
+    b = u + 1e-3 * rng.standard_normal(u.shape)
+    b[0] = rng.standard_normal(n) * 0.1       # arbitrary Dirichlet data
+    b[-1] = 0.1 + rng.standard_normal(n) * 0.01
+    ref = mom.solve_helmholtz(b, beta)
+    g = grid(n)
+    x = g.field(0.0)
+    o = bf.default_opts(bf.OP_HELM, rtol=1e-12,
+                        mg_precision=bf.MG_F32 if prec == "f32" else bf.MG_F64)
+    st = g.solve_helmholtz(beta, D(b, dev), x, o)
+    xs = to_np(x)
+    e = relw(xs, ref)
+    print(f"  status={st.status} iters={st.iters} res={st.rel_res_true:.2e} err={e:.2e}")
+    assert st.status in (bf.OK, bf.AT_FLOOR)
+    assert e <= 1e-10
+    assert np.array_equal(xs[[0, -1]], b[[0, -1]])
+
+
+def test_vcycle_leaves_wall_rows_zero(dev):
+    n = 256
+    rng = np.random.default_rng(5)
+    r = rng.standard_normal((n + 1, n))
+    r[0] = r[-1] = 0.0
+    for prec in (bf.MG_F64, bf.MG_F32):
+        z = grid(n).vcycle(bf.OP_HELM, 0.05, D(r, dev),
+                           opts=bf.default_opts(bf.OP_HELM, mg_precision=prec))
+        zs = to_np(z)
+        assert not zs[0].any() and not zs[-1].any()
+        assert np.isfinite(zs).all() and np.abs(zs).max() > 0
+
+
+def test_zero_beta_is_identity_and_gmres(dev):
+    n = 128
+    rng = np.random.default_rng(9)
+    b = rng.standard_normal((n + 1, n))
+    g = grid(n)
+    x = g.field(0.0)
+    g.solve_helmholtz(0.0, D(b, dev), x, bf.default_opts(bf.OP_HELM, rtol=1e-13))
+    assert relw(to_np(x), b) <= 1e-13
+    beta = 0.5 * DT * NU_PAPER
+    x = g.field(0.0)
+    st = g.solve_helmholtz(beta, D(b, dev), x,
+                           bf.default_opts(bf.OP_HELM, rtol=1e-12, ksp=bf.KSP_GMRES))
+    assert st.status in (bf.OK, bf.AT_FLOOR)
+    assert relw(to_np(x), mom.solve_helmholtz(b, beta)) <= 1e-10
+
+
+@pytest.mark.parametrize("n", [64, 256, 1024])
+@pytest.mark.parametrize("theta", [0.5, 1.0])
+def test_predictor_matches_oracle(dev, n, theta):
+    print(f"momentum predict n={n} theta={theta}", flush=True)
+    U = 0.1
+    u, v = velocity(n, U)
+    ru, rv = mom.predict(u, v, dt=DT, nu=NU_PAPER, theta=theta, U=U)
+    g = grid(n)
+    o = bf.default_opts(bf.OP_HELM, rtol=1e-12)
+    us, vs, (su, sv) = g.momentum_predict(DT, NU_PAPER, theta, U, D(u, dev), D(v, dev), opts=o)
+    eu, ev = relw(to_np(us), ru), relw(to_np(vs), rv)
+    print(f"  u: it={su.iters} err={eu:.2e}  v: it={sv.iters} err={ev:.2e}")
+    assert su.status in (bf.OK, bf.AT_FLOOR) and sv.status in (bf.OK, bf.AT_FLOOR)
+    assert eu <= 1e-10 and ev <= 1e-10
+    # in place (u* written over u, v* over v) gives the same fields
+    ud, vd = D(u, dev), D(v, dev)
+    g.momentum_predict(DT, NU_PAPER, theta, U, ud, vd, ud, vd, opts=o)
+    assert torch.equal(ud, us) and torch.equal(vd, vs)
+
+
+def test_couette_flow_is_a_fixed_point(dev):
+    n, U = 512, 0.1
+    Y, _ = S.node_coords(n)
+    g = grid(n)
+    us, vs, _ = g.momentum_predict(DT, NU_PAPER, 0.5, U, D(U * Y, dev), g.field(0.0),
+                                   opts=bf.default_opts(bf.OP_HELM, rtol=1e-12))
+    assert np.max(np.abs(to_np(us) - U * Y)) <= 1e-13
+    assert np.max(np.abs(to_np(vs))) <= 1e-13
+
+
+def test_predictor_4096_matches_oracle(dev):
+    """The benchmark configuration: 4096^2, Crank-Nicolson viscous term,
+    paper viscous scale, mixed-precision multigrid.  At s = beta n^2 = 8e5
+    the operator's condition number is about 3e6, so the default rtol 1e-10
+    bounds the forward error only to about 1e-9 (measured 9e-10 on the y
+    component); the solves take rtol 1e-12 for the 1e-10 forward-error bar."""
+    n, U = 4096, 0.1
+    print(f"momentum predict n={n}", flush=True)
+    u, v = velocity(n, U)
+    ru, rv = mom.predict(u, v, dt=DT, nu=NU_PAPER, theta=0.5, U=U)
+    g = grid(n)
+    o = bf.default_opts(bf.OP_HELM, rtol=1e-12, mg_precision=bf.MG_F32)
+    us, vs, (su, sv) = g.momentum_predict(DT, NU_PAPER, 0.5, U, D(u, dev), D(v, dev), opts=o)
+    eu, ev = relw(to_np(us), ru), relw(to_np(vs), rv)
+    print(f"  u: it={su.iters} {su.ms:.2f} ms err={eu:.2e}  v: it={sv.iters} {sv.ms:.2f} ms "
+          f"err={ev:.2e}")
+    assert su.status in (bf.OK, bf.AT_FLOOR) and sv.status in (bf.OK, bf.AT_FLOOR)
+    assert eu <= 1e-10 and ev <= 1e-10

@@ -30,6 +30,9 @@ Biofilm Flow using the Modified Cahn-Hilliard Equation", arXiv:1811.11842):
                  eq. nopressmomentum): explicit advection, theta-implicit
                  viscous term, i.e. one 5-point Helmholtz solve per velocity
                  component with Dirichlet walls.
+  * mobility  -- the Cahn-Hilliard step with the phi-dependent mobility of
+                 the modified equation (Sec. 2.2, eq. modCH): the
+                 variable-coefficient operator I + dt*kappa*L_m L.
 
 Only tests, the smoke check and the benchmark's CPU-baseline leg may import
 this package.  It shares no code with the HIP path and must never be used as
@@ -38,4 +41,4 @@ a fallback for it.
 Every function cites the passage it follows.  Pins (checks against what the
 paper and mathematics fix, not against this code) live in tests/test_oracle_*.py.
 """
-from . import ops, fh, spectral, dense, cg, mg, step, adjoint, cn, momentum  # noqa: F401
+from . import ops, fh, spectral, dense, cg, mg, step, adjoint, cn, momentum, mobility  # noqa: F401

@@ -159,6 +159,33 @@ int bf_solve_pressure(bf_grid* g, const double* rhs, double* p,
 int bf_solve_helmholtz(bf_grid* g, double beta, const double* b, double* x,
                        const bf_solver_opts* o, bf_solve_stats* st);
 
+/* Cahn-Hilliard operator with a variable mobility (the phi-dependent
+ * mobility of the modified equation, Sec. 2.2 eq. modCH):
+ *   y = x + c * L_m L x,  L_m f = div_h(m grad_h f)
+ *     = n^2 sum over the four faces of m_face (f_nb - f), m_face = (m + m_nb)/2,
+ * L the 5-point Laplacian; x, f and m reflected evenly across the walls
+ * (eq. discreteBC), periodic x.  m: device field of node mobilities (> 0).
+ * Evaluated in double-double, rounded once.  Asynchronous. */
+int bf_apply_mob(bf_grid* g, double c, const double* m, const double* x, double* y);
+
+/* Solve (I + c L_m L) x = b (the operator of bf_apply_mob).  L_m L is not
+ * symmetric: the solve is GMRES (o->ksp must be BF_KSP_GMRES; o == NULL gives
+ * GMRES(30) + multigrid, rtol 1e-10) right-preconditioned by the
+ * constant-mobility V-cycle of I + c mbar L^2, mbar the weighted mean of m
+ * rounded to 6 significant bits.  Residuals in double-double; the constant
+ * mode is corrected as in bf_solve_ch (L_m conserves the weighted sum).
+ * x: in = initial guess, out = solution.  Synchronous. */
+int bf_solve_ch_mob(bf_grid* g, double c, const double* m, const double* b, double* x,
+                    const bf_solver_opts* o, bf_solve_stats* st);
+
+/* One Cahn-Hilliard step with the phi-dependent mobility m = M clamp(phi^n):
+ *   b = phi + dt L_m mu_FH(clamp(phi)),
+ *   (I + dt*kappa*L_m L) phi' = b,  solved in place from a zero guess
+ * (bf_solve_ch_mob).  Synchronous; stats (may be NULL) receives the solve's
+ * statistics and the clamp count. */
+int bf_step_ch_mob(bf_grid* g, const bf_params* prm, double* phi, const bf_solver_opts* o,
+                   bf_solve_stats* stats);
+
 /* Momentum predictor of the projection method (Sec. 4, eq. nopressmomentum),
  * without the stress term R, viscosity nu = 1/(rho Re_a) constant:
  *   (I - theta*dt*nu*L_D) u* = u - dt*(u u_x + v u_y) + (1-theta)*dt*nu*L_D u

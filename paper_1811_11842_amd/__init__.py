@@ -106,6 +106,13 @@ def lib():
                                                    ctypes.c_double, ctypes.c_double, _P, _P, _P,
                                                    _P, ctypes.POINTER(SolverOpts),
                                                    ctypes.POINTER(SolveStats)]),
+            "bf_apply_mob": (ctypes.c_int, [_P, ctypes.c_double, _P, _P, _P]),
+            "bf_solve_ch_mob": (ctypes.c_int, [_P, ctypes.c_double, _P, _P, _P,
+                                               ctypes.POINTER(SolverOpts),
+                                               ctypes.POINTER(SolveStats)]),
+            "bf_step_ch_mob": (ctypes.c_int, [_P, ctypes.POINTER(Params), _P,
+                                              ctypes.POINTER(SolverOpts),
+                                              ctypes.POINTER(SolveStats)]),
             "bf_ch_rhs": (ctypes.c_int, [_P, ctypes.POINTER(Params), _P, _P, _P]),
             "bf_pressure_rhs": (ctypes.c_int, [_P, ctypes.c_double, _P, _P, _P]),
             "bf_velocity_correct": (ctypes.c_int, [_P, ctypes.c_double, _P, _P, _P, _P, _P]),
@@ -270,6 +277,29 @@ class Grid:
         _check(lib().bf_solve_helmholtz(self._h, beta, self._ptr(b, "b"), self._ptr(x, "x"),
                                         ctypes.byref(opts) if opts is not None else None,
                                         ctypes.byref(st)))
+        return st
+
+    def apply_mob(self, c, m, x, y=None):
+        """y = x + c L_m L x for the node mobilities m."""
+        y = self.field() if y is None else y
+        _check(lib().bf_apply_mob(self._h, c, self._ptr(m, "m"), self._ptr(x, "x"),
+                                  self._ptr(y, "y")))
+        return y
+
+    def solve_ch_mob(self, c, m, b, x, opts=None) -> SolveStats:
+        st = SolveStats()
+        _check(lib().bf_solve_ch_mob(self._h, c, self._ptr(m, "m"), self._ptr(b, "b"),
+                                     self._ptr(x, "x"),
+                                     ctypes.byref(opts) if opts is not None else None,
+                                     ctypes.byref(st)))
+        return st
+
+    def step_ch_mob(self, params: Params, phi, opts=None) -> SolveStats:
+        """One Cahn-Hilliard step in place with the mobility M clamp(phi)."""
+        st = SolveStats()
+        _check(lib().bf_step_ch_mob(self._h, ctypes.byref(params), self._ptr(phi, "phi"),
+                                    ctypes.byref(opts) if opts is not None else None,
+                                    ctypes.byref(st)))
         return st
 
     def momentum_predict(self, dt, nu, theta, U, u, v, ustar=None, vstar=None, opts=None):

@@ -66,6 +66,11 @@ using Level = LevelT<double>;
 constexpr int kCoarseN = 4;
 constexpr int kCoarseSize = (kCoarseN + 1) * kCoarseN;
 
+// Internal operator code of the variable-mobility Cahn-Hilliard operator
+// I + c L_m L (bf_solve_ch_mob): applied by its own double-double kernel,
+// solved by GMRES, preconditioned by the constant-mobility V-cycle.
+constexpr int kOpMob = 3;
+
 }  // namespace
 
 struct bf_grid {
@@ -80,6 +85,9 @@ struct bf_grid {
   double *work_p = nullptr;   // projected pressure right-hand side
   double *work_e = nullptr;   // adjoint: W^{-1} eta (allocated on first use)
   double *work_mu = nullptr;  // chemical potential of the right-hand side
+  double *work_m = nullptr;   // mobility field of bf_step_ch_mob (allocated on first use)
+  const double* mob = nullptr;  // mobility field of the current variable-mobility solve
+  double mob_pre = 0.0;         // the mean rounded to 6 bits (preconditioner coefficient)
   double* scal = nullptr;     // device scalars (kNumSlots)
   double* partials = nullptr; // reduction partials (kMaxRedBlocks * 72)
   double* coarse_ch = nullptr;
@@ -331,6 +339,9 @@ OpDesc level_op(int op, int n, double c) {
     A.coef = c * (double)n * (double)n;
     A.dinv_int = 1.0 / (1.0 + 4.0 * A.coef);
     A.dinv_edge = 0.0;  // wall rows: Dirichlet data, never smoothed
+  } else if (op == kOpMob) {
+    A.coef = c;  // the mobility field comes from the grid (g->mob)
+    A.dinv_int = A.dinv_edge = 0.0;
   } else {
     const double s = c * std::pow((double)n, 4);
     A.coef = s;
@@ -681,12 +692,16 @@ double column_sq(const OpDesc& A) {
 int true_residual(bf_grid* g, const OpDesc& A, const double* b, const double* x, double* r,
                   double bn, KrylovState& ks) {
   const int np = nparts_of(g);
-  const int nr = launch_residual_dd(A, x, b, r, g->partials, np, g->stream);
+  const int nr = A.op == kOpMob
+                     ? launch_mob(g->n, A.coef, g->mob, x, b, r, g->partials, np, g->stream)
+                     : launch_residual_dd(A, x, b, r, g->partials, np, g->stream);
   launch_finalize(g->partials, nr, g->scal, F_STORE, S_RTRUE, g->n, g->stream);
   launch_finalize(g->partials + nr, nr, g->scal, F_STORE, S_ULP2, g->n, g->stream);
   TRY(read_scalars(g, S_ULP2 + 1));
   ks.rel_true = std::sqrt(g->h_scal[S_RTRUE]) / bn;
-  ks.floor_est = std::sqrt(g->h_scal[S_ULP2] / 12.0 * column_sq(A)) / bn;
+  // (variable mobility: the kernel already weights ulp(x)^2 by the local column sum)
+  const double csq = A.op == kOpMob ? 1.0 : column_sq(A);
+  ks.floor_est = std::sqrt(g->h_scal[S_ULP2] / 12.0 * csq) / bn;
   if (!std::isfinite(ks.rel_true)) return fail(BF_ENONFINITE, "true residual is not finite");
   return BF_OK;
 }
@@ -840,7 +855,7 @@ int run_gmres(bf_grid* g, int op, double c, const double* b, double* x, const bf
   double last_true = HUGE_VAL;
   for (int cycle = 0;; ++cycle) {
     // r0 = b - A x (double-double), V0 = r0 / ||r0||
-    if (op == BF_OP_CH && cycle > 0) mass_correct(g, b, x);
+    if ((op == BF_OP_CH || op == kOpMob) && cycle > 0) mass_correct(g, b, x);
     TRY(true_residual(g, A, b, x, g->gm_V, bn, ks));
     ks.rel = ks.rel_true;
     if (cycle == 0) {
@@ -868,9 +883,13 @@ int run_gmres(bf_grid* g, int op, double c, const double* b, double* x, const bf
       double* Vk = g->gm_V + (int64_t)k * N;
       double* Zk = g->gm_Z + (int64_t)k * N;
       double* w = g->gm_V + (int64_t)(k + 1) * N;
-      double* zk = precondition(g, op, c, o, Vk);
+      double* zk = op == kOpMob ? precondition(g, BF_OP_CH, c * g->mob_pre, o, Vk)
+                                : precondition(g, op, c, o, Vk);
       launch_copy(N, zk, Zk, st);
-      launch_apply_dot(A, Zk, w, g->partials, np, st, op == BF_OP_CH);
+      if (op == kOpMob)
+        launch_mob(g->n, c, g->mob, Zk, nullptr, w, nullptr, 0, st);
+      else
+        launch_apply_dot(A, Zk, w, g->partials, np, st, op == BF_OP_CH);
       // CGS2: h = V^T_W w, w -= V h, twice
       for (int pass = 0; pass < 2; ++pass) {
         launch_mdot(g->n, g->gm_V, k + 1, w, g->partials, np, st);
@@ -923,7 +942,13 @@ int run_gmres(bf_grid* g, int op, double c, const double* b, double* x, const bf
 int run_krylov(bf_grid* g, int op, double c, const double* b, double* x, const bf_solver_opts& o,
                bf_solve_stats* st) {
   TRY(check_opts(o));
-  TRY(ensure_coarse(g, op, c));
+  if (op == kOpMob) {
+    if (o.ksp != BF_KSP_GMRES)
+      return fail(BF_EINVAL, "the variable-mobility operator is not symmetric: use GMRES");
+    TRY(ensure_coarse(g, BF_OP_CH, c * g->mob_pre));
+  } else {
+    TRY(ensure_coarse(g, op, c));
+  }
   HIPCHK(hipEventRecord(g->ev0, g->stream));
   if (op == BF_OP_HELM) {
     // Dirichlet walls: the iterate starts (and stays) at the wall data in b
@@ -1271,6 +1296,70 @@ int bf_solve_helmholtz(bf_grid* g, double beta, const double* b, double* x,
   bf_solver_opts d;
   default_opts(BF_OP_HELM, &d);
   return run_krylov(g, BF_OP_HELM, beta, b, x, o ? *o : d, st);
+}
+
+int bf_apply_mob(bf_grid* g, double c, const double* m, const double* x, double* y) {
+  TRY(check_grid(g));
+  if (!m || !x || !y) return fail(BF_EINVAL, "null field");
+  if (y == x || y == m) return fail(BF_EINVAL, "y must not alias x or m");
+  if (!(c >= 0) || !std::isfinite(c)) return fail(BF_EINVAL, "c = %g must be finite and >= 0", c);
+  launch_mob(g->n, c, m, x, nullptr, y, nullptr, 0, g->stream);
+  HIPCHK(hipGetLastError());
+  return BF_OK;
+}
+
+int bf_solve_ch_mob(bf_grid* g, double c, const double* m, const double* b, double* x,
+                    const bf_solver_opts* o, bf_solve_stats* st) {
+  TRY(check_grid(g));
+  if (!m || !b || !x) return fail(BF_EINVAL, "null field");
+  if (b == x || m == x) return fail(BF_EINVAL, "x must not alias b or m");
+  if (!(c >= 0) || !std::isfinite(c)) return fail(BF_EINVAL, "c = %g must be finite and >= 0", c);
+  bf_solver_opts d;
+  default_opts(BF_OP_CH, &d);
+  d.ksp = BF_KSP_GMRES;
+  const bf_solver_opts& oo = o ? *o : d;
+  // the preconditioner: the constant-mobility operator at the weighted mean
+  // mobility, rounded to 6 significant bits so that steps whose mean differs
+  // only by rounding (the mass is conserved) reuse one captured V-cycle
+  wdot_async(g, m, nullptr, F_MEAN, 0);
+  TRY(read_scalars(g, S_MEAN + 1));
+  const double mm = g->h_scal[S_MEAN];
+  if (!(mm > 0) || !std::isfinite(mm))
+    return fail(BF_EINVAL, "the mobility must have a positive, finite mean");
+  int e2 = 0;
+  const double fr = std::frexp(mm, &e2);
+  g->mob = m;
+  g->mob_pre = std::ldexp(std::round(std::ldexp(fr, 6)), e2 - 6);
+  const int s = run_krylov(g, kOpMob, c, b, x, oo, st);
+  g->mob = nullptr;
+  return s;
+}
+
+int bf_step_ch_mob(bf_grid* g, const bf_params* prm, double* phi, const bf_solver_opts* o,
+                   bf_solve_stats* stats) {
+  TRY(check_grid(g));
+  if (!prm || !phi) return fail(BF_EINVAL, "null argument");
+  if (!(prm->dt > 0) || !(prm->M > 0) || !(prm->kappa >= 0) || !(prm->Npoly > 0))
+    return fail(BF_EINVAL, "dt, M, Npoly must be > 0 and kappa >= 0");
+  if (!(prm->phi_lo > 0 && prm->phi_lo < prm->phi_hi && prm->phi_hi < 1))
+    return fail(BF_EINVAL, "need 0 < phi_lo < phi_hi < 1");
+  if (!g->work_m) TRY(dalloc(g, &g->work_m, g->npts));
+  hipStream_t st = g->stream;
+  launch_fill_i32(1, g->counter, 0, st);
+  launch_mob_rhs(g->n, phi, g->work_m, g->work_mu, g->work_b, prm->M, prm->dt, 1.0 / prm->Npoly,
+                 prm->chi, prm->phi_lo, prm->phi_hi, g->counter, st);
+  launch_fill(g->npts, phi, 0.0, st);
+  HIPCHK(hipGetLastError());
+  bf_solve_stats local;
+  bf_solve_stats* S = stats ? stats : &local;
+  std::memset(S, 0, sizeof(*S));
+  const int s = bf_solve_ch_mob(g, prm->dt * prm->kappa, g->work_m, g->work_b, phi, o, S);
+  if (s < 0) return s;
+  int32_t clamped = 0;
+  HIPCHK(hipMemcpyAsync(&clamped, g->counter, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  S->clamped = clamped;
+  return s;
 }
 
 int bf_momentum_predict(bf_grid* g, double dt, double nu, double theta, double U,

@@ -475,6 +475,100 @@ __global__ void __launch_bounds__(kBlock) k_lap_axpy(Geo G, const double* __rest
   }
 }
 
+// ------------------------------------------------------------------ variable mobility
+// A_m x = x + c L_m L x with L_m f = n^2 sum_faces m_face (f_nb - f),
+// m_face = (m + m_nb)/2 (the phi-dependent mobility of the modified
+// Cahn-Hilliard equation), ghost rows reflected for x and m alike.  The whole
+// evaluation is carried in double-double (L x at the five points as exact
+// Sum2 sums, the face fluxes, the scaling by c, the addition of x, and for
+// MODE 1 the subtraction from b), so the result is accurate to a few ulps of
+// itself although c n^4 m reaches 1e7.  One node per thread: the 13 values
+// of x and 5 of m around a node come from cache.
+//   MODE 0: y = A_m x.
+//   MODE 1: y = b - A_m x, partials of ||y||_W^2 and of
+//           sum_W ulp(x_k)^2 * colsq_k, colsq_k = (1 + 20 t)^2 + 276 t^2 with
+//           t = c n^4 m_k: the squared column norm of the constant-mobility
+//           operator at the local mobility, so that the representation floor
+//           follows the mobility field (it varies by an order of magnitude).
+template <int MODE>
+__global__ void __launch_bounds__(kBlock) k_mob(Geo G, double c, const double* __restrict__ m,
+                                                const double* __restrict__ x,
+                                                const double* __restrict__ b,
+                                                double* __restrict__ y,
+                                                double* __restrict__ partials) {
+#pragma clang fp contract(off)
+  const int n = G.n, mask = G.mask;
+  const double n2 = (double)n * n;
+  double acc = 0.0, acc_ulp = 0.0;
+  GRID_STRIDE(idx, G.npts) {
+    const int i = (int)(idx & mask), j = (int)(idx >> G.log2n);
+    auto X = [&](int jj, int ii) { return x[(int64_t)refl(jj, n) * n + (ii & mask)]; };
+    auto T = [&](int jj, int ii) {  // (L x) at (ii, jj) in double-double
+      const DD s = dd_lap_sum(X(jj, ii - 1), X(jj, ii + 1), X(jj - 1, ii), X(jj + 1, ii),
+                              X(jj, ii));
+      return DD{s.hi * n2, s.lo * n2};
+    };
+    const double mc = m[idx];
+    const DD tc = T(j, i);
+    const int dj[4] = {0, 0, -1, 1}, di[4] = {-1, 1, 0, 0};
+    DD f{0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int jj = j + dj[k], ii = i + di[k];
+      const double mf = 0.5 * (mc + m[(int64_t)refl(jj, n) * n + (ii & mask)]);
+      f = dd_add(f, dd_mul_d(dd_sub(T(jj, ii), tc), mf));
+    }
+    f = DD{f.hi * n2, f.lo * n2};
+    const double xc = x[idx];
+    const DD ax = dd_add_d(dd_mul_d(f, c), xc);
+    if (MODE == 0) {
+      y[idx] = ax.hi + ax.lo;
+    } else {
+      const DD r = dd_add_d(DD{-ax.hi, -ax.lo}, b[idx]);
+      const double rv = r.hi + r.lo;
+      y[idx] = rv;
+      const double w = row_weight(j, n);
+      acc += w * rv * rv;
+      const double u = ulp_of(xc);
+      const double t = c * n2 * n2 * mc;
+      acc_ulp += w * u * u * ((1.0 + 20.0 * t) * (1.0 + 20.0 * t) + 276.0 * t * t);
+    }
+  }
+  if (MODE == 1) {
+    const double t = block_sum(acc);
+    if (threadIdx.x == 0) partials[blockIdx.x] = t;
+    const double tu = block_sum(acc_ulp);
+    if (threadIdx.x == 0) partials[gridDim.x + blockIdx.x] = tu;
+  }
+}
+
+// Variable-mobility right-hand side: m = M clamp(phi) (written), then
+// b = phi + dt L_m mu with mu from k_mu (plain float64).
+__global__ void __launch_bounds__(kBlock) k_mob_field(Geo G, const double* __restrict__ phi,
+                                                      double* __restrict__ m, double M, double lo,
+                                                      double hi) {
+  GRID_STRIDE(idx, G.npts) m[idx] = M * clampd(phi[idx], lo, hi);
+}
+
+__global__ void __launch_bounds__(kBlock) k_mob_rhs(Geo G, const double* __restrict__ phi,
+                                                    const double* __restrict__ mu,
+                                                    const double* __restrict__ m,
+                                                    double* __restrict__ b, double scale) {
+  const int n = G.n, mask = G.mask;
+  GRID_STRIDE(idx, G.npts) {
+    const int i = (int)(idx & mask), j = (int)(idx >> G.log2n);
+    const double mc = m[idx], uc = mu[idx];
+    const int dj[4] = {0, 0, -1, 1}, di[4] = {-1, 1, 0, 0};
+    double f = 0.0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int64_t o = (int64_t)refl(j + dj[k], n) * n + ((i + di[k]) & mask);
+      f += 0.5 * (mc + m[o]) * (mu[o] - uc);
+    }
+    b[idx] = phi[idx] + scale * f;
+  }
+}
+
 // rhs = (u[i+1] - u[i-1] + v[j+1] - v[j-1]) * scale, v odd across the walls.
 __global__ void __launch_bounds__(kBlock) k_divergence(Geo G, const double* __restrict__ u,
                                                        const double* __restrict__ v,
@@ -940,6 +1034,26 @@ void launch_ch_rhs(int n, const double* phi, const double* prev, const double* b
   const Geo G = make_geo(n);
   LAUNCH(k_mu, ew_blocks(G.npts), st, G, phi, prev, mu_ws, inv_npoly, chi, lo, hi, clamp_count);
   LAUNCH(k_lap_axpy, ew_blocks(G.npts), st, G, mu_ws, base, b, dtM * (double)n * (double)n);
+}
+
+int launch_mob(int n, double c, const double* m, const double* x, const double* b, double* y,
+               double* partials, int nparts, hipStream_t st) {
+  const Geo G = make_geo(n);
+  if (!b) {
+    LAUNCH(k_mob<0>, ew_blocks(G.npts), st, G, c, m, x, nullptr, y, nullptr);
+    return 0;
+  }
+  LAUNCH(k_mob<1>, nparts, st, G, c, m, x, b, y, partials);
+  return nparts;
+}
+
+void launch_mob_rhs(int n, const double* phi, double* m, double* mu_ws, double* b, double M,
+                    double dt, double inv_npoly, double chi, double lo, double hi,
+                    int32_t* clamp_count, hipStream_t st) {
+  const Geo G = make_geo(n);
+  LAUNCH(k_mu, ew_blocks(G.npts), st, G, phi, nullptr, mu_ws, inv_npoly, chi, lo, hi, clamp_count);
+  LAUNCH(k_mob_field, ew_blocks(G.npts), st, G, phi, m, M, lo, hi);
+  LAUNCH(k_mob_rhs, ew_blocks(G.npts), st, G, phi, mu_ws, m, b, dt * (double)n * (double)n);
 }
 
 void launch_divergence(int n, const double* u, const double* v, double* rhs, double scale,

@@ -195,6 +195,16 @@ void launch_ch_rhs(int n, const double* phi, const double* prev, const double* b
                    int32_t* clamp_count, hipStream_t st);
 void launch_divergence(int n, const double* u, const double* v, double* rhs, double scale,
                        hipStream_t st);
+// Variable-mobility Cahn-Hilliard operator A_m = I + c L_m L (double-double
+// evaluation): y = A_m x (b == nullptr) or y = b - A_m x with partials of
+// ||y||_W^2 and of sum_W ulp(x)^2 times the local squared column norm (two
+// groups; returns the group size).
+int launch_mob(int n, double c, const double* m, const double* x, const double* b, double* y,
+               double* partials, int nparts, hipStream_t st);
+// m = M clamp(phi); mu_ws = mu_FH(clamp(phi)); b = phi + dt L_m mu_ws.
+void launch_mob_rhs(int n, const double* phi, double* m, double* mu_ws, double* b, double M,
+                    double dt, double inv_npoly, double chi, double lo, double hi,
+                    int32_t* clamp_count, hipStream_t st);
 void launch_momentum_rhs(int n, const double* u, const double* v, double dt, double e, double U,
                          double* bu, double* bv, hipStream_t st);
 void launch_velocity(int n, const double* p, const double* us, const double* vs, double* u,

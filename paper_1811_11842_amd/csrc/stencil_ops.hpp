@@ -149,6 +149,60 @@ __device__ __forceinline__ void two_prod(double a, double b, double& p, double& 
   e = fma(a, b, -p);
 }
 
+// Double-double numbers (hi + lo, |lo| <= ulp(hi)/2) for the variable-
+// mobility operator, whose coefficients are not small integers: sums and
+// products by float64 values carried with the error-free transformations
+// above (Dekker/Knuth; relative error of a few u^2).
+struct DD {
+  double hi, lo;
+};
+
+__device__ __forceinline__ DD dd_norm(double s, double e) {
+#pragma clang fp contract(off)
+  const double hi = s + e;
+  return DD{hi, e - (hi - s)};
+}
+
+__device__ __forceinline__ DD dd_add(DD a, DD b) {
+#pragma clang fp contract(off)
+  double s, e;
+  two_sum(a.hi, b.hi, s, e);
+  e += a.lo + b.lo;
+  return dd_norm(s, e);
+}
+
+__device__ __forceinline__ DD dd_add_d(DD a, double b) {
+#pragma clang fp contract(off)
+  double s, e;
+  two_sum(a.hi, b, s, e);
+  e += a.lo;
+  return dd_norm(s, e);
+}
+
+__device__ __forceinline__ DD dd_sub(DD a, DD b) { return dd_add(a, DD{-b.hi, -b.lo}); }
+
+__device__ __forceinline__ DD dd_mul_d(DD a, double b) {
+#pragma clang fp contract(off)
+  double p, e;
+  two_prod(a.hi, b, p, e);
+  e = fma(a.lo, b, e);
+  return dd_norm(p, e);
+}
+
+// (a + b + c + d - 4 e) as a double-double (Sum2 cascade; 4 e is exact).
+__device__ __forceinline__ DD dd_lap_sum(double a, double b, double c, double d, double e) {
+#pragma clang fp contract(off)
+  const double t[4] = {b, c, d, -4.0 * e};
+  double hi = a, lo = 0.0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    double err;
+    two_sum(hi, t[k], hi, err);
+    lo += err;
+  }
+  return dd_norm(hi, lo);
+}
+
 // b - A x with the stencil sum carried in double-double: the integer stencil
 // weights make every term exact (20 c through two_prod, the others are
 // power-of-two multiples), the cascaded two_sum (Ogita-Rump-Oishi Sum2)

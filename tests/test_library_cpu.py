@@ -14,7 +14,7 @@ def test_header_declares_the_entry_points():
     names = bf.declared_symbols()
     for must in ("bf_grid_create", "bf_step", "bf_solve_ch", "bf_solve_pressure",
                  "bf_adjoint_step", "bf_apply", "bf_last_error", "bf_solve_helmholtz",
-                 "bf_momentum_predict"):
+                 "bf_momentum_predict", "bf_apply_mob", "bf_solve_ch_mob", "bf_step_ch_mob"):
         assert must in names
 
 
@@ -64,6 +64,9 @@ def test_invalid_grid_arguments_rejected_before_any_device_work():
     assert L.bf_solve_helmholtz(None, 0.0, None, None, None, None) == bf.EINVAL
     assert L.bf_momentum_predict(None, 1e-3, 1.0, 0.5, 0.0, None, None, None, None, None,
                                  None) == bf.EINVAL
+    assert L.bf_apply_mob(None, 0.0, None, None, None) == bf.EINVAL
+    assert L.bf_solve_ch_mob(None, 0.0, None, None, None, None, None) == bf.EINVAL
+    assert L.bf_step_ch_mob(None, None, None, None, None) == bf.EINVAL
 
 
 def test_missing_library_fails_loudly(tmp_path, monkeypatch):

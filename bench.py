@@ -287,6 +287,27 @@ def time_predictor(g, n, calls=5):
     return res
 
 
+def time_mobility(g, n, steps=3):
+    """Cahn-Hilliard steps with the phi-dependent mobility (bf_step_ch_mob:
+    GMRES(30) preconditioned by the constant-mobility float32 V-cycle, rtol
+    1e-10): wall time per step."""
+    phi = torch.from_numpy(S.initial_phi(n)).to(g.device)
+    prm = bf.make_params(**S.DEFAULT_PARAMS)
+    o = bf.default_opts(bf.OP_CH, ksp=bf.KSP_GMRES, mg_precision=bf.MG_F32)
+    g.step_ch_mob(prm, phi, o)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its, sts = [], []
+    for _ in range(steps):
+        st = g.step_ch_mob(prm, phi, o)
+        its.append(st.iters)
+        sts.append(st.status)
+    torch.cuda.synchronize()
+    return {"n": n, "steps": steps, "ms_per_step": round((time.perf_counter() - t0) / steps * 1e3, 3),
+            "gmres_iters_mean": float(np.mean(its)),
+            "status": sorted({bf.STATUS_NAMES.get(s, str(s)) for s in sts})}
+
+
 def time_adjoint(n=2048, steps=20, every=5):
     """Gradient of the upper-half mass after `steps` advected Cahn-Hilliard
     steps with respect to phi0, chi and the inflow speed (checkpoints every
@@ -442,6 +463,8 @@ def main():
             out["crank_nicolson"] = time_cn(g, n)
             log("momentum predictor (two Helmholtz solves)")
             out["momentum_predictor"] = time_predictor(g, n)
+            log("variable-mobility Cahn-Hilliard steps")
+            out["variable_mobility"] = time_mobility(g, n)
         out["adjoint"] = time_adjoint()
     if not (a.no_ensemble or a.spmv_only or a.steps_only or a.smooth_only):
         log("batched ensemble: 64 instances, 10 steps (and the same one by one)")

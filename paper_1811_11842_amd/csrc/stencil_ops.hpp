@@ -112,9 +112,8 @@ __host__ __device__ __forceinline__ double row_coef(double coef, int j, int n) {
 // Smoother weight D^{-1} on row j: the 13-point operator's diagonal is 21 s
 // on rows 1 and n-1 (dinv_edge there); OP 2 leaves its wall rows alone
 // (dinv_edge = 0 there).
-template <int OP>
-__host__ __device__ __forceinline__ double row_dinv(double dinv_int, double dinv_edge, int j,
-                                                    int n) {
+template <int OP, typename R = double>
+__host__ __device__ __forceinline__ R row_dinv(R dinv_int, R dinv_edge, int j, int n) {
   if (OP == 1) return (j == 1 || j == n - 1) ? dinv_edge : dinv_int;
   if (OP == 2) return (j == 0 || j == n) ? dinv_edge : dinv_int;
   return dinv_int;

@@ -91,21 +91,29 @@ struct StreamArgs {
 };
 
 // Lane i receives the value of lane i-1 (DPP wave_shr:1) or of lane i+1
-// (wave_shl:1); lanes without a source receive 0 (replaced by the caller).
-__device__ __forceinline__ float from_left(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, false));
+// (wave_shl:1).  The lane without a source (lane 0, resp. lane 63) keeps
+// `edge` -- the DPP's old value -- which is where the caller puts the halo
+// column that lane loaded itself, so no select follows the shift.
+__device__ __forceinline__ float from_left(float v, float edge) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(edge), __float_as_int(v), 0x138,
+                                                    0xf, 0xf, false));
 }
-__device__ __forceinline__ float from_right(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, false));
+__device__ __forceinline__ float from_right(float v, float edge) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(edge), __float_as_int(v), 0x130,
+                                                    0xf, 0xf, false));
 }
-__device__ __forceinline__ double from_left(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x138, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x138, 0xf, 0xf, false);
+__device__ __forceinline__ double from_left(double v, double edge) {
+  const int lo = __builtin_amdgcn_update_dpp(__double2loint(edge), __double2loint(v), 0x138, 0xf,
+                                             0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(__double2hiint(edge), __double2hiint(v), 0x138, 0xf,
+                                             0xf, false);
   return __hiloint2double(hi, lo);
 }
-__device__ __forceinline__ double from_right(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x130, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x130, 0xf, 0xf, false);
+__device__ __forceinline__ double from_right(double v, double edge) {
+  const int lo = __builtin_amdgcn_update_dpp(__double2loint(edge), __double2loint(v), 0x130, 0xf,
+                                             0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(__double2hiint(edge), __double2hiint(v), 0x130, 0xf,
+                                             0xf, false);
   return __hiloint2double(hi, lo);
 }
 
@@ -173,12 +181,17 @@ __global__ void __launch_bounds__(kStreamTPB) k_stream(StreamArgs<T, TO> P) {
       alpha_prev = P.scal[(int64_t)inst * kNumSlots + S_ALPHA];
     }
   }
-  auto dinv_row = [&](int jr) -> T { return T(row_dinv<OP>(di, de, jr, n)); };
+  const T tdi = T(di), tde = T(de), tcoef = T(cf);
+  auto dinv_row = [&](int jr) -> T { return row_dinv<OP, T>(tdi, tde, jr, n); };
   double acc = 0.0, acc2 = 0.0;
   const bool skip = P.active && !P.active[inst];
 
   const int wpb = kStreamTPB / 64;
-  for (int t = lblock * wpb + (threadIdx.x >> 6); !skip && t < P.tiles; t += P.bpi * wpb) {
+  // the tile index is the same on every lane of a wavefront: keeping it in a
+  // scalar register makes the row arithmetic (reflection, row addresses,
+  // bounds) scalar
+  const int t0 = __builtin_amdgcn_readfirstlane(lblock * wpb + (threadIdx.x >> 6));
+  for (int t = t0; !skip && t < P.tiles; t += P.bpi * wpb) {
     const int rg = t / P.wstrips;
     const int strip = t - rg * P.wstrips;
     const int j0 = rg * RPW;
@@ -234,22 +247,11 @@ __global__ void __launch_bounds__(kStreamTPB) k_stream(StreamArgs<T, TO> P) {
     }
 
     // neighbours across lanes: column c-1, c-2 (left) and c+V, c+V+1 (right)
-    auto left1 = [&](const XRow<T, V>& r) {
-      const T v = from_left(r.o[V - 1]);
-      return hl ? r.h1 : v;
-    };
-    auto left2 = [&](const XRow<T, V>& r) {
-      const T v = from_left(r.o[V - 2]);
-      return hl ? r.h0 : v;
-    };
-    auto right1 = [&](const XRow<T, V>& r) {
-      const T v = from_right(r.o[0]);
-      return hr ? r.h0 : v;
-    };
-    auto right2 = [&](const XRow<T, V>& r) {
-      const T v = from_right(r.o[1]);
-      return hr ? r.h1 : v;
-    };
+    // (lane 0 holds columns c-2, c-1 in h0, h1; lane 63 columns c+V, c+V+1)
+    auto left1 = [&](const XRow<T, V>& r) { return from_left(r.o[V - 1], r.h1); };
+    auto left2 = [&](const XRow<T, V>& r) { return from_left(r.o[V - 2], r.h0); };
+    auto right1 = [&](const XRow<T, V>& r) { return from_right(r.o[0], r.h0); };
+    auto right2 = [&](const XRow<T, V>& r) { return from_right(r.o[1], r.h1); };
 
 #pragma unroll
     for (int s = 0; s < RPW; ++s) {
@@ -306,7 +308,7 @@ __global__ void __launch_bounds__(kStreamTPB) k_stream(StreamArgs<T, TO> P) {
       const int64_t o = (int64_t)j * n + c;
       const double wgt = row_weight(j, n);
       const double cfj = row_coef<OP>(cf, j, n);
-      const T coefj = T(cfj);
+      const T coefj = (OP == 2 && (j == 0 || j == n)) ? T(0) : tcoef;
       VT bcur{}, pcur{};
       if constexpr (NEEDB) bcur = *reinterpret_cast<const VT*>(Bp + o);
       if constexpr (NEEDP) {

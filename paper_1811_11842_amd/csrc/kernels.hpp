@@ -104,10 +104,11 @@ template <typename T>
 void stream_restrict(int nf, const T* fine, T* coarse, hipStream_t st);
 
 // Coarse tail: all levels 8 <= n <= kTailTop plus the exact 5 x 4 solve in
-// one workgroup with the fields in LDS (tail.hip).
-constexpr int kTailTop = 32;
-constexpr int kTailMaxLevels = 3;     // n = 32, 16, 8
-constexpr int kTailMaxDoubles = 5640; // 4 (33*32 + 17*16 + 9*8) + 2 * 20
+// one workgroup with the fields in LDS (tail.hip): three fields per level
+// (two iterates, right-hand side), 16720 elements = 134 KB in float64.
+constexpr int kTailTop = 64;
+constexpr int kTailMaxLevels = 4;      // n = 64, 32, 16, 8
+constexpr int kTailMaxDoubles = 16720; // 3 (65*64 + 33*32 + 17*16 + 9*8) + 2 * 20
 struct TailLevel {
   int n;
   int degree;

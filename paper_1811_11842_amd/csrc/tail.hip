@@ -1,9 +1,10 @@
-// Coarse tail of the V-cycle: every level with n <= 32 (down to the exact
+// Coarse tail of the V-cycle: every level with n <= 64 (down to the exact
 // solve on the 5 x 4 grid) runs inside one workgroup of 1024 threads, with all
-// fields of those levels resident in LDS (about 45 KB).  On these levels a
-// separate launch per sweep would cost far more than the arithmetic (each
-// grid is at most 33 x 32 nodes), so the whole lower part of the cycle is a
-// single launch whose phases are separated by workgroup barriers.
+// fields of those levels resident in LDS (134 KB in float64, of the 160 KB of
+// a CU).  On these levels a separate launch per sweep would cost far more
+// than the arithmetic (each grid is at most 65 x 64 nodes), so the whole lower
+// part of the cycle is a single launch whose phases are separated by
+// workgroup barriers.
 //
 // The operations are those of the global-memory kernels (same device
 // helpers): the polynomial smoother, the residual, R and P, and x = G b on the
@@ -18,13 +19,18 @@ namespace bf {
 
 constexpr int kTailThreads = 1024;
 
-// LDS layout: for each smoothing level (n = top, top/2, ..., 8) four arrays
-// xa, xb, b, r of (n+1) n doubles, then the coarsest x and b (20 each).
+// LDS layout: for each smoothing level (n = top, top/2, ..., 8) three arrays
+// xa, xb, b of (n+1) n elements, then the coarsest x and b (20 each).  The
+// residual of the downward leg goes into whichever of xa, xb the
+// pre-smoothing no longer needs (the first post-smoothing sweep, with
+// Chebyshev coefficient g = 0, does not read it).
 __host__ __device__ inline int tail_lds_doubles(int top) {
   int total = 0;
-  for (int n = top; n > 4; n /= 2) total += 4 * (n + 1) * n;
+  for (int n = top; n > 4; n /= 2) total += 3 * (n + 1) * n;
   return total + 2 * 20;
 }
+static_assert(kTailMaxDoubles >= 3 * (65 * 64 + 33 * 32 + 17 * 16 + 9 * 8) + 40,
+              "tail LDS too small for its top level");
 
 template <int OP, typename T>
 __device__ void tail_sweep(const TailLevel& L, const T* x, const T* xprev, const T* b, T* xout,
@@ -52,15 +58,13 @@ __device__ void tail_body(const TailArgs& P, const T* b_in, T* x_out) {
   T* xa[kTailMaxLevels];
   T* xb[kTailMaxLevels];
   T* bb[kTailMaxLevels];
-  T* rr[kTailMaxLevels];
   int off = 0;
   for (int l = 0; l < P.nlev; ++l) {
     const int npts = (P.lev[l].n + 1) * P.lev[l].n;
     xa[l] = lds + off;
     xb[l] = xa[l] + npts;
     bb[l] = xb[l] + npts;
-    rr[l] = bb[l] + npts;
-    off += 4 * npts;
+    off += 3 * npts;
   }
   T* xc = lds + off;  // coarsest x (20)
   T* bc = xc + 20;    // coarsest b (20)
@@ -93,11 +97,12 @@ __device__ void tail_body(const TailArgs& P, const T* b_in, T* x_out) {
       cur = o;
       o = t;
     }
-    // residual
+    // residual, into the iterate buffer the sweeps are done with
+    T* rl = o;
     for (int idx = tid; idx < npts; idx += kTailThreads) {
       const int i = idx & (n - 1), j = idx / n;
       const Nb13T<T> v = gather<OP>(cur, i, j, n, n - 1);
-      rr[l][idx] = bb[l][idx] - apply_vals<OP>(v, T(row_coef<OP>(L.coef, j, n)));
+      rl[idx] = bb[l][idx] - apply_vals<OP>(v, T(row_coef<OP>(L.coef, j, n)));
     }
     __syncthreads();
     // restriction to the next level (or to the coarsest grid)
@@ -105,7 +110,7 @@ __device__ void tail_body(const TailArgs& P, const T* b_in, T* x_out) {
     T* bnext = (l + 1 < P.nlev) ? bb[l + 1] : bc;
     for (int idx = tid; idx < cpts; idx += kTailThreads) {
       const int I = idx & (nc - 1), J = idx / nc;
-      bnext[idx] = restrict_at(rr[l], n, n - 1, I, J);
+      bnext[idx] = restrict_at(rl, n, n - 1, I, J);
     }
     __syncthreads();
     res[l] = cur;

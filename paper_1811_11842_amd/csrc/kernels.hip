@@ -920,7 +920,8 @@ void launch_jacobi_pc(const OpDesc& A, const double* r, double* z, hipStream_t s
 
 template <typename T>
 void launch_restrict(int nf, const T* fine, T* coarse, hipStream_t st) {
-  if (transfer_stream_ok(nf)) {
+  // (a batch of instances fills the GPU with tiles already from nf = 256)
+  if (transfer_stream_ok(nf) || (batch_count() > 1 && nf >= 256)) {
     stream_restrict<T>(nf, fine, coarse, st);
     return;
   }
@@ -932,7 +933,7 @@ template void launch_restrict<float>(int, const float*, float*, hipStream_t);
 
 template <typename T>
 void launch_prolong_add(int nf, const T* coarse, T* fine, hipStream_t st) {
-  if (transfer_stream_ok(nf)) {
+  if (transfer_stream_ok(nf) || (batch_count() > 1 && nf >= 256)) {
     stream_prolong_add<T>(nf, coarse, fine, st);
     return;
   }

@@ -13,6 +13,8 @@
 // row-group-major, so the resident wavefronts cover one compact band of rows.
 #include <hip/hip_runtime.h>
 
+#include <cstdlib>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -210,7 +212,19 @@ TArgs targs(int nf, int& blocks) {
 
 }  // namespace
 
-bool transfer_stream_ok(int nf) { return nf >= 256; }
+// Single fine grids from 2048 up use the tiled transfers; below, the
+// one-node-per-thread kernels, whose many short threads finish sooner there
+// (measured per launch, float32: nf = 1024 restriction 6.5 us against 8.4
+// tiled, 512 and 256 about 4.7 against 7-8; nf = 2048 prolongation 21 us
+// against 9.8 tiled).  BF_TRANSFER_TILE_MIN overrides the threshold (>= 256).
+bool transfer_stream_ok(int nf) {
+  static const int lim = [] {
+    const char* v = std::getenv("BF_TRANSFER_TILE_MIN");
+    const int x = v ? std::atoi(v) : 0;
+    return x >= 256 ? x : 2048;
+  }();
+  return nf >= lim;
+}
 
 template <typename T>
 void stream_prolong_add(int nf, const T* coarse, T* fine, hipStream_t st) {

@@ -97,7 +97,7 @@ def test_smooth_sweep_and_copy_match_oracle(dev, n, op):
     assert np.array_equal(y, x)
 
 
-@pytest.mark.parametrize("nf", [8, 16, 128, 256, 512, 1024])
+@pytest.mark.parametrize("nf", [8, 16, 128, 256, 512, 1024, 2048, 4096])
 def test_restrict_and_prolong_match_oracle(dev, nf):
     g = grid(max(nf, 8))
     f = S.random_field(nf, seed=7 + nf)

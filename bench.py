@@ -466,6 +466,13 @@ def main():
             log("variable-mobility Cahn-Hilliard steps")
             out["variable_mobility"] = time_mobility(g, n)
         out["adjoint"] = time_adjoint()
+        log("float64 steps at 1024^2 (the plain float64 baseline configuration)")
+        with bf.Grid(1024) as g1:
+            ms1, _, st1, _ = time_steps(g1, 1024, 10, 2, bf.MG_F64)
+        out["fp64_1024"] = {"n": 1024, "steps": 10, "ms_per_step": round(ms1, 4),
+                            "ch_iters_mean": float(np.mean([s[0].iters for s in st1])),
+                            "scaled_to_4096_ms": round(ms1 * 16, 3),
+                            "note": "x16 points; measured 4096^2 float64 is fp64_ms_per_step"}
     if not (a.no_ensemble or a.spmv_only or a.steps_only or a.smooth_only):
         log("batched ensemble: 64 instances, 10 steps (and the same one by one)")
         out["ensemble"] = time_ensemble()

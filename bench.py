@@ -289,11 +289,11 @@ def time_predictor(g, n, calls=5):
 
 def time_mobility(g, n, steps=3):
     """Cahn-Hilliard steps with the phi-dependent mobility (bf_step_ch_mob:
-    GMRES(30) preconditioned by the constant-mobility float32 V-cycle, rtol
+    GMRES(10) preconditioned by the constant-mobility float32 V-cycle, rtol
     1e-10): wall time per step."""
     phi = torch.from_numpy(S.initial_phi(n)).to(g.device)
     prm = bf.make_params(**S.DEFAULT_PARAMS)
-    o = bf.default_opts(bf.OP_CH, ksp=bf.KSP_GMRES, mg_precision=bf.MG_F32)
+    o = bf.default_opts(bf.OP_CH, ksp=bf.KSP_GMRES, restart=10, mg_precision=bf.MG_F32)
     g.step_ch_mob(prm, phi, o)
     torch.cuda.synchronize()
     t0 = time.perf_counter()

@@ -170,7 +170,7 @@ int bf_apply_mob(bf_grid* g, double c, const double* m, const double* x, double*
 
 /* Solve (I + c L_m L) x = b (the operator of bf_apply_mob).  L_m L is not
  * symmetric: the solve is GMRES (o->ksp must be BF_KSP_GMRES; o == NULL gives
- * GMRES(30) + multigrid, rtol 1e-10) right-preconditioned by the
+ * GMRES(10) + multigrid, rtol 1e-10) right-preconditioned by the
  * constant-mobility V-cycle of I + c mbar L^2, mbar the weighted mean of m
  * rounded to 6 significant bits.  Residuals in double-double; the constant
  * mode is corrected as in bf_solve_ch (L_m conserves the weighted sum).

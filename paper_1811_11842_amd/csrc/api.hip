@@ -1317,6 +1317,7 @@ int bf_solve_ch_mob(bf_grid* g, double c, const double* m, const double* b, doub
   bf_solver_opts d;
   default_opts(BF_OP_CH, &d);
   d.ksp = BF_KSP_GMRES;
+  d.restart = 10;  // at 4096^2: 231 ms per step against 320 with GMRES(30) (orthogonalisation)
   const bf_solver_opts& oo = o ? *o : d;
   // the preconditioner: the constant-mobility operator at the weighted mean
   // mobility, rounded to 6 significant bits so that steps whose mean differs

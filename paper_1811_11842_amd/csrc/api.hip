@@ -80,6 +80,8 @@ struct bf_grid {
   std::vector<Level> lv;
   std::vector<LevelT<float>> lvf;  // float32 hierarchy (allocated on first mixed use)
   float* r32 = nullptr;            // float32 copy of the V-cycle's level-0 input
+  float* z32 = nullptr;            // float32 V-cycle output read by the mixed CG step
+  bool want_z32 = false;           // the float32 V-cycle writes z32 instead of z
   double *r = nullptr, *z = nullptr, *p = nullptr, *p2 = nullptr, *q = nullptr;
   double *work_b = nullptr;   // Cahn-Hilliard right-hand side inside bf_step
   double *work_p = nullptr;   // projected pressure right-hand side
@@ -101,7 +103,7 @@ struct bf_grid {
   // Captured V-cycles (one hipGraphExec per operator / coefficient / options /
   // input buffer), replayed with a single launch; captured on cap_stream.
   struct VcGraph {
-    int op, smoother, degree, rz, prec;
+    int op, smoother, degree, rz, prec, z32;
     double c, ratio, omega;
     const void* b;
     hipGraphExec_t exec;
@@ -169,9 +171,12 @@ int ensure_mixed(bf_grid* g) {
     lv.push_back(L);
   }
   float* r32 = nullptr;
+  float* z32 = nullptr;
   TRY(fal(&r32, g->npts));
+  TRY(fal(&z32, g->npts));
   g->lvf = lv;
   g->r32 = r32;
+  g->z32 = z32;
   return BF_OK;
 }
 
@@ -416,14 +421,16 @@ Smoother make_smoother(int op, int n, double c, const bf_solver_opts& o) {
 // caller must reduce <b, z>_W itself).
 //
 // float32 hierarchy (mixed precision): level 0 must be given zout, the
-// float64 output, and bd, the float64 right-hand side that b rounds.  The
-// last sweep writes z into zout and partials of <b, z>_W (first group) and
-// <z, q>_W (second group, q = g->q) into g->partials; *rz_parts (if given)
-// receives the group size.  Returns nullptr at level 0 (the result is zout).
+// float64 output, or (streamed level 0 only) zout32, a float32 one, and bd,
+// the float64 right-hand side that b rounds.  The last sweep writes z into
+// zout / zout32 and partials of <b, z>_W (first group) and <z, q>_W (second
+// group, q = g->q) into g->partials; *rz_parts (if given) receives the group
+// size.  Returns nullptr at level 0 (the result is zout / zout32).
 template <typename T>
 T* vcycle_level(bf_grid* g, std::vector<LevelT<T>>& lv, int op, double c,
                 const bf_solver_opts& o, int l, const T* b, int* rz_parts = nullptr,
-                double* zout = nullptr, const double* bd = nullptr) {
+                double* zout = nullptr, const double* bd = nullptr,
+                float* zout32 = nullptr) {
   constexpr bool F32 = std::is_same<T, float>::value;
   LevelT<T>& L = lv[l];
   hipStream_t st = g->stream;
@@ -504,9 +511,12 @@ T* vcycle_level(bf_grid* g, std::vector<LevelT<T>>& lv, int op, double c,
     const T* prev = S.g[k] != 0.0 ? oth : nullptr;
     const bool last = k == S.degree - 1;
     if constexpr (F32) {
-      if (last && zout) {
+      if (last && (zout || zout32)) {
         int np;
-        if (streamed) {
+        if (streamed && zout32) {
+          np = stream_smooth_dot2_f32(A, cur, prev, b, zout32, g->q, S.a[k], S.g[k], g->partials,
+                                      st);
+        } else if (streamed) {
           np = stream_smooth_dot2(A, cur, prev, b, zout, g->q, S.a[k], S.g[k], g->partials, st);
         } else {
           np = nparts_of(g);
@@ -536,7 +546,8 @@ T* vcycle_level(bf_grid* g, std::vector<LevelT<T>>& lv, int op, double c,
 double* vcycle_top(bf_grid* g, int op, double c, const bf_solver_opts& o, const double* r,
                    int* rz_parts) {
   if (o.mg_precision == BF_MG_F32) {
-    vcycle_level<float>(g, g->lvf, op, c, o, 0, g->r32, rz_parts, g->z, r);
+    vcycle_level<float>(g, g->lvf, op, c, o, 0, g->r32, rz_parts, g->want_z32 ? nullptr : g->z,
+                        r, g->want_z32 ? g->z32 : nullptr);
     return g->z;
   }
   return vcycle_level<double>(g, g->lv, op, c, o, 0, r, rz_parts);
@@ -572,7 +583,7 @@ double* vcycle_graph(bf_grid* g, int op, double c, const bf_solver_opts& o, cons
   for (auto& e : g->graphs) {
     if (e.op == op && e.c == c && e.smoother == o.smoother && e.degree == o.degree &&
         e.ratio == o.ratio && e.omega == o.omega && e.b == b && e.rz == rz &&
-        e.prec == o.mg_precision) {
+        e.prec == o.mg_precision && e.z32 == (g->want_z32 ? 1 : 0)) {
       if (hipGraphLaunch(e.exec, g->stream) != hipSuccess) return nullptr;
       if (rz_parts) *rz_parts = e.rz_parts;
       return e.result;
@@ -592,6 +603,7 @@ double* vcycle_graph(bf_grid* g, int op, double c, const bf_solver_opts& o, cons
   e.b = b;
   e.rz = rz;
   e.prec = o.mg_precision;
+  e.z32 = g->want_z32 ? 1 : 0;
   e.rz_parts = 0;
   hipStream_t user = g->stream;
   if (hipStreamBeginCapture(g->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
@@ -764,6 +776,13 @@ int run_cg(bf_grid* g, int op, double c, const double* b, double* x, const bf_so
   // smoothing sweep reduces together with rho_k = <r_k, z_k>_W.
   const bool mixed = o.pc == BF_PC_MG && o.mg_precision == BF_MG_F32;
   if (mixed) TRY(ensure_mixed(g));
+  // streamed top level: the float32 V-cycle hands z over in float32 (z32)
+  const bool zf32 = mixed && stream_ok(g->n, 4);
+  struct Z32Scope {
+    bf_grid* g;
+    ~Z32Scope() { g->want_z32 = false; }
+  } z32_scope{g};
+  g->want_z32 = zf32;
   double* pcur = g->p;
   double* pnext = g->p2;
   for (;;) {
@@ -780,7 +799,8 @@ int run_cg(bf_grid* g, int op, double c, const double* b, double* x, const bf_so
     while (ks.iters < o.maxit) {
       // p' = z + beta p, q = A p' (+ <p', q>), and the deferred x += alpha p
       const int npq =
-          launch_cg_p(A, z, pcur, pnext, g->q, x, g->scal, first, g->partials, np, st);
+          zf32 ? stream_cg_p32(A, g->z32, pcur, pnext, g->q, x, g->scal, first, g->partials, st)
+               : launch_cg_p(A, z, pcur, pnext, g->q, x, g->scal, first, g->partials, np, st);
       launch_finalize(g->partials, npq, g->scal, F_ALPHA, 0, g->n, st);
       std::swap(pcur, pnext);
       first = false;

@@ -78,6 +78,13 @@ void stream_smooth_prev_from_b(const OpDesc& A, const T* x, const T* b, T* xout,
 int stream_smooth_dot2(const OpDesc& A, const float* x, const float* xprev, const float* b,
                        double* xout, const double* q, double a, double g, double* partials,
                        hipStream_t st);
+// The same sweep writing z in float32 (the CG step then reads it with
+// stream_cg_p32; z is a float32 result, so nothing is lost).
+int stream_smooth_dot2_f32(const OpDesc& A, const float* x, const float* xprev, const float* b,
+                           float* xout, const double* q, double a, double g, double* partials,
+                           hipStream_t st);
+int stream_cg_p32(const OpDesc& A, const float* z, const double* p_old, double* p_new, double* q,
+                  double* x, const double* scal, bool first, double* partials, hipStream_t st);
 // Smoothing sweep that also writes partials of <b, xout>_W; returns their count.
 int stream_smooth_dot(const OpDesc& A, const double* x, const double* xprev, const double* b,
                       double* xout, double a, double g, double* partials, hipStream_t st);

@@ -47,7 +47,9 @@ enum Epi {
   E_CG_P = 10,         // CG step: p' = z + beta p formed on load; out = A p' (double-double
                        // for the CH operator), out2 = p', partials of <p', A p'>_W, and the
                        // deferred x += alpha p (alpha, beta from device scalars)
-  E_SMOOTH_DOT2 = 11   // E_SMOOTH and partials of <b, out>_W and <out, q>_W (q float64)
+  E_SMOOTH_DOT2 = 11,  // E_SMOOTH and partials of <b, out>_W and <out, q>_W (q float64)
+  E_CG_P32 = 12        // E_CG_P with z read from a float32 field (z32): the float32
+                       // V-cycle's output, stored at the precision it has
 };
 
 constexpr int kStreamTPB = 256;         // 4 wavefronts per workgroup
@@ -77,6 +79,7 @@ struct StreamArgs {
   const double* scal;  // E_CG_P: device scalars (alpha, beta)
   const double* q;     // E_SMOOTH_DOT2: second vector of the extra dot
   int first;           // E_CG_P: first step after a (re)start: p' = z, no x update
+  const float* z32;    // E_CG_P32: z
   // Batch of equal-sized instances stored bstride elements apart: workgroups
   // bpi * i .. bpi * (i+1) - 1 work on instance i (their partials are the
   // instance's), device scalars are kNumSlots apart.  bcoef (optional): per
@@ -142,6 +145,7 @@ __global__ void __launch_bounds__(kStreamTPB) k_stream(StreamArgs<T, TO> P) {
                            EPI == E_SMOOTH_DOT || EPI == E_SMOOTH_DOT2);
   constexpr bool RED = (EPI == E_APPLY_DOT || EPI == E_RESID_NORM || EPI == E_APPLY_DOT_DD ||
                         EPI == E_RESID_DD || EPI == E_SMOOTH_DOT || EPI == E_CG_P ||
+                        EPI == E_CG_P32 ||
                         EPI == E_SMOOTH_DOT2);
   constexpr bool RED2 = (EPI == E_RESID_DD || EPI == E_SMOOTH_DOT2);
   constexpr bool NEEDB = (EPI == E_RESID || EPI == E_RESID_NORM || SMOOTH || EPI == E_RESID_DD);
@@ -175,7 +179,8 @@ __global__ void __launch_bounds__(kStreamTPB) k_stream(StreamArgs<T, TO> P) {
   }
   const T ca = T(pa), cg = T(pg), ca0 = T(pa0);
   double beta = 0.0, alpha_prev = 0.0;
-  if constexpr (EPI == E_CG_P) {
+  constexpr bool CGP = (EPI == E_CG_P || EPI == E_CG_P32);
+  if constexpr (CGP) {
     if (!P.first) {
       beta = P.scal[(int64_t)inst * kNumSlots + S_BETA];
       alpha_prev = P.scal[(int64_t)inst * kNumSlots + S_ALPHA];
@@ -226,8 +231,23 @@ __global__ void __launch_bounds__(kStreamTPB) k_stream(StreamArgs<T, TO> P) {
         continue;
       }
       const int jr = refl(jj, n);
-      load_row(Xp, jr, halo, xr[k]);
-      if constexpr (EPI == E_CG_P) {
+      if constexpr (EPI == E_CG_P32) {
+        // z in float32: the lane's V values (8 bytes) and, on lanes 0 and 63,
+        // the two columns beyond the wavefront's edge, widened to T
+        const float* zr = P.z32 + ioff + (int64_t)jr * n;
+        const float2 zv = *reinterpret_cast<const float2*>(zr + c);
+        xr[k].o[0] = T(zv.x);
+        xr[k].o[1] = T(zv.y);
+        xr[k].h0 = xr[k].h1 = T(0);
+        if (halo && (hl || hr)) {
+          const float2 zh = *reinterpret_cast<const float2*>(zr + hcol);
+          xr[k].h0 = T(zh.x);
+          xr[k].h1 = T(zh.y);
+        }
+      } else {
+        load_row(Xp, jr, halo, xr[k]);
+      }
+      if constexpr (CGP) {
         if (!P.first) {
           XRow<T, V> po;
           load_row(XPp, jr, halo, po);
@@ -357,7 +377,7 @@ __global__ void __launch_bounds__(kStreamTPB) k_stream(StreamArgs<T, TO> P) {
             res.v[i] = -residual_dd_vals<OP>(nb[i], 0.0, cfj);
             acc += wgt * nb[i].c * res.v[i];
           }
-        } else if constexpr (EPI == E_CG_P) {
+        } else if constexpr (CGP) {
           VecN<double, V> pn;
 #pragma unroll
           for (int i = 0; i < V; ++i) {
@@ -556,6 +576,30 @@ int stream_cg_p(const OpDesc& A, const double* z, const double* p_old, double* p
   if (A.op == 0) return dispatch<0, E_CG_P>(c, P, st);
   if (A.op == 2) return dispatch<2, E_CG_P>(c, P, st);
   return dispatch<1, E_CG_P>(c, P, st);
+}
+int stream_cg_p32(const OpDesc& A, const float* z, const double* p_old, double* p_new, double* q,
+                  double* x, const double* scal, bool first, double* partials, hipStream_t st) {
+  const StreamCfg c = stream_cfg(A.n, 8);
+  StreamArgs<double, double> P{};
+  P.A = A;
+  P.G = make_geo(A.n);
+  P.z32 = z;
+  P.xprev = p_old;
+  P.out = q;
+  P.out2 = p_new;
+  P.xu = x;
+  P.scal = scal;
+  P.first = first ? 1 : 0;
+  P.partials = partials;
+  if (A.op == 0) return dispatch<0, E_CG_P32>(c, P, st);
+  if (A.op == 2) return dispatch<2, E_CG_P32>(c, P, st);
+  return dispatch<1, E_CG_P32>(c, P, st);
+}
+int stream_smooth_dot2_f32(const OpDesc& A, const float* x, const float* xprev, const float* b,
+                           float* xout, const double* q, double a, double g, double* partials,
+                           hipStream_t st) {
+  return stream_launch<E_SMOOTH_DOT2, float, float>(A, x, b, xprev, xout, partials, a, g, st,
+                                                    0.0, q);
 }
 
 template int stream_residual<double>(const OpDesc&, const double*, const double*, double*,

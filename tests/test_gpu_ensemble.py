@@ -67,7 +67,7 @@ def test_layout_and_classes(dev):
     # classes by size, instances in input order within a class, blocks contiguous
     assert ens.info()[0][:2] == (128, 2) and ens.info()[1][:2] == (256, 2)
     assert ens.info()[2][:2] == (512, 1)
-    assert all(r in (4, 8) for _, _, r in ens.info())
+    assert all(r in (4, 5, 8) for _, _, r in ens.info())  # the autotuner's tile heights
     o = ens.offsets
     assert o[1] == 0 and o[4] == 129 * 128 and o[0] == 2 * 129 * 128
     assert o[2] == o[0] + 257 * 256 and o[3] == o[2] + 257 * 256

@@ -344,7 +344,7 @@ int build_tables(EClass& C, int op, const std::vector<double>& c) {
     ETRY(host_coarse_operator(op, c[k], G));
     std::copy(G.begin(), G.end(), coarse.begin() + (size_t)k * G.size());
   }
-  // tail arguments: the levels n = 32, 16, 8 of each instance (the tail
+  // tail arguments: the levels n = 64, 32, 16, 8 of each instance (the tail
   // works on them in LDS; they are not part of the table above)
   for (int k = 0; k < C.count; ++k) {
     TailArgs& T = tails[k];

@@ -170,9 +170,11 @@ int bf_apply_mob(bf_grid* g, double c, const double* m, const double* x, double*
 
 /* Solve (I + c L_m L) x = b (the operator of bf_apply_mob).  L_m L is not
  * symmetric: the solve is GMRES (o->ksp must be BF_KSP_GMRES; o == NULL gives
- * GMRES(10) + multigrid, rtol 1e-10) right-preconditioned by the
- * constant-mobility V-cycle of I + c mbar L^2, mbar the weighted mean of m
- * rounded to 6 significant bits.  Residuals in double-double; the constant
+ * GMRES(10) + multigrid, rtol 1e-10) right-preconditioned by a V-cycle
+ * that rediscretises the operator with the node mobilities on every level
+ * above 64 x 64 (m injected level to level) and uses I + c mbar L^2 below,
+ * mbar the weighted mean of m rounded to 6 significant bits (with a Jacobi
+ * or no preconditioner, that of I + c mbar L^2).  Residuals in double-double; the constant
  * mode is corrected as in bf_solve_ch (L_m conserves the weighted sum).
  * x: in = initial guess, out = solution.  Synchronous. */
 int bf_solve_ch_mob(bf_grid* g, double c, const double* m, const double* b, double* x,

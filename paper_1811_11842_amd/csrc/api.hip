@@ -60,6 +60,7 @@ struct LevelT {
   T* xb = nullptr;
   T* r = nullptr;   // residual
   T* b = nullptr;   // right-hand side (levels >= 1)
+  T* m = nullptr;   // node mobilities of the variable-mobility V-cycle (on first use)
 };
 using Level = LevelT<double>;
 
@@ -553,6 +554,65 @@ double* vcycle_top(bf_grid* g, int op, double c, const bf_solver_opts& o, const 
   return vcycle_level<double>(g, g->lv, op, c, o, 0, r, rz_parts);
 }
 
+// Node mobilities of every level above the coarse tail (level 0: m itself,
+// then injection), for the variable-mobility V-cycle; allocated on first use.
+template <typename T>
+int setup_mob_levels(bf_grid* g, std::vector<LevelT<T>>& lv, const double* m) {
+  for (size_t l = 0; l < lv.size() && lv[l].n > kTailTop; ++l) {
+    if (!lv[l].m) {
+      void* ptr = nullptr;
+      if (hipMalloc(&ptr, sizeof(T) * (size_t)lv[l].npts) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(BF_ENOMEM, "mobility level allocation failed");
+      }
+      g->allocs.push_back(ptr);
+      lv[l].m = (T*)ptr;
+    }
+  }
+  if (lv.empty() || lv[0].n <= kTailTop) return BF_OK;
+  if constexpr (std::is_same<T, float>::value)
+    launch_to_float(lv[0].npts, m, lv[0].m, g->stream);
+  else
+    launch_copy(lv[0].npts, m, lv[0].m, g->stream);
+  for (size_t l = 0; l + 1 < lv.size() && lv[l + 1].n > kTailTop; ++l)
+    launch_inject<T>(lv[l].n, lv[l].m, lv[l + 1].m, g->stream);
+  return BF_OK;
+}
+
+// One V-cycle of the variable-mobility operator I + c L_m L from level l:
+// on every level above the coarse tail the operator is rediscretised with the
+// level's mobilities (smoothing and residual by the k_mob_* kernels, the same
+// Chebyshev polynomial as the constant-mobility cycle at the mean mobility);
+// the tail and the exact coarsest solve use the constant mean mobility.
+template <typename T>
+T* vcycle_mob(bf_grid* g, std::vector<LevelT<T>>& lv, double c, const bf_solver_opts& o, int l,
+              const T* b) {
+  LevelT<T>& L = lv[l];
+  if (L.n <= kTailTop) return vcycle_level<T>(g, lv, BF_OP_CH, c * g->mob_pre, o, l, b);
+  hipStream_t st = g->stream;
+  const double cs = c * std::pow((double)L.n, 4);
+  const Smoother S = make_smoother(BF_OP_CH, L.n, c * g->mob_pre, o);
+  T* cur = L.xa;
+  T* oth = L.xb;
+  launch_mob_smooth0<T>(L.n, cs, L.m, b, cur, S.a[0], st);
+  for (int k = 1; k < S.degree; ++k) {
+    launch_mob_smooth<T>(L.n, cs, L.m, cur, (k == 1 || S.g[k] == 0.0) ? nullptr : oth, b, oth,
+                         S.a[k], S.g[k], st);
+    std::swap(cur, oth);
+  }
+  launch_mob_residual<T>(L.n, cs, L.m, cur, b, L.r, st);
+  LevelT<T>& C = lv[l + 1];
+  launch_restrict<T>(L.n, L.r, C.b, st);
+  T* e = vcycle_mob<T>(g, lv, c, o, l + 1, C.b);
+  launch_prolong_add<T>(L.n, e, cur, st);
+  for (int k = 0; k < S.degree; ++k) {
+    launch_mob_smooth<T>(L.n, cs, L.m, cur, S.g[k] != 0.0 ? oth : nullptr, b, oth, S.a[k],
+                         S.g[k], st);
+    std::swap(cur, oth);
+  }
+  return cur;
+}
+
 int check_opts(const bf_solver_opts& o) {
   if (o.ksp != BF_KSP_CG && o.ksp != BF_KSP_GMRES) return fail(BF_EINVAL, "ksp %d", o.ksp);
   if (o.pc < BF_PC_NONE || o.pc > BF_PC_MG) return fail(BF_EINVAL, "pc %d", o.pc);
@@ -652,6 +712,19 @@ double* precondition(bf_grid* g, int op, double c, const bf_solver_opts& o, cons
       launch_copy(g->npts, r, g->z, g->stream);
       return g->z;
   }
+}
+
+// z = M r for the variable-mobility operator: the variable-mobility V-cycle
+// (multigrid), else the constant-mobility preconditioner at the mean mobility.
+double* precondition_mob(bf_grid* g, double c, const bf_solver_opts& o, const double* r) {
+  if (o.pc != BF_PC_MG) return precondition(g, BF_OP_CH, c * g->mob_pre, o, r);
+  if (o.mg_precision == BF_MG_F32) {
+    launch_to_float(g->npts, r, g->r32, g->stream);
+    float* zf = vcycle_mob<float>(g, g->lvf, c, o, 0, g->r32);
+    launch_to_double(g->npts, zf, g->z, g->stream);
+    return g->z;
+  }
+  return vcycle_mob<double>(g, g->lv, c, o, 0, r);
 }
 
 // Reduce <x, y>_W into scal[slot] (asynchronous).
@@ -903,8 +976,7 @@ int run_gmres(bf_grid* g, int op, double c, const double* b, double* x, const bf
       double* Vk = g->gm_V + (int64_t)k * N;
       double* Zk = g->gm_Z + (int64_t)k * N;
       double* w = g->gm_V + (int64_t)(k + 1) * N;
-      double* zk = op == kOpMob ? precondition(g, BF_OP_CH, c * g->mob_pre, o, Vk)
-                                : precondition(g, op, c, o, Vk);
+      double* zk = op == kOpMob ? precondition_mob(g, c, o, Vk) : precondition(g, op, c, o, Vk);
       launch_copy(N, zk, Zk, st);
       if (op == kOpMob)
         launch_mob(g->n, c, g->mob, Zk, nullptr, w, nullptr, 0, st);
@@ -1351,6 +1423,14 @@ int bf_solve_ch_mob(bf_grid* g, double c, const double* m, const double* b, doub
   const double fr = std::frexp(mm, &e2);
   g->mob = m;
   g->mob_pre = std::ldexp(std::round(std::ldexp(fr, 6)), e2 - 6);
+  if (oo.pc == BF_PC_MG) {
+    if (oo.mg_precision == BF_MG_F32) {
+      TRY(ensure_mixed(g));
+      TRY(setup_mob_levels<float>(g, g->lvf, m));
+    } else {
+      TRY(setup_mob_levels<double>(g, g->lv, m));
+    }
+  }
   const int s = run_krylov(g, kOpMob, c, b, x, oo, st);
   g->mob = nullptr;
   return s;

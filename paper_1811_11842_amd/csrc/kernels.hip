@@ -542,6 +542,87 @@ __global__ void __launch_bounds__(kBlock) k_mob(Geo G, double c, const double* _
   }
 }
 
+// Variable-mobility multigrid (the preconditioner of bf_solve_ch_mob on the
+// levels above the coarse tail): the operator rediscretised on each level
+// with that level's node mobilities, applied in plain T arithmetic (a
+// preconditioner needs no more), one node per thread.  cs = c n^4 of the
+// level; the smoother's diagonal is the interior one, 1 + 5 cs sum_faces m_f.
+template <typename T>
+__device__ __forceinline__ T mob_apply_at(const T* __restrict__ x, const T* __restrict__ m, int i,
+                                          int j, int n, int mask, T cs, T& diag) {
+  auto X = [&](int jj, int ii) { return x[(int64_t)refl(jj, n) * n + (ii & mask)]; };
+  auto Lh = [&](int jj, int ii) {
+    return (X(jj, ii - 1) + X(jj, ii + 1)) + (X(jj - 1, ii) + X(jj + 1, ii)) - T(4) * X(jj, ii);
+  };
+  const T mc = m[(int64_t)j * n + i];
+  const T tc = Lh(j, i);
+  const int dj[4] = {0, 0, -1, 1}, di[4] = {-1, 1, 0, 0};
+  T f = T(0), sm = T(0);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int jj = j + dj[k], ii = i + di[k];
+    const T mf = T(0.5) * (mc + m[(int64_t)refl(jj, n) * n + (ii & mask)]);
+    f += mf * (Lh(jj, ii) - tc);
+    sm += mf;
+  }
+  diag = T(1) + T(5) * cs * sm;
+  return X(j, i) + cs * f;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_mob_smooth(Geo G, T cs, const T* __restrict__ m,
+                                                       const T* __restrict__ x, const T* xprev,
+                                                       const T* __restrict__ b, T* xout, T a,
+                                                       T g) {
+  GRID_STRIDE(idx, G.npts) {
+    const int i = (int)(idx & G.mask), j = (int)(idx >> G.log2n);
+    T d;
+    const T ax = mob_apply_at(x, m, i, j, G.n, G.mask, cs, d);
+    const T c = x[idx];
+    const T prev = xprev ? xprev[idx] : T(0);
+    xout[idx] = c + a / d * (b[idx] - ax) + g * (c - prev);
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_mob_smooth0(Geo G, T cs, const T* __restrict__ m,
+                                                        const T* __restrict__ b,
+                                                        T* __restrict__ xout, T a0) {
+  const int n = G.n;
+  GRID_STRIDE(idx, G.npts) {
+    const int i = (int)(idx & G.mask), j = (int)(idx >> G.log2n);
+    const T mc = m[idx];
+    T sm = T(0);
+    const int dj[4] = {0, 0, -1, 1}, di[4] = {-1, 1, 0, 0};
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      sm += T(0.5) * (mc + m[(int64_t)refl(j + dj[k], n) * n + ((i + di[k]) & G.mask)]);
+    xout[idx] = a0 / (T(1) + T(5) * cs * sm) * b[idx];
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_mob_residual(Geo G, T cs, const T* __restrict__ m,
+                                                         const T* __restrict__ x,
+                                                         const T* __restrict__ b,
+                                                         T* __restrict__ r) {
+  GRID_STRIDE(idx, G.npts) {
+    const int i = (int)(idx & G.mask), j = (int)(idx >> G.log2n);
+    T d;
+    r[idx] = b[idx] - mob_apply_at(x, m, i, j, G.n, G.mask, cs, d);
+  }
+}
+
+// coarse m = fine m at the coinciding (even) nodes
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_inject(Geo F, Geo C, const T* __restrict__ fine,
+                                                   T* __restrict__ coarse) {
+  GRID_STRIDE(idx, C.npts) {
+    const int I = (int)(idx & C.mask), J = (int)(idx >> C.log2n);
+    coarse[idx] = fine[(int64_t)(2 * J) * F.n + 2 * I];
+  }
+}
+
 // Variable-mobility right-hand side: m = M clamp(phi) (written), then
 // b = phi + dt L_m mu with mu from k_mu (plain float64).
 __global__ void __launch_bounds__(kBlock) k_mob_field(Geo G, const double* __restrict__ phi,
@@ -1047,6 +1128,40 @@ int launch_mob(int n, double c, const double* m, const double* x, const double* 
   LAUNCH(k_mob<1>, nparts, st, G, c, m, x, b, y, partials);
   return nparts;
 }
+
+template <typename T>
+void launch_mob_smooth(int n, double cs, const T* m, const T* x, const T* xprev, const T* b,
+                       T* xout, double a, double g, hipStream_t st) {
+  const Geo G = make_geo(n);
+  LAUNCH(k_mob_smooth<T>, ew_blocks(G.npts), st, G, T(cs), m, x, xprev, b, xout, T(a), T(g));
+}
+template <typename T>
+void launch_mob_smooth0(int n, double cs, const T* m, const T* b, T* xout, double a0,
+                        hipStream_t st) {
+  const Geo G = make_geo(n);
+  LAUNCH(k_mob_smooth0<T>, ew_blocks(G.npts), st, G, T(cs), m, b, xout, T(a0));
+}
+template <typename T>
+void launch_mob_residual(int n, double cs, const T* m, const T* x, const T* b, T* r,
+                         hipStream_t st) {
+  const Geo G = make_geo(n);
+  LAUNCH(k_mob_residual<T>, ew_blocks(G.npts), st, G, T(cs), m, x, b, r);
+}
+template <typename T>
+void launch_inject(int nf, const T* fine, T* coarse, hipStream_t st) {
+  const Geo F = make_geo(nf), C = make_geo(nf / 2);
+  LAUNCH(k_inject<T>, ew_blocks(C.npts), st, F, C, fine, coarse);
+}
+#define BF_MOB_INST(T)                                                                         \
+  template void launch_mob_smooth<T>(int, double, const T*, const T*, const T*, const T*, T*,   \
+                                     double, double, hipStream_t);                             \
+  template void launch_mob_smooth0<T>(int, double, const T*, const T*, T*, double, hipStream_t); \
+  template void launch_mob_residual<T>(int, double, const T*, const T*, const T*, T*,          \
+                                       hipStream_t);                                           \
+  template void launch_inject<T>(int, const T*, T*, hipStream_t);
+BF_MOB_INST(double)
+BF_MOB_INST(float)
+#undef BF_MOB_INST
 
 void launch_mob_rhs(int n, const double* phi, double* m, double* mu_ws, double* b, double M,
                     double dt, double inv_npoly, double chi, double lo, double hi,

@@ -209,6 +209,21 @@ void launch_divergence(int n, const double* u, const double* v, double* rhs, dou
 // groups; returns the group size).
 int launch_mob(int n, double c, const double* m, const double* x, const double* b, double* y,
                double* partials, int nparts, hipStream_t st);
+// Variable-mobility V-cycle pieces (plain T arithmetic, one node per
+// thread; cs = c n^4 of the level, m the level's node mobilities):
+// Chebyshev/Jacobi sweep, first sweep from zero, residual, and injection of
+// m onto the next coarser level.
+template <typename T>
+void launch_mob_smooth(int n, double cs, const T* m, const T* x, const T* xprev, const T* b,
+                       T* xout, double a, double g, hipStream_t st);
+template <typename T>
+void launch_mob_smooth0(int n, double cs, const T* m, const T* b, T* xout, double a0,
+                        hipStream_t st);
+template <typename T>
+void launch_mob_residual(int n, double cs, const T* m, const T* x, const T* b, T* r,
+                         hipStream_t st);
+template <typename T>
+void launch_inject(int nf, const T* fine, T* coarse, hipStream_t st);
 // m = M clamp(phi); mu_ws = mu_FH(clamp(phi)); b = phi + dt L_m mu_ws.
 void launch_mob_rhs(int n, const double* phi, double* m, double* mu_ws, double* b, double M,
                     double dt, double inv_npoly, double chi, double lo, double hi,

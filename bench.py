@@ -71,6 +71,8 @@ def parse():
                     help="only time the smoothing sweep (for profiling that kernel)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a plain device copy of one field (for HBM counter calibration)")
+    ap.add_argument("--leg", choices=["predictor", "mobility", "cn", "adjoint"],
+                    help="only time one of the variant legs (for profiling it)")
     return ap.parse_args()
 
 
@@ -400,6 +402,15 @@ def main():
            "dtype": "f64", "data": "synthetic"}
     if a.ensemble:
         print(json.dumps({"ensemble": time_ensemble()}), flush=True)
+        return
+    if a.leg:
+        if a.leg == "adjoint":
+            res = time_adjoint()
+        else:
+            with bf.Grid(n) as g:
+                res = {"predictor": time_predictor, "mobility": time_mobility,
+                       "cn": time_cn}[a.leg](g, n)
+        print(json.dumps({a.leg: res}), flush=True)
         return
     with bf.Grid(n) as g:
         if a.smooth_only:

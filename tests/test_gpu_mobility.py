@@ -122,6 +122,19 @@ def test_step_matches_oracle(dev, n):
     assert dm <= 1e-13
 
 
+def test_uniform_state_is_a_fixed_point(dev):
+    """A uniform phi has a constant mu and mobility: b = phi and the solution is
+    phi.  (The preconditioned Krylov space is not the constant mode alone -- the
+    smoother's diagonal differs next to the walls -- so the iterate is exact only
+    to the solve's tolerance: rtol 1e-13, bound 1e-13 absolute.)"""
+    n = 256
+    g = grid(n)
+    phi = g.field(0.25)
+    st = g.step_ch_mob(bf.make_params(**PRM), phi, gmres_opts(rtol=1e-13))
+    assert st.status in (bf.OK, bf.AT_FLOOR)
+    assert np.abs(to_np(phi) - 0.25).max() <= 1e-13
+
+
 @pytest.mark.parametrize("n", [1024, 4096])
 def test_step_residual_and_mass_at_scale(dev, n):
     print(f"step_ch_mob n={n}", flush=True)

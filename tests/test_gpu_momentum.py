@@ -167,6 +167,27 @@ def test_couette_flow_is_a_fixed_point(dev):
     assert np.max(np.abs(to_np(vs))) <= 1e-13
 
 
+@pytest.mark.parametrize("nu,theta", [(0.0, 0.5), (NU_PAPER, 0.0), (1.0, 1.0)])
+def test_predictor_degenerate_coefficients(dev, nu, theta):
+    """nu = 0 (no viscosity) and theta = 0 (explicit viscous term) make beta = 0:
+    the Helmholtz solve is the identity and u* the explicit update."""
+    n, U = 128, 0.1
+    u, v = velocity(n, U)
+    ru, rv = mom.predict(u, v, dt=DT, nu=nu, theta=theta, U=U)
+    us, vs, (su, sv) = grid(n).momentum_predict(DT, nu, theta, U, D(u, dev), D(v, dev),
+                                                opts=bf.default_opts(bf.OP_HELM, rtol=1e-12))
+    assert su.status in (bf.OK, bf.AT_FLOOR) and sv.status in (bf.OK, bf.AT_FLOOR)
+    assert relw(to_np(us), ru) <= 1e-12 and relw(to_np(vs), rv) <= 1e-12
+
+
+def test_helmholtz_zero_rhs_gives_zero(dev):
+    n = 256
+    g = grid(n)
+    x = g.field(0.7)
+    st = g.solve_helmholtz(0.05, g.field(0.0), x)
+    assert st.status == bf.OK and not to_np(x).any()
+
+
 def test_predictor_4096_matches_oracle(dev):
     """The benchmark configuration: 4096^2, Crank-Nicolson viscous term,
     paper viscous scale, mixed-precision multigrid.  At s = beta n^2 = 8e5

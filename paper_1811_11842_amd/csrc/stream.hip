@@ -1,8 +1,10 @@
 // Stencil kernels for the large grid levels.
 //
-// Tiling: every wavefront owns one tile of RPW output rows by 64 V columns
-// (V adjacent columns per lane, 16-byte loads and stores: V = 2 for float64,
-// 4 for float32).  It issues all loads of the tile at once -- the RPW + 2R
+// Tiling: every wavefront owns one tile of RPW output rows by 128 columns
+// (two adjacent columns per lane: 16-byte loads and stores for float64, 8-byte
+// for float32; four float32 columns per lane, 256 per wavefront, measured 4%
+// slower on the float32 V-cycle of the 4096^2 step: half as many wavefronts,
+// more registers each).  It issues all loads of the tile at once -- the RPW + 2R
 // input rows of its columns (R = 1 for the 5-point and 2 for the 13-point
 // operator; ghost rows are the reflected rows of the two-layer even
 // reflection, paper Sec. 4, eq. discreteBC) and the epilogue's other inputs
@@ -53,11 +55,12 @@ enum Epi {
 };
 
 constexpr int kStreamTPB = 256;         // 4 wavefronts per workgroup
+constexpr int kLaneCols = 2;            // columns per lane
 constexpr int kStreamMaxBlocks = 16384; // beyond this, wavefronts loop over tiles
 
-// 16-byte vector of V elements of T.
+// Vector of V elements of T (one load or store).
 template <typename T, int V>
-struct alignas(16) VecN {
+struct alignas(sizeof(T) * V) VecN {
   T v[V];
 };
 
@@ -138,7 +141,7 @@ __device__ __forceinline__ void store_nt(VecN<T, V>* dst, const VecN<T, V>& v) {
 
 template <int OP, int EPI, int RPW, typename T, typename TO>
 __global__ void __launch_bounds__(kStreamTPB) k_stream(StreamArgs<T, TO> P) {
-  constexpr int V = 16 / sizeof(T);
+  constexpr int V = kLaneCols;
   constexpr int R = (OP == 1) ? 2 : 1;
   constexpr int NR = RPW + 2 * R;
   constexpr bool SMOOTH = (EPI == E_SMOOTH || EPI == E_SMOOTH_XB || EPI == E_SMOOTH_PB ||
@@ -445,7 +448,7 @@ StreamCfg stream_cfg(int n, int elem_bytes, bool apply) {
   c.rpw = apply ? 5 : 4;
   if (rpw_env == 4 || rpw_env == 5 || rpw_env == 8) c.rpw = rpw_env;
   if (g_batch.rpw == 4 || g_batch.rpw == 5 || g_batch.rpw == 8) c.rpw = g_batch.rpw;
-  c.wstrips = n / (64 * (16 / elem_bytes));
+  c.wstrips = n / (64 * kLaneCols);
   c.rgroups = (n + 1 + c.rpw - 1) / c.rpw;
   c.tiles = c.wstrips * c.rgroups;
   const int wpb = kStreamTPB / 64;

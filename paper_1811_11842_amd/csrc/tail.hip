@@ -44,25 +44,72 @@ __device__ __forceinline__ int log2_of(int n) {
   return lg;
 }
 
+// Calls f(j, i) for every node of an (n+1) x n level (n <= 64, a power of
+// two): thread t takes column i = t mod n of rows t / n, t / n + 1024 / n, ...
+// The column arithmetic is then loop-invariant, and with n = 64 every
+// wavefront covers exactly one row, so the row index and everything derived
+// from it (reflection, row offsets, row coefficients) stays in scalar
+// registers.  The tail runs on one CU and is bound by vector instructions.
+template <typename F>
+__device__ __forceinline__ void for_nodes(int n, int lg, F f) {
+  const int i = threadIdx.x & (n - 1);
+  const int jstep = kTailThreads >> lg;
+  if (n >= 64) {
+    for (int j = __builtin_amdgcn_readfirstlane(threadIdx.x >> lg); j <= n; j += jstep) f(j, i);
+  } else {
+    for (int j = threadIdx.x >> lg; j <= n; j += jstep) f(j, i);
+  }
+}
+
+// Stencil values around (i, j) of an LDS field (rows reflected, columns
+// wrapped), with row offsets by shifts (n = 2^lg).
+template <int OP, typename T>
+__device__ __forceinline__ Nb13T<T> tail_gather(const T* x, int i, int j, int n, int lg) {
+  const int mask = n - 1;
+  const T* r0 = x + (j << lg);
+  const T* rm1 = x + (refl(j - 1, n) << lg);
+  const T* rp1 = x + (refl(j + 1, n) << lg);
+  const int im1 = (i - 1) & mask, ip1 = (i + 1) & mask;
+  Nb13T<T> v;
+  v.c = r0[i];
+  v.xm1 = r0[im1];
+  v.xp1 = r0[ip1];
+  v.ym1 = rm1[i];
+  v.yp1 = rp1[i];
+  if (OP == 1) {
+    const T* rm2 = x + (refl(j - 2, n) << lg);
+    const T* rp2 = x + (refl(j + 2, n) << lg);
+    v.dmm = rm1[im1];
+    v.dmp = rm1[ip1];
+    v.dpm = rp1[im1];
+    v.dpp = rp1[ip1];
+    v.xm2 = r0[(i - 2) & mask];
+    v.xp2 = r0[(i + 2) & mask];
+    v.ym2 = rm2[i];
+    v.yp2 = rp2[i];
+  }
+  return v;
+}
+
 // xout = x + a D^{-1} (b - A x) + g (x - xprev)  (xprev < 0: no xprev term)
 template <int OP, typename T>
 __device__ void tail_sweep(T* lds, const TailLevel& L, int x, int xprev, int b, int xout,
                            double a, double g) {
-  const int n = L.n, mask = n - 1, npts = (n + 1) * n, lg = log2_of(n);
+  const int n = L.n, lg = log2_of(n);
   const T ta = T(a), tg = T(g);
   const bool hp = xprev >= 0;
   const T* X = lds + x;
   const T* XP = lds + (hp ? xprev : x);
   const T* B = lds + b;
   T* O = lds + xout;
-  for (int idx = threadIdx.x; idx < npts; idx += kTailThreads) {
-    const int i = idx & mask, j = idx >> lg;
-    const Nb13T<T> v = gather<OP>(X, i, j, n, mask);
+  for_nodes(n, lg, [&](int j, int i) {
+    const int idx = (j << lg) + i;
+    const Nb13T<T> v = tail_gather<OP>(X, i, j, n, lg);
     const T ax = apply_vals<OP>(v, T(row_coef<OP>(L.coef, j, n)));
-    const T dinv = T(row_dinv<OP>(L.dinv_int, L.dinv_edge, j, n));
+    const T ad = ta * T(row_dinv<OP>(L.dinv_int, L.dinv_edge, j, n));
     const T prev = hp ? XP[idx] : T(0);
-    O[idx] = v.c + ta * dinv * (B[idx] - ax) + tg * (v.c - prev);
-  }
+    O[idx] = v.c + ad * (B[idx] - ax) + tg * (v.c - prev);
+  });
   __syncthreads();
 }
 
@@ -96,17 +143,16 @@ __device__ void tail_body(const TailArgs& P, const T* b_in, T* x_out) {
   // downward leg
   for (int l = 0; l < P.nlev; ++l) {
     const TailLevel& L = P.lev[l];
-    const int n = L.n, npts = (n + 1) * n, lg = log2_of(n);
+    const int n = L.n, lg = log2_of(n);
     int cur = xa[l];
     int o = xb[l];
     {
       T* C = lds + cur;
       const T* B = lds + bb[l];
-      for (int idx = tid; idx < npts; idx += kTailThreads) {
-        const int j = idx >> lg;
-        const double dinv = row_dinv<OP>(L.dinv_int, L.dinv_edge, j, n);
-        C[idx] = T(L.a[0] * dinv) * B[idx];
-      }
+      for_nodes(n, lg, [&](int j, int i) {
+        const int idx = (j << lg) + i;
+        C[idx] = T(L.a[0] * row_dinv<OP>(L.dinv_int, L.dinv_edge, j, n)) * B[idx];
+      });
     }
     __syncthreads();
     for (int k = 1; k < L.degree; ++k) {
@@ -121,11 +167,11 @@ __device__ void tail_body(const TailArgs& P, const T* b_in, T* x_out) {
       const T* C = lds + cur;
       const T* B = lds + bb[l];
       T* R = lds + o;
-      for (int idx = tid; idx < npts; idx += kTailThreads) {
-        const int i = idx & (n - 1), j = idx >> lg;
-        const Nb13T<T> v = gather<OP>(C, i, j, n, n - 1);
+      for_nodes(n, lg, [&](int j, int i) {
+        const int idx = (j << lg) + i;
+        const Nb13T<T> v = tail_gather<OP>(C, i, j, n, lg);
         R[idx] = B[idx] - apply_vals<OP>(v, T(row_coef<OP>(L.coef, j, n)));
-      }
+      });
     }
     __syncthreads();
     // restriction to the next level (or to the coarsest grid)

@@ -111,7 +111,7 @@ def test_restrict_and_prolong_match_oracle(dev, nf):
     assert np.abs(to_np(fd) - ref).max() <= 8 * U * (1.6 * np.abs(c).max() + np.abs(base).max())
 
 
-@pytest.mark.parametrize("n", [4, 8, 32, 256, 1024])
+@pytest.mark.parametrize("n", [4, 8, 16, 32, 64, 256, 1024])
 @pytest.mark.parametrize("op", ["lap", "ch"])
 @pytest.mark.parametrize("smoother", ["chebyshev", "jacobi"])
 def test_vcycle_matches_oracle(dev, n, op, smoother):

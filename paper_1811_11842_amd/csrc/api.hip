@@ -483,7 +483,10 @@ T* vcycle_level(bf_grid* g, std::vector<LevelT<T>>& lv, int op, double c,
   // pre-smoothing from zero
   T* cur = L.xa;
   T* oth = L.xb;
-  if (fused) {
+  if (fused && S.degree == 3 && smooth3_ok(L.n) && g_batch.count <= 1) {
+    // all three sweeps in one pass (x1 and x2 stay in registers)
+    stream_smooth3_from_zero<T>(A, b, cur, S.a[0], S.a[1], S.g[1], S.a[2], S.g[2], st);
+  } else if (fused) {
     // sweeps 0 and 1 in one pass (x1 = a0 D^-1 b is never stored), sweep 2
     // re-forms x1 from b for its (x - x_prev) term
     stream_smooth_from_zero<T>(A, b, cur, S.a[0], S.a[1], S.g[1], st);
@@ -508,8 +511,33 @@ T* vcycle_level(bf_grid* g, std::vector<LevelT<T>>& lv, int op, double c,
   launch_restrict<T>(L.n, L.r, C.b, st);
   T* e = vcycle_level<T>(g, lv, op, c, o, l + 1, C.b);
   launch_prolong_add<T>(L.n, e, cur, st);
-  // post-smoothing (same polynomial)
+  // post-smoothing (same polynomial); on streamed single grids the last two
+  // sweeps run as one pass, whose result goes to L.r (free on the way up:
+  // the pass still reads the two previous iterates)
+  const bool pair = streamed && S.degree >= 2 && smooth_last2_ok(L.n) && g_batch.count <= 1;
   for (int k = 0; k < S.degree; ++k) {
+    if (pair && k == S.degree - 2) {
+      const int k2 = k + 1;
+      if constexpr (F32) {
+        if (zout32 || zout) {
+          const int np =
+              zout32 ? stream_smooth_last2_dot2_f32(A, cur, oth, b, zout32, g->q, S.a[k], S.g[k],
+                                                    S.a[k2], S.g[k2], g->partials, st)
+                     : stream_smooth_last2_dot2(A, cur, oth, b, zout, g->q, S.a[k], S.g[k],
+                                                S.a[k2], S.g[k2], g->partials, st);
+          if (rz_parts) *rz_parts = np;
+          return nullptr;
+        }
+      } else {
+        if (rz_parts) {
+          *rz_parts = stream_smooth_last2_dot(A, cur, oth, b, L.r, S.a[k], S.g[k], S.a[k2],
+                                              S.g[k2], g->partials, st);
+          return L.r;
+        }
+      }
+      stream_smooth_last2<T>(A, cur, oth, b, L.r, S.a[k], S.g[k], S.a[k2], S.g[k2], st);
+      return L.r;
+    }
     const T* prev = S.g[k] != 0.0 ? oth : nullptr;
     const bool last = k == S.degree - 1;
     if constexpr (F32) {

@@ -73,6 +73,32 @@ void stream_smooth_from_zero(const OpDesc& A, const T* b, T* xout, double a0, do
 template <typename T>
 void stream_smooth_prev_from_b(const OpDesc& A, const T* x, const T* b, T* xout, double a0,
                                double a, double g, hipStream_t st);
+// Three sweeps from a zero guess in one pass (single grids, streamed levels):
+// x1 = a0 D^{-1} b, x2 = x1 + a1 D^{-1}(b - A x1) + g1 x1,
+// xout = x2 + a2 D^{-1}(b - A x2) + g2 (x2 - x1).
+bool smooth3_ok(int n);
+template <typename T>
+void stream_smooth3_from_zero(const OpDesc& A, const T* b, T* xout, double a0, double a1,
+                              double g1, double a2, double g2, hipStream_t st);
+// The last two sweeps of a smoother in one pass (single grids, streamed
+// levels): x2 = x1 + a1 D^{-1}(b - A x1) + g1 (x1 - x0),
+// xout = x2 + a2 D^{-1}(b - A x2) + g2 (x2 - x1); xout aliases neither x1
+// nor x0 (x0 unused when g1 == 0).  The _dot forms also leave partials of
+// <b, xout>_W (and of <xout, q>_W) and return their count.
+bool smooth_last2_ok(int n);
+template <typename T>
+void stream_smooth_last2(const OpDesc& A, const T* x1, const T* x0, const T* b, T* xout,
+                         double a1, double g1, double a2, double g2, hipStream_t st);
+int stream_smooth_last2_dot(const OpDesc& A, const double* x1, const double* x0, const double* b,
+                            double* xout, double a1, double g1, double a2, double g2,
+                            double* partials, hipStream_t st);
+int stream_smooth_last2_dot2(const OpDesc& A, const float* x1, const float* x0, const float* b,
+                             double* xout, const double* q, double a1, double g1, double a2,
+                             double g2, double* partials, hipStream_t st);
+int stream_smooth_last2_dot2_f32(const OpDesc& A, const float* x1, const float* x0,
+                                 const float* b, float* xout, const double* q, double a1,
+                                 double g1, double a2, double g2, double* partials,
+                                 hipStream_t st);
 // Float32 smoothing sweep writing a float64 result, with partials of <b, out>_W
 // (partials[0..np)) and <out, q>_W (partials[np..2 np)); returns np.
 int stream_smooth_dot2(const OpDesc& A, const float* x, const float* xprev, const float* b,

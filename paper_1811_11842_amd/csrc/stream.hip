@@ -25,6 +25,7 @@
 // Outputs are stored non-temporally.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdlib>
 #include <type_traits>
 
@@ -419,6 +420,264 @@ __global__ void __launch_bounds__(kStreamTPB) k_stream(StreamArgs<T, TO> P) {
   }
 }
 
+// Three sweeps of the smoother from a zero iterate in one pass:
+//   x1 = a0 D^{-1} b,  x2 = x1 + a1 D^{-1}(b - A x1) + g1 x1,
+//   x3 = x2 + a2 D^{-1}(b - A x2) + g2 (x2 - x1).
+// x1 is pointwise in b and x2 is formed in registers over the tile's rows
+// widened by the stencil's reach, so the pass reads b and writes x3 only
+// (the two-pass form also writes and re-reads x2).  x2 at a column needs x1
+// two columns either side, and x3 needs x2 two columns either side, so the
+// wavefronts overlap: each loads 128 columns (two per lane) but only lanes
+// 2 .. 61 produce x3 (120 columns per wavefront, strips 120 columns apart,
+// wrapped); the neighbours across lanes come from DPP shifts, and the values
+// the edge lanes receive from outside the wavefront (zero) only reach lanes
+// whose results are discarded.  Rows beyond the walls are the reflected rows;
+// a stage-two value on a ghost row equals the one on its mirror row because
+// the stencils are symmetric in y and every row coefficient is taken at the
+// reflected index.
+constexpr int kS3Lanes = 60;            // output lanes per wavefront
+constexpr int kS3Cols = 2 * kS3Lanes;   // output columns per wavefront
+
+template <typename T>
+struct Smooth3Args {
+  OpDesc A;
+  const T* b;
+  T* out;
+  double a0, a1, g1, a2, g2;
+  int wstrips, tiles;
+};
+
+// A x at row k of a register window of rows (V = 2 values per lane), the
+// horizontal neighbours by DPP (zero from outside the wavefront).
+template <int OP, typename T, int N>
+__device__ __forceinline__ void window_apply(const T (&w)[N][2], int k, T coef, T (&ax)[2]) {
+  constexpr int V = 2;
+  const T z = T(0);
+  T e[V + 4];
+  e[0] = OP == 1 ? from_left(w[k][0], z) : z;
+  e[1] = from_left(w[k][1], z);
+  e[2] = w[k][0];
+  e[3] = w[k][1];
+  e[4] = from_right(w[k][0], z);
+  e[5] = OP == 1 ? from_right(w[k][1], z) : z;
+  Nb13T<T> nb[V];
+#pragma unroll
+  for (int i = 0; i < V; ++i) {
+    nb[i].c = e[i + 2];
+    nb[i].xm1 = e[i + 1];
+    nb[i].xp1 = e[i + 3];
+    nb[i].ym1 = w[k - 1][i];
+    nb[i].yp1 = w[k + 1][i];
+  }
+  if constexpr (OP == 1) {
+    T m[V + 2], p[V + 2];
+    m[0] = from_left(w[k - 1][1], z);
+    m[1] = w[k - 1][0];
+    m[2] = w[k - 1][1];
+    m[3] = from_right(w[k - 1][0], z);
+    p[0] = from_left(w[k + 1][1], z);
+    p[1] = w[k + 1][0];
+    p[2] = w[k + 1][1];
+    p[3] = from_right(w[k + 1][0], z);
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
+      nb[i].xm2 = e[i];
+      nb[i].xp2 = e[i + 4];
+      nb[i].ym2 = w[k - 2][i];
+      nb[i].yp2 = w[k + 2][i];
+      nb[i].dmm = m[i];
+      nb[i].dmp = m[i + 2];
+      nb[i].dpm = p[i];
+      nb[i].dpp = p[i + 2];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < V; ++i) ax[i] = apply_vals<OP>(nb[i], coef);
+}
+
+template <int OP, int RPW, typename T>
+__global__ void __launch_bounds__(kStreamTPB) k_smooth3(Smooth3Args<T> P) {
+  constexpr int R = (OP == 1) ? 2 : 1;
+  constexpr int NB = RPW + 4 * R;  // b (and x1) rows j0-2R .. jl+2R
+  constexpr int NX = RPW + 2 * R;  // x2 rows j0-R .. jl+R
+  using V2 = VecN<T, 2>;
+  const int n = P.A.n, mask = n - 1;
+  const int lane = threadIdx.x & 63;
+  const T tdi = T(P.A.dinv_int), tde = T(P.A.dinv_edge), tcoef = T(P.A.coef);
+  const T ca0 = T(P.a0), ca1 = T(P.a1), cg1 = T(P.g1), ca2 = T(P.a2), cg2 = T(P.g2);
+  auto dinv_row = [&](int jr) -> T { return row_dinv<OP, T>(tdi, tde, jr, n); };
+  auto coef_row = [&](int jr) -> T { return (OP == 2 && (jr == 0 || jr == n)) ? T(0) : tcoef; };
+  const int wpb = kStreamTPB / 64;
+  const int t0 = __builtin_amdgcn_readfirstlane(blockIdx.x * wpb + (threadIdx.x >> 6));
+  for (int t = t0; t < P.tiles; t += gridDim.x * wpb) {
+    const int rg = t / P.wstrips;
+    const int strip = t - rg * P.wstrips;
+    const int j0 = rg * RPW;
+    const int jl = min(j0 + RPW, n + 1) - 1;
+    const int col = strip * kS3Cols + 2 * (lane - 2);  // this lane's first column (unwrapped)
+    const int cm = col & mask;                          // even, so cm + 1 < n
+
+    // b and x1 over rows j0-2R .. jl+2R (reflected); rows past the tile's reach are unused
+    T bw[NB][2], x1[NB][2];
+    int jrb[NB];
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+      const int jj = j0 - 2 * R + k;
+      jrb[k] = refl(min(jj, jl + 2 * R), n);
+      const V2 v = *reinterpret_cast<const V2*>(P.b + (int64_t)jrb[k] * n + cm);
+      const T d0 = ca0 * dinv_row(jrb[k]);
+      bw[k][0] = v.v[0];
+      bw[k][1] = v.v[1];
+      x1[k][0] = d0 * v.v[0];
+      x1[k][1] = d0 * v.v[1];
+    }
+    // x2 over rows j0-R .. jl+R
+    T x2[NX][2];
+#pragma unroll
+    for (int k2 = 0; k2 < NX; ++k2) {
+      const int k = k2 + R;  // the same row in the b window
+      const int jr = jrb[k];
+      T ax[2];
+      window_apply<OP>(x1, k, coef_row(jr), ax);
+      const T ad = ca1 * dinv_row(jr);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+        x2[k2][i] = x1[k][i] + ad * (bw[k][i] - ax[i]) + cg1 * x1[k][i];
+    }
+    // x3 on the tile's rows, stored by lanes 2 .. 61 for columns inside the row
+    const bool own = lane >= 2 && lane < 2 + kS3Lanes && col < n;
+#pragma unroll
+    for (int s = 0; s < RPW; ++s) {
+      const int j = j0 + s;
+      if (j > jl) break;
+      const int k2 = s + R, k = s + 2 * R;
+      T ax[2];
+      window_apply<OP>(x2, k2, coef_row(j), ax);
+      const T ad = ca2 * dinv_row(j);
+      V2 o;
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+        o.v[i] = x2[k2][i] + ad * (bw[k][i] - ax[i]) + cg2 * (x2[k2][i] - x1[k][i]);
+      if (own) store_nt(reinterpret_cast<V2*>(P.out + (int64_t)j * n + col), o);
+    }
+  }
+}
+
+// The last two sweeps of the post-smoother in one pass:
+//   x2 = x1 + a1 D^{-1}(b - A x1) + g1 (x1 - x0),
+//   x3 = x2 + a2 D^{-1}(b - A x2) + g2 (x2 - x1),
+// with x2 in registers over the tile's rows widened by the stencil's reach
+// (same overlapping strips as k_smooth3).  Reads x1 (stencil window), x0 and
+// b (pointwise) and, for the reductions, q; writes x3, which must not alias
+// x1 or x0 (neighbouring tiles still read them).  Epilogues: none, partials
+// of <b, x3>_W (S2_DOT), or of <b, x3>_W and <x3, q>_W (S2_DOT2), taken on
+// x3 as stored (TO).
+enum { S2_NONE = 0, S2_DOT = 1, S2_DOT2 = 2 };
+
+template <typename T, typename TO>
+struct Smooth2Args {
+  OpDesc A;
+  const T* x1;
+  const T* x0;      // nullptr when g1 == 0
+  const T* b;
+  const double* q;  // S2_DOT2
+  TO* out;
+  double* partials;
+  double a1, g1, a2, g2;
+  int wstrips, tiles;
+};
+
+template <int OP, int EP, int RPW, typename T, typename TO>
+__global__ void __launch_bounds__(kStreamTPB) k_smooth2(Smooth2Args<T, TO> P) {
+  constexpr int R = (OP == 1) ? 2 : 1;
+  constexpr int NW = RPW + 4 * R;  // x1 rows j0-2R .. jl+2R
+  constexpr int NX = RPW + 2 * R;  // x2 rows j0-R .. jl+R
+  using V2 = VecN<T, 2>;
+  const int n = P.A.n, mask = n - 1;
+  const int lane = threadIdx.x & 63;
+  const int wpb = kStreamTPB / 64;
+  const int t0 = __builtin_amdgcn_readfirstlane(blockIdx.x * wpb + (threadIdx.x >> 6));
+  double acc = 0.0, acc2 = 0.0;
+  // (every wavefront reaches the reductions below, which synchronise the block)
+  for (int t = t0; t < P.tiles; t += gridDim.x * wpb) {
+    const int rg = t / P.wstrips;
+    const int strip = t - rg * P.wstrips;
+    const int j0 = rg * RPW;
+    const int jl = min(j0 + RPW, n + 1) - 1;
+    const int col = strip * kS3Cols + 2 * (lane - 2);
+    const int cm = col & mask;
+    const T tdi = T(P.A.dinv_int), tde = T(P.A.dinv_edge), tcoef = T(P.A.coef);
+    const T ca1 = T(P.a1), cg1 = T(P.g1), ca2 = T(P.a2), cg2 = T(P.g2);
+    auto dinv_row = [&](int jr) -> T { return row_dinv<OP, T>(tdi, tde, jr, n); };
+    auto coef_row = [&](int jr) -> T { return (OP == 2 && (jr == 0 || jr == n)) ? T(0) : tcoef; };
+
+    T x1[NW][2];
+    int jrw[NW];
+#pragma unroll
+    for (int k = 0; k < NW; ++k) {
+      const int jj = j0 - 2 * R + k;
+      jrw[k] = refl(min(jj, jl + 2 * R), n);
+      const V2 v = *reinterpret_cast<const V2*>(P.x1 + (int64_t)jrw[k] * n + cm);
+      x1[k][0] = v.v[0];
+      x1[k][1] = v.v[1];
+    }
+    T x2[NX][2], bw[NX][2];
+#pragma unroll
+    for (int k2 = 0; k2 < NX; ++k2) {
+      const int k = k2 + R;
+      const int jr = jrw[k];
+      const int64_t o = (int64_t)jr * n + cm;
+      const V2 bv = *reinterpret_cast<const V2*>(P.b + o);
+      V2 pv{};
+      if (P.x0) pv = *reinterpret_cast<const V2*>(P.x0 + o);
+      T ax[2];
+      window_apply<OP>(x1, k, coef_row(jr), ax);
+      const T ad = ca1 * dinv_row(jr);
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        bw[k2][i] = bv.v[i];
+        x2[k2][i] = x1[k][i] + ad * (bv.v[i] - ax[i]) + cg1 * (x1[k][i] - pv.v[i]);
+      }
+    }
+    const bool own = lane >= 2 && lane < 2 + kS3Lanes && col < n;
+#pragma unroll
+    for (int s = 0; s < RPW; ++s) {
+      const int j = j0 + s;
+      if (j > jl) break;
+      const int k2 = s + R, k = s + 2 * R;
+      T ax[2];
+      window_apply<OP>(x2, k2, coef_row(j), ax);
+      const T ad = ca2 * dinv_row(j);
+      VecN<TO, 2> o;
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+        o.v[i] = TO(x2[k2][i] + ad * (bw[k2][i] - ax[i]) + cg2 * (x2[k2][i] - x1[k][i]));
+      if (own) {
+        const int64_t off = (int64_t)j * n + col;
+        store_nt(reinterpret_cast<VecN<TO, 2>*>(P.out + off), o);
+        if constexpr (EP != S2_NONE) {
+          const double wgt = row_weight(j, n);
+#pragma unroll
+          for (int i = 0; i < 2; ++i) acc += wgt * double(bw[k2][i]) * double(o.v[i]);
+          if constexpr (EP == S2_DOT2) {
+            const VecN<double, 2> qv = *reinterpret_cast<const VecN<double, 2>*>(P.q + off);
+#pragma unroll
+            for (int i = 0; i < 2; ++i) acc2 += wgt * double(o.v[i]) * qv.v[i];
+          }
+        }
+      }
+    }
+  }
+  if constexpr (EP != S2_NONE) {
+    const double s1 = block_sum_n<kStreamTPB>(acc);
+    if (threadIdx.x == 0) P.partials[blockIdx.x] = s1;
+    if constexpr (EP == S2_DOT2) {
+      const double s2 = block_sum_n<kStreamTPB>(acc2);
+      if (threadIdx.x == 0) P.partials[gridDim.x + blockIdx.x] = s2;
+    }
+  }
+}
+
 // ------------------------------------------------------------------ launch
 namespace {
 
@@ -603,6 +862,123 @@ int stream_smooth_dot2_f32(const OpDesc& A, const float* x, const float* xprev, 
                            hipStream_t st) {
   return stream_launch<E_SMOOTH_DOT2, float, float>(A, x, b, xprev, xout, partials, a, g, st,
                                                     0.0, q);
+}
+
+// The three-sweep pass on every streamed level (n >= 128; measured on the
+// 4096^2 step against a 1024 threshold: 20.15 against 20.33 ms mixed, 25.0
+// against 25.3 ms float64 -- on the small levels it saves a launch).
+// BF_NO_SMOOTH3=1: the two-pass form; BF_SMOOTH3_MIN=m: from n = m up.
+bool smooth3_ok(int n) {
+  static const bool off = [] {
+    const char* v = std::getenv("BF_NO_SMOOTH3");
+    return v && v[0] == '1';
+  }();
+  static const int lim = [] {
+    const int m = env_int("BF_SMOOTH3_MIN", 0);
+    return m >= 128 ? m : 128;
+  }();
+  return !off && n >= lim;
+}
+
+template <typename T>
+void stream_smooth3_from_zero(const OpDesc& A, const T* b, T* xout, double a0, double a1,
+                              double g1, double a2, double g2, hipStream_t st) {
+  constexpr int RPW = 4;
+  Smooth3Args<T> P;
+  P.A = A;
+  P.b = b;
+  P.out = xout;
+  P.a0 = a0;
+  P.a1 = a1;
+  P.g1 = g1;
+  P.a2 = a2;
+  P.g2 = g2;
+  P.wstrips = (A.n + kS3Cols - 1) / kS3Cols;
+  P.tiles = P.wstrips * ((A.n + 1 + RPW - 1) / RPW);
+  const int wpb = kStreamTPB / 64;
+  const int blocks = std::min((P.tiles + wpb - 1) / wpb, kStreamMaxBlocks);
+  if (A.op == 0)
+    hipLaunchKernelGGL((k_smooth3<0, RPW, T>), dim3(blocks), dim3(kStreamTPB), 0, st, P);
+  else if (A.op == 2)
+    hipLaunchKernelGGL((k_smooth3<2, RPW, T>), dim3(blocks), dim3(kStreamTPB), 0, st, P);
+  else
+    hipLaunchKernelGGL((k_smooth3<1, RPW, T>), dim3(blocks), dim3(kStreamTPB), 0, st, P);
+}
+template void stream_smooth3_from_zero<double>(const OpDesc&, const double*, double*, double,
+                                               double, double, double, double, hipStream_t);
+template void stream_smooth3_from_zero<float>(const OpDesc&, const float*, float*, double, double,
+                                              double, double, double, hipStream_t);
+
+// The fused last two sweeps on every streamed level (BF_NO_LAST2=1: one
+// sweep per pass).
+bool smooth_last2_ok(int n) {
+  static const bool off = [] {
+    const char* v = std::getenv("BF_NO_LAST2");
+    return v && v[0] == '1';
+  }();
+  return !off && n >= 128;
+}
+
+template <int EP, typename T, typename TO>
+int stream_smooth2(const OpDesc& A, const T* x1, const T* x0, const T* b, TO* xout,
+                   const double* q, double a1, double g1, double a2, double g2,
+                   double* partials, hipStream_t st) {
+  constexpr int RPW = 4;
+  Smooth2Args<T, TO> P;
+  P.A = A;
+  P.x1 = x1;
+  P.x0 = g1 != 0.0 ? x0 : nullptr;
+  P.b = b;
+  P.q = q;
+  P.out = xout;
+  P.partials = partials;
+  P.a1 = a1;
+  P.g1 = g1;
+  P.a2 = a2;
+  P.g2 = g2;
+  P.wstrips = (A.n + kS3Cols - 1) / kS3Cols;
+  P.tiles = P.wstrips * ((A.n + 1 + RPW - 1) / RPW);
+  const int wpb = kStreamTPB / 64;
+  // at most kStreamMaxBlocks workgroups (wavefronts loop over tiles), which
+  // bounds the partials to 2 kStreamMaxBlocks
+  const int blocks = std::min((P.tiles + wpb - 1) / wpb, kStreamMaxBlocks);
+  if (A.op == 0)
+    hipLaunchKernelGGL((k_smooth2<0, EP, RPW, T, TO>), dim3(blocks), dim3(kStreamTPB), 0, st, P);
+  else if (A.op == 2)
+    hipLaunchKernelGGL((k_smooth2<2, EP, RPW, T, TO>), dim3(blocks), dim3(kStreamTPB), 0, st, P);
+  else
+    hipLaunchKernelGGL((k_smooth2<1, EP, RPW, T, TO>), dim3(blocks), dim3(kStreamTPB), 0, st, P);
+  return blocks;
+}
+
+template <typename T>
+void stream_smooth_last2(const OpDesc& A, const T* x1, const T* x0, const T* b, T* xout,
+                         double a1, double g1, double a2, double g2, hipStream_t st) {
+  stream_smooth2<S2_NONE, T, T>(A, x1, x0, b, xout, nullptr, a1, g1, a2, g2, nullptr, st);
+}
+template void stream_smooth_last2<double>(const OpDesc&, const double*, const double*,
+                                          const double*, double*, double, double, double,
+                                          double, hipStream_t);
+template void stream_smooth_last2<float>(const OpDesc&, const float*, const float*, const float*,
+                                         float*, double, double, double, double, hipStream_t);
+int stream_smooth_last2_dot(const OpDesc& A, const double* x1, const double* x0, const double* b,
+                            double* xout, double a1, double g1, double a2, double g2,
+                            double* partials, hipStream_t st) {
+  return stream_smooth2<S2_DOT, double, double>(A, x1, x0, b, xout, nullptr, a1, g1, a2, g2,
+                                                partials, st);
+}
+int stream_smooth_last2_dot2(const OpDesc& A, const float* x1, const float* x0, const float* b,
+                             double* xout, const double* q, double a1, double g1, double a2,
+                             double g2, double* partials, hipStream_t st) {
+  return stream_smooth2<S2_DOT2, float, double>(A, x1, x0, b, xout, q, a1, g1, a2, g2, partials,
+                                                st);
+}
+int stream_smooth_last2_dot2_f32(const OpDesc& A, const float* x1, const float* x0,
+                                 const float* b, float* xout, const double* q, double a1,
+                                 double g1, double a2, double g2, double* partials,
+                                 hipStream_t st) {
+  return stream_smooth2<S2_DOT2, float, float>(A, x1, x0, b, xout, q, a1, g1, a2, g2, partials,
+                                               st);
 }
 
 template int stream_residual<double>(const OpDesc&, const double*, const double*, double*,

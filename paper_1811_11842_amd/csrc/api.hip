@@ -483,7 +483,14 @@ T* vcycle_level(bf_grid* g, std::vector<LevelT<T>>& lv, int op, double c,
   // pre-smoothing from zero
   T* cur = L.xa;
   T* oth = L.xb;
-  if (fused && S.degree == 3 && smooth3_ok(L.n) && g_batch.count <= 1) {
+  bool have_r = false;  // the residual of the pre-smoothed iterate is in L.r
+  if (fused && S.degree == 3 && smooth3r_ok(L.n, (int)sizeof(T)) && g_batch.count <= 1) {
+    // all three sweeps and the residual in one pass (x1, x2 in registers)
+    if constexpr (F32) {
+      stream_smooth3_resid<T>(A, b, cur, L.r, S.a[0], S.a[1], S.g[1], S.a[2], S.g[2], st);
+      have_r = true;
+    }
+  } else if (fused && S.degree == 3 && smooth3_ok(L.n) && g_batch.count <= 1) {
     // all three sweeps in one pass (x1 and x2 stay in registers)
     stream_smooth3_from_zero<T>(A, b, cur, S.a[0], S.a[1], S.g[1], S.a[2], S.g[2], st);
   } else if (fused) {
@@ -506,7 +513,7 @@ T* vcycle_level(bf_grid* g, std::vector<LevelT<T>>& lv, int op, double c,
     }
   }
   // coarse-grid correction
-  launch_residual<T>(A, cur, b, L.r, nullptr, 0, st);
+  if (!have_r) launch_residual<T>(A, cur, b, L.r, nullptr, 0, st);
   LevelT<T>& C = lv[l + 1];
   launch_restrict<T>(L.n, L.r, C.b, st);
   T* e = vcycle_level<T>(g, lv, op, c, o, l + 1, C.b);

@@ -80,6 +80,11 @@ bool smooth3_ok(int n);
 template <typename T>
 void stream_smooth3_from_zero(const OpDesc& A, const T* b, T* xout, double a0, double a1,
                               double g1, double a2, double g2, hipStream_t st);
+// The same three sweeps followed by r = b - A xout, in one pass (float32).
+bool smooth3r_ok(int n, int elem_bytes);
+template <typename T>
+void stream_smooth3_resid(const OpDesc& A, const T* b, T* xout, T* r, double a0, double a1,
+                          double g1, double a2, double g2, hipStream_t st);
 // The last two sweeps of a smoother in one pass (single grids, streamed
 // levels): x2 = x1 + a1 D^{-1}(b - A x1) + g1 (x1 - x0),
 // xout = x2 + a2 D^{-1}(b - A x2) + g2 (x2 - x1); xout aliases neither x1

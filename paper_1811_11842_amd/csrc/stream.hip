@@ -563,6 +563,107 @@ __global__ void __launch_bounds__(kStreamTPB) k_smooth3(Smooth3Args<T> P) {
   }
 }
 
+// k_smooth3 followed by the residual of its result, r = b - A x3, in the
+// same pass (x3 over the tile's rows widened by the stencil's reach): reads
+// b, writes x3 and r, where the separate residual pass would read x3 and b
+// again.  One more stencil level narrows the valid lanes to 3 .. 60 (116
+// columns per wavefront).
+constexpr int kS3RLanes = 58;
+constexpr int kS3RCols = 2 * kS3RLanes;
+
+template <typename T>
+struct Smooth3RArgs {
+  OpDesc A;
+  const T* b;
+  T* out;
+  T* r;
+  double a0, a1, g1, a2, g2;
+  int wstrips, tiles;
+};
+
+template <int OP, int RPW, typename T>
+__global__ void __launch_bounds__(kStreamTPB) k_smooth3r(Smooth3RArgs<T> P) {
+  constexpr int R = (OP == 1) ? 2 : 1;
+  constexpr int NB = RPW + 6 * R;  // b and x1 rows j0-3R .. jl+3R
+  constexpr int N2 = RPW + 4 * R;  // x2 rows j0-2R .. jl+2R
+  constexpr int N3 = RPW + 2 * R;  // x3 rows j0-R .. jl+R
+  using V2 = VecN<T, 2>;
+  const int n = P.A.n, mask = n - 1;
+  const int lane = threadIdx.x & 63;
+  const T tdi = T(P.A.dinv_int), tde = T(P.A.dinv_edge), tcoef = T(P.A.coef);
+  const T ca0 = T(P.a0), ca1 = T(P.a1), cg1 = T(P.g1), ca2 = T(P.a2), cg2 = T(P.g2);
+  auto dinv_row = [&](int jr) -> T { return row_dinv<OP, T>(tdi, tde, jr, n); };
+  auto coef_row = [&](int jr) -> T { return (OP == 2 && (jr == 0 || jr == n)) ? T(0) : tcoef; };
+  const int wpb = kStreamTPB / 64;
+  const int t0 = __builtin_amdgcn_readfirstlane(blockIdx.x * wpb + (threadIdx.x >> 6));
+  for (int t = t0; t < P.tiles; t += gridDim.x * wpb) {
+    const int rg = t / P.wstrips;
+    const int strip = t - rg * P.wstrips;
+    const int j0 = rg * RPW;
+    const int jl = min(j0 + RPW, n + 1) - 1;
+    const int col = strip * kS3RCols + 2 * (lane - 3);
+    const int cm = col & mask;
+
+    T bw[NB][2], x1[NB][2];
+    int jrb[NB];
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+      const int jj = j0 - 3 * R + k;
+      jrb[k] = refl(min(jj, jl + 3 * R), n);
+      const V2 v = *reinterpret_cast<const V2*>(P.b + (int64_t)jrb[k] * n + cm);
+      const T d0 = ca0 * dinv_row(jrb[k]);
+      bw[k][0] = v.v[0];
+      bw[k][1] = v.v[1];
+      x1[k][0] = d0 * v.v[0];
+      x1[k][1] = d0 * v.v[1];
+    }
+    T x2[N2][2];
+#pragma unroll
+    for (int k2 = 0; k2 < N2; ++k2) {
+      const int k = k2 + R;
+      const int jr = jrb[k];
+      T ax[2];
+      window_apply<OP>(x1, k, coef_row(jr), ax);
+      const T ad = ca1 * dinv_row(jr);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+        x2[k2][i] = x1[k][i] + ad * (bw[k][i] - ax[i]) + cg1 * x1[k][i];
+    }
+    T x3[N3][2];
+#pragma unroll
+    for (int k3 = 0; k3 < N3; ++k3) {
+      const int k2 = k3 + R, k = k3 + 2 * R;
+      const int jr = jrb[k];
+      T ax[2];
+      window_apply<OP>(x2, k2, coef_row(jr), ax);
+      const T ad = ca2 * dinv_row(jr);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+        x3[k3][i] = x2[k2][i] + ad * (bw[k][i] - ax[i]) + cg2 * (x2[k2][i] - x1[k][i]);
+    }
+    const bool own = lane >= 3 && lane < 3 + kS3RLanes && col < n;
+#pragma unroll
+    for (int s = 0; s < RPW; ++s) {
+      const int j = j0 + s;
+      if (j > jl) break;
+      const int k3 = s + R, k = s + 3 * R;
+      T ax[2];
+      window_apply<OP>(x3, k3, coef_row(j), ax);
+      V2 xo, ro;
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        xo.v[i] = x3[k3][i];
+        ro.v[i] = bw[k][i] - ax[i];
+      }
+      if (own) {
+        const int64_t off = (int64_t)j * n + col;
+        store_nt(reinterpret_cast<V2*>(P.out + off), xo);
+        store_nt(reinterpret_cast<V2*>(P.r + off), ro);
+      }
+    }
+  }
+}
+
 // The last two sweeps of the post-smoother in one pass:
 //   x2 = x1 + a1 D^{-1}(b - A x1) + g1 (x1 - x0),
 //   x3 = x2 + a2 D^{-1}(b - A x2) + g2 (x2 - x1),
@@ -879,6 +980,44 @@ bool smooth3_ok(int n) {
   }();
   return !off && n >= lim;
 }
+
+// The fused residual form for float32 levels (BF_NO_SMOOTH3R=1: off); in
+// float64 the extra stencil level would not fit the registers.
+bool smooth3r_ok(int n, int elem_bytes) {
+  static const bool off = [] {
+    const char* v = std::getenv("BF_NO_SMOOTH3R");
+    return v && v[0] == '1';
+  }();
+  return !off && elem_bytes == 4 && smooth3_ok(n);
+}
+
+template <typename T>
+void stream_smooth3_resid(const OpDesc& A, const T* b, T* xout, T* r, double a0, double a1,
+                          double g1, double a2, double g2, hipStream_t st) {
+  constexpr int RPW = 4;
+  Smooth3RArgs<T> P;
+  P.A = A;
+  P.b = b;
+  P.out = xout;
+  P.r = r;
+  P.a0 = a0;
+  P.a1 = a1;
+  P.g1 = g1;
+  P.a2 = a2;
+  P.g2 = g2;
+  P.wstrips = (A.n + kS3RCols - 1) / kS3RCols;
+  P.tiles = P.wstrips * ((A.n + 1 + RPW - 1) / RPW);
+  const int wpb = kStreamTPB / 64;
+  const int blocks = std::min((P.tiles + wpb - 1) / wpb, kStreamMaxBlocks);
+  if (A.op == 0)
+    hipLaunchKernelGGL((k_smooth3r<0, RPW, T>), dim3(blocks), dim3(kStreamTPB), 0, st, P);
+  else if (A.op == 2)
+    hipLaunchKernelGGL((k_smooth3r<2, RPW, T>), dim3(blocks), dim3(kStreamTPB), 0, st, P);
+  else
+    hipLaunchKernelGGL((k_smooth3r<1, RPW, T>), dim3(blocks), dim3(kStreamTPB), 0, st, P);
+}
+template void stream_smooth3_resid<float>(const OpDesc&, const float*, float*, float*, double,
+                                          double, double, double, double, hipStream_t);
 
 template <typename T>
 void stream_smooth3_from_zero(const OpDesc& A, const T* b, T* xout, double a0, double a1,

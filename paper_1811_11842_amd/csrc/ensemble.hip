@@ -399,7 +399,11 @@ double* e_vcycle(EClass& C, int op, int l, const double* b, int* rz_parts) {
   double* cur = Lv.xa;
   double* oth = Lv.xb;
   const bool streamed = stream_ok(Lv.n, 8);
-  if (streamed && deg >= 2) {
+  if (streamed && deg == 3 && smooth3_ok(Lv.n)) {
+    // the three sweeps in one pass (weights from the instance records)
+    set_sweep(0, 0, 0);
+    stream_smooth3_from_zero<double>(A, b, cur, 0.0, 0.0, 0.0, 0.0, 0.0, st);
+  } else if (streamed && deg >= 2) {
     set_sweep(1, 1, 0);
     stream_smooth_from_zero<double>(A, b, cur, 0.0, 0.0, 0.0, st);
     for (int k = 2; k < deg; ++k) {
@@ -425,8 +429,19 @@ double* e_vcycle(EClass& C, int op, int l, const double* b, int* rz_parts) {
   // e_vcycle's scope ended: restore this level's batch context
   BatchScope scope2(C, Lv.npts, sc, level_coef(C, op, l), l == 0 ? C.active : nullptr, C.rpw);
   launch_prolong_add<double>(Lv.n, ec, cur, st);
+  // the last two sweeps in one pass, into Lv.r (see vcycle_level)
+  const bool pair = streamed && deg >= 2 && smooth_last2_ok(Lv.n);
   for (int k = 0; k < deg; ++k) {
     set_sweep(k, k, 0);
+    if (pair && k == deg - 2) {
+      if (rz_parts)
+        *rz_parts = stream_smooth_last2_dot(A, cur, oth, b, Lv.r, 0.0, 0.0, 0.0, 0.0, C.partials,
+                                            st) /
+                    C.count;
+      else
+        stream_smooth_last2<double>(A, cur, oth, b, Lv.r, 0.0, 0.0, 0.0, 0.0, st);
+      return Lv.r;
+    }
     const double* prev = k == 0 ? nullptr : oth;
     if (rz_parts && k == deg - 1 && streamed)
       *rz_parts = stream_smooth_dot(A, cur, prev, b, oth, 0.0, 0.0, C.partials, st) / C.count;

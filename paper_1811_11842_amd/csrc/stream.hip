@@ -438,13 +438,66 @@ __global__ void __launch_bounds__(kStreamTPB) k_stream(StreamArgs<T, TO> P) {
 constexpr int kS3Lanes = 60;            // output lanes per wavefront
 constexpr int kS3Cols = 2 * kS3Lanes;   // output columns per wavefront
 
+// Batches of equal-sized instances for the fused passes (as for k_stream:
+// workgroups bpi * i .. bpi * (i+1) - 1 work on instance i, fields bstride
+// elements apart; with bcoef the coefficients and the smoother weights of
+// sweeps k0, k0+1, k0+2 come from instance i's record; instances with
+// active[i] == 0 are skipped).  Single grids: bpi = all workgroups.
+struct FusedBatch {
+  int bpi;
+  int64_t bstride;
+  const double* bcoef;
+  int k0;
+  const int* active;
+};
+
+// Per-instance view: field offset, operator coefficients and the weights a[k0+m], g[k0+m].
+struct FusedInst {
+  int64_t off;
+  int lblock;
+  bool skip;
+  double coef, dinv_int, dinv_edge;
+  double a[3], g[3];
+};
+
+__device__ __forceinline__ FusedInst fused_inst(const FusedBatch& B, const OpDesc& A,
+                                                const double (&a)[3], const double (&g)[3]) {
+  FusedInst I;
+  const int inst = blockIdx.x / B.bpi;
+  I.lblock = blockIdx.x - inst * B.bpi;
+  I.off = (int64_t)inst * B.bstride;
+  I.skip = B.active && !B.active[inst];
+  I.coef = A.coef;
+  I.dinv_int = A.dinv_int;
+  I.dinv_edge = A.dinv_edge;
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+    I.a[m] = a[m];
+    I.g[m] = g[m];
+  }
+  if (B.bcoef) {
+    const double* rc = B.bcoef + (int64_t)inst * kCoefStride;
+    I.coef = rc[0];
+    I.dinv_int = rc[1];
+    I.dinv_edge = rc[2];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      const int k = min(B.k0 + m, 7);
+      I.a[m] = rc[3 + k];
+      I.g[m] = rc[11 + k];
+    }
+  }
+  return I;
+}
+
 template <typename T>
 struct Smooth3Args {
   OpDesc A;
   const T* b;
   T* out;
-  double a0, a1, g1, a2, g2;
+  double a[3], g[3];  // sweeps 0, 1, 2 (a[0] = a0; g[0] unused)
   int wstrips, tiles;
+  FusedBatch B;
 };
 
 // A x at row k of a register window of rows (V = 2 values per lane), the
@@ -503,13 +556,16 @@ __global__ void __launch_bounds__(kStreamTPB) k_smooth3(Smooth3Args<T> P) {
   using V2 = VecN<T, 2>;
   const int n = P.A.n, mask = n - 1;
   const int lane = threadIdx.x & 63;
-  const T tdi = T(P.A.dinv_int), tde = T(P.A.dinv_edge), tcoef = T(P.A.coef);
-  const T ca0 = T(P.a0), ca1 = T(P.a1), cg1 = T(P.g1), ca2 = T(P.a2), cg2 = T(P.g2);
+  const FusedInst I = fused_inst(P.B, P.A, P.a, P.g);
+  const T* const Bp = P.b + I.off;
+  T* const Op = P.out + I.off;
+  const T tdi = T(I.dinv_int), tde = T(I.dinv_edge), tcoef = T(I.coef);
+  const T ca0 = T(I.a[0]), ca1 = T(I.a[1]), cg1 = T(I.g[1]), ca2 = T(I.a[2]), cg2 = T(I.g[2]);
   auto dinv_row = [&](int jr) -> T { return row_dinv<OP, T>(tdi, tde, jr, n); };
   auto coef_row = [&](int jr) -> T { return (OP == 2 && (jr == 0 || jr == n)) ? T(0) : tcoef; };
   const int wpb = kStreamTPB / 64;
-  const int t0 = __builtin_amdgcn_readfirstlane(blockIdx.x * wpb + (threadIdx.x >> 6));
-  for (int t = t0; t < P.tiles; t += gridDim.x * wpb) {
+  const int t0 = __builtin_amdgcn_readfirstlane(I.lblock * wpb + (threadIdx.x >> 6));
+  for (int t = t0; !I.skip && t < P.tiles; t += P.B.bpi * wpb) {
     const int rg = t / P.wstrips;
     const int strip = t - rg * P.wstrips;
     const int j0 = rg * RPW;
@@ -524,7 +580,7 @@ __global__ void __launch_bounds__(kStreamTPB) k_smooth3(Smooth3Args<T> P) {
     for (int k = 0; k < NB; ++k) {
       const int jj = j0 - 2 * R + k;
       jrb[k] = refl(min(jj, jl + 2 * R), n);
-      const V2 v = *reinterpret_cast<const V2*>(P.b + (int64_t)jrb[k] * n + cm);
+      const V2 v = *reinterpret_cast<const V2*>(Bp + (int64_t)jrb[k] * n + cm);
       const T d0 = ca0 * dinv_row(jrb[k]);
       bw[k][0] = v.v[0];
       bw[k][1] = v.v[1];
@@ -558,7 +614,7 @@ __global__ void __launch_bounds__(kStreamTPB) k_smooth3(Smooth3Args<T> P) {
 #pragma unroll
       for (int i = 0; i < 2; ++i)
         o.v[i] = x2[k2][i] + ad * (bw[k][i] - ax[i]) + cg2 * (x2[k2][i] - x1[k][i]);
-      if (own) store_nt(reinterpret_cast<V2*>(P.out + (int64_t)j * n + col), o);
+      if (own) store_nt(reinterpret_cast<V2*>(Op + (int64_t)j * n + col), o);
     }
   }
 }
@@ -679,13 +735,14 @@ template <typename T, typename TO>
 struct Smooth2Args {
   OpDesc A;
   const T* x1;
-  const T* x0;      // nullptr when g1 == 0
+  const T* x0;      // nullptr when g1 == 0 (x1 - x0 then not formed)
   const T* b;
   const double* q;  // S2_DOT2
   TO* out;
   double* partials;
-  double a1, g1, a2, g2;
+  double a[3], g[3];  // a[0], g[0]: the first of the two sweeps, a[1], g[1]: the second
   int wstrips, tiles;
+  FusedBatch B;
 };
 
 template <int OP, int EP, int RPW, typename T, typename TO>
@@ -697,18 +754,24 @@ __global__ void __launch_bounds__(kStreamTPB) k_smooth2(Smooth2Args<T, TO> P) {
   const int n = P.A.n, mask = n - 1;
   const int lane = threadIdx.x & 63;
   const int wpb = kStreamTPB / 64;
-  const int t0 = __builtin_amdgcn_readfirstlane(blockIdx.x * wpb + (threadIdx.x >> 6));
+  const FusedInst I = fused_inst(P.B, P.A, P.a, P.g);
+  const T* const X1p = P.x1 + I.off;
+  const T* const X0p = P.x0 ? P.x0 + I.off : nullptr;
+  const T* const Bp = P.b + I.off;
+  const double* const Qp = P.q ? P.q + I.off : nullptr;
+  TO* const Op = P.out + I.off;
+  const int t0 = __builtin_amdgcn_readfirstlane(I.lblock * wpb + (threadIdx.x >> 6));
   double acc = 0.0, acc2 = 0.0;
   // (every wavefront reaches the reductions below, which synchronise the block)
-  for (int t = t0; t < P.tiles; t += gridDim.x * wpb) {
+  for (int t = t0; !I.skip && t < P.tiles; t += P.B.bpi * wpb) {
     const int rg = t / P.wstrips;
     const int strip = t - rg * P.wstrips;
     const int j0 = rg * RPW;
     const int jl = min(j0 + RPW, n + 1) - 1;
     const int col = strip * kS3Cols + 2 * (lane - 2);
     const int cm = col & mask;
-    const T tdi = T(P.A.dinv_int), tde = T(P.A.dinv_edge), tcoef = T(P.A.coef);
-    const T ca1 = T(P.a1), cg1 = T(P.g1), ca2 = T(P.a2), cg2 = T(P.g2);
+    const T tdi = T(I.dinv_int), tde = T(I.dinv_edge), tcoef = T(I.coef);
+    const T ca1 = T(I.a[0]), cg1 = T(I.g[0]), ca2 = T(I.a[1]), cg2 = T(I.g[1]);
     auto dinv_row = [&](int jr) -> T { return row_dinv<OP, T>(tdi, tde, jr, n); };
     auto coef_row = [&](int jr) -> T { return (OP == 2 && (jr == 0 || jr == n)) ? T(0) : tcoef; };
 
@@ -718,7 +781,7 @@ __global__ void __launch_bounds__(kStreamTPB) k_smooth2(Smooth2Args<T, TO> P) {
     for (int k = 0; k < NW; ++k) {
       const int jj = j0 - 2 * R + k;
       jrw[k] = refl(min(jj, jl + 2 * R), n);
-      const V2 v = *reinterpret_cast<const V2*>(P.x1 + (int64_t)jrw[k] * n + cm);
+      const V2 v = *reinterpret_cast<const V2*>(X1p + (int64_t)jrw[k] * n + cm);
       x1[k][0] = v.v[0];
       x1[k][1] = v.v[1];
     }
@@ -728,9 +791,9 @@ __global__ void __launch_bounds__(kStreamTPB) k_smooth2(Smooth2Args<T, TO> P) {
       const int k = k2 + R;
       const int jr = jrw[k];
       const int64_t o = (int64_t)jr * n + cm;
-      const V2 bv = *reinterpret_cast<const V2*>(P.b + o);
+      const V2 bv = *reinterpret_cast<const V2*>(Bp + o);
       V2 pv{};
-      if (P.x0) pv = *reinterpret_cast<const V2*>(P.x0 + o);
+      if (X0p) pv = *reinterpret_cast<const V2*>(X0p + o);
       T ax[2];
       window_apply<OP>(x1, k, coef_row(jr), ax);
       const T ad = ca1 * dinv_row(jr);
@@ -755,13 +818,13 @@ __global__ void __launch_bounds__(kStreamTPB) k_smooth2(Smooth2Args<T, TO> P) {
         o.v[i] = TO(x2[k2][i] + ad * (bw[k2][i] - ax[i]) + cg2 * (x2[k2][i] - x1[k][i]));
       if (own) {
         const int64_t off = (int64_t)j * n + col;
-        store_nt(reinterpret_cast<VecN<TO, 2>*>(P.out + off), o);
+        store_nt(reinterpret_cast<VecN<TO, 2>*>(Op + off), o);
         if constexpr (EP != S2_NONE) {
           const double wgt = row_weight(j, n);
 #pragma unroll
           for (int i = 0; i < 2; ++i) acc += wgt * double(bw[k2][i]) * double(o.v[i]);
           if constexpr (EP == S2_DOT2) {
-            const VecN<double, 2> qv = *reinterpret_cast<const VecN<double, 2>*>(P.q + off);
+            const VecN<double, 2> qv = *reinterpret_cast<const VecN<double, 2>*>(Qp + off);
 #pragma unroll
             for (int i = 0; i < 2; ++i) acc2 += wgt * double(o.v[i]) * qv.v[i];
           }
@@ -965,6 +1028,21 @@ int stream_smooth_dot2_f32(const OpDesc& A, const float* x, const float* xprev, 
                                                     0.0, q);
 }
 
+// Batch context of a fused pass from this thread's batch (see BatchCtx);
+// returns the workgroup count for `tiles` tiles per instance.
+static int fused_batch(FusedBatch& B, int tiles, int k0) {
+  const int wpb = kStreamTPB / 64;
+  const BatchCtx& G = g_batch;
+  const int count = G.count > 1 ? G.count : 1;
+  const int per = std::min((tiles + wpb - 1) / wpb, kStreamMaxBlocks / count);
+  B.bpi = per > 0 ? per : 1;
+  B.bstride = count > 1 ? G.stride : 0;
+  B.bcoef = count > 1 ? G.coef : nullptr;
+  B.k0 = k0;
+  B.active = count > 1 ? G.active : nullptr;
+  return B.bpi * count;
+}
+
 // The three-sweep pass on every streamed level (n >= 128; measured on the
 // 4096^2 step against a 1024 threshold: 20.15 against 20.33 ms mixed, 25.0
 // against 25.3 ms float64 -- on the small levels it saves a launch).
@@ -1030,15 +1108,15 @@ void stream_smooth3_from_zero(const OpDesc& A, const T* b, T* xout, double a0, d
   P.A = A;
   P.b = b;
   P.out = xout;
-  P.a0 = a0;
-  P.a1 = a1;
-  P.g1 = g1;
-  P.a2 = a2;
-  P.g2 = g2;
+  P.a[0] = a0;
+  P.a[1] = a1;
+  P.a[2] = a2;
+  P.g[0] = 0.0;
+  P.g[1] = g1;
+  P.g[2] = g2;
   P.wstrips = (A.n + kS3Cols - 1) / kS3Cols;
   P.tiles = P.wstrips * ((A.n + 1 + RPW - 1) / RPW);
-  const int wpb = kStreamTPB / 64;
-  const int blocks = std::min((P.tiles + wpb - 1) / wpb, kStreamMaxBlocks);
+  const int blocks = fused_batch(P.B, P.tiles, 0);
   if (A.op == 0)
     hipLaunchKernelGGL((k_smooth3<0, RPW, T>), dim3(blocks), dim3(kStreamTPB), 0, st, P);
   else if (A.op == 2)
@@ -1071,21 +1149,24 @@ int stream_smooth2(const OpDesc& A, const T* x1, const T* x0, const T* b, TO* xo
   Smooth2Args<T, TO> P;
   P.A = A;
   P.x1 = x1;
-  P.x0 = g1 != 0.0 ? x0 : nullptr;
   P.b = b;
   P.q = q;
   P.out = xout;
   P.partials = partials;
-  P.a1 = a1;
-  P.g1 = g1;
-  P.a2 = a2;
-  P.g2 = g2;
+  P.a[0] = a1;
+  P.g[0] = g1;
+  P.a[1] = a2;
+  P.g[1] = g2;
+  P.a[2] = P.g[2] = 0.0;
   P.wstrips = (A.n + kS3Cols - 1) / kS3Cols;
   P.tiles = P.wstrips * ((A.n + 1 + RPW - 1) / RPW);
-  const int wpb = kStreamTPB / 64;
   // at most kStreamMaxBlocks workgroups (wavefronts loop over tiles), which
-  // bounds the partials to 2 kStreamMaxBlocks
-  const int blocks = std::min((P.tiles + wpb - 1) / wpb, kStreamMaxBlocks);
+  // bounds the partials to 2 kStreamMaxBlocks; a batch takes its weights from
+  // the instance records, sweeps g_batch.ia and ia + 1 (x0 is then read when
+  // the first of the two sweeps is not sweep 0, whose g is zero)
+  const int k0 = g_batch.count > 1 ? g_batch.ia : 0;
+  const int blocks = fused_batch(P.B, P.tiles, k0);
+  P.x0 = (g_batch.count > 1 ? k0 > 0 : g1 != 0.0) ? x0 : nullptr;
   if (A.op == 0)
     hipLaunchKernelGGL((k_smooth2<0, EP, RPW, T, TO>), dim3(blocks), dim3(kStreamTPB), 0, st, P);
   else if (A.op == 2)

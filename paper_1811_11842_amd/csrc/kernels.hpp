@@ -38,12 +38,13 @@ struct BatchCtx {
 };
 extern thread_local BatchCtx g_batch;
 
-// Launch shape of the tiled stencil kernels (stream.hip), used for grid
-// levels with n >= 64 V (V = 2 float64 or 4 float32 values per lane);
-// smaller levels use the one-thread-per-node kernels.
+// Launch shape of the tiled stencil kernels (stream.hip), two values per
+// lane, 128 columns per wavefront; used for grid levels with n >= 128
+// (float64) or n >= 256 (float32), smaller levels use the
+// one-thread-per-node kernels.
 struct StreamCfg {
   int rpw;      // output rows per wavefront tile
-  int wstrips;  // column strips of 64 V columns
+  int wstrips;  // column strips of 128 columns
   int rgroups;  // row groups of rpw rows
   int tiles;    // wstrips * rgroups (one wavefront each)
   int blocks;   // workgroups of 4 wavefronts (capped; wavefronts then loop)

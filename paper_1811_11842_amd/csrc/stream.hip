@@ -76,7 +76,7 @@ struct StreamArgs {
   double* partials;
   double a, g, a0;
   int rgroups;         // row groups of RPW rows
-  int wstrips;         // column strips of 64 V columns
+  int wstrips;         // column strips of 128 columns
   int tiles;           // rgroups * wstrips
   double* out2;        // E_CG_P: p'
   double* xu;          // E_CG_P: x (updated in place)
@@ -856,6 +856,9 @@ int env_int(const char* name, int dflt) {
 // count 1 = a single field).
 thread_local BatchCtx g_batch;
 
+// Tiled kernels from n = 128 in float64 and n = 256 in float32 (a float32 128^2
+// level is left to the one-node-per-thread kernels, the thresholds of the
+// original four-values-per-lane float32 tiling).
 bool stream_ok(int n, int elem_bytes) { return n >= 64 * (16 / elem_bytes); }
 
 // Rows per tile: 5 for the operator applications (y = A x, q = A p: on

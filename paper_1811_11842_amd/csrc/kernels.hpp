@@ -39,9 +39,8 @@ struct BatchCtx {
 extern thread_local BatchCtx g_batch;
 
 // Launch shape of the tiled stencil kernels (stream.hip), two values per
-// lane, 128 columns per wavefront; used for grid levels with n >= 128
-// (float64) or n >= 256 (float32), smaller levels use the
-// one-thread-per-node kernels.
+// lane, 128 columns per wavefront; used for grid levels with n >= 128,
+// smaller levels use the one-thread-per-node kernels.
 struct StreamCfg {
   int rpw;      // output rows per wavefront tile
   int wstrips;  // column strips of 128 columns

@@ -856,10 +856,14 @@ int env_int(const char* name, int dflt) {
 // count 1 = a single field).
 thread_local BatchCtx g_batch;
 
-// Tiled kernels from n = 128 in float64 and n = 256 in float32 (a float32 128^2
-// level is left to the one-node-per-thread kernels, the thresholds of the
-// original four-values-per-lane float32 tiling).
-bool stream_ok(int n, int elem_bytes) { return n >= 64 * (16 / elem_bytes); }
+// Tiled kernels from n = 128, one 128-column strip (below, the
+// one-node-per-thread kernels).  The float32 128^2 level gains from the fused
+// smoother passes (4096^2 mixed step 18.82-18.84 ms against 18.91-18.93 with
+// that level left to the one-node-per-thread kernels).
+bool stream_ok(int n, int elem_bytes) {
+  (void)elem_bytes;  // two values per lane in either precision
+  return n >= 128;
+}
 
 // Rows per tile: 5 for the operator applications (y = A x, q = A p: on
 // 4096^2 the 13-point SpMV measured 47.8-48.8 us with 5 rows against

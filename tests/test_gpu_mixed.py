@@ -59,7 +59,7 @@ def opts(op, **kw):
     return bf.default_opts(op, mg_precision=bf.MG_F32, **kw)
 
 
-@pytest.mark.parametrize("n", [4, 8, 16, 32, 64, 256, 1024])
+@pytest.mark.parametrize("n", [4, 8, 16, 32, 64, 128, 256, 1024])
 @pytest.mark.parametrize("op", ["lap", "ch"])
 def test_vcycle_f32_close_to_oracle(dev, n, op):
     """One float32 V-cycle against the oracle's float64 V-cycle.  Each float32

@@ -484,13 +484,19 @@ T* vcycle_level(bf_grid* g, std::vector<LevelT<T>>& lv, int op, double c,
   T* cur = L.xa;
   T* oth = L.xb;
   bool have_r = false;  // the residual of the pre-smoothed iterate is in L.r
-  if (fused && S.degree == 3 && smooth3r_ok(L.n, (int)sizeof(T)) && g_batch.count <= 1) {
+  // the fused passes take their coefficients from the arguments: single grids only
+  const bool single = !g_batch.coef && g_batch.count <= 1;
+  if (fused && S.degree == 3 && smooth3r_ok(L.n, (int)sizeof(T)) && single) {
     // all three sweeps and the residual in one pass (x1, x2 in registers)
     if constexpr (F32) {
       stream_smooth3_resid<T>(A, b, cur, L.r, S.a[0], S.a[1], S.g[1], S.a[2], S.g[2], st);
       have_r = true;
     }
-  } else if (fused && S.degree == 3 && smooth3_ok(L.n) && g_batch.count <= 1) {
+  } else if (fused && S.degree == 2 && smooth3_ok(L.n) && single) {
+    // both sweeps and the residual in one pass
+    stream_smooth2_resid<T>(A, b, cur, L.r, S.a[0], S.a[1], S.g[1], st);
+    have_r = true;
+  } else if (fused && S.degree == 3 && smooth3_ok(L.n) && single) {
     // all three sweeps in one pass (x1 and x2 stay in registers)
     stream_smooth3_from_zero<T>(A, b, cur, S.a[0], S.a[1], S.g[1], S.a[2], S.g[2], st);
   } else if (fused) {
@@ -521,7 +527,7 @@ T* vcycle_level(bf_grid* g, std::vector<LevelT<T>>& lv, int op, double c,
   // post-smoothing (same polynomial); on streamed single grids the last two
   // sweeps run as one pass, whose result goes to L.r (free on the way up:
   // the pass still reads the two previous iterates)
-  const bool pair = streamed && S.degree >= 2 && smooth_last2_ok(L.n) && g_batch.count <= 1;
+  const bool pair = streamed && S.degree >= 2 && smooth_last2_ok(L.n) && single;
   for (int k = 0; k < S.degree; ++k) {
     if (pair && k == S.degree - 2) {
       const int k2 = k + 1;

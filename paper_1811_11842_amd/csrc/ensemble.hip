@@ -399,10 +399,16 @@ double* e_vcycle(EClass& C, int op, int l, const double* b, int* rz_parts) {
   double* cur = Lv.xa;
   double* oth = Lv.xb;
   const bool streamed = stream_ok(Lv.n, 8);
+  bool have_r = false;  // the residual of the pre-smoothed iterate is in Lv.r
   if (streamed && deg == 3 && smooth3_ok(Lv.n)) {
     // the three sweeps in one pass (weights from the instance records)
     set_sweep(0, 0, 0);
     stream_smooth3_from_zero<double>(A, b, cur, 0.0, 0.0, 0.0, 0.0, 0.0, st);
+  } else if (streamed && deg == 2 && smooth3_ok(Lv.n)) {
+    // both sweeps and the residual in one pass
+    set_sweep(0, 0, 0);
+    stream_smooth2_resid<double>(A, b, cur, Lv.r, 0.0, 0.0, 0.0, st);
+    have_r = true;
   } else if (streamed && deg >= 2) {
     set_sweep(1, 1, 0);
     stream_smooth_from_zero<double>(A, b, cur, 0.0, 0.0, 0.0, st);
@@ -423,7 +429,7 @@ double* e_vcycle(EClass& C, int op, int l, const double* b, int* rz_parts) {
       std::swap(cur, oth);
     }
   }
-  launch_residual<double>(A, cur, b, Lv.r, nullptr, 0, st);
+  if (!have_r) launch_residual<double>(A, cur, b, Lv.r, nullptr, 0, st);
   launch_restrict<double>(Lv.n, Lv.r, C.lv[l + 1].b, st);
   double* ec = e_vcycle(C, op, l + 1, C.lv[l + 1].b, nullptr);
   // e_vcycle's scope ended: restore this level's batch context

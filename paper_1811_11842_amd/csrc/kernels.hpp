@@ -80,6 +80,12 @@ bool smooth3_ok(int n);
 template <typename T>
 void stream_smooth3_from_zero(const OpDesc& A, const T* b, T* xout, double a0, double a1,
                               double g1, double a2, double g2, hipStream_t st);
+// Two sweeps from a zero guess and the residual, in one pass (degree-2
+// smoothers): x1 = a0 D^{-1} b, xout = x1 + a1 D^{-1}(b - A x1) + g1 x1,
+// r = b - A xout.
+template <typename T>
+void stream_smooth2_resid(const OpDesc& A, const T* b, T* xout, T* r, double a0, double a1,
+                          double g1, hipStream_t st);
 // The same three sweeps followed by r = b - A xout, in one pass (float32).
 bool smooth3r_ok(int n, int elem_bytes);
 template <typename T>

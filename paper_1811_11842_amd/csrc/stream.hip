@@ -495,6 +495,7 @@ struct Smooth3Args {
   OpDesc A;
   const T* b;
   T* out;
+  T* r;  // MODE 1: the residual
   double a[3], g[3];  // sweeps 0, 1, 2 (a[0] = a0; g[0] unused)
   int wstrips, tiles;
   FusedBatch B;
@@ -548,7 +549,9 @@ __device__ __forceinline__ void window_apply(const T (&w)[N][2], int k, T coef, 
   for (int i = 0; i < V; ++i) ax[i] = apply_vals<OP>(nb[i], coef);
 }
 
-template <int OP, int RPW, typename T>
+// MODE 1 (degree-2 smoothers): two sweeps, then the residual of their
+// result, r = b - A x2, instead of the third sweep; stores x2 and r.
+template <int OP, int RPW, int MODE, typename T>
 __global__ void __launch_bounds__(kStreamTPB) k_smooth3(Smooth3Args<T> P) {
   constexpr int R = (OP == 1) ? 2 : 1;
   constexpr int NB = RPW + 4 * R;  // b (and x1) rows j0-2R .. jl+2R
@@ -609,12 +612,26 @@ __global__ void __launch_bounds__(kStreamTPB) k_smooth3(Smooth3Args<T> P) {
       const int k2 = s + R, k = s + 2 * R;
       T ax[2];
       window_apply<OP>(x2, k2, coef_row(j), ax);
-      const T ad = ca2 * dinv_row(j);
-      V2 o;
+      if constexpr (MODE == 1) {
+        V2 xo, ro;
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
-        o.v[i] = x2[k2][i] + ad * (bw[k][i] - ax[i]) + cg2 * (x2[k2][i] - x1[k][i]);
-      if (own) store_nt(reinterpret_cast<V2*>(Op + (int64_t)j * n + col), o);
+        for (int i = 0; i < 2; ++i) {
+          xo.v[i] = x2[k2][i];
+          ro.v[i] = bw[k][i] - ax[i];
+        }
+        if (own) {
+          const int64_t off = (int64_t)j * n + col;
+          store_nt(reinterpret_cast<V2*>(Op + off), xo);
+          store_nt(reinterpret_cast<V2*>(P.r + I.off + off), ro);
+        }
+      } else {
+        const T ad = ca2 * dinv_row(j);
+        V2 o;
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+          o.v[i] = x2[k2][i] + ad * (bw[k][i] - ax[i]) + cg2 * (x2[k2][i] - x1[k][i]);
+        if (own) store_nt(reinterpret_cast<V2*>(Op + (int64_t)j * n + col), o);
+      }
     }
   }
 }
@@ -1035,8 +1052,10 @@ int stream_smooth_dot2_f32(const OpDesc& A, const float* x, const float* xprev, 
                                                     0.0, q);
 }
 
-// Batch context of a fused pass from this thread's batch (see BatchCtx);
-// returns the workgroup count for `tiles` tiles per instance.
+// Batch context of a fused pass from this thread's batch (see BatchCtx; as
+// for k_stream, the coefficient records and the mask apply whenever the batch
+// supplies them, also to a batch of one); returns the workgroup count for
+// `tiles` tiles per instance.
 static int fused_batch(FusedBatch& B, int tiles, int k0) {
   const int wpb = kStreamTPB / 64;
   const BatchCtx& G = g_batch;
@@ -1044,9 +1063,9 @@ static int fused_batch(FusedBatch& B, int tiles, int k0) {
   const int per = std::min((tiles + wpb - 1) / wpb, kStreamMaxBlocks / count);
   B.bpi = per > 0 ? per : 1;
   B.bstride = count > 1 ? G.stride : 0;
-  B.bcoef = count > 1 ? G.coef : nullptr;
+  B.bcoef = G.coef;
   B.k0 = k0;
-  B.active = count > 1 ? G.active : nullptr;
+  B.active = G.active;
   return B.bpi * count;
 }
 
@@ -1107,14 +1126,15 @@ void stream_smooth3_resid(const OpDesc& A, const T* b, T* xout, T* r, double a0,
 template void stream_smooth3_resid<float>(const OpDesc&, const float*, float*, float*, double,
                                           double, double, double, double, hipStream_t);
 
-template <typename T>
-void stream_smooth3_from_zero(const OpDesc& A, const T* b, T* xout, double a0, double a1,
-                              double g1, double a2, double g2, hipStream_t st) {
+template <int MODE, typename T>
+static void launch_smooth3(const OpDesc& A, const T* b, T* xout, T* r, double a0, double a1,
+                           double g1, double a2, double g2, hipStream_t st) {
   constexpr int RPW = 4;
   Smooth3Args<T> P;
   P.A = A;
   P.b = b;
   P.out = xout;
+  P.r = r;
   P.a[0] = a0;
   P.a[1] = a1;
   P.a[2] = a2;
@@ -1125,12 +1145,28 @@ void stream_smooth3_from_zero(const OpDesc& A, const T* b, T* xout, double a0, d
   P.tiles = P.wstrips * ((A.n + 1 + RPW - 1) / RPW);
   const int blocks = fused_batch(P.B, P.tiles, 0);
   if (A.op == 0)
-    hipLaunchKernelGGL((k_smooth3<0, RPW, T>), dim3(blocks), dim3(kStreamTPB), 0, st, P);
+    hipLaunchKernelGGL((k_smooth3<0, RPW, MODE, T>), dim3(blocks), dim3(kStreamTPB), 0, st, P);
   else if (A.op == 2)
-    hipLaunchKernelGGL((k_smooth3<2, RPW, T>), dim3(blocks), dim3(kStreamTPB), 0, st, P);
+    hipLaunchKernelGGL((k_smooth3<2, RPW, MODE, T>), dim3(blocks), dim3(kStreamTPB), 0, st, P);
   else
-    hipLaunchKernelGGL((k_smooth3<1, RPW, T>), dim3(blocks), dim3(kStreamTPB), 0, st, P);
+    hipLaunchKernelGGL((k_smooth3<1, RPW, MODE, T>), dim3(blocks), dim3(kStreamTPB), 0, st, P);
 }
+
+template <typename T>
+void stream_smooth3_from_zero(const OpDesc& A, const T* b, T* xout, double a0, double a1,
+                              double g1, double a2, double g2, hipStream_t st) {
+  launch_smooth3<0, T>(A, b, xout, nullptr, a0, a1, g1, a2, g2, st);
+}
+
+template <typename T>
+void stream_smooth2_resid(const OpDesc& A, const T* b, T* xout, T* r, double a0, double a1,
+                          double g1, hipStream_t st) {
+  launch_smooth3<1, T>(A, b, xout, r, a0, a1, g1, 0.0, 0.0, st);
+}
+template void stream_smooth2_resid<double>(const OpDesc&, const double*, double*, double*,
+                                           double, double, double, hipStream_t);
+template void stream_smooth2_resid<float>(const OpDesc&, const float*, float*, float*, double,
+                                          double, double, hipStream_t);
 template void stream_smooth3_from_zero<double>(const OpDesc&, const double*, double*, double,
                                                double, double, double, double, hipStream_t);
 template void stream_smooth3_from_zero<float>(const OpDesc&, const float*, float*, double, double,
@@ -1168,12 +1204,13 @@ int stream_smooth2(const OpDesc& A, const T* x1, const T* x0, const T* b, TO* xo
   P.wstrips = (A.n + kS3Cols - 1) / kS3Cols;
   P.tiles = P.wstrips * ((A.n + 1 + RPW - 1) / RPW);
   // at most kStreamMaxBlocks workgroups (wavefronts loop over tiles), which
-  // bounds the partials to 2 kStreamMaxBlocks; a batch takes its weights from
-  // the instance records, sweeps g_batch.ia and ia + 1 (x0 is then read when
-  // the first of the two sweeps is not sweep 0, whose g is zero)
-  const int k0 = g_batch.count > 1 ? g_batch.ia : 0;
+  // bounds the partials to 2 kStreamMaxBlocks; a batch with coefficient
+  // records takes its weights from them, sweeps g_batch.ia and ia + 1 (x0 is
+  // then read when the first of the two sweeps is not sweep 0, whose g is zero)
+  const bool records = g_batch.coef != nullptr;
+  const int k0 = records ? g_batch.ia : 0;
   const int blocks = fused_batch(P.B, P.tiles, k0);
-  P.x0 = (g_batch.count > 1 ? k0 > 0 : g1 != 0.0) ? x0 : nullptr;
+  P.x0 = (records ? k0 > 0 : g1 != 0.0) ? x0 : nullptr;
   if (A.op == 0)
     hipLaunchKernelGGL((k_smooth2<0, EP, RPW, T, TO>), dim3(blocks), dim3(kStreamTPB), 0, st, P);
   else if (A.op == 2)

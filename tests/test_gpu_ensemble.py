@@ -93,6 +93,21 @@ def test_ensemble_step_matches_oracle(dev):
         assert e[0] <= 1e-10 and e[1] <= 1e-9 and e[2] <= 1e-10 and e[3] <= 1e-10
 
 
+def test_single_instance_class_matches_oracle(dev):
+    """A size class holding one instance (a batch of one) takes its
+    coefficients from the per-instance records like larger classes."""
+    specs = S.ensemble_specs(3, seed=21, sizes=(128,))
+    specs[2]["n"] = 256
+    ens, inst, phi, p, u, v, stats, _ = run(specs, dev)
+    assert sorted(c[:2] for c in ens.info()) == [(128, 2), (256, 1)]
+    for i, (ph0, u0, v0, prm) in enumerate(inst):
+        rphi, rp, ru, rv = oracle.step.step(ph0, u0, v0, **prm)
+        sc, sp = stats[0][i]
+        assert sc.status in (bf.OK, bf.AT_FLOOR) and sp.status == bf.OK
+        assert relw(unpack(ens, phi, i), rphi) <= 1e-10
+        assert relw(unpack(ens, p, i), rp) <= 1e-9
+
+
 def test_ensemble_agrees_with_single_grid(dev):
     specs = S.ensemble_specs(4, seed=5, sizes=(128, 256))
     ens, inst, phi, p, u, v, stats, _ = run(specs, dev)

@@ -813,6 +813,7 @@ void mass_correct(bf_grid* g, const double* b, double* x) {
 // Final status from the true residual (residual replacement / floor logic).
 struct KrylovState {
   int iters = 0, restarts = 0;
+  int x_updates = 0;  // rounded additions the iterate went through (see floor_accept)
   double rel = 0, rel_true = 0, floor_est = 0;
   double rel_est_cycle = HUGE_VAL;  // GMRES: residual estimate at the end of a cycle
 };
@@ -850,26 +851,27 @@ int true_residual(bf_grid* g, const OpDesc& A, const double* b, const double* x,
 // the true residual whether to stop (BF_OK / BF_AT_FLOOR / BF_NOT_CONVERGED)
 // or to restart from it (returns -1 = restart).
 //  - true residual <= rtol: converged;
-//  - true residual within 2x the representation floor: the residual left is
-//    the rounding of x to float64 (the estimate assumes one rounding per
-//    entry; the Krylov updates leave a little more), no float64 vector does
-//    much better (BF_AT_FLOOR; the recursive residual, which does not see that
-//    rounding, met rtol);
+//  - true residual within the floor bound of the iterate (floor_accept: the
+//    rounding noise of an iterate built by ks.x_updates rounded additions),
+//    BF_AT_FLOOR: no float64 vector formed that way does much better, and the
+//    recursive residual, which does not see that rounding, met rtol;
 //  - otherwise restart (iterative refinement) while each restart at least
 //    halves the true residual, up to max_restarts;
-//  - a restart that stops improving within 4x the floor is also BF_AT_FLOOR;
+//  - a restart that stops improving within twice the floor bound is also
+//    BF_AT_FLOOR;
 //  - else BF_NOT_CONVERGED.
 int decide_after_cycle(const bf_solver_opts& o, KrylovState& ks, double& last_true,
                        bool hit_maxit) {
   if (ks.rel_true <= o.rtol) return BF_OK;
   if (hit_maxit) return BF_NOT_CONVERGED;
-  if (ks.rel_true <= 2.0 * ks.floor_est) return BF_AT_FLOOR;
+  const double fb = floor_accept(ks.floor_est, ks.x_updates);
+  if (ks.rel_true <= fb) return BF_AT_FLOOR;
   if (ks.restarts < o.max_restarts && ks.rel_true < 0.5 * last_true) {
     ks.restarts++;
     last_true = ks.rel_true;
     return -1;
   }
-  return ks.rel_true <= 4.0 * ks.floor_est ? BF_AT_FLOOR : BF_NOT_CONVERGED;
+  return ks.rel_true <= 2.0 * fb ? BF_AT_FLOOR : BF_NOT_CONVERGED;
 }
 
 // Residual norms of a CG cycle, for deciding when the host may read the next
@@ -970,6 +972,7 @@ int run_cg(bf_grid* g, int op, double c, const double* b, double* x, const bf_so
       launch_r_update(g->n, g->r, g->q, g->scal, g->partials, np, st, mixed ? g->r32 : nullptr);
       launch_finalize(g->partials, np, g->scal, F_STORE, S_RR, g->n, st);
       ks.iters++;
+      ks.x_updates++;
       bool deferred = false;
       if (ks.iters % o.check_every == 0 || ks.iters == o.maxit) {
         TRY(copy_scalars_async(g, S_RR + 1));
@@ -1005,7 +1008,10 @@ int run_cg(bf_grid* g, int op, double c, const double* b, double* x, const bf_so
       }
     }
     if (pending) launch_x_update(g->n, x, pcur, g->scal, st);
-    if (op == BF_OP_CH) mass_correct(g, b, x);
+    if (op == BF_OP_CH) {
+      mass_correct(g, b, x);
+      ks.x_updates++;
+    }
     TRY(true_residual(g, A, b, x, g->r, bn, ks));
     const int d = decide_after_cycle(o, ks, last_true, !converged);
     if (d >= 0) return d;
@@ -1054,7 +1060,10 @@ int run_gmres(bf_grid* g, int op, double c, const double* b, double* x, const bf
   double last_true = HUGE_VAL;
   for (int cycle = 0;; ++cycle) {
     // r0 = b - A x (double-double), V0 = r0 / ||r0||
-    if ((op == BF_OP_CH || op == kOpMob) && cycle > 0) mass_correct(g, b, x);
+    if ((op == BF_OP_CH || op == kOpMob) && cycle > 0) {
+      mass_correct(g, b, x);
+      ks.x_updates++;
+    }
     TRY(true_residual(g, A, b, x, g->gm_V, bn, ks));
     ks.rel = ks.rel_true;
     if (cycle == 0) {
@@ -1133,6 +1142,7 @@ int run_gmres(bf_grid* g, int op, double c, const double* b, double* x, const bf
     }
     HIPCHK(hipMemcpyAsync(g->gm_y, y.data(), sizeof(double) * k, hipMemcpyHostToDevice, st));
     launch_axpy_multi(g->n, g->gm_Z, k, g->gm_y, x, st);
+    ks.x_updates++;
     HIPCHK(hipStreamSynchronize(st));  // y is a host vector reused next cycle
   }
 }

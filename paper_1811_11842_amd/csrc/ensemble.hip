@@ -610,7 +610,7 @@ int e_cg_pass(EClass& C, int op, const double* bn, double* x, const bf_solver_op
 // MG-preconditioned CG on every instance of the class (x starts at zero),
 // then per instance: the constant-mode correction (CH), the double-double
 // true residual and the status; an instance whose true residual is above
-// rtol and above twice its float64 floor restarts from that residual while
+// rtol and above the floor bound of its iterate (floor_accept) restarts from that residual while
 // each restart at least halves it (at most o.max_restarts), as on the
 // single grid.
 int e_solve(EClass& C, int op, const std::vector<double>& c, const double* b, double* x,
@@ -665,11 +665,14 @@ int e_solve(EClass& C, int op, const std::vector<double>& c, const double* b, do
       if (!std::isfinite(S.rel_res_true)) return efail(BF_ENONFINITE, "true residual is not finite");
       todo[k] = 0;
       const bool hit_maxit = S.rel_res > o.rtol;
+      // rounded additions to the iterate: one per CG iteration, plus the
+      // constant-mode correction of each pass (see floor_accept)
+      const double fb = floor_accept(S.floor_est, S.iters + S.restarts + 1);
       if (S.rel_res_true <= o.rtol) {
         S.status = BF_OK;
       } else if (hit_maxit) {
         S.status = BF_NOT_CONVERGED;
-      } else if (S.rel_res_true <= 2.0 * S.floor_est) {
+      } else if (S.rel_res_true <= fb) {
         S.status = BF_AT_FLOOR;
       } else if (S.restarts < o.max_restarts && S.rel_res_true < 0.5 * last[k]) {
         S.restarts++;
@@ -677,7 +680,7 @@ int e_solve(EClass& C, int op, const std::vector<double>& c, const double* b, do
         todo[k] = 1;
         again = true;
       } else {
-        S.status = S.rel_res_true <= 4.0 * S.floor_est ? BF_AT_FLOOR : BF_NOT_CONVERGED;
+        S.status = S.rel_res_true <= 2.0 * fb ? BF_AT_FLOOR : BF_NOT_CONVERGED;
       }
     }
     if (!again) break;

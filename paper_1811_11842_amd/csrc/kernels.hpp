@@ -1,6 +1,8 @@
 // Launchers of the device kernels (host-callable, asynchronous on `st`).
 #pragma once
 
+#include <cmath>
+
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -28,6 +30,18 @@ struct OpDesc {
 // per-instance device scalars kNumSlots apart; reductions return the
 // partial count of all instances (instance i owns the i-th equal share).
 constexpr int kCoefStride = 20;
+// Relative true residual at which a Krylov iterate counts as at its float64
+// floor: floor_est is the residual of one rounding of every entry (uniform,
+// variance ulp^2/12); an iterate built by `updates` rounded additions (CG: one
+// per iteration, plus the constant-mode correction) carries about sqrt(updates)
+// such roundings (a random walk: measured 3.75 floor_est after 14 CG updates
+// at 4096^2, against sqrt(15) = 3.87), so the bound is 1.5 sqrt(updates + 1)
+// floor_est.  The recursive residual has then met rtol, and what is left is
+// that rounding noise, which A^{-1} damps: no refinement restart is needed.
+inline double floor_accept(double floor_est, int updates) {
+  return 1.5 * std::sqrt((double)(updates > 0 ? updates : 0) + 1.0) * floor_est;
+}
+
 struct BatchCtx {
   int count = 1;
   int64_t stride = 0, stride_c = 0;

@@ -45,8 +45,8 @@ enum bf_status {
   BF_OK = 0,
   BF_NOT_CONVERGED = 1,   /* maxit reached before the tolerance            */
   BF_AT_FLOOR = 2,        /* recursive residual met rtol; the true one is  */
-                          /* at the float64 representation floor (above    */
-                          /* rtol): no float64 vector has a smaller one    */
+                          /* at the float64 representation floor of the    */
+                          /* iterate (above rtol): its rounding noise      */
   BF_EINVAL = -1,         /* bad argument (null pointer, n, option value)  */
   BF_ENOMEM = -2,         /* device allocation failed                      */
   BF_EHIP = -3,           /* HIP runtime error                             */
@@ -104,8 +104,11 @@ typedef struct {
   double  ms;            /* device time of the call (HIP events)            */
   double  floor_est;     /* expected rel_res_true of x rounded to float64:   */
                          /* sqrt(sum_W ulp(x)^2/12 * sum_j A_jk^2)/||b||_W;  */
-                         /* BF_AT_FLOOR: rel_res_true <= 2 floor_est (4 after */
-                         /* a refinement restart that stopped improving)    */
+                         /* BF_AT_FLOOR: rel_res_true <= 1.5 sqrt(k+1)       */
+                         /* floor_est for an iterate built by k rounded      */
+                         /* updates (CG iterations, GMRES cycles, constant-  */
+                         /* mode corrections; twice that after a refinement  */
+                         /* restart that stopped improving)                  */
 } bf_solve_stats;
 
 /* Parameters of the reduced semi-implicit step (dimensionless). */

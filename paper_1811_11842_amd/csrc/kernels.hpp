@@ -36,10 +36,13 @@ constexpr int kCoefStride = 20;
 // per iteration, plus the constant-mode correction) carries about sqrt(updates)
 // such roundings (a random walk: measured 3.75 floor_est after 14 CG updates
 // at 4096^2, against sqrt(15) = 3.87), so the bound is 1.5 sqrt(updates + 1)
-// floor_est.  The recursive residual has then met rtol, and what is left is
-// that rounding noise, which A^{-1} damps: no refinement restart is needed.
+// floor_est, with updates capped at 64 (long runs are not given a looser bound
+// than about 12 floor_est).  The recursive residual has then met rtol, and
+// what is left is that rounding noise, which A^{-1} damps: no refinement
+// restart is needed.
 inline double floor_accept(double floor_est, int updates) {
-  return 1.5 * std::sqrt((double)(updates > 0 ? updates : 0) + 1.0) * floor_est;
+  const int k = updates < 0 ? 0 : (updates > 64 ? 64 : updates);
+  return 1.5 * std::sqrt((double)k + 1.0) * floor_est;
 }
 
 struct BatchCtx {

@@ -1430,6 +1430,33 @@ int pressure_half(bf_grid* h, const bf_params* prm, const double* ustar, const d
   return s;
 }
 
+// Initial guess of the Cahn-Hilliard solve of a time step (x holds phi^n on
+// entry): x0 = gamma phi^n with gamma minimising ||b - gamma A phi^n||_W, or 0
+// when no gamma beats the zero guess (<b, A phi^n>_W <= 0).  Once phi is
+// smooth, phi^n is close to phi^{n+1}: at 4096^2 its relative residual is
+// 3e-2 ... 8e-3 from the third step on (against 1 for the zero guess), about
+// three CG iterations fewer; on the first steps from the noisy initial state
+// c L^2 phi^n is huge (relative residual 3e5, then 50) and gamma is tiny.
+int ch_guess(bf_grid* g, double c, const double* b, double* x) {
+  const OpDesc A = level_op(BF_OP_CH, g->n, c);
+  hipStream_t st = g->stream;
+  launch_apply(A, x, g->q, st);  // q = A phi^n (float64: only gamma depends on it)
+  wdot_async(g, b, g->q, F_STORE, S_GB);
+  wdot_async(g, g->q, g->q, F_STORE, S_GG);
+  TRY(read_scalars(g, S_GG + 1));
+  const double bq = g->h_scal[S_GB], qq = g->h_scal[S_GG];
+  if (!std::isfinite(bq) || !std::isfinite(qq)) return fail(BF_ENONFINITE, "phi is not finite");
+  if (!(bq > 0.0 && qq > 0.0)) {
+    launch_fill(g->npts, x, 0.0, st);
+    return BF_OK;
+  }
+  g->h_scal[S_GAMMA] = bq / qq;
+  HIPCHK(hipMemcpyAsync(g->scal + S_GAMMA, g->h_scal + S_GAMMA, sizeof(double),
+                        hipMemcpyHostToDevice, st));
+  launch_scale(g->n, x, x, g->scal, S_GAMMA, 0, st);
+  return BF_OK;
+}
+
 int ensure_twin(bf_grid* g) {
   if (g->twin) return BF_OK;
   HIPCHK(hipStreamCreateWithFlags(&g->twin_stream, hipStreamNonBlocking));
@@ -1462,11 +1489,10 @@ int bf_step(bf_grid* g, const bf_params* prm, double* phi, const double* ustar,
       s2 = pressure_half(g->twin, prm, ustar, vstar, p, u, v, pr, &S[1]);
       if (s2 < 0) err2 = bf_last_error();
     });
+    const double c = prm->dt * prm->M * prm->kappa;
     int s1 = bf_ch_rhs(g, prm, phi, g->work_b, g->counter);
-    if (s1 >= 0) {
-      launch_fill(g->npts, phi, 0.0, g->stream);
-      s1 = bf_solve_ch(g, prm->dt * prm->M * prm->kappa, g->work_b, phi, ch, &S[0]);
-    }
+    if (s1 >= 0) s1 = ch_guess(g, c, g->work_b, phi);
+    if (s1 >= 0) s1 = bf_solve_ch(g, c, g->work_b, phi, ch, &S[0]);
     th.join();
     HIPCHK(hipEventRecord(g->ev_join, g->twin_stream));
     HIPCHK(hipStreamWaitEvent(g->stream, g->ev_join, 0));
@@ -1481,8 +1507,9 @@ int bf_step(bf_grid* g, const bf_params* prm, double* phi, const double* ustar,
   }
   (void)hipGetLastError();
   TRY(bf_ch_rhs(g, prm, phi, g->work_b, g->counter));
-  launch_fill(g->npts, phi, 0.0, g->stream);
-  const int s1 = bf_solve_ch(g, prm->dt * prm->M * prm->kappa, g->work_b, phi, ch, &S[0]);
+  const double c = prm->dt * prm->M * prm->kappa;
+  TRY(ch_guess(g, c, g->work_b, phi));
+  const int s1 = bf_solve_ch(g, c, g->work_b, phi, ch, &S[0]);
   if (s1 < 0) return s1;
   TRY(bf_pressure_rhs(g, prm->dt, ustar, vstar, g->work_b));
   launch_fill(g->npts, p, 0.0, g->stream);

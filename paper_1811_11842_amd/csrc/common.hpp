@@ -28,6 +28,9 @@ enum Slot {
   S_RTRUE = 8, // ||b - A x||_W^2
   S_TMP = 9,
   S_ULP2 = 10, // sum_W ulp(x)^2 (representation floor estimate)
+  S_GB = 11,   // initial guess: <b, A x0>_W
+  S_GG = 12,   // initial guess: <A x0, A x0>_W
+  S_GAMMA = 13,  // initial guess: its scale factor
   S_GM = 16,   // GMRES scalars start here (up to 64+ slots)
   kNumSlots = 256
 };

@@ -225,11 +225,12 @@ int bf_velocity_correct(bf_grid* g, double dt, const double* p,
                         const double* ustar, const double* vstar,
                         double* u, double* v);
 
-/* One time step: Cahn-Hilliard right-hand side and solve (phi in/out, solved
- * from a zero initial guess), pressure right-hand side and solve (p out,
- * zero initial guess), velocity correction (u, v may be NULL to skip).
- * stats[0] = Cahn-Hilliard solve, stats[1] = pressure solve.  ch / pr may be
- * NULL for the defaults. */
+/* One time step: Cahn-Hilliard right-hand side and solve (phi in/out; the
+ * solve starts from gamma phi^n, gamma minimising the initial residual, or
+ * from zero when no gamma helps -- nothing is carried over between calls),
+ * pressure right-hand side and solve (p out, zero initial guess), velocity
+ * correction (u, v may be NULL to skip).  stats[0] = Cahn-Hilliard solve,
+ * stats[1] = pressure solve.  ch / pr may be NULL for the defaults. */
 int bf_step(bf_grid* g, const bf_params* prm, double* phi, const double* ustar,
             const double* vstar, double* p, double* u, double* v,
             const bf_solver_opts* ch, const bf_solver_opts* pr,

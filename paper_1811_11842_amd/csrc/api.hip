@@ -1670,8 +1670,9 @@ int bf_step_ch(bf_grid* g, const bf_params* prm, double* phi, const double* u, c
   std::memset(S, 0, sizeof(*S));
   TRY(bf_ch_rhs(g, prm, phi, g->work_b, g->counter));
   if (u) launch_advect_sub(g->n, phi, u, v, g->work_b, prm->dt, g->stream);
-  launch_fill(g->npts, phi, 0.0, g->stream);
-  const int s = bf_solve_ch(g, prm->dt * prm->M * prm->kappa, g->work_b, phi, o, S);
+  const double c = prm->dt * prm->M * prm->kappa;
+  TRY(ch_guess(g, c, g->work_b, phi));
+  const int s = bf_solve_ch(g, c, g->work_b, phi, o, S);
   if (s < 0) return s;
   int32_t clamped = 0;
   HIPCHK(hipMemcpyAsync(&clamped, g->counter, sizeof(int32_t), hipMemcpyDeviceToHost, g->stream));
@@ -1703,7 +1704,7 @@ int bf_step_ch_cn(bf_grid* g, const bf_params* prm, double* phi, double* phi_pre
                 prm->dt * prm->M, 1.0 / prm->Npoly, prm->chi, prm->phi_lo, prm->phi_hi,
                 g->counter, st);
   launch_copy(g->npts, phi, phi_prev, st);
-  launch_fill(g->npts, phi, 0.0, st);
+  TRY(ch_guess(g, 0.5 * c, g->work_b, phi));
   const int s = bf_solve_ch(g, 0.5 * c, g->work_b, phi, o, S);
   if (s < 0) return s;
   int32_t clamped = 0;

@@ -208,6 +208,15 @@ __global__ void __launch_bounds__(kBlock) ke_x_update(Geo G, int64_t stride, dou
   EGRID(idx, G.npts) x[idx] += alpha * p[idx];
 }
 
+// x *= scal[S_GAMMA] of the instance.
+__global__ void __launch_bounds__(kBlock) ke_scale(Geo G, int64_t stride, double* __restrict__ x,
+                                                   const double* __restrict__ scal) {
+  const int inst = blockIdx.y;
+  const double g = scal[(int64_t)inst * kNumSlots + S_GAMMA];
+  x += inst * stride;
+  EGRID(idx, G.npts) x[idx] *= g;
+}
+
 // y = x + sign * mean (mean = scal[S_MEAN] of the instance).
 __global__ void __launch_bounds__(kBlock) ke_add_mean(Geo G, int64_t stride, const double* x,
                                                       double* y, const double* __restrict__ scal,
@@ -613,12 +622,24 @@ int e_cg_pass(EClass& C, int op, const double* bn, double* x, const bf_solver_op
 // rtol and above the floor bound of its iterate (floor_accept) restarts from that residual while
 // each restart at least halves it (at most o.max_restarts), as on the
 // single grid.
+// guess: x holds a field on entry and every instance starts from gamma x,
+// gamma = <b, A x>_W / <A x, A x>_W (the least-squares multiple; zero when
+// that is not positive); otherwise from zero.
 int e_solve(EClass& C, int op, const std::vector<double>& c, const double* b, double* x,
-            const bf_solver_opts& o, std::vector<bf_solve_stats>& stats) {
+            const bf_solver_opts& o, std::vector<bf_solve_stats>& stats, bool guess) {
   hipStream_t st = C.stream;
   const Geo G = make_geo(C.n);
   const int B = C.count;
   if (op == BF_OP_CH && C.cvals != c) ETRY(build_tables(C, op, c));
+  const OpDesc A0 = host_level_op(op, C.n, 0.0);
+  if (guess) {
+    {
+      BatchScope scope(C, C.npts, 0, level_coef(C, op, 0), nullptr, C.rpw);
+      launch_apply(A0, x, C.q, st);
+    }
+    e_wdot(C, b, C.q, 0, F_STORE, S_GB);
+    e_wdot(C, C.q, C.q, 0, F_STORE, S_GG);
+  }
   e_wdot(C, b, b, 0, F_STORE, S_BN2);
   ETRY(e_read(C));
   std::vector<double> bn(B), last(B, HUGE_VAL);
@@ -630,10 +651,24 @@ int e_solve(EClass& C, int op, const std::vector<double>& c, const double* b, do
     stats[k] = bf_solve_stats();
     stats[k].status = BF_OK;
     todo[k] = bn[k] > 0 ? 1 : 0;
+    if (guess) {
+      double* sc = C.h_scal + (size_t)k * kNumSlots;
+      const double bq = sc[S_GB], qq = sc[S_GG];
+      sc[S_GAMMA] = bq > 0.0 && qq > 0.0 && std::isfinite(bq / qq) ? bq / qq : 0.0;
+    }
   }
-  launch_fill(C.npts * B, x, 0.0, st);
-  launch_copy(C.npts * B, b, C.r, st);
-  const OpDesc A0 = host_level_op(op, C.n, 0.0);
+  if (guess) {
+    // the host copy of the scalars is current (read above): send it back with gamma
+    ECHK(hipMemcpyAsync(C.scal, C.h_scal, sizeof(double) * kNumSlots * B, hipMemcpyHostToDevice,
+                        st));
+    hipLaunchKernelGGL(ke_scale, dim3(ew_blocks(C.npts), B), dim3(kBlock), 0, st, G, C.npts, x,
+                       C.scal);
+    BatchScope scope(C, C.npts, 0, level_coef(C, op, 0), nullptr, C.rpw);
+    launch_residual_dd(A0, x, b, C.r, C.partials, 0, st);
+  } else {
+    launch_fill(C.npts * B, x, 0.0, st);
+    launch_copy(C.npts * B, b, C.r, st);
+  }
   const std::vector<double>& h_coef = C.h_coef0[op];
   std::vector<int> ran;
   for (;;) {
@@ -716,18 +751,18 @@ int e_step_class(bf_ensemble* e, EClass& C, const bf_params* prm, double* phi,
   }
   ECHK(hipMemcpyAsync(C.prm, hp.data(), sizeof(EParam) * B, hipMemcpyHostToDevice, st));
   launch_fill_i32(B, C.clamped, 0, st);
-  // Cahn-Hilliard: b = phi + dt M L mu(phi), solve from zero into phi
+  // Cahn-Hilliard: b = phi + dt M L mu(phi), solve into phi from gamma phi
   hipLaunchKernelGGL(ke_ch_rhs, dim3(ew_blocks(C.npts), B), dim3(kBlock), 0, st, G, C.npts, C.prm,
                      phi + o, C.work_b, C.clamped);
   std::vector<bf_solve_stats> sch(B), spr(B);
-  ETRY(e_solve(C, BF_OP_CH, c, C.work_b, phi + o, och, sch));
+  ETRY(e_solve(C, BF_OP_CH, c, C.work_b, phi + o, och, sch, true));
   // pressure: rhs = div(u*)/dt, weighted mean removed; solve; mean of p removed
   hipLaunchKernelGGL(ke_divergence, dim3(ew_blocks(C.npts), B), dim3(kBlock), 0, st, G, C.npts,
                      C.prm, ustar + o, vstar + o, C.work_b);
   e_wdot(C, C.work_b, nullptr, 0, F_MEAN, 0);
   hipLaunchKernelGGL(ke_add_mean, dim3(ew_blocks(C.npts), B), dim3(kBlock), 0, st, G, C.npts,
                      C.work_b, C.work_p, C.scal, -1.0, nullptr);
-  ETRY(e_solve(C, BF_OP_LAP, zeros, C.work_p, p + o, opr, spr));
+  ETRY(e_solve(C, BF_OP_LAP, zeros, C.work_p, p + o, opr, spr, false));
   e_wdot(C, p + o, nullptr, 0, F_MEAN, 0);
   hipLaunchKernelGGL(ke_add_mean, dim3(ew_blocks(C.npts), B), dim3(kBlock), 0, st, G, C.npts,
                      p + o, p + o, C.scal, -1.0, nullptr);

@@ -123,6 +123,36 @@ def test_ensemble_agrees_with_single_grid(dev):
             assert relw(unpack(ens, p, i), pp.cpu().numpy()) <= 1e-10
 
 
+def test_ensemble_step_depends_only_on_its_arguments(dev):
+    """An ensemble keeps nothing between steps: the same states stepped again
+    after a step from other states (and with other values in the output
+    arrays) give bit-identical fields and iteration counts."""
+    specs = S.ensemble_specs(3, sizes=(128, 256))
+    inst = [S.ensemble_instance(s) for s in specs]
+    other = [S.ensemble_instance(dict(s, seed_phi=s["seed_phi"] + 500)) for s in specs]
+    ens = bf.Ensemble([s["n"] for s in specs])
+    prms = [bf.make_params(**a[3]) for a in inst]
+    oc = bf.default_opts(bf.OP_CH, rtol=1e-10)
+    op = bf.default_opts(bf.OP_LAP, rtol=1e-10)
+
+    def one(states, fill):
+        phi = pack(ens, [a[0] for a in states], dev)
+        us = pack(ens, [a[1] for a in states], dev)
+        vs = pack(ens, [a[2] for a in states], dev)
+        p, u, v = ens.field(fill), ens.field(fill), ens.field(fill)
+        st, _ = ens.step(prms, phi, us, vs, p, u, v, oc, op)
+        torch.cuda.synchronize()
+        return ([t.cpu().numpy() for t in (phi, p, u, v)],
+                [(s.iters, s.restarts) for pair in st for s in pair])
+
+    first, it1 = one(inst, 0.0)
+    one(other, 0.0)
+    again, it2 = one(inst, 2.0)
+    assert it1 == it2
+    for a, b in zip(first, again):
+        assert np.array_equal(a, b)
+
+
 def test_masked_instance_next_to_iterating_ones(dev):
     """Instance 1 has no flow: its pressure right-hand side is zero, so it is
     masked from the start and must come out as p = 0, u = v = 0, while its

@@ -407,6 +407,35 @@ def test_step_small_matches_oracle(dev):
     assert stats[0][0].clamped == 0
 
 
+def test_step_depends_only_on_its_arguments(dev):
+    """bf_step keeps nothing between calls (its Cahn-Hilliard warm start is
+    built from phi^n alone; p, u, v are outputs only): a state stepped again on
+    the same grid after a step from another state, with other values in the
+    output arrays, gives bit-identical fields and iteration counts, and so does
+    a fresh grid."""
+    n = 256
+    phi0 = S.initial_phi(n)
+    u0, v0 = S.inflow_velocity(n)
+    oc = bf.default_opts(bf.OP_CH, rtol=1e-10)
+    op = bf.default_opts(bf.OP_LAP, rtol=1e-10)
+    prm = bf.make_params(**PRM)
+
+    def one(g, phi_np, fill):
+        phi, us, vs = to_dev(phi_np, dev), to_dev(u0, dev), to_dev(v0, dev)
+        p, u, v = g.field(fill), g.field(fill), g.field(fill)
+        st = g.step(prm, phi, us, vs, p, u, v, oc, op)
+        return [to_np(t) for t in (phi, p, u, v)], [(s.iters, s.restarts) for s in st]
+
+    g = grid(n)
+    first, it1 = one(g, phi0, 0.0)
+    one(g, S.initial_phi(n, seed=4242), 0.0)
+    again, it2 = one(g, phi0, 3.0)
+    fresh, it3 = one(bf.Grid(n), phi0, -1.0)
+    assert it1 == it2 == it3
+    for a, b, c in zip(first, again, fresh):
+        assert np.array_equal(a, b) and np.array_equal(a, c)
+
+
 def test_step_1024_three_steps_and_mass(dev):
     n = 1024
     phi0, u0, v0, phi, p, u, v, stats = _run_step(dev, n, 3)

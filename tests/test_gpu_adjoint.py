@@ -28,8 +28,8 @@ import synthetic as S
 from oracle import adjoint as adj
 from oracle import ops
 
-bf = pytest.importorskip("paper_1811_11842_amd")
-from paper_1811_11842_amd import adjoint as bfa  # noqa: E402
+import paper_1811_11842_amd as bf  # loads the HIP library on first use; raises if it is missing
+from paper_1811_11842_amd import adjoint as bfa
 
 pytestmark = pytest.mark.gpu
 PRM = dict(dt=1e-4, M=1.0, kappa=1e-3, Npoly=100.0)

@@ -21,7 +21,7 @@ import torch
 
 from oracle import spectral
 
-bf = pytest.importorskip("paper_1811_11842_amd")
+import paper_1811_11842_amd as bf  # loads the HIP library on first use; raises if it is missing
 
 pytestmark = pytest.mark.gpu
 N = 32768

@@ -22,7 +22,7 @@ import synthetic as S
 from oracle import mobility as mob
 from oracle import ops
 
-bf = pytest.importorskip("paper_1811_11842_amd")
+import paper_1811_11842_amd as bf  # loads the HIP library on first use; raises if it is missing
 
 pytestmark = pytest.mark.gpu
 PRM = S.DEFAULT_PARAMS

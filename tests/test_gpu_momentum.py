@@ -21,7 +21,7 @@ import synthetic as S
 from oracle import momentum as mom
 from oracle import ops
 
-bf = pytest.importorskip("paper_1811_11842_amd")
+import paper_1811_11842_amd as bf  # loads the HIP library on first use; raises if it is missing
 
 pytestmark = pytest.mark.gpu
 DT = 1e-4

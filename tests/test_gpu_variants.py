@@ -11,7 +11,7 @@ import oracle
 import synthetic as S
 from oracle import cn, fh, ops, spectral
 
-bf = pytest.importorskip("paper_1811_11842_amd")
+import paper_1811_11842_amd as bf  # loads the HIP library on first use; raises if it is missing
 
 pytestmark = pytest.mark.gpu
 PRM = S.DEFAULT_PARAMS

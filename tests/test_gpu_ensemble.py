@@ -123,6 +123,33 @@ def test_ensemble_agrees_with_single_grid(dev):
             assert relw(unpack(ens, p, i), pp.cpu().numpy()) <= 1e-10
 
 
+def test_ensemble_largest_instance_size(dev):
+    """An 8192 x 8192 instance (the largest size an ensemble accepts) next to
+    a 128 x 128 one: the large instance against the single-grid step of the
+    same state, the small one against the oracle."""
+    specs = S.ensemble_specs(2, seed=31, sizes=(128,))
+    specs[0]["n"] = 8192
+    print("ensemble 8192 + 128", flush=True)
+    ens, inst, phi, p, u, v, stats, ms = run(specs, dev)
+    for sc, sp in stats[0]:
+        assert sc.status in (bf.OK, bf.AT_FLOOR) and sp.status == bf.OK
+    ph0, u0, v0, prm = inst[0]
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
+    with bf.Grid(8192) as g:
+        ph, pp, uu, vv = t(ph0), g.field(0.0), g.field(0.0), g.field(0.0)
+        g.step(bf.make_params(**prm), ph, t(u0), t(v0), pp, uu, vv,
+               bf.default_opts(bf.OP_CH, rtol=1e-10), bf.default_opts(bf.OP_LAP, rtol=1e-10))
+        torch.cuda.synchronize()
+        e = (relw(unpack(ens, phi, 0), ph.cpu().numpy()), relw(unpack(ens, p, 0), pp.cpu().numpy()),
+             relw(unpack(ens, u, 0), uu.cpu().numpy()))
+    print(f"step {ms:.1f} ms, 8192 instance vs single grid {e}", flush=True)
+    assert e[0] <= 1e-10 and e[1] <= 1e-9 and e[2] <= 1e-10
+    ph0, u0, v0, prm = inst[1]
+    rphi, rp, ru, rv = oracle.step.step(ph0, u0, v0, **prm)
+    assert relw(unpack(ens, phi, 1), rphi) <= 1e-10
+    assert relw(unpack(ens, p, 1), rp) <= 1e-9
+
+
 def test_ensemble_step_depends_only_on_its_arguments(dev):
     """An ensemble keeps nothing between steps: the same states stepped again
     after a step from other states (and with other values in the output

@@ -150,6 +150,28 @@ def test_ensemble_largest_instance_size(dev):
     assert relw(unpack(ens, p, 1), rp) <= 1e-9
 
 
+def test_ensemble_rejects_bad_parameters_and_options(dev):
+    """Per-instance parameters and the solver options are checked before any
+    work is queued; the fields are left as they were."""
+    ens = bf.Ensemble([128, 256])
+    phi = ens.field(0.25)
+    z = ens.field(0.0)
+    good = bf.make_params(**S.DEFAULT_PARAMS)
+    bad = bf.make_params(**dict(S.DEFAULT_PARAMS, dt=0.0))
+    with pytest.raises(bf.BiofilmError, match="EINVAL"):
+        ens.step([good, bad], phi, z, z, ens.field(0.0))
+    with pytest.raises(bf.BiofilmError, match="EUNSUPPORTED"):
+        ens.step([good, good], phi, z, z, ens.field(0.0),
+                 ch=bf.default_opts(bf.OP_CH, mg_precision=bf.MG_F32))
+    with pytest.raises(bf.BiofilmError, match="EUNSUPPORTED"):
+        ens.step([good, good], phi, z, z, ens.field(0.0),
+                 pr=bf.default_opts(bf.OP_LAP, ksp=bf.KSP_GMRES))
+    with pytest.raises(ValueError):
+        ens.step([good], phi, z, z, ens.field(0.0))
+    torch.cuda.synchronize()
+    assert bool(torch.all(phi == 0.25))
+
+
 def test_ensemble_step_depends_only_on_its_arguments(dev):
     """An ensemble keeps nothing between steps: the same states stepped again
     after a step from other states (and with other values in the output

@@ -69,6 +69,22 @@ def test_invalid_grid_arguments_rejected_before_any_device_work():
     assert L.bf_step_ch_mob(None, None, None, None, None) == bf.EINVAL
 
 
+def test_invalid_ensemble_arguments_rejected_before_any_device_work():
+    L = bf.lib()
+    h = ctypes.c_void_p()
+    for sizes in ((64,), (128, 100), (16384,), (256, 128, 8193)):
+        n = (ctypes.c_int32 * len(sizes))(*sizes)
+        assert L.bf_ensemble_create(n, len(sizes), None, ctypes.byref(h)) == bf.EINVAL
+        assert b"powers of two in [128, 8192]" in L.bf_last_error()
+        assert h.value is None
+    n = (ctypes.c_int32 * 1)(128)
+    assert L.bf_ensemble_create(n, 0, None, ctypes.byref(h)) == bf.EINVAL
+    assert L.bf_ensemble_create(None, 1, None, ctypes.byref(h)) == bf.EINVAL
+    assert L.bf_ensemble_step(None, None, None, None, None, None, None, None, None, None, None,
+                              None) == bf.EINVAL
+    assert L.bf_ensemble_destroy(None) == bf.OK
+
+
 def test_missing_library_fails_loudly(tmp_path, monkeypatch):
     monkeypatch.setattr(bf, "LIB_PATH", str(tmp_path / "nope.so"))
     monkeypatch.setattr(bf, "_lib", None)

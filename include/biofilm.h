@@ -308,7 +308,9 @@ int bf_ensemble_info(const bf_ensemble* e, int32_t* nclasses, int32_t* class_n,
                      int32_t* class_count, int32_t* class_rpw);
 
 /* One step of every instance (bf_step semantics: phi in/out, p out, u, v out
- * or both NULL) with the parameters prm[i].  ch / pr: only rtol and maxit may
+ * or both NULL; each instance's Cahn-Hilliard solve starts from its own
+ * least-squares multiple of phi, its pressure solve from zero; nothing is
+ * carried over between calls) with the parameters prm[i].  ch / pr: only rtol and maxit may
  * differ from the defaults (float64 CG with the default multigrid; others
  * return BF_EUNSUPPORTED); no refinement restarts.  stats[2 i] / stats[2 i + 1]
  * receive the Cahn-Hilliard / pressure solve of instance i.  ms (host, may be

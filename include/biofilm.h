@@ -185,8 +185,9 @@ int bf_solve_ch_mob(bf_grid* g, double c, const double* m, const double* b, doub
 
 /* One Cahn-Hilliard step with the phi-dependent mobility m = M clamp(phi^n):
  *   b = phi + dt L_m mu_FH(clamp(phi)),
- *   (I + dt*kappa*L_m L) phi' = b,  solved in place from a zero guess
- * (bf_solve_ch_mob).  Synchronous; stats (may be NULL) receives the solve's
+ *   (I + dt*kappa*L_m L) phi' = b,  solved in place (bf_solve_ch_mob) from
+ * gamma phi, the least-squares multiple of phi for this operator (zero when
+ * no positive gamma helps).  Synchronous; stats (may be NULL) receives the solve's
  * statistics and the clamp count. */
 int bf_step_ch_mob(bf_grid* g, const bf_params* prm, double* phi, const bf_solver_opts* o,
                    bf_solve_stats* stats);
@@ -241,7 +242,9 @@ int bf_step(bf_grid* g, const bf_params* prm, double* phi, const double* ustar,
  *   b = phi + dt*M*L mu_FH(clamp(phi)) - dt*D(phi; u, v),
  *   D(phi; u, v) = div_h(phi*u, phi*v)  (2h central, phi even and v odd
  *   across the walls),
- *   (I + dt*M*kappa*L^2) phi' = b, solved in place from a zero guess.
+ *   (I + dt*M*kappa*L^2) phi' = b, solved in place from gamma phi (the
+ *   least-squares multiple of phi for this b, zero when no positive gamma
+ *   helps, as in bf_step).
  * u, v: device fields of the advecting velocity (both NULL: no advection,
  * the Cahn-Hilliard half of bf_step); they must not alias phi.  Synchronous;
  * stats (may be NULL) receives the solve's statistics and the clamp count. */
@@ -252,7 +255,7 @@ int bf_step_ch(bf_grid* g, const bf_params* prm, double* phi, const double* u,
  * (the paper's second-order time scheme, Sec. 4):
  *   (I + c/2 L^2) phi^{n+1} = (I - c/2 L^2) phi^n + dt*M*L mu_FH(clamp(phi*)),
  *   phi* = (3 phi^n - phi^{n-1}) / 2,  c = dt*M*kappa,
- * solved from a zero guess.  phi: in phi^n, out phi^{n+1}; phi_prev: in
+ * solved from gamma phi^n (as in bf_step_ch).  phi: in phi^n, out phi^{n+1}; phi_prev: in
  * phi^{n-1} (ignored when first != 0, then phi* = phi^n), out phi^n.  They
  * must not alias.  Synchronous; stats as in bf_step_ch. */
 int bf_step_ch_cn(bf_grid* g, const bf_params* prm, double* phi, double* phi_prev,

@@ -1430,6 +1430,8 @@ int pressure_half(bf_grid* h, const bf_params* prm, const double* ustar, const d
   return s;
 }
 
+int scale_guess(bf_grid* g, const double* b, double* x);
+
 // Initial guess of the Cahn-Hilliard solve of a time step (x holds phi^n on
 // entry): x0 = gamma phi^n with gamma minimising ||b - gamma A phi^n||_W, or 0
 // when no gamma beats the zero guess (<b, A phi^n>_W <= 0).  Once phi is
@@ -1439,8 +1441,15 @@ int pressure_half(bf_grid* h, const bf_params* prm, const double* ustar, const d
 // c L^2 phi^n is huge (relative residual 3e5, then 50) and gamma is tiny.
 int ch_guess(bf_grid* g, double c, const double* b, double* x) {
   const OpDesc A = level_op(BF_OP_CH, g->n, c);
+  launch_apply(A, x, g->q, g->stream);  // q = A phi^n (float64: only gamma depends on it)
+  return scale_guess(g, b, x);
+}
+
+// The common part of the least-squares initial guesses: with q = A x in g->q,
+// x = gamma x, gamma = <b, q>_W / <q, q>_W, or x = 0 when gamma would not be
+// positive.
+int scale_guess(bf_grid* g, const double* b, double* x) {
   hipStream_t st = g->stream;
-  launch_apply(A, x, g->q, st);  // q = A phi^n (float64: only gamma depends on it)
   wdot_async(g, b, g->q, F_STORE, S_GB);
   wdot_async(g, g->q, g->q, F_STORE, S_GG);
   TRY(read_scalars(g, S_GG + 1));
@@ -1594,8 +1603,10 @@ int bf_step_ch_mob(bf_grid* g, const bf_params* prm, double* phi, const bf_solve
   launch_fill_i32(1, g->counter, 0, st);
   launch_mob_rhs(g->n, phi, g->work_m, g->work_mu, g->work_b, prm->M, prm->dt, 1.0 / prm->Npoly,
                  prm->chi, prm->phi_lo, prm->phi_hi, g->counter, st);
-  launch_fill(g->npts, phi, 0.0, st);
+  // start from gamma phi^n, the least-squares multiple for the mobility operator
+  launch_mob(g->n, prm->dt * prm->kappa, g->work_m, phi, nullptr, g->q, nullptr, 0, st);
   HIPCHK(hipGetLastError());
+  TRY(scale_guess(g, g->work_b, phi));
   bf_solve_stats local;
   bf_solve_stats* S = stats ? stats : &local;
   std::memset(S, 0, sizeof(*S));

@@ -122,6 +122,32 @@ def test_step_matches_oracle(dev, n):
     assert dm <= 1e-13
 
 
+def test_step_depends_only_on_its_arguments(dev):
+    """bf_step_ch_mob keeps nothing between calls (its warm start is built from
+    phi^n alone): a state stepped again after a step from another state gives
+    bit-identical phi and iteration counts, and so does a fresh grid."""
+    n = 256
+    prm = bf.make_params(**PRM)
+    o = gmres_opts(rtol=1e-12)
+    g = grid(n)
+    phi = D(S.initial_phi(n), dev)
+    g.step_ch_mob(prm, phi, o)
+    state = to_np(phi)  # one step in: the least-squares gamma is far from zero
+
+    def one(grid_, ph):
+        t = D(ph, dev)
+        st = grid_.step_ch_mob(prm, t, o)
+        return to_np(t), (st.iters, st.restarts)
+
+    a, ia = one(g, state)
+    one(g, S.initial_phi(n, seed=4242))
+    b, ib = one(g, state)
+    with bf.Grid(n) as h:
+        c, ic = one(h, state)
+    assert ia == ib == ic
+    assert np.array_equal(a, b) and np.array_equal(a, c)
+
+
 def test_uniform_state_is_a_fixed_point(dev):
     """A uniform phi has a constant mu and mobility: b = phi and the solution is
     phi.  (The preconditioned Krylov space is not the constant mode alone -- the

@@ -59,6 +59,34 @@ def test_crank_nicolson_steps_match_oracle(dev, n):
         assert relw(to_np(prev), ref2) <= 1e-10
 
 
+def test_crank_nicolson_step_depends_only_on_its_arguments(dev):
+    """bf_step_ch_cn keeps nothing between calls: the same (phi^n, phi^{n-1})
+    stepped again after a step from other states gives bit-identical fields
+    and iteration counts, and so does a fresh grid."""
+    n = 256
+    prm = bf.make_params(**PRM)
+    o = bf.default_opts(bf.OP_CH, rtol=1e-10)
+
+    def one(g, cur, old):
+        ph, pv = torch.from_numpy(cur).to(dev), torch.from_numpy(old).to(dev)
+        st = g.step_ch_cn(prm, ph, pv, first=False, opts=o)
+        return to_np(ph), to_np(pv), (st.iters, st.restarts)
+
+    with bf.Grid(n) as g:
+        phi = torch.from_numpy(S.initial_phi(n)).to(dev)
+        prev = g.field(0.0)
+        g.step_ch_cn(prm, phi, prev, first=True, opts=o)
+        cur, old = to_np(phi), to_np(prev)
+        r1 = one(g, cur, old)
+        one(g, S.initial_phi(n, seed=4242), S.initial_phi(n, seed=4243))
+        r2 = one(g, cur, old)
+    with bf.Grid(n) as h:
+        r3 = one(h, cur, old)
+    assert r1[2] == r2[2] == r3[2]
+    for k in range(2):
+        assert np.array_equal(r1[k], r2[k]) and np.array_equal(r1[k], r3[k])
+
+
 def test_crank_nicolson_conserves_mass(dev):
     n = 256
     phi0 = S.initial_phi(n)

@@ -407,6 +407,28 @@ def test_step_small_matches_oracle(dev):
     assert stats[0][0].clamped == 0
 
 
+def test_step_with_the_paper_table_parameters(dev):
+    """One step with the Flory-Huggins parameters of the paper's parameter
+    table (Sec. 5: chi = 0.58, N = 1e3) instead of the workload's (0.6, 100):
+    they enter the right-hand side only; parity with the oracle as for the
+    workload's parameters."""
+    n = 256
+    prm = dict(PRM, chi=0.58, Npoly=1000.0)
+    phi0 = S.initial_phi(n)
+    u0, v0 = S.inflow_velocity(n)
+    g = grid(n)
+    phi = to_dev(phi0, dev)
+    us, vs = to_dev(u0, dev), to_dev(v0, dev)
+    p, u, v = g.field(), g.field(), g.field()
+    sc, sp = g.step(bf.make_params(**prm), phi, us, vs, p, u, v,
+                    bf.default_opts(bf.OP_CH, rtol=1e-10), bf.default_opts(bf.OP_LAP, rtol=1e-10))
+    rphi, rp, ru, rv = oracle.step.step(phi0, u0, v0, **prm)
+    assert sc.status in (bf.OK, bf.AT_FLOOR) and sp.status == bf.OK
+    assert relw(to_np(phi), rphi) <= 1e-10
+    assert relw(to_np(p), rp) <= 1e-9
+    assert relw(to_np(u), ru) <= 1e-10 and relw(to_np(v), rv) <= 1e-10
+
+
 def test_step_depends_only_on_its_arguments(dev):
     """bf_step keeps nothing between calls (its Cahn-Hilliard warm start is
     built from phi^n alone; p, u, v are outputs only): a state stepped again on

@@ -19,7 +19,21 @@ from __future__ import annotations
 
 import torch
 
-from . import (OP_CH, OP_LAP, MG_F64, Grid, SolverOpts, default_opts, make_params)
+from . import (NOT_CONVERGED, OP_CH, OP_LAP, MG_F64, Grid, SolverOpts, default_opts,
+               make_params)
+
+
+class ConvergenceError(RuntimeError):
+    """A solve of the rollout (forward step, adjoint step or velocity
+    projection) stopped at its iteration limit: the gradient would be built
+    on an unconverged state, so none is returned."""
+
+
+def _converged(st, what):
+    if st.status == NOT_CONVERGED:
+        raise ConvergenceError(f"{what}: not converged after {st.iters} iterations "
+                               f"(relative residual {st.rel_res_true:.3e})")
+    return st
 
 
 class Rollout:
@@ -51,7 +65,7 @@ class Rollout:
         g, dt = self.g, self.params.get("dt", 1e-4)
         rhs = g.pressure_rhs(dt, ustar, vstar)
         p = g.field(0.0)
-        g.solve_pressure(rhs, p, self.opts_p)
+        _converged(g.solve_pressure(rhs, p, self.opts_p), "pressure solve")
         return g.velocity_correct(dt, p, ustar, vstar)
 
     def velocity(self, U):
@@ -69,7 +83,8 @@ class Rollout:
         for s in range(self.steps):
             if s % self.k == 0:
                 ckpt[s] = phi.clone()
-            self.stats.append(self.g.step_ch(prm, phi, u, v, self.opts_ch))
+            self.stats.append(_converged(self.g.step_ch(prm, phi, u, v, self.opts_ch),
+                                         f"forward step {s}"))
         return phi, ckpt
 
     def backward(self, lam_N, ckpt, chi, U):
@@ -84,12 +99,12 @@ class Rollout:
             states = [ckpt[s0].clone()]
             for _ in range(s0, s1 - 1):          # recompute the segment
                 nxt = states[-1].clone()
-                self.g.step_ch(prm, nxt, u, v, self.opts_ch)
+                _converged(self.g.step_ch(prm, nxt, u, v, self.opts_ch), "recomputed step")
                 states.append(nxt)
             for s in range(s1 - 1, s0 - 1, -1):
                 lam, (a, b), st = self.g.adjoint_step(prm, states[s - s0], lam, lam, u, v,
                                                       du, dv, self.opts_adj)
-                self.stats.append(st)
+                self.stats.append(_converged(st, f"adjoint step {s}"))
                 gchi += a
                 gU += b
         return lam, gchi, gU

@@ -1207,6 +1207,34 @@ int check_grid(const bf_grid* g) {
   return BF_OK;
 }
 
+// Parameters of a time step, checked before the step writes anything: a step
+// that returns BF_EINVAL leaves the caller's fields as they were.
+int check_params(const bf_params* prm) {
+  if (!prm) return fail(BF_EINVAL, "null parameters");
+  if (!(prm->dt > 0) || !std::isfinite(prm->dt)) return fail(BF_EINVAL, "dt must be finite and > 0");
+  if (!(prm->M >= 0) || !std::isfinite(prm->M)) return fail(BF_EINVAL, "M must be finite and >= 0");
+  if (!(prm->kappa >= 0) || !std::isfinite(prm->kappa))
+    return fail(BF_EINVAL, "kappa must be finite and >= 0");
+  if (!(prm->Npoly > 0) || !std::isfinite(prm->Npoly) || !std::isfinite(prm->chi))
+    return fail(BF_EINVAL, "Npoly must be finite and > 0, chi finite");
+  if (!(prm->phi_lo > 0 && prm->phi_lo < prm->phi_hi && prm->phi_hi < 1))
+    return fail(BF_EINVAL, "need 0 < phi_lo < phi_hi < 1");
+  const double c = prm->dt * prm->M * prm->kappa;
+  if (!std::isfinite(c)) return fail(BF_EINVAL, "dt*M*kappa must be finite");
+  return BF_OK;
+}
+
+// The options a solve of operator op will use (o, or the defaults when o is
+// NULL), checked up front.
+int resolve_opts(int op, const bf_solver_opts* o, bf_solver_opts* out) {
+  if (o) {
+    *out = *o;
+  } else {
+    default_opts(op, out);
+  }
+  return check_opts(*out);
+}
+
 }  // namespace
 
 // Host helpers shared with the ensemble driver (host.hpp).
@@ -1485,6 +1513,15 @@ int bf_step(bf_grid* g, const bf_params* prm, double* phi, const double* ustar,
             const bf_solver_opts* pr, bf_solve_stats stats[2]) {
   TRY(check_grid(g));
   if (!prm || !phi || !ustar || !vstar || !p) return fail(BF_EINVAL, "null argument");
+  if (phi == p || phi == ustar || phi == vstar || (u && u == phi) || (v && v == phi))
+    return fail(BF_EINVAL, "phi must not alias p, u*, v*, u or v");
+  // everything either half could reject is checked before phi or p is written
+  TRY(check_params(prm));
+  bf_solver_opts och, opr;
+  TRY(resolve_opts(BF_OP_CH, ch, &och));
+  TRY(resolve_opts(BF_OP_LAP, pr, &opr));
+  ch = &och;
+  pr = &opr;
   bf_solve_stats local[2];
   bf_solve_stats* S = stats ? stats : local;
   std::memset(S, 0, sizeof(bf_solve_stats) * 2);
@@ -1594,10 +1631,14 @@ int bf_step_ch_mob(bf_grid* g, const bf_params* prm, double* phi, const bf_solve
                    bf_solve_stats* stats) {
   TRY(check_grid(g));
   if (!prm || !phi) return fail(BF_EINVAL, "null argument");
-  if (!(prm->dt > 0) || !(prm->M > 0) || !(prm->kappa >= 0) || !(prm->Npoly > 0))
-    return fail(BF_EINVAL, "dt, M, Npoly must be > 0 and kappa >= 0");
-  if (!(prm->phi_lo > 0 && prm->phi_lo < prm->phi_hi && prm->phi_hi < 1))
-    return fail(BF_EINVAL, "need 0 < phi_lo < phi_hi < 1");
+  TRY(check_params(prm));
+  if (!(prm->M > 0)) return fail(BF_EINVAL, "M must be > 0 (the mobility is M clamp(phi))");
+  if (o) {
+    bf_solver_opts oo;
+    TRY(resolve_opts(BF_OP_CH, o, &oo));
+    if (oo.ksp != BF_KSP_GMRES)
+      return fail(BF_EINVAL, "the variable-mobility operator is not symmetric: use GMRES");
+  }
   if (!g->work_m) TRY(dalloc(g, &g->work_m, g->npts));
   hipStream_t st = g->stream;
   launch_fill_i32(1, g->counter, 0, st);
@@ -1676,6 +1717,10 @@ int bf_step_ch(bf_grid* g, const bf_params* prm, double* phi, const double* u, c
   if (!prm || !phi) return fail(BF_EINVAL, "null argument");
   if ((u == nullptr) != (v == nullptr)) return fail(BF_EINVAL, "u and v must both be given or both be null");
   if (u && (u == phi || v == phi)) return fail(BF_EINVAL, "u, v must not alias phi");
+  TRY(check_params(prm));
+  bf_solver_opts oo;
+  TRY(resolve_opts(BF_OP_CH, o, &oo));
+  o = &oo;
   bf_solve_stats local;
   bf_solve_stats* S = stats ? stats : &local;
   std::memset(S, 0, sizeof(*S));
@@ -1697,10 +1742,12 @@ int bf_step_ch_cn(bf_grid* g, const bf_params* prm, double* phi, double* phi_pre
   TRY(check_grid(g));
   if (!prm || !phi || !phi_prev) return fail(BF_EINVAL, "null argument");
   if (phi == phi_prev) return fail(BF_EINVAL, "phi and phi_prev must not alias");
-  if (!(prm->Npoly > 0) || !(prm->phi_lo > 0) || !(prm->phi_hi < 1) || !(prm->phi_lo < prm->phi_hi))
-    return fail(BF_EINVAL, "bad Flory-Huggins parameters");
+  // checked before phi_prev receives phi^n or phi the initial guess
+  TRY(check_params(prm));
+  bf_solver_opts oo;
+  TRY(resolve_opts(BF_OP_CH, o, &oo));
+  o = &oo;
   const double c = prm->dt * prm->M * prm->kappa;
-  if (!(c >= 0) || !std::isfinite(c)) return fail(BF_EINVAL, "dt*M*kappa must be finite and >= 0");
   bf_solve_stats local;
   bf_solve_stats* S = stats ? stats : &local;
   std::memset(S, 0, sizeof(*S));
@@ -1736,8 +1783,10 @@ int bf_adjoint_step(bf_grid* g, const bf_params* prm, const double* phi_n, const
   if (lambda_out == phi_n || (u && (lambda_out == u || lambda_out == v)) ||
       (du && (lambda_out == du || lambda_out == dv)))
     return fail(BF_EINVAL, "lambda_out must not alias phi_n, u, v, du or dv");
-  if (!(prm->Npoly > 0) || !(prm->phi_lo > 0) || !(prm->phi_hi < 1) || !(prm->phi_lo < prm->phi_hi))
-    return fail(BF_EINVAL, "bad Flory-Huggins parameters");
+  TRY(check_params(prm));
+  bf_solver_opts oo;
+  TRY(resolve_opts(BF_OP_CH, o, &oo));
+  o = &oo;
   if (!g->work_e) TRY(dalloc(g, &g->work_e, g->npts));
   hipStream_t st = g->stream;
   // eta = A^{-T} lam = W A^{-1} W^{-1} lam: solve A e = W^{-1} lam, eta = W e

@@ -8,8 +8,8 @@ Tolerances
   * one adjoint step: lambda_out relative <= 1e-9 and the two scalar
     contributions relative <= 1e-8 (transpose solve at rtol 1e-12; the oracle
     solves exactly);
-  * rollout gradients vs the oracle: relative <= 1e-8 (dJ/dU, about 1e-11 in
-    size, absolute 1e-15);
+  * rollout gradients vs the oracle: relative <= 1e-8, at 64 x 64 (6 steps)
+    and at the configured 2048 x 2048 (20 steps);
   * rollout gradients vs finite differences: relative <= 1e-6.  The finite
     differences carry the rounding of J divided by eps; J is about 1e-2 and
     accurate to about 4e-17 here, so the small scalars dJ/dchi and dJ/dU take
@@ -18,10 +18,12 @@ Tolerances
     1e-2) eps = 1e-6; dJ/dU (about 1e-11) is below what the difference
     quotient resolves and gets an absolute bound (see _fd_check).
 """
+import os
 import time
 
 import numpy as np
 import pytest
+import scipy.fft
 import torch
 
 import synthetic as S
@@ -32,6 +34,7 @@ import paper_1811_11842_amd as bf  # loads the HIP library on first use; raises 
 from paper_1811_11842_amd import adjoint as bfa
 
 pytestmark = pytest.mark.gpu
+WORKERS = max(1, min(16, os.cpu_count() or 1))
 PRM = dict(dt=1e-4, M=1.0, kappa=1e-3, Npoly=100.0)
 CHI = 0.6
 
@@ -186,14 +189,49 @@ def _fd_check(n, steps, k, ndir, dev):
         worst = max(worst, abs(ad - fd) / abs(fd))
     print(f"  dJ/dphi0 . d over {ndir} seeded directions: worst rel {worst:.2e}")
     assert worst <= 1e-6
+    return phi0, base, nu, nv, (J, gphi, gchi, gU)
 
 
 def test_rollout_gradient_matches_finite_differences_256(dev):
     _fd_check(256, 10, 5, 4, dev)
 
 
+@pytest.mark.timeout(900)
 def test_rollout_gradient_2048_20_steps(dev):
     """The differentiation configuration: 2048 x 2048, float64, 20 steps,
-    checkpoints every 5 steps, dJ/dchi, dJ/dU and 16 seeded directions of
-    dJ/dphi0 against central finite differences."""
-    _fd_check(2048, 20, 5, 16, dev)
+    checkpoints every 5 steps: dJ/dchi, dJ/dU and 16 seeded directions of
+    dJ/dphi0 against central finite differences, and J, dJ/dchi, dJ/dU and
+    the whole field dJ/dphi0 against the oracle's rollout gradient (all
+    states kept, exact spectral solves) to 1e-8 relative, which pins dJ/dU
+    (about 1e-11, below what the difference quotient resolves) at this size."""
+    n, steps = 2048, 20
+    phi0, base, nu, nv, (J, gphi, gchi, gU) = _fd_check(n, steps, 5, 16, dev)
+    with scipy.fft.set_workers(WORKERS):
+        rJ, rphi, rchi, rU = adj.rollout_grad(phi0, 1.0, steps, nu, nv, base, chi=CHI, **PRM)
+    e_phi = relw(gphi, rphi)
+    print(f"  vs oracle: J {abs(J - rJ) / abs(rJ):.1e}  dJ/dphi0 {e_phi:.1e}  "
+          f"dJ/dchi {abs(gchi - rchi) / abs(rchi):.1e}  dJ/dU {abs(gU - rU) / abs(rU):.1e} "
+          f"({gU:.10e} vs {rU:.10e})")
+    assert abs(J - rJ) <= 1e-12 * abs(rJ)
+    assert e_phi <= 1e-8
+    assert abs(gchi - rchi) <= 1e-8 * abs(rchi)
+    assert abs(gU - rU) <= 1e-8 * abs(rU)
+
+
+def test_rollout_raises_when_a_solve_does_not_converge(dev):
+    """A rollout whose forward solves stop at the iteration limit (maxit 1)
+    raises instead of returning a gradient; so does one whose adjoint solves
+    stop there."""
+    n, steps = 64, 2
+    phi0, base, nu, nv, ro = _rollout(n, steps, 1, dev)
+    ro.opts_ch.maxit = 1
+    with pytest.raises(bfa.ConvergenceError, match="forward step"):
+        _grad(ro, phi0, CHI, 1.0, dev)
+    phi0, base, nu, nv, ro = _rollout(n, steps, 1, dev)
+    ro.opts_adj.maxit = 1
+    with pytest.raises(bfa.ConvergenceError, match="adjoint step"):
+        _grad(ro, phi0, CHI, 1.0, dev)
+    phi0, base, nu, nv, ro = _rollout(n, steps, 1, dev)
+    ro.opts_p.maxit = 1
+    with pytest.raises(bfa.ConvergenceError, match="pressure solve"):
+        _grad(ro, phi0, CHI, 1.0, dev)

@@ -1,11 +1,14 @@
 """GPU parity of the batched ensemble (bf_ensemble_*): every instance of an
 uneven ensemble against the CPU oracle step with that instance's parameters
-(relative W-norm error <= 1e-10 for phi, u, v and 1e-9 for p, the float64
-bar of the single grid), against the single-grid path, and the edge cases
+(relative W-norm error <= 1e-10 for phi, p, u, v, the float64 bar of the
+single grid; the pressure solves run at rtol 1e-12, where p meets it), against the single-grid path, and the edge cases
 of the batch (an instance whose pressure right-hand side vanishes, so it is
 masked from the first iteration, next to instances that iterate)."""
+import os
+
 import numpy as np
 import pytest
+import scipy.fft
 import torch
 
 import oracle
@@ -15,6 +18,7 @@ from oracle import ops
 import paper_1811_11842_amd as bf  # loads the HIP library on first use; raises if it is missing
 
 pytestmark = pytest.mark.gpu
+WORKERS = max(1, min(16, os.cpu_count() or 1))
 
 
 @pytest.fixture(scope="module")
@@ -57,7 +61,7 @@ def run(specs, dev, steps=1, zero_flow=()):
     stats = []
     for _ in range(steps):
         st, ms = ens.step(prms, phi, us, vs, p, u, v, bf.default_opts(bf.OP_CH, rtol=1e-10),
-                          bf.default_opts(bf.OP_LAP, rtol=1e-10))
+                          bf.default_opts(bf.OP_LAP, rtol=1e-12))
         stats.append(st)
     return ens, inst, phi, p, u, v, stats, ms
 
@@ -90,7 +94,7 @@ def test_ensemble_step_matches_oracle(dev):
         print(f"  inst {i} n={specs[i]['n']} chi={specs[i]['chi']:.3f} dt={specs[i]['dt']:.2e}: "
               f"CH it={sc.iters} {bf.STATUS_NAMES[sc.status]}  P it={sp.iters}  err {e}")
         assert sc.status in (bf.OK, bf.AT_FLOOR) and sp.status == bf.OK
-        assert e[0] <= 1e-10 and e[1] <= 1e-9 and e[2] <= 1e-10 and e[3] <= 1e-10
+        assert e[0] <= 1e-10 and e[1] <= 1e-10 and e[2] <= 1e-10 and e[3] <= 1e-10
 
 
 def test_single_instance_class_matches_oracle(dev):
@@ -105,7 +109,7 @@ def test_single_instance_class_matches_oracle(dev):
         sc, sp = stats[0][i]
         assert sc.status in (bf.OK, bf.AT_FLOOR) and sp.status == bf.OK
         assert relw(unpack(ens, phi, i), rphi) <= 1e-10
-        assert relw(unpack(ens, p, i), rp) <= 1e-9
+        assert relw(unpack(ens, p, i), rp) <= 1e-10
 
 
 def test_ensemble_agrees_with_single_grid(dev):
@@ -117,7 +121,7 @@ def test_ensemble_agrees_with_single_grid(dev):
             t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
             ph, pp, uu, vv = t(ph0), g.field(0.0), g.field(0.0), g.field(0.0)
             g.step(bf.make_params(**prm), ph, t(u0), t(v0), pp, uu, vv,
-                   bf.default_opts(bf.OP_CH, rtol=1e-10), bf.default_opts(bf.OP_LAP, rtol=1e-10))
+                   bf.default_opts(bf.OP_CH, rtol=1e-10), bf.default_opts(bf.OP_LAP, rtol=1e-12))
             torch.cuda.synchronize()
             assert relw(unpack(ens, phi, i), ph.cpu().numpy()) <= 1e-11
             assert relw(unpack(ens, p, i), pp.cpu().numpy()) <= 1e-10
@@ -138,16 +142,16 @@ def test_ensemble_largest_instance_size(dev):
     with bf.Grid(8192) as g:
         ph, pp, uu, vv = t(ph0), g.field(0.0), g.field(0.0), g.field(0.0)
         g.step(bf.make_params(**prm), ph, t(u0), t(v0), pp, uu, vv,
-               bf.default_opts(bf.OP_CH, rtol=1e-10), bf.default_opts(bf.OP_LAP, rtol=1e-10))
+               bf.default_opts(bf.OP_CH, rtol=1e-10), bf.default_opts(bf.OP_LAP, rtol=1e-12))
         torch.cuda.synchronize()
         e = (relw(unpack(ens, phi, 0), ph.cpu().numpy()), relw(unpack(ens, p, 0), pp.cpu().numpy()),
              relw(unpack(ens, u, 0), uu.cpu().numpy()))
     print(f"step {ms:.1f} ms, 8192 instance vs single grid {e}", flush=True)
-    assert e[0] <= 1e-10 and e[1] <= 1e-9 and e[2] <= 1e-10
+    assert e[0] <= 1e-10 and e[1] <= 1e-10 and e[2] <= 1e-10
     ph0, u0, v0, prm = inst[1]
     rphi, rp, ru, rv = oracle.step.step(ph0, u0, v0, **prm)
     assert relw(unpack(ens, phi, 1), rphi) <= 1e-10
-    assert relw(unpack(ens, p, 1), rp) <= 1e-9
+    assert relw(unpack(ens, p, 1), rp) <= 1e-10
 
 
 def test_ensemble_rejects_bad_parameters_and_options(dev):
@@ -182,7 +186,7 @@ def test_ensemble_step_depends_only_on_its_arguments(dev):
     ens = bf.Ensemble([s["n"] for s in specs])
     prms = [bf.make_params(**a[3]) for a in inst]
     oc = bf.default_opts(bf.OP_CH, rtol=1e-10)
-    op = bf.default_opts(bf.OP_LAP, rtol=1e-10)
+    op = bf.default_opts(bf.OP_LAP, rtol=1e-12)
 
     def one(states, fill):
         phi = pack(ens, [a[0] for a in states], dev)
@@ -213,14 +217,15 @@ def test_masked_instance_next_to_iterating_ones(dev):
     for i in (0, 2):
         ph0, u0, v0, prm = inst[i]
         rphi, rp, ru, rv = oracle.step.step(ph0, u0, v0, **prm)
-        assert relw(unpack(ens, p, i), rp) <= 1e-9
+        assert relw(unpack(ens, p, i), rp) <= 1e-10
         assert relw(unpack(ens, phi, i), rphi) <= 1e-10
 
 
+@pytest.mark.timeout(900)
 def test_ensemble_configuration_64_instances_10_steps(dev):
     """The batched-ensemble configuration: 64 seeded instances of sizes in
-    {128, 256, 512, 1024}, 10 steps; every solve ends OK / AT_FLOOR, and one
-    instance of each size is compared with 10 oracle steps."""
+    {128, 256, 512, 1024}, 10 steps; every solve ends OK / AT_FLOOR, and every
+    instance is compared with 10 oracle steps of its own parameters."""
     specs = S.ensemble_specs(64)
     ens, inst, phi, p, u, v, stats, ms = run(specs, dev, steps=10)
     print("classes", ens.info(), f"last step {ms:.1f} ms")
@@ -232,14 +237,15 @@ def test_ensemble_configuration_64_instances_10_steps(dev):
     its = [sc.iters for st in stats for sc, _ in st]
     print(f"  CH iterations {min(its)}..{max(its)}, restarts "
           f"{sum(sc.restarts for st in stats for sc, _ in st)}")
-    seen = set()
-    for i, s in enumerate(specs):
-        if s["n"] in seen:
-            continue
-        seen.add(s["n"])
-        ph0, u0, v0, prm = inst[i]
-        rphi, rp, ru, rv = oracle.step.run(ph0, u0, v0, 10, **prm)
-        e = relw(unpack(ens, phi, i), rphi)
-        print(f"  inst {i} n={s['n']}: phi error after 10 steps {e:.2e}")
-        assert e <= 1e-10
-        assert relw(unpack(ens, p, i), rp) <= 1e-9
+    worst = {}
+    with scipy.fft.set_workers(WORKERS):
+        for i, s in enumerate(specs):
+            ph0, u0, v0, prm = inst[i]
+            rphi, rp, ru, rv = oracle.step.run(ph0, u0, v0, 10, **prm)
+            e = (relw(unpack(ens, phi, i), rphi), relw(unpack(ens, p, i), rp),
+                 relw(unpack(ens, u, i), ru), relw(unpack(ens, v, i), rv))
+            worst[s["n"]] = max(worst.get(s["n"], 0.0), max(e))
+            assert max(e) <= 1e-10, (i, s, e)
+    print("  worst error after 10 steps per size (phi, p, u, v): "
+          + ", ".join(f"{n}: {w:.1e}" for n, w in sorted(worst.items())))
+    assert len(worst) == 4

@@ -180,11 +180,11 @@ def test_step_4096_mixed_matches_oracle(dev):
     us, vs = to_dev(u0, dev), to_dev(v0, dev)
     p, u, v = g.field(), g.field(), g.field()
     st = g.step(bf.make_params(**PRM), phi, us, vs, p, u, v,
-                opts(bf.OP_CH, rtol=1e-10), opts(bf.OP_LAP, rtol=1e-10))
+                opts(bf.OP_CH, rtol=1e-10), opts(bf.OP_LAP, rtol=1e-12))
     print("stats", st[0], st[1], flush=True)
     rphi, rp, ru, rv = oracle.step.step(phi0, u0, v0, **PRM)
     assert relw(to_np(phi), rphi) <= 1e-10
-    assert relw(to_np(p), rp) <= 1e-9
+    assert relw(to_np(p), rp) <= 1e-10
     assert relw(to_np(u), ru) <= 1e-10 and relw(to_np(v), rv) <= 1e-10
     assert st[0].status in (bf.OK, bf.AT_FLOOR)
     assert st[1].status == bf.OK
@@ -202,10 +202,10 @@ def test_step_512_mixed_error(dev):
     us, vs = to_dev(u0, dev), to_dev(v0, dev)
     p, u, v = g.field(), g.field(), g.field()
     st = g.step(bf.make_params(**PRM), phi, us, vs, p, u, v,
-                opts(bf.OP_CH, rtol=1e-10), opts(bf.OP_LAP, rtol=1e-10))
+                opts(bf.OP_CH, rtol=1e-10), opts(bf.OP_LAP, rtol=1e-12))
     rphi, rp, ru, rv = oracle.step.step(phi0, u0, v0, **PRM)
     e_phi, e_p = relw(to_np(phi), rphi), relw(to_np(p), rp)
     print(f"512^2 mixed step: error phi {e_phi:.3e}, p {e_p:.3e}, "
           f"iters CH {st[0].iters} P {st[1].iters}")
     assert e_phi <= 1e-10
-    assert e_p <= 1e-9
+    assert e_p <= 1e-10

@@ -348,6 +348,26 @@ int bf_prolong_add(bf_grid* g, int32_t nf, const double* coarse, double* fine);
 int bf_residual(bf_grid* g, int32_t op, double c, const double* b, const double* x,
                 double* r, int32_t accurate, double* rel_norm, double* floor_est);
 
+/* Allocation-free variant of bf_residual (accurate), for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  It takes no grid handle, allocates
+ * nothing (no hipMalloc, hipFree or allocating library call) and never
+ * synchronises:
+ *   r = b - A x  for op (BF_OP_LAP, BF_OP_CH or BF_OP_HELM with coefficient
+ *   c, as in bf_apply) on a grid of n intervals (power of two, 4 <= n <=
+ *   32768; larger n returns BF_EINVAL), evaluated with the double-double
+ *   stencil sum, and the device array norms[3] (caller-owned, 8-byte
+ *   aligned): norms[0] = ||r||_W / ||b||_W, norms[1] = the float64 floor
+ *   estimate of bf_residual's floor_est, norms[2] = ||b||_W (b = 0: the
+ *   ratios divide by 1).
+ * b, x, r: device fields of the (n+1) x n layout; r must not alias x or b.
+ * stream: hipStream_t the work is enqueued on (0 = default).  Asynchronous.
+ * Its reductions use a fixed device array of 264 KB per GPU that the library
+ * holds until the process ends; calls on one GPU share it, so calls that
+ * overlap on one GPU (other streams, other host threads) race. */
+int bf_residual_noalloc(int32_t n, int32_t op, double c, const double* b, const double* x,
+                        double* r, double* norms, void* stream);
+
 /* One smoothing sweep of the multigrid preconditioner (the paper's Jacobi
  * preconditioner of Sec. 4.1, listing "Creating PETSc KSP and PC objects",
  * in the three-term Chebyshev form):

@@ -139,6 +139,8 @@ def lib():
             "bf_residual": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_double, _P, _P, _P,
                                            ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                            ctypes.POINTER(ctypes.c_double)]),
+            "bf_residual_noalloc": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                                                   _P, _P, _P, _P, _P]),
             "bf_ensemble_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int32), ctypes.c_int32,
                                                   _P, ctypes.POINTER(_P)]),
             "bf_ensemble_destroy": (ctypes.c_int, [_P]),
@@ -423,6 +425,28 @@ class Grid:
         out = ctypes.c_double()
         _check(lib().bf_wdot(self._h, self._ptr(x, "x"), self._ptr(y, "y"), ctypes.byref(out)))
         return out.value
+
+
+def residual_noalloc(op, c, b, x, r, norms, stream: torch.cuda.Stream | None = None):
+    """bf_residual_noalloc: r = b - A x (double-double) and norms[0:3] =
+    (||r||_W / ||b||_W, float64 floor estimate, ||b||_W), both on the device;
+    no grid handle, no allocation, no synchronisation.  b, x, r: float64 CUDA
+    tensors of shape (n+1, n); norms: a float64 CUDA tensor of 3 elements."""
+    for name, t in (("b", b), ("x", x), ("r", r)):
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64
+                and t.is_contiguous() and t.dim() == 2 and t.shape[0] == t.shape[1] + 1):
+            raise TypeError(f"{name} must be a contiguous float64 CUDA tensor of shape (n+1, n)")
+        if t.shape != b.shape:
+            raise TypeError(f"{name} has shape {tuple(t.shape)}, b has {tuple(b.shape)}")
+    if not (isinstance(norms, torch.Tensor) and norms.is_cuda and norms.dtype == torch.float64
+            and norms.is_contiguous() and norms.numel() >= 3):
+        raise TypeError("norms must be a contiguous float64 CUDA tensor of at least 3 elements")
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    _check(lib().bf_residual_noalloc(b.shape[1], op, c, _P(b.data_ptr()), _P(x.data_ptr()),
+                                     _P(r.data_ptr()), _P(norms.data_ptr()),
+                                     _P(stream.cuda_stream)))
+    return r, norms
 
 
 grid_create = Grid

@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <type_traits>
@@ -1237,6 +1238,48 @@ int resolve_opts(int op, const bf_solver_opts* o, bf_solver_opts* out) {
 
 }  // namespace
 
+// ------------------------------------------------ allocation-free scratch
+// Device memory of the allocation-free entry point (bf_residual_noalloc):
+// two groups of reduction partials (at most kStreamMaxBlocks each: a tiled
+// reduction launches at most that many workgroups, the one-thread-per-node
+// form red_blocks(n) <= kMaxRedBlocks) and the scalar slots their finalize
+// kernels write.  264 KB per GPU, held until the process ends; every call on
+// a GPU shares that GPU's copy, so calls that overlap on one GPU race.
+namespace {
+constexpr int kScratchParts = kStreamMaxBlocks;
+constexpr int kScratchSlots = 16;
+static_assert(kMaxRedBlocks <= kScratchParts, "partials of the untiled reductions");
+static_assert(S_ULP2 < kScratchSlots && S_RTRUE < kScratchSlots && S_BN2 < kScratchSlots,
+              "scalar slots of the residual norms");
+constexpr int kScratchDevices = 64;
+constexpr int kNoallocMaxN = 32768;  // the largest grid the library accepts
+
+static __device__ __align__(256) double scratch[2 * kScratchParts + kScratchSlots];
+
+std::mutex g_scratch_mu;
+double* g_scratch_dev[kScratchDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per
+// device (each GPU holds its own copy at its own address; in host code the
+// array's name is only a stand-in and must not be passed to a kernel).
+int scratch_on_current_device(double** out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kScratchDevices)
+    return fail(BF_EUNSUPPORTED, "device %d: the scratch table covers devices 0..%d", dev,
+                kScratchDevices - 1);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(BF_EHIP, "hipGetSymbolAddress returned a null address");
+    g_scratch_dev[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_dev[dev];
+  return BF_OK;
+}
+}  // namespace
+
 // Host helpers shared with the ensemble driver (host.hpp).
 namespace bf {
 int host_fail(int code, const char* msg) { return fail(code, "%s", msg); }
@@ -1884,6 +1927,38 @@ int bf_residual(bf_grid* g, int32_t op, double c, const double* b, const double*
   TRY(true_residual(g, A, b, x, r, bn > 0 ? bn : 1.0, ks));
   if (rel_norm) *rel_norm = ks.rel_true;
   if (floor_est) *floor_est = ks.floor_est;
+  return BF_OK;
+}
+
+int bf_residual_noalloc(int32_t n, int32_t op, double c, const double* b, const double* x,
+                        double* r, double* norms, void* stream) {
+  if (!is_pow2(n) || n < 4 || n > kNoallocMaxN)
+    return fail(BF_EINVAL, "n = %d: bf_residual_noalloc takes powers of two in [4, %d]", n,
+                kNoallocMaxN);
+  if (!b || !x || !r || !norms) return fail(BF_EINVAL, "null field");
+  if (r == x || r == b) return fail(BF_EINVAL, "r must not alias x or b");
+  if (op != BF_OP_LAP && op != BF_OP_CH && op != BF_OP_HELM) return fail(BF_EINVAL, "op %d", op);
+  if (!(c >= 0) || !std::isfinite(c)) return fail(BF_EINVAL, "c = %g must be finite and >= 0", c);
+  const int np = red_blocks((int64_t)(n + 1) * n);
+  const int nr_expected = stream_ok(n) ? stream_cfg(n).blocks : np;
+  if (nr_expected > kScratchParts || g_batch.count > 1)
+    return fail(BF_EINVAL, "n = %d needs %d reduction partials, the scratch holds %d", n,
+                nr_expected, kScratchParts);
+  double* s = nullptr;
+  TRY(scratch_on_current_device(&s));
+  double* parts = s;
+  double* scal = s + 2 * kScratchParts;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const OpDesc A = level_op(op, n, c);
+  // ||b||_W^2, then r = b - A x (double-double) with ||r||_W^2 and sum_W ulp(x)^2;
+  // every partial and slot read below is written earlier on the same stream
+  launch_dot(n, b, b, parts, np, st);
+  launch_finalize(parts, np, scal, F_STORE, S_BN2, n, st);
+  const int nr = launch_residual_dd(A, x, b, r, parts, np, st);
+  launch_finalize(parts, nr, scal, F_STORE, S_RTRUE, n, st);
+  launch_finalize(parts + nr, nr, scal, F_STORE, S_ULP2, n, st);
+  launch_residual_norms(scal, column_sq(A), norms, st);
+  HIPCHK(hipGetLastError());
   return BF_OK;
 }
 

@@ -316,6 +316,17 @@ __global__ void __launch_bounds__(kBlock) k_finalize(const double* __restrict__ 
   }
 }
 
+__global__ void __launch_bounds__(64) k_residual_norms(const double* __restrict__ scal, double csq,
+                                                     double* __restrict__ out) {
+  if (threadIdx.x == 0) {
+    const double bn = sqrt(scal[S_BN2]);
+    const double d = bn > 0.0 ? bn : 1.0;
+    out[0] = sqrt(scal[S_RTRUE]) / d;
+    out[1] = sqrt(scal[S_ULP2] / 12.0 * csq) / d;
+    out[2] = bn;
+  }
+}
+
 // Flexible (Polak-Ribiere) CG coefficient from two groups of partials:
 // rho = sum partials[0..np) = <r_k, z_k>_W, gamma = sum partials[np..2 np) =
 // <z_k, q_{k-1}>_W; beta = (rho - <z_k, r_{k-1}>) / rho_old = -alpha gamma / rho_old
@@ -1051,6 +1062,10 @@ void launch_dot(int n, const double* x, const double* y, double* partials, int n
 void launch_wsum_diff(int n, const double* x, const double* y, double* partials, int nparts,
                       hipStream_t st) {
   LAUNCH(k_wsum_diff, nparts, st, make_geo(n), x, y, partials);
+}
+
+void launch_residual_norms(const double* scal, double csq, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_residual_norms, dim3(1), dim3(64), 0, st, scal, csq, out);
 }
 
 void launch_finalize(const double* partials, int nparts, double* scal, int mode, int slot, int n,

@@ -58,6 +58,7 @@ extern thread_local BatchCtx g_batch;
 // Launch shape of the tiled stencil kernels (stream.hip), two values per
 // lane, 128 columns per wavefront; used for grid levels with n >= 128,
 // smaller levels use the one-thread-per-node kernels.
+constexpr int kStreamMaxBlocks = 16384;  // workgroups per launch; beyond, wavefronts loop over tiles
 struct StreamCfg {
   int rpw;      // output rows per wavefront tile
   int wstrips;  // column strips of 128 columns
@@ -236,6 +237,11 @@ void launch_wsum_diff(int n, const double* x, const double* y, double* partials,
 // Reduce partials in a fixed order and update scalars (see FinalizeMode).
 void launch_finalize(const double* partials, int nparts, double* scal, int mode, int slot,
                      int n, hipStream_t st);
+// Norms of a residual from the scalars of its reductions (scal[S_BN2] =
+// ||b||_W^2, scal[S_RTRUE] = ||r||_W^2, scal[S_ULP2] = sum_W ulp(x)^2):
+// out[0] = ||r||_W / ||b||_W, out[1] = sqrt(scal[S_ULP2] / 12 * csq) / ||b||_W
+// (the float64 floor estimate), out[2] = ||b||_W; ||b||_W = 0 divides by 1.
+void launch_residual_norms(const double* scal, double csq, double* out, hipStream_t st);
 // Flexible CG: scal[S_RZ] = rho (partials[0..np)), scal[S_BETA] =
 // -scal[S_ALPHA] * gamma / rho_old with gamma = sum partials[np..2 np).
 void launch_finalize_flex(const double* partials, int nparts, double* scal, hipStream_t st);

@@ -57,7 +57,6 @@ enum Epi {
 
 constexpr int kStreamTPB = 256;         // 4 wavefronts per workgroup
 constexpr int kLaneCols = 2;            // columns per lane
-constexpr int kStreamMaxBlocks = 16384; // beyond this, wavefronts loop over tiles
 
 // Vector of V elements of T (one load or store).
 template <typename T, int V>

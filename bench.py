@@ -4,7 +4,8 @@ A step is the whole hot path over one 4096 x 4096 grid with float64 fields:
 the Flory-Huggins right-hand side, the Cahn-Hilliard solve (13-point
 operator, MG-preconditioned CG to rtol 1e-10, stopping at the float64 floor),
 the pressure right-hand side, the pressure Poisson solve (5-point operator,
-MG-preconditioned CG to rtol 1e-10) and the velocity correction.  Inputs are
+MG-preconditioned CG to rtol 1e-12, where p meets the 1e-10 forward-error bar)
+and the velocity correction.  Inputs are
 synthetic (seeded initial biofilm and inflow) and resident in HBM before the
 timed region.
 
@@ -80,6 +81,13 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+# Relative residual of the pressure solves: at 1e-10 the 4096^2 pressure
+# forward error against the oracle is 1.00e-10 (the low Laplacian modes keep
+# what the residual leaves), at 1e-12 it is 3.3e-12 for one more iteration,
+# so the step meets the 1e-10 forward-error bar on p as it does on phi.
+PRESSURE_RTOL = 1e-12
+
+
 def time_steps(g, n, steps, warmup, mg_precision):
     """Warm up on a copy of the initial state, then time `steps` steps from
     the initial state itself; returns device ms/step, wall ms/step, stats and
@@ -92,7 +100,7 @@ def time_steps(g, n, steps, warmup, mg_precision):
     us, vs = torch.from_numpy(u0).to(dev), torch.from_numpy(v0).to(dev)
     p, u, v = g.field(0.0), g.field(0.0), g.field(0.0)
     oc = bf.default_opts(bf.OP_CH, rtol=1e-10, mg_precision=mg_precision)
-    op = bf.default_opts(bf.OP_LAP, rtol=1e-10, mg_precision=mg_precision)
+    op = bf.default_opts(bf.OP_LAP, rtol=PRESSURE_RTOL, mg_precision=mg_precision)
     phw = phi.clone()
     for k in range(warmup):
         st = g.step(prm, phw, us, vs, p, u, v, oc, op)
@@ -200,7 +208,7 @@ def time_ensemble(steps=10, warmup=1, count=64):
     us, vs = pack([a[1] for a in inst]), pack([a[2] for a in inst])
     p, u, v = ens.field(0.0), ens.field(0.0), ens.field(0.0)
     prms = [bf.make_params(**a[3]) for a in inst]
-    oc, op = bf.default_opts(bf.OP_CH, rtol=1e-10), bf.default_opts(bf.OP_LAP, rtol=1e-10)
+    oc, op = bf.default_opts(bf.OP_CH, rtol=1e-10), bf.default_opts(bf.OP_LAP, rtol=PRESSURE_RTOL)
     phi = phi0.clone()
     for _ in range(warmup):
         ens.step(prms, phi, us, vs, p, u, v, oc, op)
@@ -359,14 +367,39 @@ def recorded_traffic(kernel, n):
     return int(k["fetch_kib"] * 1024 * rec["fetch_scale"] + k["write_kib"] * 1024 * rec["write_scale"])
 
 
-def cpu_baseline(n, steps):
+def cpu_threads():
+    """Host threads this process may use (its affinity set, at most 16: the
+    CPU share of one GPU on the measurement hosts)."""
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        avail = os.cpu_count() or 1
+    return max(1, min(16, avail))
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(n, steps, workers):
+    """Oracle steps at n x n (numpy/scipy float64, spectral solves), timed as
+    the oracle stands, with scipy.fft using `workers` threads."""
+    import scipy.fft
     import oracle  # the CPU oracle, timed as it stands
     phi = S.initial_phi(n)
     u, v = S.inflow_velocity(n)
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        phi, p, uu, vv = oracle.step.step(phi, u, v, **S.DEFAULT_PARAMS)
-    dt = time.perf_counter() - t0
+    with scipy.fft.set_workers(workers):
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            phi, p, uu, vv = oracle.step.step(phi, u, v, **S.DEFAULT_PARAMS)
+        dt = time.perf_counter() - t0
     return dt / steps * 1e3
 
 
@@ -463,8 +496,10 @@ def main():
     prec = {"both": "float32 V-cycle in float64 CG (value) and plain float64",
             "mixed": "float32 V-cycle in float64 CG", "f64": "plain float64"}[a.precision]
     out["config"] = {"workload": f"{n}x{n} grid, {a.steps} steps: Flory-Huggins RHS + MG-PCG "
-                                 f"Cahn-Hilliard solve + MG-PCG pressure solve + velocity "
-                                 f"correction, rtol 1e-10, {prec}",
+                                 f"Cahn-Hilliard solve (rtol 1e-10) + MG-PCG pressure solve "
+                                 f"(rtol {PRESSURE_RTOL:g}) + velocity correction, forward "
+                                 f"error <= 1e-10, {prec}",
+                     "ch_rtol": 1e-10, "pressure_rtol": PRESSURE_RTOL,
                      "precision": a.precision, "mg_precision_value": "f32" if a.precision != "f64" else "f64",
                      "n": n, "rows": n + 1, "cols": n, "points": npts,
                      "dt": S.DEFAULT_PARAMS["dt"], "kappa": S.DEFAULT_PARAMS["kappa"],
@@ -488,13 +523,19 @@ def main():
         log("batched ensemble: 64 instances, 10 steps (and the same one by one)")
         out["ensemble"] = time_ensemble()
     if not a.no_cpu_baseline and not a.spmv_only:
-        log(f"cpu baseline: {a.cpu_steps} oracle steps at {n}x{n}")
-        cms = cpu_baseline(n, a.cpu_steps)
-        out["cpu_baseline"] = {"value": round(cms, 1), "unit": "ms/step", "cores": 1,
+        nt = cpu_threads()
+        log(f"cpu baseline: {a.cpu_steps} oracle steps at {n}x{n}, {nt} FFT threads, then 2 "
+            f"steps on one thread")
+        cms = cpu_baseline(n, a.cpu_steps, nt)
+        cms1 = cpu_baseline(n, 2, 1)
+        out["cpu_baseline"] = {"value": round(cms, 1), "unit": "ms/step", "cores": nt,
                                "kind": "oracle",
-                               "sample": f"{a.cpu_steps} oracle steps at {n}x{n} (numpy/scipy "
-                                         f"float64, spectral solves, scipy.fft default single "
-                                         f"worker)"}
+                               "sample": f"{a.cpu_steps} oracle steps at {n}x{n} from the "
+                                         f"benchmark's initial state (numpy/scipy float64, "
+                                         f"spectral solves; scipy.fft on {nt} threads, numpy "
+                                         f"elementwise work on one)",
+                               "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
+                               "one_thread_ms_per_step": round(cms1, 1)}
     print(json.dumps(out), flush=True)
 
 

@@ -226,12 +226,23 @@ int bf_velocity_correct(bf_grid* g, double dt, const double* p,
                         const double* ustar, const double* vstar,
                         double* u, double* v);
 
-/* One time step: Cahn-Hilliard right-hand side and solve (phi in/out; the
- * solve starts from gamma phi^n, gamma minimising the initial residual, or
- * from zero when no gamma helps -- nothing is carried over between calls),
- * pressure right-hand side and solve (p out, zero initial guess), velocity
- * correction (u, v may be NULL to skip).  stats[0] = Cahn-Hilliard solve,
- * stats[1] = pressure solve.  ch / pr may be NULL for the defaults. */
+/* One time step of the reduced biofilm-flow model:
+ *   Cahn-Hilliard (Sec. 2.2, eq. modCH, constant mobility, the bulk
+ *   Flory-Huggins potential explicit and the gradient-energy term implicit):
+ *     b = phi + dt*M*L mu_FH(clamp(phi)),  (I + dt*M*kappa*L^2) phi' = b,
+ *   then the projection of Sec. 4 (eqs. pressuresolve and velocityupdate):
+ *     L p = div_h(u*, v*)/dt (weighted mean removed),  (u, v) = (u*, v*) -
+ *     dt grad_h p.
+ * phi: in phi^n, out phi^{n+1} (the solve starts from gamma phi^n, gamma
+ * minimising the initial residual, or from zero when no gamma helps --
+ * nothing is carried over between calls); p: out (zero initial guess); u, v:
+ * out (both may be NULL to skip the velocity correction; u may alias u*
+ * and v may alias v*, neither may alias phi).  stats[0] = Cahn-Hilliard solve, stats[1] =
+ * pressure solve (may be NULL).  ch / pr may be NULL for the defaults.  The
+ * parameters and both options are checked before anything is written: a
+ * BF_EINVAL return leaves phi, p, u and v as they were.  The two solves are
+ * independent and run concurrently (the pressure half on a second stream).
+ * Synchronous. */
 int bf_step(bf_grid* g, const bf_params* prm, double* phi, const double* ustar,
             const double* vstar, double* p, double* u, double* v,
             const bf_solver_opts* ch, const bf_solver_opts* pr,

@@ -524,6 +524,28 @@ T* vcycle_level(bf_grid* g, std::vector<LevelT<T>>& lv, int op, double c,
   LevelT<T>& C = lv[l + 1];
   launch_restrict<T>(L.n, L.r, C.b, st);
   T* e = vcycle_level<T>(g, lv, op, c, o, l + 1, C.b);
+  if (streamed && single && post_ok(L.n, op, S.degree, S.g[0], (int)sizeof(T))) {
+    // the correction and the whole post-smoother in one pass, into L.r
+    const double pa[3] = {S.a[0], S.a[1], S.a[2]};
+    const double pg[3] = {0.0, S.g[1], S.g[2]};
+    if constexpr (F32) {
+      if (zout32 || zout) {
+        const int np = zout32 ? stream_post_dot2_f32(A, S.degree, cur, e, b, zout32, g->q, pa, pg,
+                                                     g->partials, st)
+                              : stream_post_dot2(A, S.degree, cur, e, b, zout, g->q, pa, pg,
+                                                 g->partials, st);
+        if (rz_parts) *rz_parts = np;
+        return nullptr;
+      }
+    } else {
+      if (rz_parts) {
+        *rz_parts = stream_post_dot(A, S.degree, cur, e, b, L.r, pa, pg, g->partials, st);
+        return L.r;
+      }
+    }
+    stream_post<T>(A, S.degree, cur, e, b, L.r, pa, pg, st);
+    return L.r;
+  }
   launch_prolong_add<T>(L.n, e, cur, st);
   // post-smoothing (same polynomial); on streamed single grids the last two
   // sweeps run as one pass, whose result goes to L.r (free on the way up:

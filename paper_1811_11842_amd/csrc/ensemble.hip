@@ -27,6 +27,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <cstddef>
 #include <string>
 #include <thread>
 #include <vector>
@@ -49,36 +50,6 @@ struct EParam {
   double dtMn2, inv_npoly, chi, lo, hi;  // Flory-Huggins right-hand side
   double div_scale, vel_scale;           // n / (2 dt), dt n / 2
 };
-
-__device__ __forceinline__ double mu_fh_e(double f, double inv_npoly, double chi) {
-  return log(f) * inv_npoly + inv_npoly - log1p(-f) - 1.0 + chi * (1.0 - 2.0 * f);
-}
-
-__global__ void __launch_bounds__(kBlock) ke_ch_rhs(Geo G, int64_t stride, const EParam* prm,
-                                                    const double* __restrict__ phi,
-                                                    double* __restrict__ b,
-                                                    int32_t* __restrict__ clamped) {
-  const int inst = blockIdx.y;
-  const EParam P = prm[inst];
-  phi += inst * stride;
-  b += inst * stride;
-  int cnt = 0;
-  auto cl = [&](double v) { return v < P.lo ? P.lo : (v > P.hi ? P.hi : v); };
-  EGRID(idx, G.npts) {
-    const int i = (int)(idx & G.mask), j = (int)(idx >> G.log2n);
-    const int n = G.n;
-    const double* r0 = phi + (int64_t)j * n;
-    const double c = r0[i];
-    cnt += (c < P.lo || c > P.hi) ? 1 : 0;
-    const double mc = mu_fh_e(cl(c), P.inv_npoly, P.chi);
-    const double ml = mu_fh_e(cl(r0[(i - 1) & G.mask]), P.inv_npoly, P.chi);
-    const double mr = mu_fh_e(cl(r0[(i + 1) & G.mask]), P.inv_npoly, P.chi);
-    const double md = mu_fh_e(cl(phi[(int64_t)refl(j - 1, n) * n + i]), P.inv_npoly, P.chi);
-    const double mu = mu_fh_e(cl(phi[(int64_t)refl(j + 1, n) * n + i]), P.inv_npoly, P.chi);
-    b[idx] = c + P.dtMn2 * ((ml + mr) + (md + mu) - 4.0 * mc);
-  }
-  if (cnt) atomicAdd(&clamped[inst], cnt);
-}
 
 __global__ void __launch_bounds__(kBlock) ke_divergence(Geo G, int64_t stride, const EParam* prm,
                                                         const double* __restrict__ u,
@@ -752,8 +723,10 @@ int e_step_class(bf_ensemble* e, EClass& C, const bf_params* prm, double* phi,
   ECHK(hipMemcpyAsync(C.prm, hp.data(), sizeof(EParam) * B, hipMemcpyHostToDevice, st));
   launch_fill_i32(B, C.clamped, 0, st);
   // Cahn-Hilliard: b = phi + dt M L mu(phi), solve into phi from gamma phi
-  hipLaunchKernelGGL(ke_ch_rhs, dim3(ew_blocks(C.npts), B), dim3(kBlock), 0, st, G, C.npts, C.prm,
-                     phi + o, C.work_b, C.clamped);
+  static_assert(offsetof(EParam, dtMn2) == 0 && offsetof(EParam, hi) == 4 * sizeof(double),
+                "the right-hand side reads dtMn2, inv_npoly, chi, lo, hi in this order");
+  launch_ch_rhs_batch(C.n, B, C.npts, phi + o, C.work_b, reinterpret_cast<const double*>(C.prm),
+                      (int)(sizeof(EParam) / sizeof(double)), C.clamped, st);
   std::vector<bf_solve_stats> sch(B), spr(B);
   ETRY(e_solve(C, BF_OP_CH, c, C.work_b, phi + o, och, sch, true));
   // pressure: rhs = div(u*)/dt, weighted mean removed; solve; mean of p removed

@@ -287,12 +287,30 @@ __global__ void __launch_bounds__(kBlock) k_wsum_diff(Geo G, const double* __res
   if (threadIdx.x == 0) partials[blockIdx.x] = t;
 }
 
-__global__ void __launch_bounds__(kBlock) k_finalize(const double* __restrict__ partials, int nparts,
-                                                     double* __restrict__ scal, int mode, int slot,
-                                                     double nn) {
-  double acc = 0.0;
-  for (int k = threadIdx.x; k < nparts; k += kBlock) acc += partials[k];
-  const double s = block_sum(acc);
+// Sum of partials[0 .. nparts) by one workgroup of kFinTPB threads, each
+// with four independent accumulators (the loads of a thread are issued
+// together; a reducing kernel leaves up to 16384 partials, which one
+// 256-thread workgroup summed in 12 us).  The order of the additions depends
+// on nparts only, so the value is reproducible bit for bit.
+constexpr int kFinTPB = 1024;
+
+__device__ __forceinline__ double fin_sum(const double* __restrict__ p, int nparts) {
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  int k = threadIdx.x;
+  for (; k + 3 * kFinTPB < nparts; k += 4 * kFinTPB) {
+    a0 += p[k];
+    a1 += p[k + kFinTPB];
+    a2 += p[k + 2 * kFinTPB];
+    a3 += p[k + 3 * kFinTPB];
+  }
+  for (; k < nparts; k += kFinTPB) a0 += p[k];
+  return block_sum_n<kFinTPB>((a0 + a1) + (a2 + a3));
+}
+
+__global__ void __launch_bounds__(kFinTPB) k_finalize(const double* __restrict__ partials, int nparts,
+                                                      double* __restrict__ scal, int mode, int slot,
+                                                      double nn) {
+  const double s = fin_sum(partials, nparts);
   if (threadIdx.x == 0) {
     switch (mode) {
       case F_STORE:
@@ -331,15 +349,10 @@ __global__ void __launch_bounds__(64) k_residual_norms(const double* __restrict_
 // rho = sum partials[0..np) = <r_k, z_k>_W, gamma = sum partials[np..2 np) =
 // <z_k, q_{k-1}>_W; beta = (rho - <z_k, r_{k-1}>) / rho_old = -alpha gamma / rho_old
 // since r_k = r_{k-1} - alpha q_{k-1}.
-__global__ void __launch_bounds__(kBlock) k_finalize_flex(const double* __restrict__ partials,
-                                                          int nparts, double* __restrict__ scal) {
-  double a1 = 0.0, a2 = 0.0;
-  for (int k = threadIdx.x; k < nparts; k += kBlock) {
-    a1 += partials[k];
-    a2 += partials[nparts + k];
-  }
-  const double rho = block_sum(a1);
-  const double gamma = block_sum(a2);
+__global__ void __launch_bounds__(kFinTPB) k_finalize_flex(const double* __restrict__ partials,
+                                                           int nparts, double* __restrict__ scal) {
+  const double rho = fin_sum(partials, nparts);
+  const double gamma = fin_sum(partials + nparts, nparts);
   if (threadIdx.x == 0) {
     const double old = scal[S_RZ];
     scal[S_RZOLD] = old;
@@ -453,11 +466,102 @@ __device__ __forceinline__ double clampd(double f, double lo, double hi) {
   return fmin(fmax(f, lo), hi);
 }
 
-// Flory-Huggins right-hand side in two passes, so that the logarithms are
-// evaluated once per node (not five times, as a one-pass five-point stencil
-// of mu would): mu = mu_FH(clamp(phi*)) with phi* = phi, or the extrapolation
-// 3/2 phi - 1/2 prev when prev is given (Crank-Nicolson), counting clamped
-// nodes; then b = base + dtM n^2 (axis - 4 c) of mu (base may alias b).
+// Flory-Huggins right-hand side (Sec. 2.2, eq. modCH with the parameters chi,
+// N of the Sec. 5 table): b = base + dtM n^2 (axis - 4 c) of mu, mu =
+// mu_FH(clamp(phi*)) with phi* = phi, or the extrapolation 3/2 phi - 1/2 prev
+// when prev is given (Crank-Nicolson); clamped nodes are counted; base may
+// alias b.
+//
+// One pass (k_ch_rhs_tile, grids of n >= 128): a workgroup owns a tile of
+// kRhsRows x kRhsCols nodes, evaluates mu once per node of the tile widened
+// by the Laplacian's reach (one row above and below, one column either side)
+// into LDS, and applies the 5-point Laplacian from there, so phi is read from
+// HBM once, mu never leaves the chip, and the logarithms -- the bulk of the
+// work: two float64 logs per node -- are evaluated (18 x 130) / (16 x 128) =
+// 1.14 times per node.  Smaller grids take two passes (k_mu, k_lap_axpy).
+constexpr int kRhsCols = 128;  // 64 lane pairs
+constexpr int kRhsRows = 16;
+
+__global__ void __launch_bounds__(kBlock) k_ch_rhs_tile(Geo G, int64_t stride, int strips,
+                                                        const double* __restrict__ phi,
+                                                        const double* __restrict__ prev,
+                                                        const double* base, double* b,
+                                                        RhsCoef C0,
+                                                        const double* __restrict__ icoef,
+                                                        int icoef_stride,
+                                                        int32_t* __restrict__ clamp_count) {
+  __shared__ double mu[kRhsRows + 2][kRhsCols + 2];
+  __shared__ int cnt_s;
+  const int inst = blockIdx.y;
+  RhsCoef C = C0;
+  if (icoef) {
+    const double* rc = icoef + (int64_t)inst * icoef_stride;
+    C.dtMn2 = rc[0];
+    C.inv_npoly = rc[1];
+    C.chi = rc[2];
+    C.lo = rc[3];
+    C.hi = rc[4];
+  }
+  const int64_t off = (int64_t)inst * stride;
+  phi += off;
+  if (prev) prev += off;
+  base += off;
+  b += off;
+  const int n = G.n, mask = G.mask;
+  const int rg = blockIdx.x / strips;
+  const int c0 = (blockIdx.x - rg * strips) * kRhsCols;
+  const int j0 = rg * kRhsRows;
+  const int rows = min(j0 + kRhsRows, n + 1) - j0;  // output rows of the tile
+  if (threadIdx.x == 0) cnt_s = 0;
+  int cnt = 0;
+  // mu on rows j0-1 .. j0+rows (reflected), columns c0 .. c0+127 (two per thread)
+  for (int s = threadIdx.x; s < (rows + 2) * 64; s += kBlock) {
+    const int r = s >> 6, l = s & 63;
+    const int64_t idx = (int64_t)refl(j0 - 1 + r, n) * n + c0 + 2 * l;
+    const double2 pv = *reinterpret_cast<const double2*>(phi + idx);
+    double f0 = pv.x, f1 = pv.y;
+    if (prev) {
+      const double2 qv = *reinterpret_cast<const double2*>(prev + idx);
+      f0 = 1.5 * f0 - 0.5 * qv.x;
+      f1 = 1.5 * f1 - 0.5 * qv.y;
+    }
+    if (r >= 1 && r <= rows)
+      cnt += ((f0 < C.lo || f0 > C.hi) ? 1 : 0) + ((f1 < C.lo || f1 > C.hi) ? 1 : 0);
+    mu[r][1 + 2 * l] = mu_fh(clampd(f0, C.lo, C.hi), C.inv_npoly, C.chi);
+    mu[r][2 + 2 * l] = mu_fh(clampd(f1, C.lo, C.hi), C.inv_npoly, C.chi);
+  }
+  // the columns c0 - 1 and c0 + 128 (wrapped)
+  for (int s = threadIdx.x; s < (rows + 2) * 2; s += kBlock) {
+    const int r = s >> 1, side = s & 1;
+    const int col = side ? ((c0 + kRhsCols) & mask) : ((c0 - 1) & mask);
+    const int64_t idx = (int64_t)refl(j0 - 1 + r, n) * n + col;
+    const double f = prev ? 1.5 * phi[idx] - 0.5 * prev[idx] : phi[idx];
+    mu[r][side ? kRhsCols + 1 : 0] = mu_fh(clampd(f, C.lo, C.hi), C.inv_npoly, C.chi);
+  }
+  __syncthreads();
+  for (int s = threadIdx.x; s < rows * 64; s += kBlock) {
+    const int r = s >> 6, l = s & 63;
+    const int64_t idx = (int64_t)(j0 + r) * n + c0 + 2 * l;
+    const double* m = &mu[r + 1][1 + 2 * l];
+    const double* mu_dn = &mu[r][1 + 2 * l];
+    const double* mu_up = &mu[r + 2][1 + 2 * l];
+    const double lap0 = (m[-1] + m[1]) + (mu_dn[0] + mu_up[0]) - 4.0 * m[0];
+    const double lap1 = (m[0] + m[2]) + (mu_dn[1] + mu_up[1]) - 4.0 * m[1];
+    const double2 bv = *reinterpret_cast<const double2*>(base + idx);
+    double2 out;
+    out.x = bv.x + C.dtMn2 * lap0;
+    out.y = bv.y + C.dtMn2 * lap1;
+    *reinterpret_cast<double2*>(b + idx) = out;
+  }
+  if (clamp_count) {
+    if (cnt) atomicAdd(&cnt_s, cnt);
+    __syncthreads();
+    if (threadIdx.x == 0 && cnt_s) atomicAdd(clamp_count + inst, cnt_s);
+  }
+}
+
+// Two-pass form (grids below 128 columns): mu once per node, then the
+// Laplacian.
 __global__ void __launch_bounds__(kBlock) k_mu(Geo G, const double* __restrict__ phi,
                                                const double* __restrict__ prev,
                                                double* __restrict__ mu, double inv_npoly,
@@ -1051,7 +1155,7 @@ void launch_to_double(int64_t count, const float* x, double* y, hipStream_t st) 
 }
 
 void launch_finalize_flex(const double* partials, int nparts, double* scal, hipStream_t st) {
-  LAUNCH(k_finalize_flex, 1, st, partials, nparts, scal);
+  hipLaunchKernelGGL(k_finalize_flex, dim3(1), dim3(kFinTPB), 0, st, partials, nparts, scal);
 }
 
 void launch_dot(int n, const double* x, const double* y, double* partials, int nparts,
@@ -1070,7 +1174,8 @@ void launch_residual_norms(const double* scal, double csq, double* out, hipStrea
 
 void launch_finalize(const double* partials, int nparts, double* scal, int mode, int slot, int n,
                      hipStream_t st) {
-  LAUNCH(k_finalize, 1, st, partials, nparts, scal, mode, slot, (double)n * (double)n);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFinTPB), 0, st, partials, nparts, scal, mode, slot,
+                     (double)n * (double)n);
 }
 
 int launch_cg_p(const OpDesc& A, const double* z, const double* p_old, double* p_new, double* q,
@@ -1129,8 +1234,26 @@ void launch_ch_rhs(int n, const double* phi, const double* prev, const double* b
                    double* mu_ws, double dtM, double inv_npoly, double chi, double lo, double hi,
                    int32_t* clamp_count, hipStream_t st) {
   const Geo G = make_geo(n);
+  if (n >= kRhsCols) {
+    RhsCoef C{dtM * (double)n * (double)n, inv_npoly, chi, lo, hi};
+    const int strips = n / kRhsCols;
+    const int rgroups = (n + 1 + kRhsRows - 1) / kRhsRows;
+    hipLaunchKernelGGL(k_ch_rhs_tile, dim3(strips * rgroups, 1), dim3(kBlock), 0, st, G,
+                       (int64_t)0, strips, phi, prev, base, b, C, nullptr, 0, clamp_count);
+    return;
+  }
   LAUNCH(k_mu, ew_blocks(G.npts), st, G, phi, prev, mu_ws, inv_npoly, chi, lo, hi, clamp_count);
   LAUNCH(k_lap_axpy, ew_blocks(G.npts), st, G, mu_ws, base, b, dtM * (double)n * (double)n);
+}
+
+void launch_ch_rhs_batch(int n, int count, int64_t stride, const double* phi, double* b,
+                         const double* icoef, int icoef_stride, int32_t* clamp_counts,
+                         hipStream_t st) {
+  const Geo G = make_geo(n);
+  const int strips = n / kRhsCols;
+  const int rgroups = (n + 1 + kRhsRows - 1) / kRhsRows;
+  hipLaunchKernelGGL(k_ch_rhs_tile, dim3(strips * rgroups, count), dim3(kBlock), 0, st, G, stride,
+                     strips, phi, nullptr, phi, b, RhsCoef{}, icoef, icoef_stride, clamp_counts);
 }
 
 int launch_mob(int n, double c, const double* m, const double* x, const double* b, double* y,

@@ -159,6 +159,24 @@ void launch_r_update(int n, double* r, const double* q, const double* scal, doub
                      int nparts, hipStream_t st, float* r32 = nullptr);
 // x += alpha p (alpha = scal[S_ALPHA]).
 void launch_x_update(int n, double* x, const double* p, const double* scal, hipStream_t st);
+// The coarse-grid correction and the whole post-smoother of a level in one
+// pass: x0 = x + P e (e the coarse correction), then `degree` sweeps
+// x_{k+1} = x_k + a[k] D^{-1}(b - A x_k) + g[k] (x_k - x_{k-1}) (g[0] unused);
+// out = x_degree (must not alias x, e or b).  The _dot forms also leave
+// partials of <b, out>_W (and of <out, q>_W) and return their count.
+bool post_ok(int n, int op, int degree, double g0, int elem_bytes);
+template <typename T>
+void stream_post(const OpDesc& A, int degree, const T* x, const T* e, const T* b, T* out,
+                 const double* a, const double* g, hipStream_t st);
+int stream_post_dot(const OpDesc& A, int degree, const double* x, const double* e,
+                    const double* b, double* out, const double* a, const double* g,
+                    double* partials, hipStream_t st);
+int stream_post_dot2(const OpDesc& A, int degree, const float* x, const float* e, const float* b,
+                     double* out, const double* q, const double* a, const double* g,
+                     double* partials, hipStream_t st);
+int stream_post_dot2_f32(const OpDesc& A, int degree, const float* x, const float* e,
+                         const float* b, float* out, const double* q, const double* a,
+                         const double* g, double* partials, hipStream_t st);
 bool transfer_stream_ok(int nf);
 template <typename T>
 void stream_prolong_add(int nf, const T* coarse, T* fine, hipStream_t st);
@@ -256,11 +274,22 @@ void launch_fill_i32(int count, int32_t* x, int32_t v, hipStream_t st);
 void launch_copy2(int64_t count, const double* x, double* y, hipStream_t st);
 
 // Step pieces.
+// Coefficients of the Flory-Huggins right-hand side: dtM n^2, 1/N, chi, clamp.
+struct RhsCoef {
+  double dtMn2, inv_npoly, chi, lo, hi;
+};
 // b = base + dtM L mu_FH(clamp(phi*)), phi* = phi (prev null) or 3/2 phi - 1/2 prev;
-// mu_ws: a field of workspace; base may alias b; clamped nodes counted into clamp_count.
+// mu_ws: a field of workspace (used below 128 columns only); base may alias b;
+// clamped nodes counted into clamp_count.
 void launch_ch_rhs(int n, const double* phi, const double* prev, const double* base, double* b,
                    double* mu_ws, double dtM, double inv_npoly, double chi, double lo, double hi,
                    int32_t* clamp_count, hipStream_t st);
+// The same (prev null, base = phi) for `count` instances of n >= 128 stored
+// `stride` apart: instance i reads its coefficients (dtM n^2, 1/N, chi, lo,
+// hi) from icoef + i icoef_stride (device) and counts into clamp_counts[i].
+void launch_ch_rhs_batch(int n, int count, int64_t stride, const double* phi, double* b,
+                         const double* icoef, int icoef_stride, int32_t* clamp_counts,
+                         hipStream_t st);
 void launch_divergence(int n, const double* u, const double* v, double* rhs, double scale,
                        hipStream_t st);
 // Variable-mobility Cahn-Hilliard operator A_m = I + c L_m L (double-double

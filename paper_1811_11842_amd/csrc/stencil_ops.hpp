@@ -251,6 +251,41 @@ __device__ __forceinline__ double residual_dd_vals(const Nb13& v, double bval, d
   return r + (re - ve);
 }
 
+// Exact 13-point operator by splitting (the ExtractScalar step of Rump, Ogita
+// and Oishi's accurate summation).  With sigma a power of two that bounds 64
+// times every value the stencil combines, hi = fl(fl(sigma + v) - sigma) is a
+// multiple of u sigma (u = 2^-53) and lo = v - hi is exact with |lo| <= u
+// sigma.  The integer-weighted sum of the hi parts (weights 20, -8, 2, 1,
+// sum of |weights| 64) is then a multiple of u sigma of magnitude below sigma,
+// so every partial sum is representable and the float64 sum is exact in any
+// order; the lo parts sum with an absolute error of a few u^2 sigma.  The
+// split is done once per value of a wavefront's window (shared by all the
+// stencils that read it) instead of one compensated step per stencil term.
+__device__ __forceinline__ void split_sigma(double v, double sigma, double& hi, double& lo) {
+#pragma clang fp contract(off)
+  hi = (sigma + v) - sigma;
+  lo = v - hi;
+}
+
+// q = c + s * S13(v) from the split neighbourhoods vh (hi parts, centre vh.c)
+// and vl (lo parts), c = vh.c + vl.c (exact): the exact hi sum and the lo sum
+// form S13 to a few u^2 sigma, the product by s is a two_prod and the
+// addition of c a two_sum, so q is correct to about an ulp of itself.
+__device__ __forceinline__ double apply13_split(const Nb13& vh, const Nb13& vl, double c,
+                                                double s) {
+  const double sh = 20.0 * vh.c - 8.0 * ((vh.xm1 + vh.xp1) + (vh.ym1 + vh.yp1)) +
+                    2.0 * ((vh.dmm + vh.dmp) + (vh.dpm + vh.dpp)) +
+                    ((vh.xm2 + vh.xp2) + (vh.ym2 + vh.yp2));
+  const double sl = 20.0 * vl.c - 8.0 * ((vl.xm1 + vl.xp1) + (vl.ym1 + vl.yp1)) +
+                    2.0 * ((vl.dmm + vl.dmp) + (vl.dpm + vl.dpp)) +
+                    ((vl.xm2 + vl.xp2) + (vl.ym2 + vl.yp2));
+  double p, e1, w, e2;
+  two_prod(s, sh, p, e1);
+  e1 = fma(s, sl, e1);
+  two_sum(c, p, w, e2);
+  return w + (e1 + e2);
+}
+
 // ulp of a float64 value (0 for 0): spacing of the doubles around |v|.
 __device__ __forceinline__ double ulp_of(double v) {
   int e;

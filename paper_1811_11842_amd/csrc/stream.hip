@@ -269,6 +269,37 @@ __global__ void __launch_bounds__(kStreamTPB) k_stream(StreamArgs<T, TO> P) {
       }
     }
 
+    // Cahn-Hilliard CG step: q = A p' exactly rounded through the split of
+    // every window value against sigma = 2^7 times a power of two above the
+    // largest |p'| of the wavefront's window (apply13_split); xr keeps the hi
+    // parts, xl the lo parts.  The largest magnitude is found from the high
+    // words (their unsigned order is the order of |value| for finite values).
+    constexpr bool SPLIT = CGP && OP == 1 && std::is_same<T, double>::value;
+    XRow<T, V> xl[SPLIT ? NR : 1];
+    if constexpr (SPLIT) {
+      uint32_t mx = 0;
+#pragma unroll
+      for (int k = 0; k < NR; ++k) {
+#pragma unroll
+        for (int i = 0; i < V; ++i)
+          mx = max(mx, (uint32_t)__double2hiint(xr[k].o[i]) & 0x7fffffffu);
+        mx = max(mx, (uint32_t)__double2hiint(xr[k].h0) & 0x7fffffffu);
+        mx = max(mx, (uint32_t)__double2hiint(xr[k].h1) & 0x7fffffffu);
+      }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, off, 64));
+      // biased exponent eb: every |value| < 2^(eb - 1022); sigma = 2^(eb - 1015)
+      const int eb = (int)(__builtin_amdgcn_readfirstlane(mx) >> 20);
+      const double sigma = __hiloint2double(min(eb + 8, 2046) << 20, 0);
+#pragma unroll
+      for (int k = 0; k < NR; ++k) {
+#pragma unroll
+        for (int i = 0; i < V; ++i) split_sigma(xr[k].o[i], sigma, xr[k].o[i], xl[k].o[i]);
+        split_sigma(xr[k].h0, sigma, xr[k].h0, xl[k].h0);
+        split_sigma(xr[k].h1, sigma, xr[k].h1, xl[k].h1);
+      }
+    }
+
     // neighbours across lanes: column c-1, c-2 (left) and c+V, c+V+1 (right)
     // (lane 0 holds columns c-2, c-1 in h0, h1; lane 63 columns c+V, c+V+1)
     auto left1 = [&](const XRow<T, V>& r) { return from_left(r.o[V - 1], r.h1); };
@@ -276,12 +307,9 @@ __global__ void __launch_bounds__(kStreamTPB) k_stream(StreamArgs<T, TO> P) {
     auto right1 = [&](const XRow<T, V>& r) { return from_right(r.o[0], r.h0); };
     auto right2 = [&](const XRow<T, V>& r) { return from_right(r.o[1], r.h1); };
 
-#pragma unroll
-    for (int s = 0; s < RPW; ++s) {
-      const int j = j0 + s;
-      if (j > jl) break;
-      const int k = s + R;
-      const XRow<T, V>& C = xr[k];
+    // the 5 (OP 0, 2) or 13 (OP 1) values around the lane's V nodes of window row k
+    auto gather_nb = [&](const XRow<T, V>* W, int k, Nb13T<T>(&nb)[V]) {
+      const XRow<T, V>& C = W[k];
       // centre row, columns c-2 .. c+V+1
       T e[V + 4];
       e[1] = left1(C);
@@ -294,18 +322,17 @@ __global__ void __launch_bounds__(kStreamTPB) k_stream(StreamArgs<T, TO> P) {
       }
 #pragma unroll
       for (int i = 0; i < V; ++i) e[2 + i] = C.o[i];
-      Nb13T<T> nb[V];
 #pragma unroll
       for (int i = 0; i < V; ++i) {
         nb[i].c = e[i + 2];
         nb[i].xm1 = e[i + 1];
         nb[i].xp1 = e[i + 3];
-        nb[i].ym1 = xr[k - 1].o[i];
-        nb[i].yp1 = xr[k + 1].o[i];
+        nb[i].ym1 = W[k - 1].o[i];
+        nb[i].yp1 = W[k + 1].o[i];
       }
       if constexpr (OP == 1) {
-        const XRow<T, V>& Mr = xr[k - 1];
-        const XRow<T, V>& Pr = xr[k + 1];
+        const XRow<T, V>& Mr = W[k - 1];
+        const XRow<T, V>& Pr = W[k + 1];
         T m[V + 2], p[V + 2];  // rows j-1, j+1, columns c-1 .. c+V
         m[0] = left1(Mr);
         m[V + 1] = right1(Mr);
@@ -320,14 +347,23 @@ __global__ void __launch_bounds__(kStreamTPB) k_stream(StreamArgs<T, TO> P) {
         for (int i = 0; i < V; ++i) {
           nb[i].xm2 = e[i];
           nb[i].xp2 = e[i + 4];
-          nb[i].ym2 = xr[k - 2].o[i];
-          nb[i].yp2 = xr[k + 2].o[i];
+          nb[i].ym2 = W[k - 2].o[i];
+          nb[i].yp2 = W[k + 2].o[i];
           nb[i].dmm = m[i];
           nb[i].dmp = m[i + 2];
           nb[i].dpm = p[i];
           nb[i].dpp = p[i + 2];
         }
       }
+    };
+
+#pragma unroll
+    for (int s = 0; s < RPW; ++s) {
+      const int j = j0 + s;
+      if (j > jl) break;
+      const int k = s + R;
+      Nb13T<T> nb[V];
+      gather_nb(xr, k, nb);
       const int64_t o = (int64_t)j * n + c;
       const double wgt = row_weight(j, n);
       const double cfj = row_coef<OP>(cf, j, n);
@@ -382,11 +418,23 @@ __global__ void __launch_bounds__(kStreamTPB) k_stream(StreamArgs<T, TO> P) {
           }
         } else if constexpr (CGP) {
           VecN<double, V> pn;
+          if constexpr (SPLIT) {
+            Nb13T<T> nbl[V];
+            gather_nb(xl, k, nbl);
 #pragma unroll
-          for (int i = 0; i < V; ++i) {
-            res.v[i] = OP == 1 ? -residual_dd_vals<OP>(nb[i], 0.0, cfj) : apply_vals<OP>(nb[i], T(cfj));
-            acc += wgt * nb[i].c * res.v[i];
-            pn.v[i] = nb[i].c;
+            for (int i = 0; i < V; ++i) {
+              const double cv = nb[i].c + nbl[i].c;  // p' (exact: hi + lo)
+              res.v[i] = apply13_split(nb[i], nbl[i], cv, cfj);
+              acc += wgt * cv * res.v[i];
+              pn.v[i] = cv;
+            }
+          } else {
+#pragma unroll
+            for (int i = 0; i < V; ++i) {
+              res.v[i] = apply_vals<OP>(nb[i], T(cfj));
+              acc += wgt * nb[i].c * res.v[i];
+              pn.v[i] = nb[i].c;
+            }
           }
           store_nt(reinterpret_cast<VecN<double, V>*>(O2p + o), pn);
           if (!P.first) {
@@ -417,6 +465,171 @@ __global__ void __launch_bounds__(kStreamTPB) k_stream(StreamArgs<T, TO> P) {
       if (threadIdx.x == 0) P.partials[gridDim.x + blockIdx.x] = s2;
     }
   }
+}
+
+// The Cahn-Hilliard CG step of a single grid (E_CG_P / E_CG_P32 for OP 1):
+//   p' = z + beta p_old (p' = z on the first step), q = A p' = p' + s S13 p'
+//   exactly rounded (apply13_split), partials of <p', q>_W, and the deferred
+//   x += alpha_prev p_old.
+// The wavefronts overlap by one lane on each side: a wavefront loads 128
+// columns (two per lane) and lanes 1 .. 62 produce output (124 columns,
+// strips 124 apart, the last one cut at n), so no lane loads halo columns
+// and the split window holds only the lanes' own values (the register count
+// decides the occupancy of this VALU-heavy kernel).  The DPP shifts bring the
+// neighbours' columns; what lanes 0 and 63 receive from outside the
+// wavefront only reaches their own discarded results.
+constexpr int kCgLanes = 62;
+constexpr int kCgCols = 2 * kCgLanes;
+
+template <typename ZT>
+struct CgArgs {
+  OpDesc A;
+  Geo G;
+  const ZT* z;
+  const double* p_old;
+  double* p_new;
+  double* q;
+  double* x;
+  const double* scal;
+  double* partials;
+  int first;
+  int rgroups, wstrips, tiles;
+};
+
+template <int RPW, typename ZT, int WAVES>
+__global__ void __launch_bounds__(kStreamTPB) __attribute__((amdgpu_waves_per_eu(WAVES, 8)))
+k_cg_ch(CgArgs<ZT> P) {
+  constexpr int NR = RPW + 4;
+  const int n = P.G.n, mask = P.G.mask;
+  const int lane = threadIdx.x & 63;
+  double beta = 0.0, alpha_prev = 0.0;
+  if (!P.first) {
+    beta = P.scal[S_BETA];
+    alpha_prev = P.scal[S_ALPHA];
+  }
+  const double s13 = P.A.coef;
+  double acc = 0.0;
+  const int wpb = kStreamTPB / 64;
+  const int t0 = __builtin_amdgcn_readfirstlane(blockIdx.x * wpb + (threadIdx.x >> 6));
+  for (int t = t0; t < P.tiles; t += gridDim.x * wpb) {
+    const int rg = t / P.wstrips;
+    const int strip = t - rg * P.wstrips;
+    const int j0 = rg * RPW;
+    const int jl = min(j0 + RPW, n + 1) - 1;
+    const int cu = strip * kCgCols + 2 * (lane - 1);  // unwrapped first column of the lane
+    const int c = cu & mask;
+    const bool out_lane = lane >= 1 && lane <= kCgLanes && cu < n;
+    // window rows j0-2 .. jl+2 (reflected): p' = z + beta p_old
+    double w[NR][2];
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+      const int jj = j0 - 2 + k;
+      if (jj > jl + 2) {
+        w[k][0] = w[k][1] = 0.0;
+        continue;
+      }
+      const int64_t ro = (int64_t)refl(jj, n) * n + c;
+      if constexpr (std::is_same<ZT, float>::value) {
+        const float2 zv = *reinterpret_cast<const float2*>(P.z + ro);
+        w[k][0] = zv.x;
+        w[k][1] = zv.y;
+      } else {
+        const double2 zv = *reinterpret_cast<const double2*>(P.z + ro);
+        w[k][0] = zv.x;
+        w[k][1] = zv.y;
+      }
+      if (!P.first) {
+        const double2 po = *reinterpret_cast<const double2*>(P.p_old + ro);
+        w[k][0] += beta * po.x;
+        w[k][1] += beta * po.y;
+      }
+    }
+    // sigma: 2^7 times a power of two above every |p'| of the window
+    uint32_t mx = 0;
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+      mx = max(mx, (uint32_t)__double2hiint(w[k][0]) & 0x7fffffffu);
+      mx = max(mx, (uint32_t)__double2hiint(w[k][1]) & 0x7fffffffu);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, off, 64));
+    const int eb = (int)(__builtin_amdgcn_readfirstlane(mx) >> 20);
+    const double sigma = __hiloint2double(min(eb + 8, 2046) << 20, 0);
+    double wh[NR][2], wl[NR][2];
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+      split_sigma(w[k][0], sigma, wh[k][0], wl[k][0]);
+      split_sigma(w[k][1], sigma, wh[k][1], wl[k][1]);
+    }
+    // the 13 values around the lane's two nodes (columns c, c+1) of window row k
+    auto gather = [&](const double (*W)[2], int k, Nb13 (&nb)[2]) {
+      const double l0 = from_left(W[k][0], 0.0), l1 = from_left(W[k][1], 0.0);
+      const double r0 = from_right(W[k][0], 0.0), r1 = from_right(W[k][1], 0.0);
+      const double ml1 = from_left(W[k - 1][1], 0.0), mr0 = from_right(W[k - 1][0], 0.0);
+      const double pl1 = from_left(W[k + 1][1], 0.0), pr0 = from_right(W[k + 1][0], 0.0);
+      // node c: columns c-2 = l0, c-1 = l1, c+1, c+2 = r0
+      nb[0].c = W[k][0];
+      nb[0].xm1 = l1;
+      nb[0].xp1 = W[k][1];
+      nb[0].xm2 = l0;
+      nb[0].xp2 = r0;
+      nb[0].ym1 = W[k - 1][0];
+      nb[0].yp1 = W[k + 1][0];
+      nb[0].ym2 = W[k - 2][0];
+      nb[0].yp2 = W[k + 2][0];
+      nb[0].dmm = ml1;
+      nb[0].dmp = W[k - 1][1];
+      nb[0].dpm = pl1;
+      nb[0].dpp = W[k + 1][1];
+      // node c+1: columns c-1 = l1, c, c+2 = r0, c+3 = r1
+      nb[1].c = W[k][1];
+      nb[1].xm1 = W[k][0];
+      nb[1].xp1 = r0;
+      nb[1].xm2 = l1;
+      nb[1].xp2 = r1;
+      nb[1].ym1 = W[k - 1][1];
+      nb[1].yp1 = W[k + 1][1];
+      nb[1].ym2 = W[k - 2][1];
+      nb[1].yp2 = W[k + 2][1];
+      nb[1].dmm = W[k - 1][0];
+      nb[1].dmp = mr0;
+      nb[1].dpm = W[k + 1][0];
+      nb[1].dpp = pr0;
+    };
+#pragma unroll
+    for (int s = 0; s < RPW; ++s) {
+      const int j = j0 + s;
+      if (j > jl) break;
+      const int k = s + 2;
+      Nb13 nh[2], nl[2];
+      gather(wh, k, nh);
+      gather(wl, k, nl);
+      const int64_t o = (int64_t)j * n + c;
+      const double wgt = row_weight(j, n);
+      double2 qv, pv;
+      pv.x = nh[0].c + nl[0].c;
+      pv.y = nh[1].c + nl[1].c;
+      qv.x = apply13_split(nh[0], nl[0], pv.x, s13);
+      qv.y = apply13_split(nh[1], nl[1], pv.y, s13);
+      if (out_lane) {
+        acc += wgt * (pv.x * qv.x + pv.y * qv.y);
+        __builtin_nontemporal_store(pv.x, P.p_new + o);
+        __builtin_nontemporal_store(pv.y, P.p_new + o + 1);
+        __builtin_nontemporal_store(qv.x, P.q + o);
+        __builtin_nontemporal_store(qv.y, P.q + o + 1);
+        if (!P.first) {
+          const double2 po = *reinterpret_cast<const double2*>(P.p_old + o);
+          double2 xv = *reinterpret_cast<const double2*>(P.x + o);
+          xv.x += alpha_prev * po.x;
+          xv.y += alpha_prev * po.y;
+          __builtin_nontemporal_store(xv.x, P.x + o);
+          __builtin_nontemporal_store(xv.y, P.x + o + 1);
+        }
+      }
+    }
+  }
+  const double s1 = block_sum_n<kStreamTPB>(acc);
+  if (threadIdx.x == 0) P.partials[blockIdx.x] = s1;
 }
 
 // Three sweeps of the smoother from a zero iterate in one pass:
@@ -858,6 +1071,177 @@ __global__ void __launch_bounds__(kStreamTPB) k_smooth2(Smooth2Args<T, TO> P) {
   }
 }
 
+// The coarse-grid correction and the whole post-smoother of a level in one
+// pass (single grids):
+//   x_0 = x + P e   (P: tensor-product cubic interpolation of the coarse
+//                    correction e, formed on load),
+//   x_{k+1} = x_k + a_k D^{-1}(b - A x_k) + g_k (x_k - x_{k-1}),  k = 0 .. D-1
+//   (g_0 = 0: the first sweep of the Chebyshev recurrence has no x_{-1}).
+// The separate form is three passes (prolongation, one sweep, the last two
+// sweeps) that write and re-read x_0 and x_1; here x_0 .. x_{D-1} live in
+// registers over the tile's rows widened by the stencil's reach (D levels:
+// D R rows each side), so the pass reads x, e and b and writes x_D only.
+// Each lane holds two fine columns c, c+1 (c even) and loads the coarse
+// column c/2 of the coarse rows the window needs; the interpolation at c+1
+// takes the coarse columns c/2 - 1 .. c/2 + 2 from lanes -1 .. +2 (DPP), so
+// x_0 is valid on lanes 1 .. 61, and every stencil level narrows that by a
+// lane each side: lanes 1+D .. 61-D produce output (strips 2 (61 - 2D)
+// columns apart, the last cut at n).  A fine ghost row takes its
+// interpolated value from the unreflected coarse rows around it (the coarse
+// rows reflected on load): P commutes with the even reflection, so the value
+// equals the one on its mirror row, as for the stencil levels.  Epilogues as
+// for k_smooth2 (S2_NONE, S2_DOT, S2_DOT2).
+template <int D>
+struct PostGeom {
+  static constexpr int kLanes = 61 - 2 * D;
+  static constexpr int kCols = 2 * kLanes;
+};
+
+template <typename T, typename TO>
+struct PostArgs {
+  OpDesc A;
+  const T* x;       // the level's iterate before the correction
+  const T* e;       // coarse correction, (n/2 + 1) x n/2
+  const T* b;
+  const double* q;  // S2_DOT2
+  TO* out;
+  double* partials;
+  double a[3], g[3];
+  int wstrips, tiles;
+};
+
+template <int OP, int D, int EP, int RPW, typename T, typename TO>
+__global__ void __launch_bounds__(kStreamTPB) k_post(PostArgs<T, TO> P) {
+  constexpr int R = (OP == 1) ? 2 : 1;
+  static_assert((D * R) % 2 == 0 && RPW % 2 == 0, "window rows start on an even fine row");
+  constexpr int NW = RPW + 2 * D * R;  // x0 and b rows j0-DR .. j0-DR+NW-1
+  constexpr int NC = NW / 2 + 3;       // coarse rows (j0-DR)/2 - 1 .. (j0-DR)/2 + NW/2 + 1
+  constexpr int LO = 1 + D, HI = 61 - D;  // output lanes
+  using V2 = VecN<T, 2>;
+  const int n = P.A.n, mask = n - 1;
+  const int nc = n >> 1;
+  const int lane = threadIdx.x & 63;
+  const int wpb = kStreamTPB / 64;
+  const T tdi = T(P.A.dinv_int), tde = T(P.A.dinv_edge), tcoef = T(P.A.coef);
+  auto dinv_row = [&](int jr) -> T { return row_dinv<OP, T>(tdi, tde, jr, n); };
+  auto coef_row = [&](int jr) -> T { return (OP == 2 && (jr == 0 || jr == n)) ? T(0) : tcoef; };
+  const int t0 = __builtin_amdgcn_readfirstlane(blockIdx.x * wpb + (threadIdx.x >> 6));
+  double acc = 0.0, acc2 = 0.0;
+  for (int t = t0; t < P.tiles; t += gridDim.x * wpb) {
+    const int rg = t / P.wstrips;
+    const int strip = t - rg * P.wstrips;
+    const int j0 = rg * RPW;
+    const int jl = min(j0 + RPW, n + 1) - 1;
+    const int col = strip * PostGeom<D>::kCols + 2 * (lane - LO);
+    const int cm = col & mask;
+    const int ic = cm >> 1;  // this lane's coarse column
+    // coarse rows, interpolated in x at the lane's two fine columns
+    const int jc0 = ((j0 - D * R) >> 1) - 1;
+    T ce[NC][2];
+#pragma unroll
+    for (int m = 0; m < NC; ++m) {
+      const T v = P.e[(int64_t)refl(jc0 + m, nc) * nc + ic];
+      const T vm1 = from_left(v, T(0));
+      const T vp1 = from_right(v, T(0));
+      const T vp2 = from_right(vp1, T(0));
+      ce[m][0] = v;
+      ce[m][1] = (-vm1 + T(9) * v + T(9) * vp1 - vp2) * T(0.0625);
+    }
+    // x0 = x + P e and b over the window rows (rows past the tile's reach are unused)
+    T x0[NW][2], bw[NW][2];
+    int jrw[NW];
+#pragma unroll
+    for (int k = 0; k < NW; ++k) {
+      const int jj = j0 - D * R + k;
+      jrw[k] = refl(min(jj, jl + D * R), n);
+      const int64_t o = (int64_t)jrw[k] * n + cm;
+      const V2 xv = *reinterpret_cast<const V2*>(P.x + o);
+      const V2 bv = *reinterpret_cast<const V2*>(P.b + o);
+      const int m = (k >> 1) + 1;  // coarse row of jj (even), or of jj - 1 (odd)
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        T pe;
+        if ((k & 1) == 0) {
+          pe = ce[m][i];
+        } else {
+          pe = (-ce[m - 1][i] + T(9) * ce[m][i] + T(9) * ce[m + 1][i] - ce[m + 2][i]) * T(0.0625);
+        }
+        x0[k][i] = xv.v[i] + pe;
+        bw[k][i] = bv.v[i];
+      }
+    }
+    // x1 over rows j0-(D-1)R .. jl+(D-1)R
+    constexpr int N1 = NW - 2 * R;
+    T x1[N1][2];
+#pragma unroll
+    for (int k1 = 0; k1 < N1; ++k1) {
+      const int k = k1 + R;
+      T ax[2];
+      window_apply<OP>(x0, k, coef_row(jrw[k]), ax);
+      const T ad = T(P.a[0]) * dinv_row(jrw[k]);
+#pragma unroll
+      for (int i = 0; i < 2; ++i) x1[k1][i] = x0[k][i] + ad * (bw[k][i] - ax[i]);
+    }
+    // x2 over rows j0-(D-2)R .. jl+(D-2)R
+    constexpr int N2 = NW - 4 * R;
+    T x2[N2][2];
+#pragma unroll
+    for (int k2 = 0; k2 < N2; ++k2) {
+      const int k1 = k2 + R, k = k2 + 2 * R;
+      T ax[2];
+      window_apply<OP>(x1, k1, coef_row(jrw[k]), ax);
+      const T ad = T(P.a[1]) * dinv_row(jrw[k]);
+      const T g1 = T(P.g[1]);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+        x2[k2][i] = x1[k1][i] + ad * (bw[k][i] - ax[i]) + g1 * (x1[k1][i] - x0[k][i]);
+    }
+    const bool own = lane >= LO && lane <= HI && col < n;
+#pragma unroll
+    for (int s = 0; s < RPW; ++s) {
+      const int j = j0 + s;
+      if (j > jl) break;
+      const int k = s + D * R;  // the row in the x0 / b window
+      VecN<TO, 2> o;
+      if constexpr (D == 2) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i) o.v[i] = TO(x2[s][i]);
+      } else {
+        const int k2 = s + R, k1 = s + 2 * R;
+        T ax[2];
+        window_apply<OP>(x2, k2, coef_row(j), ax);
+        const T ad = T(P.a[2]) * dinv_row(j);
+        const T g2 = T(P.g[2]);
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+          o.v[i] = TO(x2[k2][i] + ad * (bw[k][i] - ax[i]) + g2 * (x2[k2][i] - x1[k1][i]));
+      }
+      if (own) {
+        const int64_t off = (int64_t)j * n + col;
+        store_nt(reinterpret_cast<VecN<TO, 2>*>(P.out + off), o);
+        if constexpr (EP != S2_NONE) {
+          const double wgt = row_weight(j, n);
+#pragma unroll
+          for (int i = 0; i < 2; ++i) acc += wgt * double(bw[k][i]) * double(o.v[i]);
+          if constexpr (EP == S2_DOT2) {
+            const VecN<double, 2> qv = *reinterpret_cast<const VecN<double, 2>*>(P.q + off);
+#pragma unroll
+            for (int i = 0; i < 2; ++i) acc2 += wgt * double(o.v[i]) * qv.v[i];
+          }
+        }
+      }
+    }
+  }
+  if constexpr (EP != S2_NONE) {
+    const double s1 = block_sum_n<kStreamTPB>(acc);
+    if (threadIdx.x == 0) P.partials[blockIdx.x] = s1;
+    if constexpr (EP == S2_DOT2) {
+      const double s2 = block_sum_n<kStreamTPB>(acc2);
+      if (threadIdx.x == 0) P.partials[gridDim.x + blockIdx.x] = s2;
+    }
+  }
+}
+
 // ------------------------------------------------------------------ launch
 namespace {
 
@@ -1008,8 +1392,62 @@ int stream_smooth_dot2(const OpDesc& A, const float* x, const float* xprev, cons
   return stream_launch<E_SMOOTH_DOT2, float, double>(A, x, b, xprev, xout, partials, a, g, st,
                                                      0.0, q);
 }
+// The overlapped-strip CH CG step (k_cg_ch): single grids only (a batch, also
+// a batch of one with coefficient records or a mask, takes k_stream).
+static bool cg_ch_ok(const OpDesc& A) {
+  static const bool off = env_int("BF_NO_CG_CH", 0) != 0;
+  const BatchCtx& B = g_batch;
+  return !off && A.op == 1 && B.count <= 1 && !B.coef && !B.active;
+}
+
+template <int RPW, int WAVES, typename ZT>
+static int launch_cg_ch_cfg(const OpDesc& A, const ZT* z, const double* p_old, double* p_new,
+                            double* q, double* x, const double* scal, bool first,
+                            double* partials, hipStream_t st) {
+  CgArgs<ZT> P{};
+  P.A = A;
+  P.G = make_geo(A.n);
+  P.z = z;
+  P.p_old = p_old;
+  P.p_new = p_new;
+  P.q = q;
+  P.x = x;
+  P.scal = scal;
+  P.partials = partials;
+  P.first = first ? 1 : 0;
+  P.wstrips = (A.n + kCgCols - 1) / kCgCols;
+  P.rgroups = (A.n + 1 + RPW - 1) / RPW;
+  P.tiles = P.wstrips * P.rgroups;
+  const int wpb = kStreamTPB / 64;
+  const int blocks = std::min((P.tiles + wpb - 1) / wpb, kStreamMaxBlocks);
+  hipLaunchKernelGGL((k_cg_ch<RPW, ZT, WAVES>), dim3(blocks), dim3(kStreamTPB), 0, st, P);
+  return blocks;
+}
+
+// Tile height and occupancy target of k_cg_ch (BF_CG_CH_CFG selects one for
+// measurements): 0 = 4 rows, at least 4 waves per SIMD (114 VGPRs); 1 = 4
+// rows, the compiler's own register count; 2 = 2 rows, at least 4 waves;
+// 3 = 8 rows, at least 3 waves.
+template <typename ZT>
+static int launch_cg_ch(const OpDesc& A, const ZT* z, const double* p_old, double* p_new,
+                        double* q, double* x, const double* scal, bool first, double* partials,
+                        hipStream_t st) {
+  static const int cfg = env_int("BF_CG_CH_CFG", 0);
+  switch (cfg) {
+    case 1:
+      return launch_cg_ch_cfg<4, 1>(A, z, p_old, p_new, q, x, scal, first, partials, st);
+    case 2:
+      return launch_cg_ch_cfg<2, 4>(A, z, p_old, p_new, q, x, scal, first, partials, st);
+    case 3:
+      return launch_cg_ch_cfg<8, 3>(A, z, p_old, p_new, q, x, scal, first, partials, st);
+    default:
+      return launch_cg_ch_cfg<4, 4>(A, z, p_old, p_new, q, x, scal, first, partials, st);
+  }
+}
+
 int stream_cg_p(const OpDesc& A, const double* z, const double* p_old, double* p_new, double* q,
                 double* x, const double* scal, bool first, double* partials, hipStream_t st) {
+  if (cg_ch_ok(A)) return launch_cg_ch(A, z, p_old, p_new, q, x, scal, first, partials, st);
   const StreamCfg c = stream_cfg(A.n, 8);
   StreamArgs<double, double> P{};
   P.A = A;
@@ -1028,6 +1466,7 @@ int stream_cg_p(const OpDesc& A, const double* z, const double* p_old, double* p
 }
 int stream_cg_p32(const OpDesc& A, const float* z, const double* p_old, double* p_new, double* q,
                   double* x, const double* scal, bool first, double* partials, hipStream_t st) {
+  if (cg_ch_ok(A)) return launch_cg_ch(A, z, p_old, p_new, q, x, scal, first, partials, st);
   const StreamCfg c = stream_cfg(A.n, 8);
   StreamArgs<double, double> P{};
   P.A = A;
@@ -1248,6 +1687,97 @@ int stream_smooth_last2_dot2_f32(const OpDesc& A, const float* x1, const float* 
   return stream_smooth2<S2_DOT2, float, float>(A, x1, x0, b, xout, q, a1, g1, a2, g2, partials,
                                                st);
 }
+
+// The coarse-grid correction and the post-smoother in one pass (k_post).
+// Single grids, streamed levels, sweep 0 without a momentum term; the
+// Cahn-Hilliard operator with degree 2 or 3, the Laplacian with degree 2 (the
+// window must start on an even fine row: D R even).  BF_NO_POST=1 switches it
+// off.
+bool post_ok(int n, int op, int degree, double g0, int elem_bytes) {
+  static const bool off = env_int("BF_NO_POST", 0) != 0;
+  // float64 levels up to 2048 (at 4096^2 the float64 window leaves one
+  // wavefront per SIMD: 280 us against 254 for the three separate passes)
+  static const int f64_max = env_int("BF_POST_F64_MAX", 2048);
+  const BatchCtx& B = g_batch;
+  const bool shape = (op == 1 && (degree == 2 || degree == 3)) || (op == 0 && degree == 2);
+  return !off && shape && n >= 128 && (elem_bytes == 4 || n <= f64_max) && g0 == 0.0 &&
+         B.count <= 1 && !B.coef && !B.active;
+}
+
+template <int EP, int RPW, typename T, typename TO>
+static int post_launch_rpw(const OpDesc& A, int degree, const T* x, const T* e, const T* b,
+                           const double* q, TO* out, const double* a, const double* g,
+                           double* partials, hipStream_t st) {
+  PostArgs<T, TO> P{};
+  P.A = A;
+  P.x = x;
+  P.e = e;
+  P.b = b;
+  P.q = q;
+  P.out = out;
+  P.partials = partials;
+  for (int k = 0; k < 3; ++k) {
+    P.a[k] = a[k];
+    P.g[k] = g[k];
+  }
+  const int cols = degree == 3 ? PostGeom<3>::kCols : PostGeom<2>::kCols;
+  P.wstrips = (A.n + cols - 1) / cols;
+  P.tiles = P.wstrips * ((A.n + 1 + RPW - 1) / RPW);
+  const int wpb = kStreamTPB / 64;
+  const int blocks = std::min((P.tiles + wpb - 1) / wpb, kStreamMaxBlocks);
+  const dim3 grid(blocks), blk(kStreamTPB);
+  if (A.op == 1) {
+    if (degree == 3)
+      hipLaunchKernelGGL((k_post<1, 3, EP, RPW, T, TO>), grid, blk, 0, st, P);
+    else
+      hipLaunchKernelGGL((k_post<1, 2, EP, RPW, T, TO>), grid, blk, 0, st, P);
+  } else {
+    hipLaunchKernelGGL((k_post<0, 2, EP, RPW, T, TO>), grid, blk, 0, st, P);  // degree 2 only
+  }
+  return blocks;
+}
+
+// Tile rows: float64 2; float32 8 by default (BF_POST_RPW=4 or 6 selects another
+// height; the window of x0 .. x2 and b lives in registers).
+template <int EP, typename T, typename TO>
+static int post_launch(const OpDesc& A, int degree, const T* x, const T* e, const T* b,
+                       const double* q, TO* out, const double* a, const double* g,
+                       double* partials, hipStream_t st) {
+  if constexpr (sizeof(T) == 8) {
+    return post_launch_rpw<EP, 2>(A, degree, x, e, b, q, out, a, g, partials, st);
+  } else {
+    static const int rpw = env_int("BF_POST_RPW", 8);
+    if (rpw == 4) return post_launch_rpw<EP, 4>(A, degree, x, e, b, q, out, a, g, partials, st);
+    if (rpw == 6) return post_launch_rpw<EP, 6>(A, degree, x, e, b, q, out, a, g, partials, st);
+    return post_launch_rpw<EP, 8>(A, degree, x, e, b, q, out, a, g, partials, st);
+  }
+}
+
+template <typename T>
+void stream_post(const OpDesc& A, int degree, const T* x, const T* e, const T* b, T* out,
+                 const double* a, const double* g, hipStream_t st) {
+  post_launch<S2_NONE, T, T>(A, degree, x, e, b, nullptr, out, a, g, nullptr, st);
+}
+int stream_post_dot(const OpDesc& A, int degree, const double* x, const double* e,
+                    const double* b, double* out, const double* a, const double* g,
+                    double* partials, hipStream_t st) {
+  return post_launch<S2_DOT, double, double>(A, degree, x, e, b, nullptr, out, a, g, partials,
+                                             st);
+}
+int stream_post_dot2(const OpDesc& A, int degree, const float* x, const float* e, const float* b,
+                     double* out, const double* q, const double* a, const double* g,
+                     double* partials, hipStream_t st) {
+  return post_launch<S2_DOT2, float, double>(A, degree, x, e, b, q, out, a, g, partials, st);
+}
+int stream_post_dot2_f32(const OpDesc& A, int degree, const float* x, const float* e,
+                         const float* b, float* out, const double* q, const double* a,
+                         const double* g, double* partials, hipStream_t st) {
+  return post_launch<S2_DOT2, float, float>(A, degree, x, e, b, q, out, a, g, partials, st);
+}
+template void stream_post<double>(const OpDesc&, int, const double*, const double*, const double*,
+                                  double*, const double*, const double*, hipStream_t);
+template void stream_post<float>(const OpDesc&, int, const float*, const float*, const float*,
+                                 float*, const double*, const double*, hipStream_t);
 
 template int stream_residual<double>(const OpDesc&, const double*, const double*, double*,
                                      double*, hipStream_t);

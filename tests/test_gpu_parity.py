@@ -164,7 +164,7 @@ def test_vcycle_graph_replays_match_eager(dev, op, monkeypatch):
 
 
 # ------------------------------------------------------------------ step pieces
-@pytest.mark.parametrize("n", [8, 64, 1024])
+@pytest.mark.parametrize("n", [8, 64, 128, 256, 1024, 4096])
 def test_ch_rhs_matches_oracle(dev, n):
     phi = S.initial_phi(n)
     g = grid(n)
@@ -189,6 +189,25 @@ def test_ch_rhs_counts_clamped_points(dev):
     assert np.all(np.isfinite(b))
     ref = fh.rhs_ch(phi, PRM["dt"], PRM["M"], PRM["Npoly"], PRM["chi"])
     np.testing.assert_allclose(b, ref, rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("n", [128, 512])
+def test_ch_rhs_counts_clamped_points_on_tile_edges(dev, n):
+    """The one-pass right-hand side (grids of 128 columns and more) counts
+    every clamped node once, also on the rows and columns where its tiles
+    (16 rows x 128 columns, each with a one-node halo) meet and on the wall
+    rows, and matches the oracle there."""
+    phi = S.initial_phi(n)
+    spots = [(0, 0), (n, n - 1), (15, 127), (16, 0), (17, n - 1), (31, 64), (n - 1, 5)]
+    for k, (j, i) in enumerate(spots):
+        phi[j, i] = (0.0, 1.0, -0.1, 1.5)[k % 4]
+    cnt = torch.zeros(1, dtype=torch.int32, device=dev)
+    b = to_np(grid(n).ch_rhs(bf.make_params(**PRM), to_dev(phi, dev), clamped=cnt))
+    assert int(cnt.item()) == len(spots) == fh.count_clamped(phi)
+    ref = fh.rhs_ch(phi, PRM["dt"], PRM["M"], PRM["Npoly"], PRM["chi"])
+    mu = fh.mu_fh(fh.clamp(phi, 1e-6, 1 - 1e-6), PRM["Npoly"], PRM["chi"])
+    scale = np.abs(phi).max() + PRM["dt"] * n * n * 8 * np.abs(mu).max()
+    assert np.abs(b - ref).max() <= 64 * U * scale
 
 
 @pytest.mark.parametrize("n", [8, 256])

@@ -109,6 +109,7 @@ def time_steps(g, n, steps, warmup, mg_precision):
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     stats = []
+    g.cg_timing(True)   # HIP events around every CG-step launch on the grid's stream
     t0 = time.perf_counter()
     e0.record()
     for k in range(steps):
@@ -121,7 +122,30 @@ def time_steps(g, n, steps, warmup, mg_precision):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms = e0.elapsed_time(e1)
-    return ms / steps, wall / steps * 1e3, stats, (phi, p)
+    cg = g.cg_timing_read()
+    g.cg_timing(False)
+    return ms / steps, wall / steps * 1e3, stats, (phi, p), cg
+
+
+# Algorithmic bytes per grid point of the Cahn-Hilliard CG step kernel: z
+# (float32 from the float32 V-cycle, float64 otherwise), p_old and x read;
+# p', q and x written.  The first step of a Krylov cycle reads z only and
+# writes p' and q.
+def cg_step_bytes(z_bytes, launches, first):
+    return (launches - first) * (z_bytes + 40) + first * (z_bytes + 16)
+
+
+def cg_roofline(n, cg, z_bytes, kernel, traffic):
+    total_ms, launches, first = cg
+    npts = (n + 1) * n
+    alg = cg_step_bytes(z_bytes, launches, first) * npts / launches
+    us = total_ms / launches * 1e3
+    gbs = alg / (us * 1e-6) / 1e9
+    return {"kernel": kernel, "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "algorithmic_bytes": int(alg), "launch_us": round(us, 3), "launches": launches,
+            "first_launches": first,
+            "timing": "HIP events on the grid's stream around every launch in the timed steps"}
 
 
 def wrel(a, b):
@@ -454,14 +478,20 @@ def main():
         if not a.spmv_only:
             res = {}
             if a.precision in ("both", "mixed"):
-                ms_m, wall_m, st_m, fin_m = time_steps(g, n, a.steps, a.warmup, bf.MG_F32)
+                ms_m, wall_m, st_m, fin_m, cg_m = time_steps(g, n, a.steps, a.warmup, bf.MG_F32)
                 res["mixed"] = fin_m
                 out.update({"value": round(ms_m, 4), "unit": "ms/step",
                             "ms_per_step": round(ms_m, 4)})
                 out.update(step_summary("", ms_m, wall_m, st_m))
+                out["roofline_step"] = cg_roofline(
+                    n, cg_m, 4, "k_cg_ch<4,float,4> (Cahn-Hilliard CG step of the value's "
+                    "steps: p' = z + beta p, q = A p' exactly rounded, <p', q>_W, x += alpha p; "
+                    "z float32)", recorded_traffic("cg_step", n))
             if a.precision in ("both", "f64"):
-                ms_d, wall_d, st_d, fin_d = time_steps(g, n, a.steps, a.warmup, bf.MG_F64)
+                ms_d, wall_d, st_d, fin_d, cg_d = time_steps(g, n, a.steps, a.warmup, bf.MG_F64)
                 res["f64"] = fin_d
+                out["fp64_roofline_step"] = cg_roofline(
+                    n, cg_d, 8, "k_cg_ch<4,double,4> (the same step with a float64 z)", None)
                 if a.precision == "f64":
                     out.update({"value": round(ms_d, 4), "unit": "ms/step",
                                 "ms_per_step": round(ms_d, 4)})
@@ -514,7 +544,7 @@ def main():
         out["adjoint"] = time_adjoint()
         log("float64 steps at 1024^2 (the plain float64 baseline configuration)")
         with bf.Grid(1024) as g1:
-            ms1, _, st1, _ = time_steps(g1, 1024, 10, 2, bf.MG_F64)
+            ms1, _, st1, _, _ = time_steps(g1, 1024, 10, 2, bf.MG_F64)
         out["fp64_1024"] = {"n": 1024, "steps": 10, "ms_per_step": round(ms1, 4),
                             "ch_iters_mean": float(np.mean([s[0].iters for s in st1])),
                             "scaled_to_4096_ms": round(ms1 * 16, 3),

@@ -139,6 +139,10 @@ def lib():
             "bf_residual": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_double, _P, _P, _P,
                                            ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                            ctypes.POINTER(ctypes.c_double)]),
+            "bf_grid_cg_timing": (ctypes.c_int, [_P, ctypes.c_int32]),
+            "bf_grid_cg_timing_read": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double),
+                                                      ctypes.POINTER(ctypes.c_int64),
+                                                      ctypes.POINTER(ctypes.c_int64)]),
             "bf_residual_noalloc": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
                                                    _P, _P, _P, _P, _P]),
             "bf_ensemble_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int32), ctypes.c_int32,
@@ -420,6 +424,17 @@ class Grid:
         y = self.field() if y is None else y
         _check(lib().bf_copy(self._h, self._ptr(x, "x"), self._ptr(y, "y")))
         return y
+
+    def cg_timing(self, enable: bool):
+        """Start (clearing the record) or stop timing the Cahn-Hilliard CG step kernel."""
+        _check(lib().bf_grid_cg_timing(self._h, 1 if enable else 0))
+
+    def cg_timing_read(self):
+        """(summed ms, launches, first-step launches) since timing started; clears the record."""
+        ms, n, nf = ctypes.c_double(), ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().bf_grid_cg_timing_read(self._h, ctypes.byref(ms), ctypes.byref(n),
+                                            ctypes.byref(nf)))
+        return ms.value, n.value, nf.value
 
     def wdot(self, x, y) -> float:
         out = ctypes.c_double()

@@ -129,6 +129,13 @@ struct bf_grid {
   hipStream_t twin_stream = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   bool overlap = true;
+  // Timing of the CG step kernel (bf_grid_cg_timing): a pair of events on the
+  // stream around each launch while recording is on; the events are pooled
+  // and reused after each read.
+  bool cg_timing = false;
+  std::vector<hipEvent_t> cg_ev;   // pool, 2 per recorded launch
+  std::vector<uint8_t> cg_first;   // per recorded launch: a first step of a Krylov cycle
+  size_t cg_used = 0;              // events of the pool in use
 };
 
 namespace {
@@ -792,6 +799,23 @@ double* precondition_mob(bf_grid* g, double c, const bf_solver_opts& o, const do
   return vcycle_mob<double>(g, g->lv, c, o, 0, r);
 }
 
+// Start the timing of one CG-step launch: takes a pair of events from the
+// pool (creating them on first use) and records the first on the stream; the
+// caller records the second after the launch.
+int cg_timing_mark(bf_grid* g, bool first) {
+  if (g->cg_used + 2 > g->cg_ev.size()) {
+    for (int k = 0; k < 2; ++k) {
+      hipEvent_t e = nullptr;
+      HIPCHK(hipEventCreate(&e));
+      g->cg_ev.push_back(e);
+    }
+  }
+  HIPCHK(hipEventRecord(g->cg_ev[g->cg_used], g->stream));
+  g->cg_used += 2;
+  g->cg_first.push_back(first ? 1 : 0);
+  return BF_OK;
+}
+
 // Reduce <x, y>_W into scal[slot] (asynchronous).
 void wdot_async(bf_grid* g, const double* x, const double* y, int mode, int slot) {
   const int np = nparts_of(g);
@@ -985,9 +1009,12 @@ int run_cg(bf_grid* g, int op, double c, const double* b, double* x, const bf_so
     };
     while (ks.iters < o.maxit) {
       // p' = z + beta p, q = A p' (+ <p', q>), and the deferred x += alpha p
+      const bool timed = g->cg_timing && op == BF_OP_CH;
+      if (timed) TRY(cg_timing_mark(g, first));
       const int npq =
           zf32 ? stream_cg_p32(A, g->z32, pcur, pnext, g->q, x, g->scal, first, g->partials, st)
                : launch_cg_p(A, z, pcur, pnext, g->q, x, g->scal, first, g->partials, np, st);
+      if (timed) HIPCHK(hipEventRecord(g->cg_ev[g->cg_used - 1], st));
       launch_finalize(g->partials, npq, g->scal, F_ALPHA, 0, g->n, st);
       std::swap(pcur, pnext);
       first = false;
@@ -1424,7 +1451,38 @@ int bf_grid_destroy(bf_grid* g) {
   if (g->ev0) (void)hipEventDestroy(g->ev0);
   if (g->ev1) (void)hipEventDestroy(g->ev1);
   if (g->ev_scal) (void)hipEventDestroy(g->ev_scal);
+  for (hipEvent_t e : g->cg_ev) (void)hipEventDestroy(e);
   delete g;
+  return BF_OK;
+}
+
+int bf_grid_cg_timing(bf_grid* g, int32_t enable) {
+  TRY(check_grid(g));
+  g->cg_timing = enable != 0;
+  if (g->cg_timing) {
+    g->cg_used = 0;
+    g->cg_first.clear();
+  }
+  return BF_OK;
+}
+
+int bf_grid_cg_timing_read(bf_grid* g, double* total_ms, int64_t* launches,
+                           int64_t* first_launches) {
+  TRY(check_grid(g));
+  HIPCHK(hipStreamSynchronize(g->stream));
+  double tot = 0.0;
+  int64_t nf = 0;
+  for (size_t k = 0; k + 1 < g->cg_used; k += 2) {
+    float ms = 0.0f;
+    HIPCHK(hipEventElapsedTime(&ms, g->cg_ev[k], g->cg_ev[k + 1]));
+    tot += ms;
+  }
+  for (uint8_t f : g->cg_first) nf += f;
+  if (total_ms) *total_ms = tot;
+  if (launches) *launches = (int64_t)g->cg_first.size();
+  if (first_launches) *first_launches = nf;
+  g->cg_used = 0;
+  g->cg_first.clear();
   return BF_OK;
 }
 

@@ -191,6 +191,25 @@ def time_spmv(g, n, reps):
     return e0.elapsed_time(e1) / reps
 
 
+def time_copy(g, n, reps):
+    """Average duration of the library's plain copy of one field (bf_copy: 16-byte
+    lanes, coalesced rows, non-temporal stores) on 4 rotating buffer pairs: the
+    ceiling of a kernel that reads one field and writes one."""
+    dev = g.device
+    xs = [torch.from_numpy(S.random_field(n, 90 + k)).to(dev) for k in range(4)]
+    ys = [g.field() for _ in range(4)]
+    for k in range(4):
+        g.copy(xs[k], ys[k])
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for r in range(reps):
+        g.copy(xs[r % 4], ys[r % 4])
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
 def time_smooth(g, n, reps):
     """Average duration of one Cahn-Hilliard smoothing sweep (x, x_prev, b -> x')."""
     dev = g.device
@@ -508,11 +527,14 @@ def main():
             gbs = alg / (t_spmv * 1e-3) / 1e9
             out["spmv_us"] = round(t_spmv * 1e3, 3)
             out["spmv_gbs"] = round(gbs, 1)
+            t_copy = time_copy(g, n, a.spmv_reps)
             out["roofline"] = {"kernel": "k_stream<1,0,5,double,double> (13-point Cahn-Hilliard SpMV, float64, 5-row tiles)",
                                "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
                                "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
                                "traffic": recorded_traffic("spmv", n), "algorithmic_bytes": alg,
-                               "launch_us": round(t_spmv * 1e3, 3)}
+                               "launch_us": round(t_spmv * 1e3, 3),
+                               "copy_us": round(t_copy * 1e3, 3),
+                               "frac_of_copy": round(t_copy / t_spmv, 4)}
             if not a.spmv_only:
                 t_sm = time_smooth(g, n, max(20, a.spmv_reps // 2))
                 alg_sm = 32 * npts   # x, x_prev, b read, x' written

@@ -166,6 +166,45 @@ __global__ void __launch_bounds__(kBlock) ke_r_update(Geo G, int64_t stride, dou
   if (threadIdx.x == 0) partials[inst * gridDim.x + blockIdx.x] = t;
 }
 
+// Convergence of every instance after an iteration's r update, on the device
+// (one workgroup): an active instance counts the iteration, keeps its
+// relative recursive residual, and leaves the mask when that meets rtol (or
+// is not finite), recording which p buffer holds its last direction; flags
+// receive the number still active and whether a norm was not finite, for the
+// host to read while the next preconditioner application runs.
+__global__ void __launch_bounds__(kBlock) ke_converge(const double* __restrict__ scal,
+                                                      const double* __restrict__ bn, double rtol,
+                                                      int* __restrict__ active,
+                                                      int* __restrict__ iters,
+                                                      int* __restrict__ parity, int parity_now,
+                                                      double* __restrict__ rel_res,
+                                                      int* __restrict__ flags, int count) {
+  int rem = 0, bad = 0;
+  for (int k = threadIdx.x; k < count; k += kBlock) {
+    if (!active[k]) continue;
+    const double rr = scal[(int64_t)k * kNumSlots + S_RR];
+    const double rel = sqrt(rr) / bn[k];
+    iters[k] += 1;
+    rel_res[k] = rel;
+    if (!isfinite(rel)) {
+      bad = 1;
+      active[k] = 0;
+      parity[k] = parity_now;
+    } else if (rel <= rtol) {
+      active[k] = 0;
+      parity[k] = parity_now;
+    } else {
+      ++rem;
+    }
+  }
+  const double r = block_sum((double)rem);
+  const double b = block_sum((double)bad);
+  if (threadIdx.x == 0) {
+    flags[0] = (int)r;
+    flags[1] = b > 0.0 ? 1 : 0;
+  }
+}
+
 // x += alpha p for the instances with sel[inst] != 0.
 __global__ void __launch_bounds__(kBlock) ke_x_update(Geo G, int64_t stride, double* __restrict__ x,
                                                       const double* __restrict__ p,
@@ -218,6 +257,16 @@ struct EClass {
   double *scal = nullptr, *partials = nullptr, *h_scal = nullptr;
   int* active = nullptr;        // device mask
   int* sel = nullptr;           // device selection for the final x updates
+  // device-side convergence of a CG pass (ke_converge): per instance ||b||_W,
+  // iteration count, buffer of the last p, relative recursive residual; two
+  // flag pairs (active count, non-finite) read back alternately, pinned
+  double* d_bn = nullptr;
+  int* d_iters = nullptr;
+  int* d_parity = nullptr;
+  double* d_rel = nullptr;
+  int* d_flags = nullptr;
+  int* h_flags = nullptr;
+  hipEvent_t ev_flags[2] = {nullptr, nullptr};
   std::vector<int> h_active;
   int32_t* clamped = nullptr;   // [count]
   EParam* prm = nullptr;        // [count]
@@ -511,13 +560,16 @@ void e_wdot(EClass& C, const double* x, const double* y, int diff, int mode, int
 // One CG pass on the active instances of the class, from the current x and
 // r = b - A x (r in C.r); a fresh Krylov space for all of them.  Leaves every
 // instance's x complete (the deferred update applied) and its recursive
-// residual and iteration count in stats.
+// residual and iteration count in stats.  Convergence is decided on the
+// device after each r update (ke_converge): converged instances leave the
+// mask that every kernel of the class honours, and the host reads only the
+// count still active, after it has queued the next preconditioner
+// application, so the class's stream never waits for the host.
 int e_cg_pass(EClass& C, int op, const double* bn, double* x, const bf_solver_opts& o,
               std::vector<bf_solve_stats>& stats, std::vector<int>& ran) {
   hipStream_t st = C.stream;
   const Geo G = make_geo(C.n);
   const int B = C.count;
-  std::vector<int> parity(B, 0);
   ran.assign(B, 0);
   int remaining = 0;
   for (int k = 0; k < B; ++k) {
@@ -526,6 +578,8 @@ int e_cg_pass(EClass& C, int op, const double* bn, double* x, const bf_solver_op
   }
   if (remaining == 0) return BF_OK;
   ECHK(hipMemcpyAsync(C.active, C.h_active.data(), sizeof(int) * B, hipMemcpyHostToDevice, st));
+  ECHK(hipMemcpyAsync(C.d_bn, bn, sizeof(double) * B, hipMemcpyHostToDevice, st));
+  launch_fill_i32(B, C.d_iters, 0, st);
   int rzp = 0;
   double* z = e_precondition(C, op, C.r, &rzp);
   e_finalize(C, 0, rzp, F_STORE, S_RZ, C.active);
@@ -534,7 +588,7 @@ int e_cg_pass(EClass& C, int op, const double* bn, double* x, const bf_solver_op
   bool first = true;
   int it = 0;
   const OpDesc A0 = host_level_op(op, C.n, 0.0);
-  while (remaining > 0 && it < o.maxit) {
+  while (it < o.maxit) {
     {
       BatchScope scope(C, C.npts, 0, level_coef(C, op, 0), C.active, C.rpw);
       const int np = stream_cg_p(A0, z, pcur, pnext, C.q, x, C.scal, first, C.partials, st) / B;
@@ -547,34 +601,39 @@ int e_cg_pass(EClass& C, int op, const double* bn, double* x, const bf_solver_op
                        C.active, C.partials);
     e_finalize(C, 0, nb, F_STORE, S_RR, C.active);
     ++it;
-    ETRY(e_read(C));
-    bool changed = false;
-    for (int k = 0; k < B; ++k) {
-      if (!C.h_active[k]) continue;
-      const double rr = C.h_scal[(size_t)k * kNumSlots + S_RR];
-      if (!std::isfinite(rr)) return efail(BF_ENONFINITE, "residual norm is not finite");
-      const double rel = std::sqrt(rr) / bn[k];
-      stats[k].iters += 1;
-      stats[k].rel_res = rel;
-      if (rel <= o.rtol) {
-        C.h_active[k] = 0;
-        parity[k] = (pcur == C.p) ? 0 : 1;  // buffer holding this instance's last p
-        changed = true;
-        --remaining;
-      }
+    const int slot = it & 1;
+    hipLaunchKernelGGL(ke_converge, dim3(1), dim3(kBlock), 0, st, C.scal, C.d_bn, o.rtol,
+                       C.active, C.d_iters, C.d_parity, pcur == C.p ? 0 : 1, C.d_rel,
+                       C.d_flags + 2 * slot, B);
+    ECHK(hipMemcpyAsync(C.h_flags + 2 * slot, C.d_flags + 2 * slot, sizeof(int) * 2,
+                        hipMemcpyDeviceToHost, st));
+    ECHK(hipEventRecord(C.ev_flags[slot], st));
+    if (it < o.maxit) {
+      // the next application for the instances still active (the others are
+      // masked); the count arrives while it runs
+      z = e_precondition(C, op, C.r, &rzp);
+      e_finalize(C, 0, rzp, F_BETA, 0, C.active);
     }
-    if (remaining == 0) break;
-    if (changed)
-      ECHK(hipMemcpyAsync(C.active, C.h_active.data(), sizeof(int) * B, hipMemcpyHostToDevice,
-                          st));
-    z = e_precondition(C, op, C.r, &rzp);
-    e_finalize(C, 0, rzp, F_BETA, 0, C.active);
+    ECHK(hipEventSynchronize(C.ev_flags[slot]));
+    if (C.h_flags[2 * slot + 1]) return efail(BF_ENONFINITE, "residual norm is not finite");
+    if (C.h_flags[2 * slot] == 0) break;
   }
-  for (int k = 0; k < B; ++k)
-    if (C.h_active[k]) {  // stopped by maxit
-      parity[k] = (pcur == C.p) ? 0 : 1;
-      C.h_active[k] = 0;
-    }
+  // per instance: iterations, recursive residual, the buffer of its last p
+  // (instances stopped by maxit hold theirs in pcur)
+  std::vector<int> iters(B), parity(B), act(B);
+  std::vector<double> rel(B);
+  ECHK(hipMemcpyAsync(iters.data(), C.d_iters, sizeof(int) * B, hipMemcpyDeviceToHost, st));
+  ECHK(hipMemcpyAsync(parity.data(), C.d_parity, sizeof(int) * B, hipMemcpyDeviceToHost, st));
+  ECHK(hipMemcpyAsync(act.data(), C.active, sizeof(int) * B, hipMemcpyDeviceToHost, st));
+  ECHK(hipMemcpyAsync(rel.data(), C.d_rel, sizeof(double) * B, hipMemcpyDeviceToHost, st));
+  ECHK(hipStreamSynchronize(st));
+  for (int k = 0; k < B; ++k) {
+    C.h_active[k] = 0;
+    if (!ran[k]) continue;
+    stats[k].iters += iters[k];
+    stats[k].rel_res = rel[k];
+    if (act[k]) parity[k] = (pcur == C.p) ? 0 : 1;
+  }
   // the pending x += alpha p of every instance of the pass, from the buffer
   // that holds its last p
   for (int par = 0; par < 2; ++par) {
@@ -836,6 +895,13 @@ int e_create(bf_ensemble* e, const int32_t* n, int count) {
     ETRY(ealloc(e, &C.partials, kEnsPartials));
     ETRY(ealloc(e, &C.active, B));
     ETRY(ealloc(e, &C.sel, 2 * B));
+    ETRY(ealloc(e, &C.d_bn, B));
+    ETRY(ealloc(e, &C.d_iters, B));
+    ETRY(ealloc(e, &C.d_parity, B));
+    ETRY(ealloc(e, &C.d_rel, B));
+    ETRY(ealloc(e, &C.d_flags, 4));
+    for (int k = 0; k < 2; ++k)
+      ECHK(hipEventCreateWithFlags(&C.ev_flags[k], hipEventDisableTiming));
     ETRY(ealloc(e, &C.clamped, B));
     ETRY(ealloc(e, &C.prm, B));
     const int L = (int)C.lv.size();
@@ -849,6 +915,11 @@ int e_create(bf_ensemble* e, const int32_t* n, int count) {
       return efail(BF_ENOMEM, "pinned host allocation failed");
     e->host_allocs.push_back(hs);
     C.h_scal = (double*)hs;
+    void* hf = nullptr;
+    if (hipHostMalloc(&hf, sizeof(int) * 4) != hipSuccess)
+      return efail(BF_ENOMEM, "pinned host allocation failed");
+    e->host_allocs.push_back(hf);
+    C.h_flags = (int*)hf;
     C.h_active.assign(B, 0);
     launch_fill((int64_t)kNumSlots * B, C.scal, 0.0, C.stream);
     launch_fill(C.npts * B, C.q, 0.0, C.stream);
@@ -889,6 +960,8 @@ int bf_ensemble_destroy(bf_ensemble* e) {
     if (C.stream) (void)hipStreamSynchronize(C.stream);
     for (int op = 0; op < 2; ++op)
       if (C.graph[op]) (void)hipGraphExecDestroy(C.graph[op]);
+    for (int k = 0; k < 2; ++k)
+      if (C.ev_flags[k]) (void)hipEventDestroy(C.ev_flags[k]);
     if (C.stream) (void)hipStreamDestroy(C.stream);
   }
   for (void* p : e->allocs) (void)hipFree(p);

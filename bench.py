@@ -193,7 +193,7 @@ def time_spmv(g, n, reps):
 
 def time_copy(g, n, reps):
     """Average duration of the library's plain copy of one field (bf_copy: 16-byte
-    lanes, coalesced rows, non-temporal stores) on 4 rotating buffer pairs: the
+    lanes, coalesced rows, ordinary loads and stores) on 4 rotating buffer pairs: the
     ceiling of a kernel that reads one field and writes one."""
     dev = g.device
     xs = [torch.from_numpy(S.random_field(n, 90 + k)).to(dev) for k in range(4)]

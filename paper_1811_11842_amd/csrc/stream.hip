@@ -548,14 +548,14 @@ struct CgArgs {
   int rgroups, wstrips, tiles;
 };
 
-template <int RPW, typename ZT, int WAVES>
+template <int RPW, typename ZT, int WAVES, bool FIRST>
 __global__ void __launch_bounds__(kStreamTPB) __attribute__((amdgpu_waves_per_eu(WAVES, 8)))
 k_cg_ch(CgArgs<ZT> P) {
   constexpr int NR = RPW + 4;
   const int n = P.G.n, mask = P.G.mask;
   const int lane = threadIdx.x & 63;
   double beta = 0.0, alpha_prev = 0.0;
-  if (!P.first) {
+  if (!FIRST) {
     beta = P.scal[S_BETA];
     alpha_prev = P.scal[S_ALPHA];
   }
@@ -574,29 +574,62 @@ k_cg_ch(CgArgs<ZT> P) {
     const int cu = strip * kCgCols + 2 * (lane - 1);  // unwrapped first column of the lane
     const int c = cu & mask;
     const bool out_lane = lane >= 1 && lane <= kCgLanes && cu < n;
-    // window rows j0-2 .. jl+2 (reflected): p' = z + beta p_old
+    // Every load of the tile is issued before any value is used (no branch
+    // between them), so their latencies overlap: the window rows j0-2 .. jl+2
+    // (reflected; the rows a short last tile does not reach repeat row jl+2,
+    // which leaves the window's largest magnitude unchanged and is never an
+    // output's neighbour) of z and p_old, and x at the output rows.
+    ZT zr[NR][2];
+    double po[FIRST ? 1 : NR][2];
+    double2 xo[FIRST ? 1 : RPW];
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+      const int64_t ro = (int64_t)refl(min(j0 - 2 + k, jl + 2), n) * n + c;
+      if constexpr (std::is_same<ZT, float>::value) {
+        const float2 zv = *reinterpret_cast<const float2*>(P.z + ro);
+        zr[k][0] = zv.x;
+        zr[k][1] = zv.y;
+      } else {
+        const double2 zv = *reinterpret_cast<const double2*>(P.z + ro);
+        zr[k][0] = zv.x;
+        zr[k][1] = zv.y;
+      }
+      if constexpr (!FIRST) {
+        const double2 pv = *reinterpret_cast<const double2*>(P.p_old + ro);
+        po[k][0] = pv.x;
+        po[k][1] = pv.y;
+      }
+    }
+    if constexpr (!FIRST) {
+#pragma unroll
+      for (int s = 0; s < RPW; ++s)
+        xo[s] = *reinterpret_cast<const double2*>(P.x + (int64_t)min(j0 + s, jl) * n + c);
+    }
+    // p' = z + beta p_old over the window
     double w[NR][2];
 #pragma unroll
     for (int k = 0; k < NR; ++k) {
-      const int jj = j0 - 2 + k;
-      if (jj > jl + 2) {
-        w[k][0] = w[k][1] = 0.0;
-        continue;
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        w[k][i] = zr[k][i];
+        if constexpr (!FIRST) w[k][i] += beta * po[k][i];
       }
-      const int64_t ro = (int64_t)refl(jj, n) * n + c;
-      if constexpr (std::is_same<ZT, float>::value) {
-        const float2 zv = *reinterpret_cast<const float2*>(P.z + ro);
-        w[k][0] = zv.x;
-        w[k][1] = zv.y;
-      } else {
-        const double2 zv = *reinterpret_cast<const double2*>(P.z + ro);
-        w[k][0] = zv.x;
-        w[k][1] = zv.y;
-      }
-      if (!P.first) {
-        const double2 po = *reinterpret_cast<const double2*>(P.p_old + ro);
-        w[k][0] += beta * po.x;
-        w[k][1] += beta * po.y;
+    }
+    // the deferred x += alpha_prev p_old at the output rows (window rows 2 ..),
+    // done first so that x and p_old leave the registers before the split
+    if constexpr (!FIRST) {
+#pragma unroll
+      for (int s = 0; s < RPW; ++s) {
+        const int j = j0 + s;
+        if (j > jl) break;
+        if (out_lane) {
+          double2 xv = xo[s];
+          xv.x += alpha_prev * po[s + 2][0];
+          xv.y += alpha_prev * po[s + 2][1];
+          const int64_t o = (int64_t)j * n + c;
+          __builtin_nontemporal_store(xv.x, P.x + o);
+          __builtin_nontemporal_store(xv.y, P.x + o + 1);
+        }
       }
     }
     // sigma: 2^7 times a power of two above every |p'| of the window
@@ -670,14 +703,6 @@ k_cg_ch(CgArgs<ZT> P) {
         __builtin_nontemporal_store(pv.y, P.p_new + o + 1);
         __builtin_nontemporal_store(qv.x, P.q + o);
         __builtin_nontemporal_store(qv.y, P.q + o + 1);
-        if (!P.first) {
-          const double2 po = *reinterpret_cast<const double2*>(P.p_old + o);
-          double2 xv = *reinterpret_cast<const double2*>(P.x + o);
-          xv.x += alpha_prev * po.x;
-          xv.y += alpha_prev * po.y;
-          __builtin_nontemporal_store(xv.x, P.x + o);
-          __builtin_nontemporal_store(xv.y, P.x + o + 1);
-        }
       }
     }
   }
@@ -1188,12 +1213,38 @@ __global__ void __launch_bounds__(kStreamTPB) k_post(PostArgs<T, TO> P) {
     const int col = strip * PostGeom<D>::kCols + 2 * (lane - LO);
     const int cm = col & mask;
     const int ic = cm >> 1;  // this lane's coarse column
-    // coarse rows, interpolated in x at the lane's two fine columns
+    // Every load of the tile is issued before any value is used, so their
+    // latencies overlap (left to itself, the compiler sinks each load to its
+    // first use to save registers, which exposes them one after another): the
+    // coarse rows, x and b over the window (rows past the tile's reach repeat
+    // its last reachable row and are never used), and q at the output rows
+    // (clamped to valid rows and columns; only the owned ones are used).
     const int jc0 = ((j0 - D * R) >> 1) - 1;
+    T ev[NC];
+#pragma unroll
+    for (int m = 0; m < NC; ++m) ev[m] = P.e[(int64_t)refl(jc0 + m, nc) * nc + ic];
+    V2 xv[NW], bv[NW];
+    int jrw[NW];
+#pragma unroll
+    for (int k = 0; k < NW; ++k) {
+      const int jj = j0 - D * R + k;
+      jrw[k] = refl(min(jj, jl + D * R), n);
+      const int64_t o = (int64_t)jrw[k] * n + cm;
+      xv[k] = *reinterpret_cast<const V2*>(P.x + o);
+      bv[k] = *reinterpret_cast<const V2*>(P.b + o);
+    }
+    VecN<double, 2> qv[EP == S2_DOT2 ? RPW : 1];
+    if constexpr (EP == S2_DOT2) {
+#pragma unroll
+      for (int s = 0; s < RPW; ++s)
+        qv[s] = *reinterpret_cast<const VecN<double, 2>*>(P.q + (int64_t)min(j0 + s, jl) * n + cm);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    // coarse rows, interpolated in x at the lane's two fine columns
     T ce[NC][2];
 #pragma unroll
     for (int m = 0; m < NC; ++m) {
-      const T v = P.e[(int64_t)refl(jc0 + m, nc) * nc + ic];
+      const T v = ev[m];
       const T vm1 = from_left(v, T(0));
       const T vp1 = from_right(v, T(0));
       const T vp2 = from_right(vp1, T(0));
@@ -1202,14 +1253,8 @@ __global__ void __launch_bounds__(kStreamTPB) k_post(PostArgs<T, TO> P) {
     }
     // x0 = x + P e and b over the window rows (rows past the tile's reach are unused)
     T x0[NW][2], bw[NW][2];
-    int jrw[NW];
 #pragma unroll
     for (int k = 0; k < NW; ++k) {
-      const int jj = j0 - D * R + k;
-      jrw[k] = refl(min(jj, jl + D * R), n);
-      const int64_t o = (int64_t)jrw[k] * n + cm;
-      const V2 xv = *reinterpret_cast<const V2*>(P.x + o);
-      const V2 bv = *reinterpret_cast<const V2*>(P.b + o);
       const int m = (k >> 1) + 1;  // coarse row of jj (even), or of jj - 1 (odd)
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
@@ -1219,8 +1264,8 @@ __global__ void __launch_bounds__(kStreamTPB) k_post(PostArgs<T, TO> P) {
         } else {
           pe = (-ce[m - 1][i] + T(9) * ce[m][i] + T(9) * ce[m + 1][i] - ce[m + 2][i]) * T(0.0625);
         }
-        x0[k][i] = xv.v[i] + pe;
-        bw[k][i] = bv.v[i];
+        x0[k][i] = xv[k].v[i] + pe;
+        bw[k][i] = bv[k].v[i];
       }
     }
     // x1 over rows j0-(D-1)R .. jl+(D-1)R
@@ -1277,9 +1322,8 @@ __global__ void __launch_bounds__(kStreamTPB) k_post(PostArgs<T, TO> P) {
 #pragma unroll
           for (int i = 0; i < 2; ++i) acc += wgt * double(bw[k][i]) * double(o.v[i]);
           if constexpr (EP == S2_DOT2) {
-            const VecN<double, 2> qv = *reinterpret_cast<const VecN<double, 2>*>(P.q + off);
 #pragma unroll
-            for (int i = 0; i < 2; ++i) acc2 += wgt * double(o.v[i]) * qv.v[i];
+            for (int i = 0; i < 2; ++i) acc2 += wgt * double(o.v[i]) * qv[s].v[i];
           }
         }
       }
@@ -1473,7 +1517,11 @@ static int launch_cg_ch_cfg(const OpDesc& A, const ZT* z, const double* p_old, d
   P.tiles = P.wstrips * P.rgroups;
   const int wpb = kStreamTPB / 64;
   const int blocks = std::min((P.tiles + wpb - 1) / wpb, kStreamMaxBlocks);
-  hipLaunchKernelGGL((k_cg_ch<RPW, ZT, WAVES>), dim3(blocks), dim3(kStreamTPB), 0, st, P);
+  if (first)
+    hipLaunchKernelGGL((k_cg_ch<RPW, ZT, WAVES, true>), dim3(blocks), dim3(kStreamTPB), 0, st, P);
+  else
+    hipLaunchKernelGGL((k_cg_ch<RPW, ZT, WAVES, false>), dim3(blocks), dim3(kStreamTPB), 0, st,
+                       P);
   return blocks;
 }
 
@@ -1586,13 +1634,24 @@ bool smooth3r_ok(int n, int elem_bytes) {
   return !off && elem_bytes == 4 && smooth3_ok(n);
 }
 
+// Tile height of the fused float32 smoother passes on the small levels, where
+// a launch has few wavefronts and its time is one wavefront's instruction
+// chain: 2 rows on levels up to 512^2 (4096^2 mixed V-cycle 490.5 us against
+// 498.6 with 8 rows everywhere; 4 rows, or 2 rows up to 1024^2, 492-494).
+// BF_SMALL_RPW (2, 4 or 8) and BF_SMALL_N override the height and the level.
+static int small_level_rpw(int n, int dflt) {
+  static const int rpw = env_int("BF_SMALL_RPW", 2);
+  static const int small_n = env_int("BF_SMALL_N", 512);
+  if (n <= small_n && (rpw == 2 || rpw == 4 || rpw == 8)) return rpw;
+  return dflt;
+}
+
 template <typename T>
 void stream_smooth3_resid(const OpDesc& A, const T* b, T* xout, T* r, double a0, double a1,
                           double g1, double a2, double g2, hipStream_t st) {
   // 8 output rows per tile: the stage-two and -three halo rows are shared by
   // more outputs (measured on the 4096^2 mixed step: 19.18 ms with 8, 19.29-19.36
   // with 6, 19.40-19.42 with 4, 19.64 with 3)
-  constexpr int RPW = 8;
   Smooth3RArgs<T> P;
   P.A = A;
   P.b = b;
@@ -1603,17 +1662,28 @@ void stream_smooth3_resid(const OpDesc& A, const T* b, T* xout, T* r, double a0,
   P.g1 = g1;
   P.a2 = a2;
   P.g2 = g2;
+  const int rpw = small_level_rpw(A.n, 8);
   P.wstrips = (A.n + kS3RCols - 1) / kS3RCols;
-  P.rgroups = (A.n + 1 + RPW - 1) / RPW;
+  P.rgroups = (A.n + 1 + rpw - 1) / rpw;
   P.tiles = grouped_tiles(P.wstrips, P.rgroups);
   const int wpb = kStreamTPB / 64;
   const int blocks = std::min((P.tiles + wpb - 1) / wpb, kStreamMaxBlocks);
-  if (A.op == 0)
-    hipLaunchKernelGGL((k_smooth3r<0, RPW, T>), dim3(blocks), dim3(kStreamTPB), 0, st, P);
-  else if (A.op == 2)
-    hipLaunchKernelGGL((k_smooth3r<2, RPW, T>), dim3(blocks), dim3(kStreamTPB), 0, st, P);
+#define BF_S3R_GO(RPW_)                                                                     \
+  do {                                                                                     \
+    if (A.op == 0)                                                                         \
+      hipLaunchKernelGGL((k_smooth3r<0, RPW_, T>), dim3(blocks), dim3(kStreamTPB), 0, st, P); \
+    else if (A.op == 2)                                                                    \
+      hipLaunchKernelGGL((k_smooth3r<2, RPW_, T>), dim3(blocks), dim3(kStreamTPB), 0, st, P); \
+    else                                                                                   \
+      hipLaunchKernelGGL((k_smooth3r<1, RPW_, T>), dim3(blocks), dim3(kStreamTPB), 0, st, P); \
+  } while (0)
+  if (rpw == 2)
+    BF_S3R_GO(2);
+  else if (rpw == 4)
+    BF_S3R_GO(4);
   else
-    hipLaunchKernelGGL((k_smooth3r<1, RPW, T>), dim3(blocks), dim3(kStreamTPB), 0, st, P);
+    BF_S3R_GO(8);
+#undef BF_S3R_GO
 }
 template void stream_smooth3_resid<float>(const OpDesc&, const float*, float*, float*, double,
                                           double, double, double, double, hipStream_t);
@@ -1803,7 +1873,9 @@ static int post_launch(const OpDesc& A, int degree, const T* x, const T* e, cons
   if constexpr (sizeof(T) == 8) {
     return post_launch_rpw<EP, 2>(A, degree, x, e, b, q, out, a, g, partials, st);
   } else {
-    static const int rpw = env_int("BF_POST_RPW", 8);
+    static const int rpw_env = env_int("BF_POST_RPW", 8);
+    const int rpw = small_level_rpw(A.n, rpw_env);
+    if (rpw == 2) return post_launch_rpw<EP, 2>(A, degree, x, e, b, q, out, a, g, partials, st);
     if (rpw == 4) return post_launch_rpw<EP, 4>(A, degree, x, e, b, q, out, a, g, partials, st);
     if (rpw == 6) return post_launch_rpw<EP, 6>(A, degree, x, e, b, q, out, a, g, partials, st);
     return post_launch_rpw<EP, 8>(A, degree, x, e, b, q, out, a, g, partials, st);

@@ -233,61 +233,105 @@ __global__ void __launch_bounds__(kStreamTPB) k_stream(StreamArgs<T, TO> P) {
     const int c = strip * (64 * V) + V * lane;
     const int hcol = hl ? ((c - V) & mask) : ((c + V) & mask);
 
-    auto load_row = [&](const T* base, int jr, bool halo, XRow<T, V>& r) {
-      const T* row = base + (int64_t)jr * n;
-      const VT v = *reinterpret_cast<const VT*>(row + c);
+    // Every load of the tile is issued before any value is used, so that
+    // their latencies overlap (a load followed by its use in the same loop
+    // iteration makes the wavefront wait for each row in turn): the window
+    // rows j0-R .. jl+R (reflected; the rows a short last tile does not reach
+    // repeat row jl+R: they are no output's neighbour and leave the window's
+    // largest magnitude unchanged), then the halo columns of lanes 0 and 63
+    // (rows 1 .. NR-2 of the window, the centre or vertical neighbours of an
+    // output, in one lane-divergent block), then the epilogue's inputs at the
+    // output rows (clamped to the last row; rows past it are not stored).
+    int jrw[NR];
 #pragma unroll
-      for (int i = 0; i < V; ++i) r.o[i] = v.v[i];
-      r.h0 = r.h1 = T(0);
-      if (halo && (hl || hr)) {
-        const VT h = *reinterpret_cast<const VT*>(row + hcol);
-        r.h0 = hl ? h.v[V - 2] : h.v[0];
-        r.h1 = hl ? h.v[V - 1] : h.v[1];
-      }
-    };
-
-    // input rows j0 - R .. jl + R (reflected); rows 1 .. NR-2 of the window
-    // are centre or vertical neighbours of an output and need their halo
+    for (int k = 0; k < NR; ++k) jrw[k] = refl(min(j0 - R + k, jl + R), n);
+    const bool cg_beta = CGP && !P.first;
     XRow<T, V> xr[NR];
+    XRow<T, V> po[CGP ? NR : 1];
 #pragma unroll
     for (int k = 0; k < NR; ++k) {
-      const int jj = j0 - R + k;
-      const bool halo = k >= 1 && k <= NR - 2;
-      if (jj > jl + R) {
-#pragma unroll
-        for (int i = 0; i < V; ++i) xr[k].o[i] = T(0);
-        xr[k].h0 = xr[k].h1 = T(0);
-        continue;
-      }
-      const int jr = refl(jj, n);
       if constexpr (EPI == E_CG_P32) {
-        // z in float32: the lane's V values (8 bytes) and, on lanes 0 and 63,
-        // the two columns beyond the wavefront's edge, widened to T
-        const float* zr = P.z32 + ioff + (int64_t)jr * n;
-        const float2 zv = *reinterpret_cast<const float2*>(zr + c);
+        // z in float32 (8 bytes per lane), widened to T
+        const float2 zv = *reinterpret_cast<const float2*>(P.z32 + ioff + (int64_t)jrw[k] * n + c);
         xr[k].o[0] = T(zv.x);
         xr[k].o[1] = T(zv.y);
-        xr[k].h0 = xr[k].h1 = T(0);
-        if (halo && (hl || hr)) {
-          const float2 zh = *reinterpret_cast<const float2*>(zr + hcol);
+      } else {
+        const VT v = *reinterpret_cast<const VT*>(Xp + (int64_t)jrw[k] * n + c);
+#pragma unroll
+        for (int i = 0; i < V; ++i) xr[k].o[i] = v.v[i];
+      }
+      xr[k].h0 = xr[k].h1 = T(0);
+    }
+    if constexpr (CGP) {
+      if (cg_beta) {
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {
+          const VT v = *reinterpret_cast<const VT*>(XPp + (int64_t)jrw[k] * n + c);
+#pragma unroll
+          for (int i = 0; i < V; ++i) po[k].o[i] = v.v[i];
+          po[k].h0 = po[k].h1 = T(0);
+        }
+      }
+    }
+    // lane 0 holds columns c-2, c-1 and lane 63 columns c+2, c+3 in h0, h1
+    if (hl || hr) {
+#pragma unroll
+      for (int k = 1; k < NR - 1; ++k) {
+        if constexpr (EPI == E_CG_P32) {
+          const float2 zh =
+              *reinterpret_cast<const float2*>(P.z32 + ioff + (int64_t)jrw[k] * n + hcol);
           xr[k].h0 = T(zh.x);
           xr[k].h1 = T(zh.y);
+        } else {
+          const VT h = *reinterpret_cast<const VT*>(Xp + (int64_t)jrw[k] * n + hcol);
+          xr[k].h0 = h.v[0];
+          xr[k].h1 = h.v[1];
         }
-      } else {
-        load_row(Xp, jr, halo, xr[k]);
+        if constexpr (CGP) {
+          if (cg_beta) {
+            const VT h = *reinterpret_cast<const VT*>(XPp + (int64_t)jrw[k] * n + hcol);
+            po[k].h0 = h.v[0];
+            po[k].h1 = h.v[1];
+          }
+        }
       }
-      if constexpr (CGP) {
-        if (!P.first) {
-          XRow<T, V> po;
-          load_row(XPp, jr, halo, po);
+    }
+    constexpr bool DOT2Q = EPI == E_SMOOTH_DOT2;
+    VT bo[NEEDB ? RPW : 1], pco[NEEDP ? RPW : 1] = {};
+    VecN<double, V> qo[DOT2Q ? RPW : 1], xo[CGP ? RPW : 1];
 #pragma unroll
-          for (int i = 0; i < V; ++i) xr[k].o[i] += beta * po.o[i];
-          xr[k].h0 += beta * po.h0;
-          xr[k].h1 += beta * po.h1;
+    for (int s = 0; s < RPW; ++s) {
+      const int64_t o = (int64_t)min(j0 + s, jl) * n + c;
+      if constexpr (NEEDB) bo[s] = *reinterpret_cast<const VT*>(Bp + o);
+      if constexpr (DOT2Q) qo[s] = *reinterpret_cast<const VecN<double, V>*>(Qp + o);
+    }
+    if constexpr (NEEDP) {
+      if (XPp) {
+#pragma unroll
+        for (int s = 0; s < RPW; ++s)
+          pco[s] = *reinterpret_cast<const VT*>(XPp + (int64_t)min(j0 + s, jl) * n + c);
+      }
+    }
+    if constexpr (CGP) {
+      if (cg_beta) {
+#pragma unroll
+        for (int s = 0; s < RPW; ++s)
+          xo[s] = *reinterpret_cast<const VecN<double, V>*>(XUp + (int64_t)min(j0 + s, jl) * n + c);
+      }
+    }
+    // p' = z + beta p_old (CG step); x1 = a0 D^{-1} b (first sweep from zero)
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+      if constexpr (CGP) {
+        if (cg_beta) {
+#pragma unroll
+          for (int i = 0; i < V; ++i) xr[k].o[i] += beta * po[k].o[i];
+          xr[k].h0 += beta * po[k].h0;
+          xr[k].h1 += beta * po[k].h1;
         }
       }
       if constexpr (EPI == E_SMOOTH_XB) {
-        const T sc = ca0 * dinv_row(jr);
+        const T sc = ca0 * dinv_row(jrw[k]);
 #pragma unroll
         for (int i = 0; i < V; ++i) xr[k].o[i] *= sc;
         xr[k].h0 *= sc;
@@ -393,10 +437,8 @@ __global__ void __launch_bounds__(kStreamTPB) k_stream(StreamArgs<T, TO> P) {
       const double cfj = row_coef<OP>(cf, j, n);
       const T coefj = (OP == 2 && (j == 0 || j == n)) ? T(0) : tcoef;
       VT bcur{}, pcur{};
-      if constexpr (NEEDB) bcur = *reinterpret_cast<const VT*>(Bp + o);
-      if constexpr (NEEDP) {
-        if (XPp) pcur = *reinterpret_cast<const VT*>(XPp + o);
-      }
+      if constexpr (NEEDB) bcur = bo[s];
+      if constexpr (NEEDP) pcur = pco[s];
       VO res;
       if constexpr (EPI == E_APPLY || EPI == E_APPLY_DOT) {
 #pragma unroll
@@ -429,9 +471,8 @@ __global__ void __launch_bounds__(kStreamTPB) k_stream(StreamArgs<T, TO> P) {
             acc += wgt * double(bcur.v[i]) * double(TO(xn));
         }
         if constexpr (EPI == E_SMOOTH_DOT2) {
-          const VecN<double, V> qv = *reinterpret_cast<const VecN<double, V>*>(Qp + o);
 #pragma unroll
-          for (int i = 0; i < V; ++i) acc2 += wgt * double(res.v[i]) * qv.v[i];
+          for (int i = 0; i < V; ++i) acc2 += wgt * double(res.v[i]) * qo[s].v[i];
         }
       } else if constexpr (std::is_same<T, double>::value) {
         if constexpr (EPI == E_APPLY_DOT_DD) {
@@ -461,11 +502,11 @@ __global__ void __launch_bounds__(kStreamTPB) k_stream(StreamArgs<T, TO> P) {
             }
           }
           store_nt(reinterpret_cast<VecN<double, V>*>(O2p + o), pn);
-          if (!P.first) {
-            const VecN<double, V> po = *reinterpret_cast<const VecN<double, V>*>(XPp + o);
-            VecN<double, V> xv = *reinterpret_cast<const VecN<double, V>*>(XUp + o);
+          if (cg_beta) {
+            // the deferred x += alpha_prev p_old (p_old of this row: window row k)
+            VecN<double, V> xv = xo[s];
 #pragma unroll
-            for (int i = 0; i < V; ++i) xv.v[i] += alpha_prev * po.v[i];
+            for (int i = 0; i < V; ++i) xv.v[i] += alpha_prev * double(po[k].o[i]);
             store_nt(reinterpret_cast<VecN<double, V>*>(XUp + o), xv);
           }
         } else if constexpr (EPI == E_RESID_DD) {

@@ -78,28 +78,37 @@ __global__ void __launch_bounds__(kTPB) k_restrict_tile(TArgs A, const T* __rest
     const int Jl = min(J0 + kCR, nc + 1) - 1;
     const int c = strip * 256 + 4 * lane;  // fine columns c .. c+3
     const int hcol = hl ? ((c - 4) & fmask) : ((c + 4) & fmask);
+    // every load of the tile first (their latencies overlap): the fine rows
+    // 2 J0 - 3 .. 2 Jl + 3 (reflected; rows a short last tile does not reach
+    // repeat row 2 Jl + 3 and are unused), then the halo columns of lanes 0
+    // and 63 (lane 0: columns c-3, c-1; lane 63: column c+5)
+    Vec<T, 4> fo[NF];
+    T e0[NF], e1[NF];
+#pragma unroll
+    for (int k = 0; k < NF; ++k) {
+      const T* row = fine + (int64_t)refl(min(2 * J0 - 3 + k, 2 * Jl + 3), nf) * nf;
+      fo[k] = *reinterpret_cast<const Vec<T, 4>*>(row + c);
+      e0[k] = e1[k] = T(0);
+    }
+    if (hl || hr) {
+#pragma unroll
+      for (int k = 0; k < NF; ++k) {
+        const T* row = fine + (int64_t)refl(min(2 * J0 - 3 + k, 2 * Jl + 3), nf) * nf;
+        const Vec<T, 4> hv = *reinterpret_cast<const Vec<T, 4>*>(row + hcol);
+        e0[k] = hv.v[1];
+        e1[k] = hv.v[3];
+      }
+    }
     T rs0[NF], rs1[NF];
 #pragma unroll
     for (int k = 0; k < NF; ++k) {
-      const int f = 2 * J0 - 3 + k;
-      if (f > 2 * Jl + 3) {
-        rs0[k] = rs1[k] = T(0);
-        continue;
-      }
-      const T* row = fine + (int64_t)refl(f, nf) * nf;
-      const Vec<T, 4> o = *reinterpret_cast<const Vec<T, 4>*>(row + c);
-      T e0 = T(0), e1 = T(0);  // lane 0: columns c-3, c-1; lane 63: column c+5
-      if (hl || hr) {
-        const Vec<T, 4> hv = *reinterpret_cast<const Vec<T, 4>*>(row + hcol);
-        e0 = hv.v[1];
-        e1 = hv.v[3];
-      }
+      const Vec<T, 4>& o = fo[k];
       T l1 = shl_in(o.v[3]), l3 = shl_in(o.v[1]), r5 = shr_in(o.v[1]);
       if (hl) {
-        l3 = e0;
-        l1 = e1;
+        l3 = e0[k];
+        l1 = e1[k];
       }
-      if (hr) r5 = e0;
+      if (hr) r5 = e0[k];
       rs0[k] = h * o.v[0] + w1 * (l1 + o.v[1]) + w3 * (l3 + o.v[3]);
       rs1[k] = h * o.v[2] + w1 * (o.v[1] + o.v[3]) + w3 * (l1 + r5);
     }
@@ -141,28 +150,41 @@ __global__ void __launch_bounds__(kTPB) k_prolong_tile(TArgs A, const T* __restr
     const int c = strip * 256 + 4 * lane;  // fine columns c .. c+3
     const int I0 = c / 2;
     const int hcol = hl ? ((I0 - 2) & cmask) : ((I0 + 2) & cmask);
+    // every load of the tile first (their latencies overlap): the coarse rows
+    // J0-1 .. Jl+2 (reflected; rows a short last tile does not reach repeat
+    // row Jl+2 and are unused), the halo columns of lanes 0 and 63 (lane 0:
+    // I0-2, I0-1; lane 63: I1+1, I1+2), and the fine rows the tile updates
+    // (clamped to valid rows; rows past the tile are not stored)
+    Vec<T, 2> eo[NC];
+    T g0[NC], g1[NC];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+      const T* row = coarse + (int64_t)refl(min(J0 - 1 + k, Jl + 2), nc) * nc;
+      eo[k] = *reinterpret_cast<const Vec<T, 2>*>(row + I0);
+      g0[k] = g1[k] = T(0);
+    }
+    if (hl || hr) {
+#pragma unroll
+      for (int k = 0; k < NC; ++k) {
+        const T* row = coarse + (int64_t)refl(min(J0 - 1 + k, Jl + 2), nc) * nc;
+        const Vec<T, 2> hv = *reinterpret_cast<const Vec<T, 2>*>(row + hcol);
+        g0[k] = hv.v[0];
+        g1[k] = hv.v[1];
+      }
+    }
+    Vec<T, 4> fv[2 * kCR];
+#pragma unroll
+    for (int r = 0; r < 2 * kCR; ++r)
+      fv[r] = *reinterpret_cast<const Vec<T, 4>*>(fine + (int64_t)min(2 * J0 + r, nf) * nf + c);
     T tx[NC][4];
 #pragma unroll
     for (int k = 0; k < NC; ++k) {
-      const int J = J0 - 1 + k;
-      if (J > Jl + 2) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) tx[k][i] = T(0);
-        continue;
-      }
-      const T* row = coarse + (int64_t)refl(J, nc) * nc;
-      const Vec<T, 2> e = *reinterpret_cast<const Vec<T, 2>*>(row + I0);
-      T g0 = T(0), g1 = T(0);  // lane 0: I0-2, I0-1; lane 63: I1+1, I1+2
-      if (hl || hr) {
-        const Vec<T, 2> hv = *reinterpret_cast<const Vec<T, 2>*>(row + hcol);
-        g0 = hv.v[0];
-        g1 = hv.v[1];
-      }
+      const Vec<T, 2>& e = eo[k];
       T em1 = shl_in(e.v[1]), ep2 = shr_in(e.v[0]), ep3 = shr_in(e.v[1]);
-      if (hl) em1 = g1;
+      if (hl) em1 = g1[k];
       if (hr) {
-        ep2 = g0;
-        ep3 = g1;
+        ep2 = g0[k];
+        ep3 = g1[k];
       }
       tx[k][0] = e.v[0];
       tx[k][1] = (-em1 + k9 * e.v[0] + k9 * e.v[1] - ep2) * k16;
@@ -176,14 +198,14 @@ __global__ void __launch_bounds__(kTPB) k_prolong_tile(TArgs A, const T* __restr
       const int k = s + 1;  // index of coarse row J
       {
         Vec<T, 4>* dst = reinterpret_cast<Vec<T, 4>*>(fine + (int64_t)(2 * J) * nf + c);
-        Vec<T, 4> v = *dst;
+        Vec<T, 4> v = fv[2 * s];
 #pragma unroll
         for (int i = 0; i < 4; ++i) v.v[i] += tx[k][i];
         *dst = v;
       }
       if (2 * J + 1 <= nf) {
         Vec<T, 4>* dst = reinterpret_cast<Vec<T, 4>*>(fine + (int64_t)(2 * J + 1) * nf + c);
-        Vec<T, 4> v = *dst;
+        Vec<T, 4> v = fv[2 * s + 1];
 #pragma unroll
         for (int i = 0; i < 4; ++i)
           v.v[i] += (-tx[k - 1][i] + k9 * tx[k][i] + k9 * tx[k + 1][i] - tx[k + 2][i]) * k16;

@@ -102,7 +102,7 @@ struct bf_grid {
   int32_t* counter = nullptr;
   double* h_scal = nullptr;   // pinned host mirror of scalars
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
-  hipEvent_t ev_scal = nullptr;  // marks the arrival of an asynchronous scalar copy
+  hipEvent_t ev_scal = nullptr;  // marks the arrival of ||r||^2 in the pinned host scalars
   // Captured V-cycles (one hipGraphExec per operator / coefficient / options /
   // input buffer), replayed with a single launch; captured on cap_stream.
   struct VcGraph {
@@ -830,14 +830,9 @@ int read_scalars(bf_grid* g, int count) {
   return BF_OK;
 }
 
-// Split form of read_scalars: queue the copy now, wait for its arrival later
-// (work queued in between keeps the GPU busy while the host waits).
-int copy_scalars_async(bf_grid* g, int count) {
-  HIPCHK(hipMemcpyAsync(g->h_scal, g->scal, sizeof(double) * count, hipMemcpyDeviceToHost,
-                        g->stream));
-  HIPCHK(hipEventRecord(g->ev_scal, g->stream));
-  return BF_OK;
-}
+// Wait for the event recorded after a finalize that also wrote its value into
+// the pinned host scalars (work queued in between keeps the GPU busy while
+// the host waits).
 int wait_scalars(bf_grid* g) {
   HIPCHK(hipEventSynchronize(g->ev_scal));
   return BF_OK;
@@ -1020,12 +1015,13 @@ int run_cg(bf_grid* g, int op, double c, const double* b, double* x, const bf_so
       first = false;
       pending = true;
       launch_r_update(g->n, g->r, g->q, g->scal, g->partials, np, st, mixed ? g->r32 : nullptr);
-      launch_finalize(g->partials, np, g->scal, F_STORE, S_RR, g->n, st);
+      // ||r||^2 also lands in the pinned host scalars: an event then says it arrived
+      launch_finalize(g->partials, np, g->scal, F_STORE, S_RR, g->n, st, g->h_scal);
       ks.iters++;
       ks.x_updates++;
       bool deferred = false;
       if (ks.iters % o.check_every == 0 || ks.iters == o.maxit) {
-        TRY(copy_scalars_async(g, S_RR + 1));
+        HIPCHK(hipEventRecord(g->ev_scal, st));
         deferred = ks.iters < o.maxit && nt.predict(ks.iters) > 4.0 * o.rtol;
         if (!deferred) {
           TRY(wait_scalars(g));

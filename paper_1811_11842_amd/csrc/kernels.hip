@@ -307,14 +307,20 @@ __device__ __forceinline__ double fin_sum(const double* __restrict__ p, int npar
   return block_sum_n<kFinTPB>((a0 + a1) + (a2 + a3));
 }
 
+// host (optional, F_STORE): pinned host memory that also receives the value,
+// so that the host reads it after an event instead of a separate copy.
 __global__ void __launch_bounds__(kFinTPB) k_finalize(const double* __restrict__ partials, int nparts,
                                                       double* __restrict__ scal, int mode, int slot,
-                                                      double nn) {
+                                                      double nn, double* __restrict__ host) {
   const double s = fin_sum(partials, nparts);
   if (threadIdx.x == 0) {
     switch (mode) {
       case F_STORE:
         scal[slot] = s;
+        if (host) {
+          host[slot] = s;
+          __threadfence_system();
+        }
         break;
       case F_ALPHA:
         scal[S_PQ] = s;
@@ -1173,9 +1179,9 @@ void launch_residual_norms(const double* scal, double csq, double* out, hipStrea
 }
 
 void launch_finalize(const double* partials, int nparts, double* scal, int mode, int slot, int n,
-                     hipStream_t st) {
+                     hipStream_t st, double* host) {
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFinTPB), 0, st, partials, nparts, scal, mode, slot,
-                     (double)n * (double)n);
+                     (double)n * (double)n, host);
 }
 
 int launch_cg_p(const OpDesc& A, const double* z, const double* p_old, double* p_new, double* q,

@@ -91,24 +91,153 @@ __device__ __forceinline__ Nb13T<T> tail_gather(const T* x, int i, int j, int n,
   return v;
 }
 
-// xout = x + a D^{-1} (b - A x) + g (x - xprev)  (xprev < 0: no xprev term)
+// The 64 x 64 level (65 rows) with each thread on four consecutive rows of
+// one column (rows 4 w .. 4 w + 3 for wavefront w; the last wavefront also
+// takes row 64): the column's values of the rows in reach are read from LDS
+// once into registers and shared by the thread's nodes, 7 reads per node
+// instead of 13 for the 13-point stencil.  scale(jr) multiplies every value
+// read from row jr (the first iterate formed from b); f(j, idx, v) receives
+// each node's stencil values.
+template <int OP, typename T, typename S, typename F>
+__device__ __forceinline__ void for_nodes64(const T* X, S scale, F f) {
+  constexpr int n = 64, lg = 6;
+  const int i = threadIdx.x & (n - 1);
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> lg));
+  const int j0 = 4 * w;
+  const int nr = w == (kTailThreads >> lg) - 1 ? 5 : 4;
+  const int im1 = (i - 1) & (n - 1), ip1 = (i + 1) & (n - 1);
+  const int im2 = (i - 2) & (n - 1), ip2 = (i + 2) & (n - 1);
+  constexpr int R = OP == 1 ? 2 : 1;
+  // column i: rows j0-R .. j0+nr-1+R; columns i-1, i+1: rows j0-1 .. j0+nr (OP 1)
+  // or j0 .. j0+nr-1; columns i-2, i+2: rows j0 .. j0+nr-1 (OP 1)
+  T cc[5 + 2 * R], cm1[7], cp1[7], cm2[5], cp2[5];
+#pragma unroll
+  for (int r = 0; r < 5 + 2 * R; ++r) {
+    if (r < nr + 2 * R) {
+      const int jr = refl(j0 - R + r, n);
+      cc[r] = X[(jr << lg) + i] * scale(jr);
+    }
+  }
+  constexpr int R1 = OP == 1 ? 1 : 0;
+#pragma unroll
+  for (int r = 0; r < 5 + 2 * R1; ++r) {
+    if (r < nr + 2 * R1) {
+      const int jr = refl(j0 - R1 + r, n);
+      const T sc = scale(jr);
+      cm1[r] = X[(jr << lg) + im1] * sc;
+      cp1[r] = X[(jr << lg) + ip1] * sc;
+    }
+  }
+  if constexpr (OP == 1) {
+#pragma unroll
+    for (int r = 0; r < 5; ++r) {
+      if (r < nr) {
+        const int jr = j0 + r;
+        const T sc = scale(jr);
+        cm2[r] = X[(jr << lg) + im2] * sc;
+        cp2[r] = X[(jr << lg) + ip2] * sc;
+      }
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < 5; ++s) {
+    if (s < nr) {
+      Nb13T<T> v;
+      v.c = cc[s + R];
+      v.ym1 = cc[s + R - 1];
+      v.yp1 = cc[s + R + 1];
+      v.xm1 = cm1[s + R1];
+      v.xp1 = cp1[s + R1];
+      if constexpr (OP == 1) {
+        v.ym2 = cc[s];
+        v.yp2 = cc[s + 4];
+        v.dmm = cm1[s];
+        v.dmp = cp1[s];
+        v.dpm = cm1[s + 2];
+        v.dpp = cp1[s + 2];
+        v.xm2 = cm2[s];
+        v.xp2 = cp2[s];
+      }
+      const int j = j0 + s;
+      f(j, (j << lg) + i, v);
+    }
+  }
+}
+
+// xout = x + a D^{-1} (b - A x) + g (x - xprev)  (xprev = -1: no xprev term;
+// xprev = kPrevFromB: xprev is the first iterate a0 D^{-1} b, formed from b)
+constexpr int kPrevFromB = -2;
 template <int OP, typename T>
 __device__ void tail_sweep(T* lds, const TailLevel& L, int x, int xprev, int b, int xout,
                            double a, double g) {
   const int n = L.n, lg = log2_of(n);
   const T ta = T(a), tg = T(g);
-  const bool hp = xprev >= 0;
+  const bool hp = xprev >= 0, pb = xprev == kPrevFromB;
   const T* X = lds + x;
   const T* XP = lds + (hp ? xprev : x);
   const T* B = lds + b;
   T* O = lds + xout;
-  for_nodes(n, lg, [&](int j, int i) {
-    const int idx = (j << lg) + i;
-    const Nb13T<T> v = tail_gather<OP>(X, i, j, n, lg);
+  auto node = [&](int j, int idx, const Nb13T<T>& v) {
     const T ax = apply_vals<OP>(v, T(row_coef<OP>(L.coef, j, n)));
     const T ad = ta * T(row_dinv<OP>(L.dinv_int, L.dinv_edge, j, n));
-    const T prev = hp ? XP[idx] : T(0);
+    const T prev = hp ? XP[idx]
+                      : pb ? T(L.a[0] * row_dinv<OP>(L.dinv_int, L.dinv_edge, j, n)) * B[idx]
+                           : T(0);
     O[idx] = v.c + ad * (B[idx] - ax) + tg * (v.c - prev);
+  };
+  if (n == 64) {
+    for_nodes64<OP, T>(X, [](int) { return T(1); }, node);
+  } else {
+    for_nodes(n, lg, [&](int j, int i) {
+      const int idx = (j << lg) + i;
+      node(j, idx, tail_gather<OP>(X, i, j, n, lg));
+    });
+  }
+  __syncthreads();
+}
+
+// The first sweep from a zero iterate, x2 = x1 + a1 D^{-1} (b - A x1) + g1 x1,
+// with x1 = a0 D^{-1} b formed where it is read, which saves the phase that
+// would store x1 (the products may be contracted into the stencil's sums, so
+// the result can differ from the stored-x1 form by rounding).
+template <int OP, typename T>
+__device__ void tail_sweep_from_b(T* lds, const TailLevel& L, int b, int xout) {
+  const int n = L.n, lg = log2_of(n);
+  const T a1 = T(L.a[1]), g1 = T(L.g[1]);
+  const T* B = lds + b;
+  T* O = lds + xout;
+  auto x1 = [&](int jr) -> T { return T(L.a[0] * row_dinv<OP>(L.dinv_int, L.dinv_edge, jr, n)); };
+  auto node = [&](int j, int idx, const Nb13T<T>& v) {
+    const T ax = apply_vals<OP>(v, T(row_coef<OP>(L.coef, j, n)));
+    const T ad = a1 * T(row_dinv<OP>(L.dinv_int, L.dinv_edge, j, n));
+    O[idx] = v.c + ad * (B[idx] - ax) + g1 * v.c;
+  };
+  if (n == 64) {
+    for_nodes64<OP, T>(B, x1, node);
+    __syncthreads();
+    return;
+  }
+  for_nodes(n, lg, [&](int j, int i) {
+    const int idx = (j << lg) + i;
+    Nb13T<T> v = tail_gather<OP>(B, i, j, n, lg);
+    const T s0 = x1(j), sm1 = x1(refl(j - 1, n)), sp1 = x1(refl(j + 1, n));
+    v.c *= s0;
+    v.xm1 *= s0;
+    v.xp1 *= s0;
+    v.ym1 *= sm1;
+    v.yp1 *= sp1;
+    if (OP == 1) {
+      const T sm2 = x1(refl(j - 2, n)), sp2 = x1(refl(j + 2, n));
+      v.xm2 *= s0;
+      v.xp2 *= s0;
+      v.dmm *= sm1;
+      v.dmp *= sm1;
+      v.dpm *= sp1;
+      v.dpp *= sp1;
+      v.ym2 *= sm2;
+      v.yp2 *= sp2;
+    }
+    node(j, idx, v);
   });
   __syncthreads();
 }
@@ -130,11 +259,18 @@ __device__ void tail_body(const TailArgs& P, const T* b_in, T* x_out) {
   const int xc = off;       // coarsest x (20)
   const int bc = off + 20;  // coarsest b (20)
 
-  // right-hand side of the top tail level
+  // right-hand side of the top tail level: every thread's loads issued
+  // together (clamped to the field), then stored to LDS
   {
     const int npts = (P.lev[0].n + 1) * P.lev[0].n;
     T* B = lds + bb[0];
-    for (int idx = tid; idx < npts; idx += kTailThreads) B[idx] = b_in[idx];
+    constexpr int kPer = (65 * 64 + kTailThreads - 1) / kTailThreads;
+    T v[kPer];
+#pragma unroll
+    for (int r = 0; r < kPer; ++r) v[r] = b_in[min(tid + r * kTailThreads, npts - 1)];
+#pragma unroll
+    for (int r = 0; r < kPer; ++r)
+      if (tid + r * kTailThreads < npts) B[tid + r * kTailThreads] = v[r];
   }
   __syncthreads();
 
@@ -146,32 +282,44 @@ __device__ void tail_body(const TailArgs& P, const T* b_in, T* x_out) {
     const int n = L.n, lg = log2_of(n);
     int cur = xa[l];
     int o = xb[l];
-    {
+    if (L.degree >= 2) {
+      // x1 = a0 D^{-1} b is never stored: the first sweep and (as x_prev) the
+      // second form it from b (64 x 64 tail level with CH, float32: 43 -> 37 us)
+      tail_sweep_from_b<OP, T>(lds, L, bb[l], o);
+      cur = xb[l];
+      o = xa[l];
+      for (int k = 2; k < L.degree; ++k) {
+        const int prev = L.g[k] == 0.0 ? -1 : (k == 2 ? kPrevFromB : o);
+        tail_sweep<OP, T>(lds, L, cur, prev, bb[l], o, L.a[k], L.g[k]);
+        const int t = cur;
+        cur = o;
+        o = t;
+      }
+    } else {
       T* C = lds + cur;
       const T* B = lds + bb[l];
       for_nodes(n, lg, [&](int j, int i) {
         const int idx = (j << lg) + i;
         C[idx] = T(L.a[0] * row_dinv<OP>(L.dinv_int, L.dinv_edge, j, n)) * B[idx];
       });
-    }
-    __syncthreads();
-    for (int k = 1; k < L.degree; ++k) {
-      tail_sweep<OP, T>(lds, L, cur, (k == 1 || L.g[k] == 0.0) ? -1 : o, bb[l], o, L.a[k],
-                        L.g[k]);
-      const int t = cur;
-      cur = o;
-      o = t;
+      __syncthreads();
     }
     // residual, into the iterate buffer the sweeps are done with
     {
       const T* C = lds + cur;
       const T* B = lds + bb[l];
       T* R = lds + o;
-      for_nodes(n, lg, [&](int j, int i) {
-        const int idx = (j << lg) + i;
-        const Nb13T<T> v = tail_gather<OP>(C, i, j, n, lg);
+      auto node = [&](int j, int idx, const Nb13T<T>& v) {
         R[idx] = B[idx] - apply_vals<OP>(v, T(row_coef<OP>(L.coef, j, n)));
-      });
+      };
+      if (n == 64) {
+        for_nodes64<OP, T>(C, [](int) { return T(1); }, node);
+      } else {
+        for_nodes(n, lg, [&](int j, int i) {
+          const int idx = (j << lg) + i;
+          node(j, idx, tail_gather<OP>(C, i, j, n, lg));
+        });
+      }
     }
     __syncthreads();
     // restriction to the next level (or to the coarsest grid)

@@ -1895,11 +1895,18 @@ int stream_smooth_last2_dot2_f32(const OpDesc& A, const float* x1, const float* 
 // off.
 bool post_ok(int n, int op, int degree, double g0, int elem_bytes) {
   static const bool off = env_int("BF_NO_POST", 0) != 0;
-  // float64 levels up to 2048 (at 4096^2 the float64 window leaves one
-  // wavefront per SIMD: 280 us against 254 for the three separate passes)
-  static const int f64_max = env_int("BF_POST_F64_MAX", 2048);
+  // float64: the 13-point operator's three-sweep window takes 230-260
+  // registers (two rows per tile), so from 2048^2 up the separate passes are
+  // faster (4096^2 float64 CH V-cycle 717.7 us with this pass up to 1024^2,
+  // 730.0 up to 2048^2, 805.8 up to 4096^2); the 5-point operator's window is
+  // small enough at every size (Laplacian V-cycle 398.0 us with the pass on
+  // every level, 430.3 up to 2048^2).  BF_POST_F64_MAX / BF_POST_F64_MAX_LAP
+  // change the largest float64 level.
+  static const int f64_max_ch = env_int("BF_POST_F64_MAX", 1024);
+  static const int f64_max_lap = env_int("BF_POST_F64_MAX_LAP", 1 << 20);
   const BatchCtx& B = g_batch;
   const bool shape = (op == 1 && (degree == 2 || degree == 3)) || (op == 0 && degree == 2);
+  const int f64_max = op == 0 ? f64_max_lap : f64_max_ch;
   return !off && shape && n >= 128 && (elem_bytes == 4 || n <= f64_max) && g0 == 0.0 &&
          B.count <= 1 && !B.coef && !B.active;
 }

@@ -47,10 +47,11 @@ HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ["paper_1811_11842_amd/csrc/stream.hip", "paper_1811_11842_amd/csrc/stencil_ops.hpp",
                   "paper_1811_11842_amd/csrc/common.hpp"]
 # HBM traffic per launch at 4096^2 from `rocprofv3 --pmc FETCH_SIZE` / `--pmc WRITE_SIZE`
-# (profiles/spmv_13pt_4096_counters.md), KiB per dispatch, scaled by the ratio of known to
+# (profiles/spmv_13pt_4096_counters.md for the SpMV and the sweep,
+# profiles/step_kernels_4096_counters.md for the CG step), KiB per dispatch, scaled by the ratio of known to
 # counted bytes of the bf_copy calibration kernel.  Valid only for the kernel sources
 # whose sha256 is recorded; otherwise the traffic is reported as null.
-TRAFFIC_RECORD = {"n": 4096, "fetch_scale": 1.9996, "write_scale": 1.0, "kernels": {"spmv": {"fetch_kib": 69692.4, "write_kib": 131104.3}, "smooth": {"fetch_kib": 200820.4, "write_kib": 131104.0}}, "sources_sha256": "97dd6b63d1265fb35ae6076aa9ac6f3e2bd132a801c34bcd449fe731b5369684"}
+TRAFFIC_RECORD = {"n": 4096, "fetch_scale": 1.9996, "write_scale": 1.0, "kernels": {"spmv": {"fetch_kib": 69687.0, "write_kib": 131104.1}, "smooth": {"fetch_kib": 200787.6, "write_kib": 131104.0}, "cg_step": {"fetch_kib": 221330.9, "write_kib": 398788.0}}, "sources_sha256": "ab687f343d15f4f588cc6c6f41ac3b75ead51f93007b1bb8d517e8a32eaa6b3b"}
 
 
 def parse():

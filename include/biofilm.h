@@ -328,8 +328,10 @@ int bf_ensemble_info(const bf_ensemble* e, int32_t* nclasses, int32_t* class_n,
  * differ from the defaults (float64 CG with the default multigrid; others
  * return BF_EUNSUPPORTED); no refinement restarts.  stats[2 i] / stats[2 i + 1]
  * receive the Cahn-Hilliard / pressure solve of instance i.  ms (host, may be
- * NULL) receives the wall time of the call.  Synchronous.  Returns the worst
- * soft status or a negative error. */
+ * NULL) receives the device time of the step in milliseconds: HIP events on
+ * the caller's stream, from the marker every size class waits for before its
+ * first kernel to the marker that waits for every class's last one.
+ * Synchronous.  Returns the worst soft status or a negative error. */
 int bf_ensemble_step(bf_ensemble* e, const bf_params* prm, double* phi, const double* ustar,
                      const double* vstar, double* p, double* u, double* v,
                      const bf_solver_opts* ch, const bf_solver_opts* pr, bf_solve_stats* stats,

@@ -523,7 +523,7 @@ class Ensemble:
 
     def step(self, params, phi, ustar, vstar, p, u=None, v=None, ch=None, pr=None):
         """One step of every instance; params: list of Params (one per instance).
-        Returns ([(ch_stats, p_stats)] per instance, wall ms)."""
+        Returns ([(ch_stats, p_stats)] per instance, device ms of the step)."""
         if len(params) != self.count:
             raise ValueError("one Params per instance")
         prm = (Params * self.count)(*params)

@@ -295,6 +295,7 @@ struct bf_ensemble {
   std::vector<void*> allocs;
   std::vector<void*> host_allocs;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  hipEvent_t ev2 = nullptr;  // end of a step on the caller's stream (timed from ev0)
 };
 
 namespace {
@@ -929,7 +930,8 @@ int e_create(bf_ensemble* e, const int32_t* n, int count) {
     ECHK(hipStreamSynchronize(C.stream));
   }
   ECHK(hipEventCreate(&e->ev0));
-  ECHK(hipEventCreate(&e->ev1));
+  ECHK(hipEventCreateWithFlags(&e->ev1, hipEventDisableTiming));
+  ECHK(hipEventCreate(&e->ev2));
   return BF_OK;
 }
 
@@ -968,6 +970,7 @@ int bf_ensemble_destroy(bf_ensemble* e) {
   for (void* p : e->host_allocs) (void)hipHostFree(p);
   if (e->ev0) (void)hipEventDestroy(e->ev0);
   if (e->ev1) (void)hipEventDestroy(e->ev1);
+  if (e->ev2) (void)hipEventDestroy(e->ev2);
   delete e;
   return BF_OK;
 }
@@ -1020,7 +1023,6 @@ int bf_ensemble_step(bf_ensemble* e, const bf_params* prm, double* phi, const do
   // every class waits for the caller's stream, the caller's stream for every class
   ECHK(hipEventRecord(e->ev0, e->stream));
   for (EClass& C : e->cls) ECHK(hipStreamWaitEvent(C.stream, e->ev0, 0));
-  const auto t0 = std::chrono::steady_clock::now();
   std::vector<int> rc(e->cls.size(), BF_OK);
   std::vector<std::string> err(e->cls.size());
   if (e->cls.size() == 1) {
@@ -1040,9 +1042,15 @@ int bf_ensemble_step(bf_ensemble* e, const bf_params* prm, double* phi, const do
     ECHK(hipEventRecord(e->ev1, C.stream));
     ECHK(hipStreamWaitEvent(e->stream, e->ev1, 0));
   }
+  // device time of the step: from the marker every class waited for to the
+  // marker that waited for every class, both on the caller's stream
+  ECHK(hipEventRecord(e->ev2, e->stream));
   ECHK(hipStreamSynchronize(e->stream));
-  if (ms)
-    *ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (ms) {
+    float dev_ms = 0.0f;
+    ECHK(hipEventElapsedTime(&dev_ms, e->ev0, e->ev2));
+    *ms = dev_ms;
+  }
   int worst = BF_OK;
   for (int i = 0; i < 2 * e->count; ++i) worst = std::max(worst, (int)stats[i].status);
   return worst;

@@ -553,6 +553,21 @@ T* vcycle_level(bf_grid* g, std::vector<LevelT<T>>& lv, int op, double c,
     stream_post<T>(A, S.degree, cur, e, b, L.r, pa, pg, st);
     return L.r;
   }
+  if constexpr (!F32) {
+    if (streamed && single && smooth_last2_ok(L.n) && post1_ok(L.n, op, S.degree, S.g[0])) {
+      // the correction and the first post-sweep in one pass (x1 into oth, x0 =
+      // x + P e into L.r, free after the restriction), then the last two
+      // sweeps in one pass, into cur (x is no longer read)
+      stream_post1<T>(A, cur, e, b, oth, L.r, S.a[0], st);
+      if (rz_parts) {
+        *rz_parts = stream_smooth_last2_dot(A, oth, L.r, b, cur, S.a[1], S.g[1], S.a[2], S.g[2],
+                                            g->partials, st);
+        return cur;
+      }
+      stream_smooth_last2<T>(A, oth, L.r, b, cur, S.a[1], S.g[1], S.a[2], S.g[2], st);
+      return cur;
+    }
+  }
   launch_prolong_add<T>(L.n, e, cur, st);
   // post-smoothing (same polynomial); on streamed single grids the last two
   // sweeps run as one pass, whose result goes to L.r (free on the way up:

@@ -165,6 +165,12 @@ void launch_x_update(int n, double* x, const double* p, const double* scal, hipS
 // out = x_degree (must not alias x, e or b).  The _dot forms also leave
 // partials of <b, out>_W (and of <out, q>_W) and return their count.
 bool post_ok(int n, int op, int degree, double g0, int elem_bytes);
+// The correction and the first post-sweep only (13-point operator, float64
+// levels where post_ok is false): x1 = sweep(x0), x0 = x + P e; writes both.
+bool post1_ok(int n, int op, int degree, double g0);
+template <typename T>
+void stream_post1(const OpDesc& A, const T* x, const T* e, const T* b, T* x1, T* x0, double a0,
+                  hipStream_t st);
 template <typename T>
 void stream_post(const OpDesc& A, int degree, const T* x, const T* e, const T* b, T* out,
                  const double* a, const double* g, hipStream_t st);

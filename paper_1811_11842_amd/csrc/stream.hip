@@ -1260,6 +1260,7 @@ struct PostArgs {
   double* partials;
   double a[3], g[3];
   int wstrips, rgroups, tiles;
+  T* x0out;  // D = 1: receives x0 = x + P e
 };
 
 template <int OP, int D, int EP, int RPW, typename T, typename TO>
@@ -1354,11 +1355,11 @@ __global__ void __launch_bounds__(kStreamTPB) k_post(PostArgs<T, TO> P) {
 #pragma unroll
       for (int i = 0; i < 2; ++i) x1[k1][i] = x0[k][i] + ad * (bw[k][i] - ax[i]);
     }
-    // x2 over rows j0-(D-2)R .. jl+(D-2)R
-    constexpr int N2 = NW - 4 * R;
+    // x2 over rows j0-(D-2)R .. jl+(D-2)R (D >= 2)
+    constexpr int N2 = D >= 2 ? NW - 4 * R : 1;
     T x2[N2][2];
 #pragma unroll
-    for (int k2 = 0; k2 < N2; ++k2) {
+    for (int k2 = 0; k2 < (D >= 2 ? N2 : 0); ++k2) {
       const int k1 = k2 + R, k = k2 + 2 * R;
       T ax[2];
       window_apply<OP>(x1, k1, coef_row(jrw[k]), ax);
@@ -1375,7 +1376,10 @@ __global__ void __launch_bounds__(kStreamTPB) k_post(PostArgs<T, TO> P) {
       if (j > jl) break;
       const int k = s + D * R;  // the row in the x0 / b window
       VecN<TO, 2> o;
-      if constexpr (D == 2) {
+      if constexpr (D == 1) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i) o.v[i] = TO(x1[s][i]);
+      } else if constexpr (D == 2) {
 #pragma unroll
         for (int i = 0; i < 2; ++i) o.v[i] = TO(x2[s][i]);
       } else {
@@ -1391,6 +1395,13 @@ __global__ void __launch_bounds__(kStreamTPB) k_post(PostArgs<T, TO> P) {
       if (own) {
         const int64_t off = (int64_t)j * n + col;
         store_nt(reinterpret_cast<VecN<TO, 2>*>(P.out + off), o);
+        if constexpr (D == 1) {
+          // x0 = x + P e as well: the next sweep's (x1 - x0) term reads it
+          VecN<T, 2> xo;
+#pragma unroll
+          for (int i = 0; i < 2; ++i) xo.v[i] = x0[k][i];
+          store_nt(reinterpret_cast<VecN<T, 2>*>(P.x0out + off), xo);
+        }
         if constexpr (EP != S2_NONE) {
           const double wgt = row_weight(j, n);
 #pragma unroll
@@ -1984,6 +1995,40 @@ int stream_post_dot2_f32(const OpDesc& A, int degree, const float* x, const floa
                          const double* g, double* partials, hipStream_t st) {
   return post_launch<S2_DOT2, float, float>(A, degree, x, e, b, q, out, a, g, partials, st);
 }
+// The coarse-grid correction and the first post-sweep in one pass (k_post
+// with D = 1, 13-point operator): x1 = x0 + a0 D^{-1}(b - A x0) with
+// x0 = x + P e formed on load; writes x1 and x0 (the next sweep's (x1 - x0)
+// term).  For the float64 levels where the three-sweep pass does not fit the
+// registers; 4-row tiles.  BF_NO_POST1=1 keeps the separate passes.
+bool post1_ok(int n, int op, int degree, double g0) {
+  static const bool off = env_int("BF_NO_POST1", 0) != 0;
+  const BatchCtx& B = g_batch;
+  return !off && op == 1 && degree == 3 && g0 == 0.0 && n >= 128 && B.count <= 1 && !B.coef &&
+         !B.active;
+}
+
+template <typename T>
+void stream_post1(const OpDesc& A, const T* x, const T* e, const T* b, T* x1, T* x0, double a0,
+                  hipStream_t st) {
+  constexpr int RPW = 4;
+  PostArgs<T, T> P{};
+  P.A = A;
+  P.x = x;
+  P.e = e;
+  P.b = b;
+  P.out = x1;
+  P.x0out = x0;
+  P.a[0] = a0;
+  P.wstrips = (A.n + PostGeom<1>::kCols - 1) / PostGeom<1>::kCols;
+  P.rgroups = (A.n + 1 + RPW - 1) / RPW;
+  P.tiles = grouped_tiles(P.wstrips, P.rgroups);
+  const int wpb = kStreamTPB / 64;
+  const int blocks = std::min((P.tiles + wpb - 1) / wpb, kStreamMaxBlocks);
+  hipLaunchKernelGGL((k_post<1, 1, S2_NONE, RPW, T, T>), dim3(blocks), dim3(kStreamTPB), 0, st, P);
+}
+template void stream_post1<double>(const OpDesc&, const double*, const double*, const double*,
+                                   double*, double*, double, hipStream_t);
+
 template void stream_post<double>(const OpDesc&, int, const double*, const double*, const double*,
                                   double*, const double*, const double*, hipStream_t);
 template void stream_post<float>(const OpDesc&, int, const float*, const float*, const float*,

@@ -103,6 +103,9 @@ struct bf_grid {
   double* h_scal = nullptr;   // pinned host mirror of scalars
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   hipEvent_t ev_scal = nullptr;  // marks the arrival of ||r||^2 in the pinned host scalars
+  // the right-hand side whose ||b||_W^2 is already in scal / h_scal[S_BN2]
+  // (formed with the initial guess); the next CG solve of that b uses it
+  const double* bn2_b = nullptr;
   // Captured V-cycles (one hipGraphExec per operator / coefficient / options /
   // input buffer), replayed with a single launch; captured on cap_stream.
   struct VcGraph {
@@ -887,12 +890,17 @@ double column_sq(const OpDesc& A) {
 // True residual r = b - A x with the double-double stencil sum, written into r;
 // returns (via ks) ||r||_W / ||b||_W and the expected float64 representation
 // floor of that quantity, sqrt(sum_W ulp(x)^2 / 12 * column_sq) / ||b||_W.
+// r32 (optional): where the tiled kernel runs, it also writes (float) r there
+// and *r32_done says so (the float32 V-cycle's input, without a separate pass).
 int true_residual(bf_grid* g, const OpDesc& A, const double* b, const double* x, double* r,
-                  double bn, KrylovState& ks) {
+                  double bn, KrylovState& ks, float* r32 = nullptr, bool* r32_done = nullptr) {
   const int np = nparts_of(g);
+  const bool fused32 = r32 && A.op != kOpMob && stream_ok(g->n);
+  if (r32_done) *r32_done = fused32;
   const int nr = A.op == kOpMob
                      ? launch_mob(g->n, A.coef, g->mob, x, b, r, g->partials, np, g->stream)
-                     : launch_residual_dd(A, x, b, r, g->partials, np, g->stream);
+                 : fused32 ? stream_residual_dd(A, x, b, r, g->partials, g->stream, r32)
+                           : launch_residual_dd(A, x, b, r, g->partials, np, g->stream);
   launch_finalize(g->partials, nr, g->scal, F_STORE, S_RTRUE, g->n, g->stream);
   launch_finalize(g->partials + nr, nr, g->scal, F_STORE, S_ULP2, g->n, g->stream);
   TRY(read_scalars(g, S_ULP2 + 1));
@@ -964,13 +972,18 @@ struct NormTrack {
 // decide_after_cycle() stops or restarts from it (residual replacement, i.e.
 // iterative refinement).
 int run_cg(bf_grid* g, int op, double c, const double* b, double* x, const bf_solver_opts& o,
-           KrylovState& ks) {
+           KrylovState& ks, bool bn2_known) {
   hipStream_t st = g->stream;
   const int np = nparts_of(g);
   const OpDesc A = level_op(op, g->n, c);
-  wdot_async(g, b, b, F_STORE, S_BN2);
-  TRY(read_scalars(g, S_BN2 + 1));
-  const double bn2 = g->h_scal[S_BN2];
+  double bn2;
+  if (bn2_known) {
+    bn2 = g->h_scal[S_BN2];  // formed with the initial guess (ch_guess)
+  } else {
+    wdot_async(g, b, b, F_STORE, S_BN2);
+    TRY(read_scalars(g, S_BN2 + 1));
+    bn2 = g->h_scal[S_BN2];
+  }
   if (!std::isfinite(bn2)) return fail(BF_ENONFINITE, "right-hand side is not finite");
   if (bn2 == 0.0) {
     launch_fill(g->npts, x, 0.0, st);
@@ -978,17 +991,18 @@ int run_cg(bf_grid* g, int op, double c, const double* b, double* x, const bf_so
     return BF_OK;
   }
   const double bn = std::sqrt(bn2);
-  TRY(true_residual(g, A, b, x, g->r, bn, ks));
-  ks.rel = ks.rel_true;
-  if (ks.rel_true <= o.rtol) return BF_OK;
-  double last_true = ks.rel_true;
-
   // With the float32 V-cycle the preconditioner changes slightly from one
   // application to the next (rounding), so beta takes the flexible
   // (Polak-Ribiere) form -alpha <z_k, q_{k-1}>_W / rho_{k-1}, which the last
   // smoothing sweep reduces together with rho_k = <r_k, z_k>_W.
   const bool mixed = o.pc == BF_PC_MG && o.mg_precision == BF_MG_F32;
   if (mixed) TRY(ensure_mixed(g));
+  // the true residual also writes (float) r for the first float32 V-cycle
+  bool r32_ready = false;
+  TRY(true_residual(g, A, b, x, g->r, bn, ks, mixed ? g->r32 : nullptr, &r32_ready));
+  ks.rel = ks.rel_true;
+  if (ks.rel_true <= o.rtol) return BF_OK;
+  double last_true = ks.rel_true;
   // streamed top level: the float32 V-cycle hands z over in float32 (z32)
   const bool zf32 = mixed && stream_ok(g->n, 4);
   struct Z32Scope {
@@ -1001,7 +1015,7 @@ int run_cg(bf_grid* g, int op, double c, const double* b, double* x, const bf_so
   for (;;) {
     // (re)start from the residual in g->r
     int rzp = 0;
-    double* z = precondition(g, op, c, o, g->r, &rzp);
+    double* z = precondition(g, op, c, o, g->r, &rzp, r32_ready);
     if (rzp > 0)
       launch_finalize(g->partials, rzp, g->scal, F_STORE, S_RZ, g->n, st);
     else
@@ -1073,7 +1087,7 @@ int run_cg(bf_grid* g, int op, double c, const double* b, double* x, const bf_so
       mass_correct(g, b, x);
       ks.x_updates++;
     }
-    TRY(true_residual(g, A, b, x, g->r, bn, ks));
+    TRY(true_residual(g, A, b, x, g->r, bn, ks, mixed ? g->r32 : nullptr, &r32_ready));
     const int d = decide_after_cycle(o, ks, last_true, !converged);
     if (d >= 0) return d;
   }
@@ -1210,6 +1224,9 @@ int run_gmres(bf_grid* g, int op, double c, const double* b, double* x, const bf
 
 int run_krylov(bf_grid* g, int op, double c, const double* b, double* x, const bf_solver_opts& o,
                bf_solve_stats* st) {
+  // ||b||_W^2 formed with the initial guess of this b (used once, by CG)
+  const bool bn2_known = g->bn2_b == b;
+  g->bn2_b = nullptr;
   TRY(check_opts(o));
   if (op == kOpMob) {
     if (o.ksp != BF_KSP_GMRES)
@@ -1227,7 +1244,8 @@ int run_krylov(bf_grid* g, int op, double c, const double* b, double* x, const b
                           hipMemcpyDeviceToDevice, g->stream));
   }
   KrylovState ks;
-  int status = o.ksp == BF_KSP_CG ? run_cg(g, op, c, b, x, o, ks) : run_gmres(g, op, c, b, x, o, ks);
+  int status = o.ksp == BF_KSP_CG ? run_cg(g, op, c, b, x, o, ks, bn2_known)
+                                  : run_gmres(g, op, c, b, x, o, ks);
   if (status < 0) return status;
 
   HIPCHK(hipEventRecord(g->ev1, g->stream));
@@ -1593,6 +1611,7 @@ int pressure_half(bf_grid* h, const bf_params* prm, const double* ustar, const d
 }
 
 int scale_guess(bf_grid* g, const double* b, double* x);
+int apply_guess(bf_grid* g, double* x);
 
 // Initial guess of the Cahn-Hilliard solve of a time step (x holds phi^n on
 // entry): x0 = gamma phi^n with gamma minimising ||b - gamma A phi^n||_W, or 0
@@ -1603,6 +1622,18 @@ int scale_guess(bf_grid* g, const double* b, double* x);
 // c L^2 phi^n is huge (relative residual 3e5, then 50) and gamma is tiny.
 int ch_guess(bf_grid* g, double c, const double* b, double* x) {
   const OpDesc A = level_op(BF_OP_CH, g->n, c);
+  g->bn2_b = nullptr;
+  if (stream_ok(g->n)) {
+    // <b, A x>, <A x, A x> and ||b||^2 in one pass (A x is not stored)
+    hipStream_t st = g->stream;
+    const int np = stream_guess(A, x, b, g->partials, st);
+    launch_finalize(g->partials, np, g->scal, F_STORE, S_GB, g->n, st);
+    launch_finalize(g->partials + np, np, g->scal, F_STORE, S_GG, g->n, st);
+    launch_finalize(g->partials + 2 * np, np, g->scal, F_STORE, S_BN2, g->n, st);
+    TRY(read_scalars(g, S_GG + 1));
+    g->bn2_b = b;
+    return apply_guess(g, x);
+  }
   launch_apply(A, x, g->q, g->stream);  // q = A phi^n (float64: only gamma depends on it)
   return scale_guess(g, b, x);
 }
@@ -1611,10 +1642,16 @@ int ch_guess(bf_grid* g, double c, const double* b, double* x) {
 // x = gamma x, gamma = <b, q>_W / <q, q>_W, or x = 0 when gamma would not be
 // positive.
 int scale_guess(bf_grid* g, const double* b, double* x) {
-  hipStream_t st = g->stream;
   wdot_async(g, b, g->q, F_STORE, S_GB);
   wdot_async(g, g->q, g->q, F_STORE, S_GG);
   TRY(read_scalars(g, S_GG + 1));
+  return apply_guess(g, x);
+}
+
+// x = gamma x with gamma = <b, q>_W / <q, q>_W from h_scal[S_GB], h_scal[S_GG],
+// or x = 0 when gamma would not be positive.
+int apply_guess(bf_grid* g, double* x) {
+  hipStream_t st = g->stream;
   const double bq = g->h_scal[S_GB], qq = g->h_scal[S_GG];
   if (!std::isfinite(bq) || !std::isfinite(qq)) return fail(BF_ENONFINITE, "phi is not finite");
   if (!(bq > 0.0 && qq > 0.0)) {

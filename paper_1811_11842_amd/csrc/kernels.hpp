@@ -77,8 +77,14 @@ int stream_apply_dot(const OpDesc& A, const double* p, double* q, double* partia
 template <typename T>
 int stream_residual(const OpDesc& A, const T* x, const T* b, T* r, double* partials,
                     hipStream_t st);
+// r32 (optional): also receives (float) r (the float32 V-cycle's input).
 int stream_residual_dd(const OpDesc& A, const double* x, const double* b, double* r,
-                       double* partials, hipStream_t st);
+                       double* partials, hipStream_t st, float* r32 = nullptr);
+// Partials of <b, A x>_W, <A x, A x>_W and <b, b>_W (three groups of the
+// returned count, in that order) without writing A x: the least-squares
+// initial guess and ||b||_W in one pass.
+int stream_guess(const OpDesc& A, const double* x, const double* b, double* partials,
+                 hipStream_t st);
 template <typename T>
 void stream_smooth(const OpDesc& A, const T* x, const T* xprev, const T* b, T* xout, double a,
                    double g, hipStream_t st);

@@ -51,8 +51,10 @@ enum Epi {
                        // for the CH operator), out2 = p', partials of <p', A p'>_W, and the
                        // deferred x += alpha p (alpha, beta from device scalars)
   E_SMOOTH_DOT2 = 11,  // E_SMOOTH and partials of <b, out>_W and <out, q>_W (q float64)
-  E_CG_P32 = 12        // E_CG_P with z read from a float32 field (z32): the float32
+  E_CG_P32 = 12,       // E_CG_P with z read from a float32 field (z32): the float32
                        // V-cycle's output, stored at the precision it has
+  E_GUESS = 13         // no output: partials of <b, A x>_W, <A x, A x>_W and <b, b>_W
+                       // (the least-squares initial guess and ||b|| in one pass)
 };
 
 constexpr int kStreamTPB = 256;         // 4 wavefronts per workgroup
@@ -83,6 +85,7 @@ struct StreamArgs {
   const double* q;     // E_SMOOTH_DOT2: second vector of the extra dot
   int first;           // E_CG_P: first step after a (re)start: p' = z, no x update
   const float* z32;    // E_CG_P32: z
+  float* out32;        // E_RESID_DD (optional): float32 copy of out
   // Batch of equal-sized instances stored bstride elements apart: workgroups
   // bpi * i .. bpi * (i+1) - 1 work on instance i (their partials are the
   // instance's), device scalars are kNumSlots apart.  bcoef (optional): per
@@ -174,10 +177,12 @@ __global__ void __launch_bounds__(kStreamTPB) k_stream(StreamArgs<T, TO> P) {
                            EPI == E_SMOOTH_DOT || EPI == E_SMOOTH_DOT2);
   constexpr bool RED = (EPI == E_APPLY_DOT || EPI == E_RESID_NORM || EPI == E_APPLY_DOT_DD ||
                         EPI == E_RESID_DD || EPI == E_SMOOTH_DOT || EPI == E_CG_P ||
-                        EPI == E_CG_P32 ||
+                        EPI == E_CG_P32 || EPI == E_GUESS ||
                         EPI == E_SMOOTH_DOT2);
-  constexpr bool RED2 = (EPI == E_RESID_DD || EPI == E_SMOOTH_DOT2);
-  constexpr bool NEEDB = (EPI == E_RESID || EPI == E_RESID_NORM || SMOOTH || EPI == E_RESID_DD);
+  constexpr bool RED2 = (EPI == E_RESID_DD || EPI == E_SMOOTH_DOT2 || EPI == E_GUESS);
+  constexpr bool RED3 = EPI == E_GUESS;
+  constexpr bool NEEDB = (EPI == E_RESID || EPI == E_RESID_NORM || SMOOTH || EPI == E_RESID_DD ||
+                          EPI == E_GUESS);
   constexpr bool NEEDP = (EPI == E_SMOOTH || EPI == E_SMOOTH_DOT || EPI == E_SMOOTH_DOT2);
   using VT = VecN<T, V>;
   using VO = VecN<TO, V>;
@@ -217,7 +222,7 @@ __global__ void __launch_bounds__(kStreamTPB) k_stream(StreamArgs<T, TO> P) {
   }
   const T tdi = T(di), tde = T(de), tcoef = T(cf);
   auto dinv_row = [&](int jr) -> T { return row_dinv<OP, T>(tdi, tde, jr, n); };
-  double acc = 0.0, acc2 = 0.0;
+  double acc = 0.0, acc2 = 0.0, acc3 = 0.0;
   const bool skip = P.active && !P.active[inst];
 
   const int wpb = kStreamTPB / 64;
@@ -447,6 +452,15 @@ __global__ void __launch_bounds__(kStreamTPB) k_stream(StreamArgs<T, TO> P) {
           res.v[i] = TO(ax);
           if (EPI == E_APPLY_DOT) acc += wgt * double(nb[i].c) * double(ax);
         }
+      } else if constexpr (EPI == E_GUESS) {
+#pragma unroll
+        for (int i = 0; i < V; ++i) {
+          const double ax = double(apply_vals<OP>(nb[i], coefj));
+          const double bv = double(bcur.v[i]);
+          acc += wgt * bv * ax;
+          acc2 += wgt * ax * ax;
+          acc3 += wgt * bv * bv;
+        }
       } else if constexpr (EPI == E_RESID || EPI == E_RESID_NORM) {
 #pragma unroll
         for (int i = 0; i < V; ++i) {
@@ -517,9 +531,15 @@ __global__ void __launch_bounds__(kStreamTPB) k_stream(StreamArgs<T, TO> P) {
             const double u = ulp_of(nb[i].c);
             acc2 += wgt * u * u;
           }
+          if (P.out32) {
+            VecN<float, V> r32;
+#pragma unroll
+            for (int i = 0; i < V; ++i) r32.v[i] = float(res.v[i]);
+            store_nt(reinterpret_cast<VecN<float, V>*>(P.out32 + ioff + o), r32);
+          }
         }
       }
-      store_nt(reinterpret_cast<VO*>(Op + o), res);
+      if constexpr (EPI != E_GUESS) store_nt(reinterpret_cast<VO*>(Op + o), res);
     }
   }
   if constexpr (RED) {
@@ -528,6 +548,10 @@ __global__ void __launch_bounds__(kStreamTPB) k_stream(StreamArgs<T, TO> P) {
     if constexpr (RED2) {
       const double s2 = block_sum_n<kStreamTPB>(acc2);
       if (threadIdx.x == 0) P.partials[gridDim.x + blockIdx.x] = s2;
+    }
+    if constexpr (RED3) {
+      const double s3 = block_sum_n<kStreamTPB>(acc3);
+      if (threadIdx.x == 0) P.partials[2 * gridDim.x + blockIdx.x] = s3;
     }
   }
 }
@@ -1506,7 +1530,7 @@ static int dispatch(const StreamCfg& c, StreamArgs<T, TO> P, hipStream_t st) {
 template <int EPI, typename T, typename TO>
 static int stream_launch(const OpDesc& A, const T* x, const T* b, const T* xprev, TO* out,
                          double* partials, double a, double g, hipStream_t st, double a0 = 0.0,
-                         const double* q = nullptr) {
+                         const double* q = nullptr, float* out32 = nullptr) {
   constexpr bool kApply = EPI == E_APPLY || EPI == E_APPLY_DOT || EPI == E_APPLY_DOT_DD;
   const StreamCfg c = stream_cfg(A.n, sizeof(T), kApply);
   StreamArgs<T, TO> P{};
@@ -1521,6 +1545,7 @@ static int stream_launch(const OpDesc& A, const T* x, const T* b, const T* xprev
   P.g = g;
   P.a0 = a0;
   P.q = q;
+  P.out32 = out32;
   if (A.op == 0) return dispatch<0, EPI>(c, P, st);
   if (A.op == 2) return dispatch<2, EPI>(c, P, st);
   return dispatch<1, EPI>(c, P, st);
@@ -1538,8 +1563,13 @@ int stream_apply_dot(const OpDesc& A, const double* p, double* q, double* partia
                                                     st);
 }
 int stream_residual_dd(const OpDesc& A, const double* x, const double* b, double* r,
-                       double* partials, hipStream_t st) {
-  return stream_launch<E_RESID_DD, double, double>(A, x, b, nullptr, r, partials, 0, 0, st);
+                       double* partials, hipStream_t st, float* r32) {
+  return stream_launch<E_RESID_DD, double, double>(A, x, b, nullptr, r, partials, 0, 0, st, 0.0,
+                                                   nullptr, r32);
+}
+int stream_guess(const OpDesc& A, const double* x, const double* b, double* partials,
+                 hipStream_t st) {
+  return stream_launch<E_GUESS, double, double>(A, x, b, nullptr, nullptr, partials, 0, 0, st);
 }
 
 template <typename T>

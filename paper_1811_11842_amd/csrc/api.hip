@@ -106,6 +106,10 @@ struct bf_grid {
   // the right-hand side whose ||b||_W^2 is already in scal / h_scal[S_BN2]
   // (formed with the initial guess); the next CG solve of that b uses it
   const double* bn2_b = nullptr;
+  // set with bn2_b when the iterate is zero and r (and, for the float32
+  // V-cycle, r32) already holds that b: the next CG solve skips its first
+  // true residual
+  bool r_is_b = false;
   // Captured V-cycles (one hipGraphExec per operator / coefficient / options /
   // input buffer), replayed with a single launch; captured on cap_stream.
   struct VcGraph {
@@ -972,7 +976,7 @@ struct NormTrack {
 // decide_after_cycle() stops or restarts from it (residual replacement, i.e.
 // iterative refinement).
 int run_cg(bf_grid* g, int op, double c, const double* b, double* x, const bf_solver_opts& o,
-           KrylovState& ks, bool bn2_known) {
+           KrylovState& ks, bool bn2_known, bool r_is_b) {
   hipStream_t st = g->stream;
   const int np = nparts_of(g);
   const OpDesc A = level_op(op, g->n, c);
@@ -999,7 +1003,14 @@ int run_cg(bf_grid* g, int op, double c, const double* b, double* x, const bf_so
   if (mixed) TRY(ensure_mixed(g));
   // the true residual also writes (float) r for the first float32 V-cycle
   bool r32_ready = false;
-  TRY(true_residual(g, A, b, x, g->r, bn, ks, mixed ? g->r32 : nullptr, &r32_ready));
+  if (r_is_b) {
+    // x = 0 and r = b - A 0 = b is in place (solve_pressure_zero)
+    ks.rel_true = 1.0;
+    ks.floor_est = 0.0;
+    r32_ready = mixed;
+  } else {
+    TRY(true_residual(g, A, b, x, g->r, bn, ks, mixed ? g->r32 : nullptr, &r32_ready));
+  }
   ks.rel = ks.rel_true;
   if (ks.rel_true <= o.rtol) return BF_OK;
   double last_true = ks.rel_true;
@@ -1226,7 +1237,9 @@ int run_krylov(bf_grid* g, int op, double c, const double* b, double* x, const b
                bf_solve_stats* st) {
   // ||b||_W^2 formed with the initial guess of this b (used once, by CG)
   const bool bn2_known = g->bn2_b == b;
+  const bool r_is_b = bn2_known && g->r_is_b;
   g->bn2_b = nullptr;
+  g->r_is_b = false;
   TRY(check_opts(o));
   if (op == kOpMob) {
     if (o.ksp != BF_KSP_GMRES)
@@ -1244,7 +1257,7 @@ int run_krylov(bf_grid* g, int op, double c, const double* b, double* x, const b
                           hipMemcpyDeviceToDevice, g->stream));
   }
   KrylovState ks;
-  int status = o.ksp == BF_KSP_CG ? run_cg(g, op, c, b, x, o, ks, bn2_known)
+  int status = o.ksp == BF_KSP_CG ? run_cg(g, op, c, b, x, o, ks, bn2_known, r_is_b)
                                   : run_gmres(g, op, c, b, x, o, ks);
   if (status < 0) return status;
 
@@ -1599,12 +1612,41 @@ int bf_velocity_correct(bf_grid* g, double dt, const double* p, const double* us
 
 namespace {
 
+// bf_solve_pressure from p = 0 (the pressure solve of a time step): one pass
+// projects the right-hand side into b, writes it as the initial residual
+// (r = b - A 0 = b; in float32 too for the float32 V-cycle) and reduces
+// ||b||_W^2, so CG starts without a residual pass and a norm pass of its own.
+int solve_pressure_zero(bf_grid* g, const double* rhs, double* p, const bf_solver_opts* o,
+                        bf_solve_stats* st) {
+  if (rhs == p) return fail(BF_EINVAL, "rhs and p must not alias");
+  bf_solver_opts d;
+  default_opts(BF_OP_LAP, &d);
+  const bf_solver_opts& oo = o ? *o : d;
+  TRY(check_opts(oo));
+  const bool mixed = oo.pc == BF_PC_MG && oo.mg_precision == BF_MG_F32;
+  if (mixed) TRY(ensure_mixed(g));
+  const int np = nparts_of(g);
+  wdot_async(g, rhs, nullptr, F_MEAN, 0);
+  launch_project_start(g->n, rhs, g->work_p, g->r, mixed ? g->r32 : nullptr, g->scal,
+                       g->partials, np, g->stream);
+  launch_finalize(g->partials, np, g->scal, F_STORE, S_BN2, g->n, g->stream);
+  launch_fill(g->npts, p, 0.0, g->stream);
+  TRY(read_scalars(g, S_BN2 + 1));
+  g->bn2_b = g->work_p;
+  g->r_is_b = oo.ksp == BF_KSP_CG;
+  const int s = run_krylov(g, BF_OP_LAP, 0.0, g->work_p, p, oo, st);
+  if (s < 0) return s;
+  wdot_async(g, p, nullptr, F_MEAN, 0);
+  launch_sub_mean(g->n, p, p, g->scal, g->stream);
+  HIPCHK(hipStreamSynchronize(g->stream));
+  return s;
+}
+
 // The pressure half of a step on grid h (its stream, its workspaces).
 int pressure_half(bf_grid* h, const bf_params* prm, const double* ustar, const double* vstar,
                   double* p, double* u, double* v, const bf_solver_opts* pr, bf_solve_stats* S) {
   TRY(bf_pressure_rhs(h, prm->dt, ustar, vstar, h->work_b));
-  launch_fill(h->npts, p, 0.0, h->stream);
-  const int s = bf_solve_pressure(h, h->work_b, p, pr, S);
+  const int s = solve_pressure_zero(h, h->work_b, p, pr, S);
   if (s < 0) return s;
   if (u || v) TRY(bf_velocity_correct(h, prm->dt, p, ustar, vstar, u, v));
   return s;
@@ -1623,6 +1665,7 @@ int apply_guess(bf_grid* g, double* x);
 int ch_guess(bf_grid* g, double c, const double* b, double* x) {
   const OpDesc A = level_op(BF_OP_CH, g->n, c);
   g->bn2_b = nullptr;
+  g->r_is_b = false;
   if (stream_ok(g->n)) {
     // <b, A x>, <A x, A x> and ||b||^2 in one pass (A x is not stored)
     hipStream_t st = g->stream;
@@ -1729,8 +1772,7 @@ int bf_step(bf_grid* g, const bf_params* prm, double* phi, const double* ustar,
   const int s1 = bf_solve_ch(g, c, g->work_b, phi, ch, &S[0]);
   if (s1 < 0) return s1;
   TRY(bf_pressure_rhs(g, prm->dt, ustar, vstar, g->work_b));
-  launch_fill(g->npts, p, 0.0, g->stream);
-  const int s2 = bf_solve_pressure(g, g->work_b, p, pr, &S[1]);
+  const int s2 = solve_pressure_zero(g, g->work_b, p, pr, &S[1]);
   if (s2 < 0) return s2;
   if (u || v) TRY(bf_velocity_correct(g, prm->dt, p, ustar, vstar, u, v));
   int32_t clamped = 0;

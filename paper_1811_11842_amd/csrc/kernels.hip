@@ -435,6 +435,29 @@ __global__ void __launch_bounds__(kBlock) k_x_update(Geo G, double* __restrict__
   GRID_STRIDE(idx, G.npts) x[idx] += alpha * p[idx];
 }
 
+// The start of a solve from a zero iterate with a projected right-hand side:
+// y = x - m (m = scal[S_MEAN]) into b and into the residual r (r = b - A 0),
+// (float) y into r32 when given, and partials of ||y||_W^2.
+__global__ void __launch_bounds__(kBlock) k_project_start(Geo G, const double* __restrict__ x,
+                                                          double* __restrict__ b,
+                                                          double* __restrict__ r,
+                                                          float* __restrict__ r32,
+                                                          const double* __restrict__ scal,
+                                                          double* __restrict__ partials) {
+  const double m = scal[S_MEAN];
+  double acc = 0.0;
+  GRID_STRIDE(idx, G.npts) {
+    const int j = (int)(idx >> G.log2n);
+    const double y = x[idx] - m;
+    b[idx] = y;
+    r[idx] = y;
+    if (r32) r32[idx] = float(y);
+    acc += row_weight(j, G.n) * y * y;
+  }
+  const double t = block_sum(acc);
+  if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
 __global__ void __launch_bounds__(kBlock) k_sub_mean(Geo G, const double* x, double* y,
                                                      const double* __restrict__ scal,
                                                      double sign) {
@@ -1211,6 +1234,11 @@ void launch_x_update(int n, double* x, const double* p, const double* scal, hipS
 void launch_sub_mean(int n, const double* x, double* y, const double* scal, hipStream_t st) {
   const Geo G = make_geo(n);
   LAUNCH(k_sub_mean, ew_blocks(G.npts), st, G, x, y, scal, 1.0);
+}
+
+void launch_project_start(int n, const double* x, double* b, double* r, float* r32,
+                          const double* scal, double* partials, int nparts, hipStream_t st) {
+  LAUNCH(k_project_start, nparts, st, make_geo(n), x, b, r, r32, scal, partials);
 }
 
 void launch_add_mean(int n, const double* x, double* y, const double* scal, hipStream_t st) {

@@ -278,6 +278,10 @@ void launch_residual_norms(const double* scal, double csq, double* out, hipStrea
 void launch_finalize_flex(const double* partials, int nparts, double* scal, hipStream_t st);
 // y = x - scal[S_MEAN]
 void launch_sub_mean(int n, const double* x, double* y, const double* scal, hipStream_t st);
+// b = r = x - scal[S_MEAN], r32 = (float) b when given, nparts partials of
+// ||b||_W^2: the start of a solve from x = 0 with a projected right-hand side.
+void launch_project_start(int n, const double* x, double* b, double* r, float* r32,
+                          const double* scal, double* partials, int nparts, hipStream_t st);
 // y = x + scal[S_MEAN]
 void launch_add_mean(int n, const double* x, double* y, const double* scal, hipStream_t st);
 void launch_fill(int64_t count, double* x, double v, hipStream_t st);

@@ -123,6 +123,9 @@ struct bf_grid {
   std::vector<VcGraph> graphs;
   hipStream_t cap_stream = nullptr;
   bool use_graphs = true;
+  // CG with the float32 V-cycle: flexible (Polak-Ribiere) beta instead of
+  // the plain one (BF_FLEX_BETA=1)
+  bool flex_beta = false;
   // GMRES workspace (allocated on first use)
   int gm_m = 0;
   double* gm_V = nullptr;  // (m+1) vectors
@@ -544,9 +547,11 @@ T* vcycle_level(bf_grid* g, std::vector<LevelT<T>>& lv, int op, double c,
     const double pg[3] = {0.0, S.g[1], S.g[2]};
     if constexpr (F32) {
       if (zout32 || zout) {
-        const int np = zout32 ? stream_post_dot2_f32(A, S.degree, cur, e, b, zout32, g->q, pa, pg,
+        // <z, q>_W only for the flexible beta
+        const double* qf = g->flex_beta ? g->q : nullptr;
+        const int np = zout32 ? stream_post_dot2_f32(A, S.degree, cur, e, b, zout32, qf, pa, pg,
                                                      g->partials, st)
-                              : stream_post_dot2(A, S.degree, cur, e, b, zout, g->q, pa, pg,
+                              : stream_post_dot2(A, S.degree, cur, e, b, zout, qf, pa, pg,
                                                  g->partials, st);
         if (rz_parts) *rz_parts = np;
         return nullptr;
@@ -995,10 +1000,14 @@ int run_cg(bf_grid* g, int op, double c, const double* b, double* x, const bf_so
     return BF_OK;
   }
   const double bn = std::sqrt(bn2);
-  // With the float32 V-cycle the preconditioner changes slightly from one
-  // application to the next (rounding), so beta takes the flexible
-  // (Polak-Ribiere) form -alpha <z_k, q_{k-1}>_W / rho_{k-1}, which the last
-  // smoothing sweep reduces together with rho_k = <r_k, z_k>_W.
+  // The float32 V-cycle is a symmetric positive definite operator up to
+  // rounding (the same Chebyshev polynomial before and after the coarse
+  // correction, restriction the weighted adjoint of the interpolation), so
+  // beta = rho_k / rho_{k-1} as with the float64 one: the flexible
+  // (Polak-Ribiere) form -alpha <z_k, q_{k-1}>_W / rho_{k-1}, for
+  // preconditioners that vary from one application to the next, took the
+  // same iterations at 4096^2 (14.3 and 8.0 per step) and costs the top
+  // post-smoothing pass a read of q (BF_FLEX_BETA=1 selects it).
   const bool mixed = o.pc == BF_PC_MG && o.mg_precision == BF_MG_F32;
   if (mixed) TRY(ensure_mixed(g));
   // the true residual also writes (float) r for the first float32 V-cycle
@@ -1074,7 +1083,7 @@ int run_cg(bf_grid* g, int op, double c, const double* b, double* x, const bf_so
         }
       }
       z = precondition(g, op, c, o, g->r, &rzp, mixed);
-      if (mixed)
+      if (mixed && g->flex_beta)
         launch_finalize_flex(g->partials, rzp, g->scal, st);
       else if (rzp > 0)
         launch_finalize(g->partials, rzp, g->scal, F_BETA, 0, g->n, st);
@@ -1456,6 +1465,8 @@ int bf_grid_create(const bf_grid_desc* desc, bf_grid** out) {
   if (s == BF_OK && hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking) != hipSuccess)
     s = fail(BF_EHIP, "capture stream creation failed");
   {
+    const char* fb = std::getenv("BF_FLEX_BETA");
+    if (fb && fb[0] == '1') g->flex_beta = true;
     const char* ng = std::getenv("BF_NO_GRAPHS");
     if (ng && ng[0] == '1') g->use_graphs = false;
     // V-cycles are replayed from captured graphs on grids up to 2048^2

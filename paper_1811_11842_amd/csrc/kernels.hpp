@@ -183,6 +183,7 @@ void stream_post(const OpDesc& A, int degree, const T* x, const T* e, const T* b
 int stream_post_dot(const OpDesc& A, int degree, const double* x, const double* e,
                     const double* b, double* out, const double* a, const double* g,
                     double* partials, hipStream_t st);
+// q null: the partials of <b, z>_W only (q is not read)
 int stream_post_dot2(const OpDesc& A, int degree, const float* x, const float* e, const float* b,
                      double* out, const double* q, const double* a, const double* g,
                      double* partials, hipStream_t st);

@@ -2015,14 +2015,17 @@ int stream_post_dot(const OpDesc& A, int degree, const double* x, const double* 
   return post_launch<S2_DOT, double, double>(A, degree, x, e, b, nullptr, out, a, g, partials,
                                              st);
 }
+// With q null only the partials of <b, z>_W (q is not read).
 int stream_post_dot2(const OpDesc& A, int degree, const float* x, const float* e, const float* b,
                      double* out, const double* q, const double* a, const double* g,
                      double* partials, hipStream_t st) {
+  if (!q) return post_launch<S2_DOT, float, double>(A, degree, x, e, b, q, out, a, g, partials, st);
   return post_launch<S2_DOT2, float, double>(A, degree, x, e, b, q, out, a, g, partials, st);
 }
 int stream_post_dot2_f32(const OpDesc& A, int degree, const float* x, const float* e,
                          const float* b, float* out, const double* q, const double* a,
                          const double* g, double* partials, hipStream_t st) {
+  if (!q) return post_launch<S2_DOT, float, float>(A, degree, x, e, b, q, out, a, g, partials, st);
   return post_launch<S2_DOT2, float, float>(A, degree, x, e, b, q, out, a, g, partials, st);
 }
 // The coarse-grid correction and the first post-sweep in one pass (k_post

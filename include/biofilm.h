@@ -88,8 +88,9 @@ typedef struct {
   int32_t mg_precision; /* BF_MG_F64, or BF_MG_F32: the multigrid V-cycle   */
                         /* (smoothing, residuals, transfers, coarse tail)   */
                         /* runs on float32 fields while the Krylov method,  */
-                        /* its residual and the iterate stay float64; CG    */
-                        /* then takes the flexible (Polak-Ribiere) beta.    */
+                        /* its residual and the iterate stay float64 (CG    */
+                        /* keeps the plain beta: the float32 V-cycle is     */
+                        /* symmetric up to rounding).                       */
                         /* The float32 hierarchy is allocated on first use. */
   int32_t reserved;     /* 0                                                */
 } bf_solver_opts;

@@ -103,6 +103,39 @@ def test_solve_ch_mixed_forward_error(dev, n):
     assert st.iters <= st64.iters + 3
 
 
+@pytest.mark.parametrize("n", [256, 2048])
+def test_flexible_beta_matches_plain(dev, n, monkeypatch):
+    """CG with the float32 V-cycle under the flexible (Polak-Ribiere) beta
+    (BF_FLEX_BETA=1, read when a grid is created): the Cahn-Hilliard and the
+    pressure solve meet the same forward-error bar against the long-double
+    spectral solutions as with the plain beta, within one iteration of it
+    (the iterates differ in their last bits: the two betas differ by rounding)."""
+    print(f"flexible beta n={n}", flush=True)
+    phi = S.initial_phi(n)
+    b = fh.rhs_ch(phi, PRM["dt"], PRM["M"], PRM["Npoly"], PRM["chi"])
+    u, v = S.inflow_velocity(n)
+    rhs = oracle.step.pressure_rhs(u, v, PRM["dt"])
+    x_ld = spectral.solve_ch(b.astype(np.longdouble), C_CH)
+    p_ld = spectral.solve_poisson(rhs.astype(np.longdouble))
+    its, xs = {}, {}
+    for flex in (False, True):
+        if flex:
+            monkeypatch.setenv("BF_FLEX_BETA", "1")
+        with bf.Grid(n) as g:
+            x, p = g.field(0.0), g.field(0.0)
+            sc = g.solve_ch(C_CH, to_dev(b, dev), x, opts(bf.OP_CH, rtol=1e-10))
+            sp = g.solve_pressure(to_dev(rhs, dev), p, opts(bf.OP_LAP, rtol=1e-12))
+            xs[flex] = to_np(x)
+            fx, fp = relw(xs[flex], x_ld), relw(to_np(p), p_ld)
+        print(f"  flex={flex}: CH iters={sc.iters} fe={fx:.2e} | P iters={sp.iters} fe={fp:.2e}")
+        assert sc.status in (bf.OK, bf.AT_FLOOR) and sp.status == bf.OK
+        assert fx <= 1e-10 and fp <= 1e-10
+        its[flex] = (sc.iters, sp.iters)
+    monkeypatch.delenv("BF_FLEX_BETA")
+    assert abs(its[True][0] - its[False][0]) <= 1 and abs(its[True][1] - its[False][1]) <= 1
+    assert not np.array_equal(xs[True], xs[False])  # the switch took effect
+
+
 @pytest.mark.parametrize("n", [8, 64, 256, 1024])
 def test_solve_pressure_mixed_forward_error(dev, n):
     print(f"solve_pressure mixed n={n}", flush=True)

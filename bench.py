@@ -128,12 +128,14 @@ def time_steps(g, n, steps, warmup, mg_precision):
     return ms / steps, wall / steps * 1e3, stats, (phi, p), cg
 
 
-# Algorithmic bytes per grid point of the Cahn-Hilliard CG step kernel: z
-# (float32 from the float32 V-cycle, float64 otherwise), p_old and x read;
-# p', q and x written.  The first step of a Krylov cycle reads z only and
-# writes p' and q.
+# Algorithmic bytes per grid point of the Cahn-Hilliard CG step kernel: z,
+# p_old and x read; p', q and x written.  z and the search directions p are
+# float32 with the float32 V-cycle, float64 otherwise; q and x are float64.
+# The first step of a Krylov cycle reads z only and writes p' and q.
 def cg_step_bytes(z_bytes, launches, first):
-    return (launches - first) * (z_bytes + 40) + first * (z_bytes + 16)
+    p_bytes = z_bytes
+    return ((launches - first) * (z_bytes + 2 * p_bytes + 24)
+            + first * (z_bytes + p_bytes + 8))
 
 
 def cg_roofline(n, cg, z_bytes, kernel, traffic):
@@ -514,12 +516,12 @@ def main():
                 out["roofline_step"] = cg_roofline(
                     n, cg_m, 4, "k_cg_ch<4,float,4> (Cahn-Hilliard CG step of the value's "
                     "steps: p' = z + beta p, q = A p' exactly rounded, <p', q>_W, x += alpha p; "
-                    "z float32)", recorded_traffic("cg_step", n))
+                    "z and p float32)", recorded_traffic("cg_step", n))
             if a.precision in ("both", "f64"):
                 ms_d, wall_d, st_d, fin_d, cg_d = time_steps(g, n, a.steps, a.warmup, bf.MG_F64)
                 res["f64"] = fin_d
                 out["fp64_roofline_step"] = cg_roofline(
-                    n, cg_d, 8, "k_cg_ch<4,double,4> (the same step with a float64 z)", None)
+                    n, cg_d, 8, "k_cg_ch<4,double,4> (the same step with float64 z and p)", None)
                 if a.precision == "f64":
                     out.update({"value": round(ms_d, 4), "unit": "ms/step",
                                 "ms_per_step": round(ms_d, 4)})

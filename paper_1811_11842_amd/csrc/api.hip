@@ -1030,6 +1030,7 @@ int run_cg(bf_grid* g, int op, double c, const double* b, double* x, const bf_so
     ~Z32Scope() { g->want_z32 = false; }
   } z32_scope{g};
   g->want_z32 = zf32;
+  // search directions (float32 when z is: stream_cg_p32)
   double* pcur = g->p;
   double* pnext = g->p2;
   for (;;) {
@@ -1056,7 +1057,9 @@ int run_cg(bf_grid* g, int op, double c, const double* b, double* x, const bf_so
       const bool timed = g->cg_timing && op == BF_OP_CH;
       if (timed) TRY(cg_timing_mark(g, first));
       const int npq =
-          zf32 ? stream_cg_p32(A, g->z32, pcur, pnext, g->q, x, g->scal, first, g->partials, st)
+          zf32 ? stream_cg_p32(A, g->z32, reinterpret_cast<const float*>(pcur),
+                               reinterpret_cast<float*>(pnext), g->q, x, g->scal, first,
+                               g->partials, st)
                : launch_cg_p(A, z, pcur, pnext, g->q, x, g->scal, first, g->partials, np, st);
       if (timed) HIPCHK(hipEventRecord(g->cg_ev[g->cg_used - 1], st));
       launch_finalize(g->partials, npq, g->scal, F_ALPHA, 0, g->n, st);
@@ -1102,7 +1105,12 @@ int run_cg(bf_grid* g, int op, double c, const double* b, double* x, const bf_so
         }
       }
     }
-    if (pending) launch_x_update(g->n, x, pcur, g->scal, st);
+    if (pending) {
+      if (zf32)
+        launch_x_update(g->n, x, reinterpret_cast<const float*>(pcur), g->scal, st);
+      else
+        launch_x_update(g->n, x, pcur, g->scal, st);
+    }
     if (op == BF_OP_CH) {
       mass_correct(g, b, x);
       ks.x_updates++;

@@ -428,11 +428,12 @@ __global__ void __launch_bounds__(kBlock) k_r_update(Geo G, double* __restrict__
   if (threadIdx.x == 0) partials[blockIdx.x] = t;
 }
 
+template <typename PT>
 __global__ void __launch_bounds__(kBlock) k_x_update(Geo G, double* __restrict__ x,
-                                                     const double* __restrict__ p,
+                                                     const PT* __restrict__ p,
                                                      const double* __restrict__ scal) {
   const double alpha = scal[S_ALPHA];
-  GRID_STRIDE(idx, G.npts) x[idx] += alpha * p[idx];
+  GRID_STRIDE(idx, G.npts) x[idx] += alpha * double(p[idx]);
 }
 
 // The start of a solve from a zero iterate with a projected right-hand side:
@@ -1228,7 +1229,11 @@ void launch_r_update(int n, double* r, const double* q, const double* scal, doub
 
 void launch_x_update(int n, double* x, const double* p, const double* scal, hipStream_t st) {
   const Geo G = make_geo(n);
-  LAUNCH(k_x_update, ew_blocks(G.npts), st, G, x, p, scal);
+  LAUNCH(k_x_update<double>, ew_blocks(G.npts), st, G, x, p, scal);
+}
+void launch_x_update(int n, double* x, const float* p, const double* scal, hipStream_t st) {
+  const Geo G = make_geo(n);
+  LAUNCH(k_x_update<float>, ew_blocks(G.npts), st, G, x, p, scal);
 }
 
 void launch_sub_mean(int n, const double* x, double* y, const double* scal, hipStream_t st) {

@@ -85,6 +85,8 @@ struct StreamArgs {
   const double* q;     // E_SMOOTH_DOT2: second vector of the extra dot
   int first;           // E_CG_P: first step after a (re)start: p' = z, no x update
   const float* z32;    // E_CG_P32: z
+  const float* p32_old;  // E_CG_P32: p_old (float32)
+  float* p32_new;        // E_CG_P32: p' rounded to float32
   float* out32;        // E_RESID_DD (optional): float32 copy of out
   // Batch of equal-sized instances stored bstride elements apart: workgroups
   // bpi * i .. bpi * (i+1) - 1 work on instance i (their partials are the
@@ -271,9 +273,16 @@ __global__ void __launch_bounds__(kStreamTPB) k_stream(StreamArgs<T, TO> P) {
       if (cg_beta) {
 #pragma unroll
         for (int k = 0; k < NR; ++k) {
-          const VT v = *reinterpret_cast<const VT*>(XPp + (int64_t)jrw[k] * n + c);
+          if constexpr (EPI == E_CG_P32) {
+            const float2 v =
+                *reinterpret_cast<const float2*>(P.p32_old + ioff + (int64_t)jrw[k] * n + c);
+            po[k].o[0] = T(v.x);
+            po[k].o[1] = T(v.y);
+          } else {
+            const VT v = *reinterpret_cast<const VT*>(XPp + (int64_t)jrw[k] * n + c);
 #pragma unroll
-          for (int i = 0; i < V; ++i) po[k].o[i] = v.v[i];
+            for (int i = 0; i < V; ++i) po[k].o[i] = v.v[i];
+          }
           po[k].h0 = po[k].h1 = T(0);
         }
       }
@@ -292,7 +301,14 @@ __global__ void __launch_bounds__(kStreamTPB) k_stream(StreamArgs<T, TO> P) {
           xr[k].h0 = h.v[0];
           xr[k].h1 = h.v[1];
         }
-        if constexpr (CGP) {
+        if constexpr (EPI == E_CG_P32) {
+          if (cg_beta) {
+            const float2 h =
+                *reinterpret_cast<const float2*>(P.p32_old + ioff + (int64_t)jrw[k] * n + hcol);
+            po[k].h0 = T(h.x);
+            po[k].h1 = T(h.y);
+          }
+        } else if constexpr (CGP) {
           if (cg_beta) {
             const VT h = *reinterpret_cast<const VT*>(XPp + (int64_t)jrw[k] * n + hcol);
             po[k].h0 = h.v[0];
@@ -333,6 +349,13 @@ __global__ void __launch_bounds__(kStreamTPB) k_stream(StreamArgs<T, TO> P) {
           for (int i = 0; i < V; ++i) xr[k].o[i] += beta * po[k].o[i];
           xr[k].h0 += beta * po[k].h0;
           xr[k].h1 += beta * po[k].h1;
+        }
+        if constexpr (EPI == E_CG_P32) {
+          // the float32 search direction: q, <p', q> and x use the rounded p'
+#pragma unroll
+          for (int i = 0; i < V; ++i) xr[k].o[i] = T(float(xr[k].o[i]));
+          xr[k].h0 = T(float(xr[k].h0));
+          xr[k].h1 = T(float(xr[k].h1));
         }
       }
       if constexpr (EPI == E_SMOOTH_XB) {
@@ -515,7 +538,14 @@ __global__ void __launch_bounds__(kStreamTPB) k_stream(StreamArgs<T, TO> P) {
               pn.v[i] = nb[i].c;
             }
           }
-          store_nt(reinterpret_cast<VecN<double, V>*>(O2p + o), pn);
+          if constexpr (EPI == E_CG_P32) {
+            VecN<float, V> pf;
+#pragma unroll
+            for (int i = 0; i < V; ++i) pf.v[i] = float(pn.v[i]);  // exact
+            store_nt(reinterpret_cast<VecN<float, V>*>(P.p32_new + ioff + o), pf);
+          } else {
+            store_nt(reinterpret_cast<VecN<double, V>*>(O2p + o), pn);
+          }
           if (cg_beta) {
             // the deferred x += alpha_prev p_old (p_old of this row: window row k)
             VecN<double, V> xv = xo[s];
@@ -598,13 +628,16 @@ __host__ __device__ inline int grouped_tiles(int wstrips, int rgroups) {
 constexpr int kCgLanes = 62;
 constexpr int kCgCols = 2 * kCgLanes;
 
+// p_old, p_new: the search directions, in the type of z (a float32 p' is
+// p' = z + beta p_old rounded to float32; q, the reduction and the x update
+// use the rounded value).
 template <typename ZT>
 struct CgArgs {
   OpDesc A;
   Geo G;
   const ZT* z;
-  const double* p_old;
-  double* p_new;
+  const ZT* p_old;
+  ZT* p_new;
   double* q;
   double* x;
   const double* scal;
@@ -660,9 +693,15 @@ k_cg_ch(CgArgs<ZT> P) {
         zr[k][1] = zv.y;
       }
       if constexpr (!FIRST) {
-        const double2 pv = *reinterpret_cast<const double2*>(P.p_old + ro);
-        po[k][0] = pv.x;
-        po[k][1] = pv.y;
+        if constexpr (std::is_same<ZT, float>::value) {
+          const float2 pv = *reinterpret_cast<const float2*>(P.p_old + ro);
+          po[k][0] = pv.x;
+          po[k][1] = pv.y;
+        } else {
+          const double2 pv = *reinterpret_cast<const double2*>(P.p_old + ro);
+          po[k][0] = pv.x;
+          po[k][1] = pv.y;
+        }
       }
     }
     if constexpr (!FIRST) {
@@ -670,14 +709,14 @@ k_cg_ch(CgArgs<ZT> P) {
       for (int s = 0; s < RPW; ++s)
         xo[s] = *reinterpret_cast<const double2*>(P.x + (int64_t)min(j0 + s, jl) * n + c);
     }
-    // p' = z + beta p_old over the window
+    // p' = z + beta p_old over the window (rounded to the type of p)
     double w[NR][2];
 #pragma unroll
     for (int k = 0; k < NR; ++k) {
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
         w[k][i] = zr[k][i];
-        if constexpr (!FIRST) w[k][i] += beta * po[k][i];
+        if constexpr (!FIRST) w[k][i] = double(ZT(w[k][i] + beta * po[k][i]));
       }
     }
     // the deferred x += alpha_prev p_old at the output rows (window rows 2 ..),
@@ -764,8 +803,8 @@ k_cg_ch(CgArgs<ZT> P) {
       qv.y = apply13_split(nh[1], nl[1], pv.y, s13);
       if (out_lane) {
         acc += wgt * (pv.x * qv.x + pv.y * qv.y);
-        __builtin_nontemporal_store(pv.x, P.p_new + o);
-        __builtin_nontemporal_store(pv.y, P.p_new + o + 1);
+        __builtin_nontemporal_store(ZT(pv.x), P.p_new + o);  // exact: pv is a ZT value
+        __builtin_nontemporal_store(ZT(pv.y), P.p_new + o + 1);
         __builtin_nontemporal_store(qv.x, P.q + o);
         __builtin_nontemporal_store(qv.y, P.q + o + 1);
       }
@@ -1613,7 +1652,7 @@ static bool cg_ch_ok(const OpDesc& A) {
 }
 
 template <int RPW, int WAVES, typename ZT>
-static int launch_cg_ch_cfg(const OpDesc& A, const ZT* z, const double* p_old, double* p_new,
+static int launch_cg_ch_cfg(const OpDesc& A, const ZT* z, const ZT* p_old, ZT* p_new,
                             double* q, double* x, const double* scal, bool first,
                             double* partials, hipStream_t st) {
   CgArgs<ZT> P{};
@@ -1645,7 +1684,7 @@ static int launch_cg_ch_cfg(const OpDesc& A, const ZT* z, const double* p_old, d
 // rows, the compiler's own register count; 2 = 2 rows, at least 4 waves;
 // 3 = 8 rows, at least 3 waves.
 template <typename ZT>
-static int launch_cg_ch(const OpDesc& A, const ZT* z, const double* p_old, double* p_new,
+static int launch_cg_ch(const OpDesc& A, const ZT* z, const ZT* p_old, ZT* p_new,
                         double* q, double* x, const double* scal, bool first, double* partials,
                         hipStream_t st) {
   static const int cfg = env_int("BF_CG_CH_CFG", 0);
@@ -1680,7 +1719,7 @@ int stream_cg_p(const OpDesc& A, const double* z, const double* p_old, double* p
   if (A.op == 2) return dispatch<2, E_CG_P>(c, P, st);
   return dispatch<1, E_CG_P>(c, P, st);
 }
-int stream_cg_p32(const OpDesc& A, const float* z, const double* p_old, double* p_new, double* q,
+int stream_cg_p32(const OpDesc& A, const float* z, const float* p_old, float* p_new, double* q,
                   double* x, const double* scal, bool first, double* partials, hipStream_t st) {
   if (cg_ch_ok(A)) return launch_cg_ch(A, z, p_old, p_new, q, x, scal, first, partials, st);
   const StreamCfg c = stream_cfg(A.n, 8);
@@ -1688,9 +1727,9 @@ int stream_cg_p32(const OpDesc& A, const float* z, const double* p_old, double* 
   P.A = A;
   P.G = make_geo(A.n);
   P.z32 = z;
-  P.xprev = p_old;
+  P.p32_old = p_old;
   P.out = q;
-  P.out2 = p_new;
+  P.p32_new = p_new;
   P.xu = x;
   P.scal = scal;
   P.first = first ? 1 : 0;

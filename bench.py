@@ -128,20 +128,30 @@ def time_steps(g, n, steps, warmup, mg_precision):
     return ms / steps, wall / steps * 1e3, stats, (phi, p), cg
 
 
-# Algorithmic bytes per grid point of the Cahn-Hilliard CG step kernel: z,
-# p_old and x read; p', q and x written.  z and the search directions p are
-# float32 with the float32 V-cycle, float64 otherwise; q and x are float64.
-# The first step of a Krylov cycle reads z only and writes p' and q.
-def cg_step_bytes(z_bytes, launches, first):
+# Algorithmic bytes per grid point of the Cahn-Hilliard CG step kernel: z and
+# p_old read, p' and q written, and x read and written for its deferred update.
+# z and the search directions p are float32 with the float32 V-cycle, float64
+# otherwise; q and x are float64.  The first step of a Krylov cycle reads z
+# only and writes p' and q.  With the float32 V-cycle on grids up to 8192^2 the
+# library keeps the directions of up to 8 steps and updates x in one separate
+# pass per batch (k_x_accum), so the step itself does not touch x.
+def cg_step_bytes(z_bytes, launches, first, x_in_step=True):
     p_bytes = z_bytes
-    return ((launches - first) * (z_bytes + 2 * p_bytes + 24)
+    xb = 16 if x_in_step else 0
+    return ((launches - first) * (z_bytes + 2 * p_bytes + 8 + xb)
             + first * (z_bytes + p_bytes + 8))
 
 
-def cg_roofline(n, cg, z_bytes, kernel, traffic):
+def x_in_cg_step(n, mg_precision):
+    """False where the library updates x in batches (float32 V-cycle, at least
+    three float32 fields of (n+1) n nodes within 1 GiB)."""
+    return not (mg_precision == bf.MG_F32 and 3 * 4 * (n + 1) * n <= 2 ** 30)
+
+
+def cg_roofline(n, cg, z_bytes, kernel, traffic, x_in_step=True):
     total_ms, launches, first = cg
     npts = (n + 1) * n
-    alg = cg_step_bytes(z_bytes, launches, first) * npts / launches
+    alg = cg_step_bytes(z_bytes, launches, first, x_in_step) * npts / launches
     us = total_ms / launches * 1e3
     gbs = alg / (us * 1e-6) / 1e9
     return {"kernel": kernel, "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
@@ -515,8 +525,10 @@ def main():
                 out.update(step_summary("", ms_m, wall_m, st_m))
                 out["roofline_step"] = cg_roofline(
                     n, cg_m, 4, "k_cg_ch<4,float,4> (Cahn-Hilliard CG step of the value's "
-                    "steps: p' = z + beta p, q = A p' exactly rounded, <p', q>_W, x += alpha p; "
-                    "z and p float32)", recorded_traffic("cg_step", n))
+                    "steps: p' = z + beta p, q = A p' exactly rounded, <p', q>_W; z and p float32"
+                    + ("; x += alpha p" if x_in_cg_step(n, bf.MG_F32) else
+                       "; x updated in batches of 8 steps by k_x_accum") + ")",
+                    recorded_traffic("cg_step", n), x_in_cg_step(n, bf.MG_F32))
             if a.precision in ("both", "f64"):
                 ms_d, wall_d, st_d, fin_d, cg_d = time_steps(g, n, a.steps, a.warmup, bf.MG_F64)
                 res["f64"] = fin_d

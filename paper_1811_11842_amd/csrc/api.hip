@@ -123,6 +123,10 @@ struct bf_grid {
   std::vector<VcGraph> graphs;
   hipStream_t cap_stream = nullptr;
   bool use_graphs = true;
+  // float32 CG search directions kept for batched iterate updates (ring_m
+  // fields, 0: none; allocated on first use)
+  float* ring[kRing] = {};
+  int ring_m = -1;
   // CG with the float32 V-cycle: flexible (Polak-Ribiere) beta instead of
   // the plain one (BF_FLEX_BETA=1)
   bool flex_beta = false;
@@ -167,6 +171,28 @@ bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
 
 // The float32 hierarchy and level-0 input of the mixed-precision V-cycle,
 // allocated on first use (half the bytes of the float64 one).
+// The ring of float32 search directions of CG with the float32 V-cycle: up
+// to kRing fields within 1 GiB (4096^2: 8; 8192^2: 3; none above, or when
+// the allocation fails: the CG step then updates x itself).  Returns ring_m.
+int ensure_ring(bf_grid* g) {
+  if (g->ring_m >= 0) return g->ring_m;
+  const size_t field = sizeof(float) * (size_t)g->npts;
+  int m = (int)std::min<size_t>(kRing, (size_t(1) << 30) / field);
+  if (m < 3) m = 0;
+  for (int i = 0; i < m; ++i) {
+    void* ptr = nullptr;
+    if (hipMalloc(&ptr, field) != hipSuccess) {
+      (void)hipGetLastError();
+      m = i;
+      break;
+    }
+    g->allocs.push_back(ptr);
+    g->ring[i] = (float*)ptr;
+  }
+  g->ring_m = m >= 3 ? m : 0;
+  return g->ring_m;
+}
+
 int ensure_mixed(bf_grid* g) {
   if (g->r32) return BF_OK;
   std::vector<LevelT<float>> lv;
@@ -1033,6 +1059,10 @@ int run_cg(bf_grid* g, int op, double c, const double* b, double* x, const bf_so
   // search directions (float32 when z is: stream_cg_p32)
   double* pcur = g->p;
   double* pnext = g->p2;
+  // With the float32 directions in the ring, the CG step leaves x alone and
+  // x += sum alpha_i p_i runs once per ring_m steps (x is read and written
+  // once per batch instead of once per step; p_i is read once more).
+  const int rm = zf32 ? ensure_ring(g) : 0;
   for (;;) {
     // (re)start from the residual in g->r
     int rzp = 0;
@@ -1043,6 +1073,14 @@ int run_cg(bf_grid* g, int op, double c, const double* b, double* x, const bf_so
       wdot_async(g, g->r, z, F_STORE, S_RZ);
     bool first = true;     // p = z (no beta term, no pending x update)
     bool pending = false;  // x still lacks alpha * pcur
+    int head = 0;          // ring: slot of the next direction
+    int nring = 0;         // ring: directions whose x update is pending
+    auto flush_ring = [&]() {
+      const float* ps[kRing];
+      for (int i = 0; i < nring; ++i) ps[i] = g->ring[(head - nring + i + rm) % rm];
+      launch_x_accum(g->n, x, ps, nring, g->scal + S_AHIST, st);
+      nring = 0;
+    };
     bool converged = false;
     NormTrack nt;
     nt.take(ks.iters, ks.rel_true);
@@ -1056,16 +1094,27 @@ int run_cg(bf_grid* g, int op, double c, const double* b, double* x, const bf_so
       // p' = z + beta p, q = A p' (+ <p', q>), and the deferred x += alpha p
       const bool timed = g->cg_timing && op == BF_OP_CH;
       if (timed) TRY(cg_timing_mark(g, first));
-      const int npq =
-          zf32 ? stream_cg_p32(A, g->z32, reinterpret_cast<const float*>(pcur),
-                               reinterpret_cast<float*>(pnext), g->q, x, g->scal, first,
-                               g->partials, st)
-               : launch_cg_p(A, z, pcur, pnext, g->q, x, g->scal, first, g->partials, np, st);
+      int npq;
+      if (rm) {
+        if (nring == rm) flush_ring();
+        npq = stream_cg_p32(A, g->z32, first ? nullptr : g->ring[(head + rm - 1) % rm],
+                            g->ring[head], g->q, nullptr, g->scal, first, g->partials, st);
+      } else {
+        npq = zf32 ? stream_cg_p32(A, g->z32, reinterpret_cast<const float*>(pcur),
+                                   reinterpret_cast<float*>(pnext), g->q, x, g->scal, first,
+                                   g->partials, st)
+                   : launch_cg_p(A, z, pcur, pnext, g->q, x, g->scal, first, g->partials, np, st);
+      }
       if (timed) HIPCHK(hipEventRecord(g->cg_ev[g->cg_used - 1], st));
-      launch_finalize(g->partials, npq, g->scal, F_ALPHA, 0, g->n, st);
-      std::swap(pcur, pnext);
+      launch_finalize(g->partials, npq, g->scal, F_ALPHA, rm ? S_AHIST + nring : 0, g->n, st);
+      if (rm) {
+        head = (head + 1) % rm;
+        nring++;
+      } else {
+        std::swap(pcur, pnext);
+        pending = true;
+      }
       first = false;
-      pending = true;
       launch_r_update(g->n, g->r, g->q, g->scal, g->partials, np, st, mixed ? g->r32 : nullptr);
       // ||r||^2 also lands in the pinned host scalars: an event then says it arrived
       launch_finalize(g->partials, np, g->scal, F_STORE, S_RR, g->n, st, g->h_scal);
@@ -1105,6 +1154,7 @@ int run_cg(bf_grid* g, int op, double c, const double* b, double* x, const bf_so
         }
       }
     }
+    if (nring > 0) flush_ring();
     if (pending) {
       if (zf32)
         launch_x_update(g->n, x, reinterpret_cast<const float*>(pcur), g->scal, st);

@@ -32,12 +32,15 @@ enum Slot {
   S_GG = 12,   // initial guess: <A x0, A x0>_W
   S_GAMMA = 13,  // initial guess: its scale factor
   S_GM = 16,   // GMRES scalars start here (up to 64+ slots)
+  S_AHIST = 240,  // CG: alpha of the steps whose iterate update is pending (kRing slots)
   kNumSlots = 256
 };
+// Search directions of CG kept for one batched iterate update (float32 CG).
+constexpr int kRing = 8;
 
 enum FinalizeMode {
   F_STORE = 0,   // scal[slot] = sum
-  F_ALPHA = 1,   // scal[S_PQ] = sum; scal[S_ALPHA] = scal[S_RZ] / sum
+  F_ALPHA = 1,   // scal[S_PQ] = sum; scal[S_ALPHA] = scal[S_RZ] / sum (also into scal[slot] if slot > 0)
   F_BETA = 2,    // scal[S_RZOLD] = scal[S_RZ]; scal[S_RZ] = sum; beta = sum / rzold
   F_MEAN = 3     // scal[S_MEAN] = sum / (n*n)
 };

@@ -325,6 +325,7 @@ __global__ void __launch_bounds__(kFinTPB) k_finalize(const double* __restrict__
       case F_ALPHA:
         scal[S_PQ] = s;
         scal[S_ALPHA] = scal[S_RZ] / s;
+        if (slot > 0) scal[slot] = scal[S_ALPHA];
         break;
       case F_BETA: {
         const double old = scal[S_RZ];
@@ -434,6 +435,41 @@ __global__ void __launch_bounds__(kBlock) k_x_update(Geo G, double* __restrict__
                                                      const double* __restrict__ scal) {
   const double alpha = scal[S_ALPHA];
   GRID_STRIDE(idx, G.npts) x[idx] += alpha * double(p[idx]);
+}
+
+// x += sum_i alpha_i p_i over m float32 search directions (alpha_i =
+// alpha[i]): the iterate update of up to kRing CG steps in one pass.  Four
+// nodes per thread (npts is a multiple of 4); the sum is formed in float64
+// registers in the order of i and added to x once.
+struct RingPtrs {
+  const float* p[kRing];
+};
+
+template <int M>
+__global__ void __launch_bounds__(kBlock) k_x_accum(int64_t nquad, double* __restrict__ x,
+                                                   RingPtrs R, const double* __restrict__ alpha) {
+  double a[M];
+#pragma unroll
+  for (int i = 0; i < M; ++i) a[i] = alpha[i];
+  GRID_STRIDE(t, nquad) {
+    float4 pv[M];
+#pragma unroll
+    for (int i = 0; i < M; ++i) pv[i] = reinterpret_cast<const float4*>(R.p[i])[t];
+    double4 xv = reinterpret_cast<const double4*>(x)[t];
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+      s0 += a[i] * double(pv[i].x);
+      s1 += a[i] * double(pv[i].y);
+      s2 += a[i] * double(pv[i].z);
+      s3 += a[i] * double(pv[i].w);
+    }
+    xv.x += s0;
+    xv.y += s1;
+    xv.z += s2;
+    xv.w += s3;
+    reinterpret_cast<double4*>(x)[t] = xv;
+  }
 }
 
 // The start of a solve from a zero iterate with a projected right-hand side:
@@ -1239,6 +1275,25 @@ void launch_x_update(int n, double* x, const float* p, const double* scal, hipSt
 void launch_sub_mean(int n, const double* x, double* y, const double* scal, hipStream_t st) {
   const Geo G = make_geo(n);
   LAUNCH(k_sub_mean, ew_blocks(G.npts), st, G, x, y, scal, 1.0);
+}
+
+void launch_x_accum(int n, double* x, const float* const* p, int m, const double* alpha,
+                    hipStream_t st) {
+  const Geo G = make_geo(n);
+  const int64_t nquad = G.npts / 4;
+  RingPtrs R{};
+  for (int i = 0; i < m; ++i) R.p[i] = p[i];
+  const int blocks = ew_blocks(nquad);
+  switch (m) {
+#define BF_XACC(M_) \
+  case M_:          \
+    LAUNCH(k_x_accum<M_>, blocks, st, nquad, x, R, alpha); \
+    break;
+    BF_XACC(1) BF_XACC(2) BF_XACC(3) BF_XACC(4) BF_XACC(5) BF_XACC(6) BF_XACC(7) BF_XACC(8)
+#undef BF_XACC
+    default:
+      break;
+  }
 }
 
 void launch_project_start(int n, const double* x, double* b, double* r, float* r32,

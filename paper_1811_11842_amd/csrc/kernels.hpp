@@ -148,6 +148,7 @@ int stream_smooth_dot2_f32(const OpDesc& A, const float* x, const float* xprev, 
 // is rounded to float32 and kept in float32 (p_old, p_new); q = A p', the
 // reduction <p', q>_W and the deferred x += alpha p_old use the rounded p',
 // so the iterate and the recursive residual stay consistent with each other.
+// x null: the step leaves x alone (the caller applies x += alpha p in batches).
 int stream_cg_p32(const OpDesc& A, const float* z, const float* p_old, float* p_new, double* q,
                   double* x, const double* scal, bool first, double* partials, hipStream_t st);
 // Smoothing sweep that also writes partials of <b, xout>_W; returns their count.
@@ -170,6 +171,9 @@ void launch_r_update(int n, double* r, const double* q, const double* scal, doub
 // x += alpha p (alpha = scal[S_ALPHA]).
 void launch_x_update(int n, double* x, const double* p, const double* scal, hipStream_t st);
 void launch_x_update(int n, double* x, const float* p, const double* scal, hipStream_t st);
+// x += sum_{i < m} alpha[i] p[i] (m <= kRing float32 fields, alpha on the device).
+void launch_x_accum(int n, double* x, const float* const* p, int m, const double* alpha,
+                    hipStream_t st);
 // The coarse-grid correction and the whole post-smoother of a level in one
 // pass: x0 = x + P e (e the coarse correction), then `degree` sweeps
 // x_{k+1} = x_k + a[k] D^{-1}(b - A x_k) + g[k] (x_k - x_{k-1}) (g[0] unused);

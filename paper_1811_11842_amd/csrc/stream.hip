@@ -80,7 +80,7 @@ struct StreamArgs {
   int wstrips;         // column strips of 128 columns
   int tiles;           // rgroups * wstrips
   double* out2;        // E_CG_P: p'
-  double* xu;          // E_CG_P: x (updated in place)
+  double* xu;          // E_CG_P: x (updated in place; null: x is not updated)
   const double* scal;  // E_CG_P: device scalars (alpha, beta)
   const double* q;     // E_SMOOTH_DOT2: second vector of the extra dot
   int first;           // E_CG_P: first step after a (re)start: p' = z, no x update
@@ -334,7 +334,7 @@ __global__ void __launch_bounds__(kStreamTPB) k_stream(StreamArgs<T, TO> P) {
       }
     }
     if constexpr (CGP) {
-      if (cg_beta) {
+      if (cg_beta && XUp) {
 #pragma unroll
         for (int s = 0; s < RPW; ++s)
           xo[s] = *reinterpret_cast<const VecN<double, V>*>(XUp + (int64_t)min(j0 + s, jl) * n + c);
@@ -546,7 +546,7 @@ __global__ void __launch_bounds__(kStreamTPB) k_stream(StreamArgs<T, TO> P) {
           } else {
             store_nt(reinterpret_cast<VecN<double, V>*>(O2p + o), pn);
           }
-          if (cg_beta) {
+          if (cg_beta && XUp) {
             // the deferred x += alpha_prev p_old (p_old of this row: window row k)
             VecN<double, V> xv = xo[s];
 #pragma unroll
@@ -639,17 +639,18 @@ struct CgArgs {
   const ZT* p_old;
   ZT* p_new;
   double* q;
-  double* x;
+  double* x;  // null: no deferred x update (the caller updates x in batches)
   const double* scal;
   double* partials;
   int first;
   int rgroups, wstrips, tiles;
 };
 
-template <int RPW, typename ZT, int WAVES, bool FIRST>
+template <int RPW, typename ZT, int WAVES, bool FIRST, bool XU>
 __global__ void __launch_bounds__(kStreamTPB) __attribute__((amdgpu_waves_per_eu(WAVES, 8)))
 k_cg_ch(CgArgs<ZT> P) {
   constexpr int NR = RPW + 4;
+  constexpr bool XUPD = !FIRST && XU;  // the deferred x += alpha_prev p_old
   const int n = P.G.n, mask = P.G.mask;
   const int lane = threadIdx.x & 63;
   double beta = 0.0, alpha_prev = 0.0;
@@ -679,7 +680,7 @@ k_cg_ch(CgArgs<ZT> P) {
     // output's neighbour) of z and p_old, and x at the output rows.
     ZT zr[NR][2];
     double po[FIRST ? 1 : NR][2];
-    double2 xo[FIRST ? 1 : RPW];
+    double2 xo[XUPD ? RPW : 1];
 #pragma unroll
     for (int k = 0; k < NR; ++k) {
       const int64_t ro = (int64_t)refl(min(j0 - 2 + k, jl + 2), n) * n + c;
@@ -704,7 +705,7 @@ k_cg_ch(CgArgs<ZT> P) {
         }
       }
     }
-    if constexpr (!FIRST) {
+    if constexpr (XUPD) {
 #pragma unroll
       for (int s = 0; s < RPW; ++s)
         xo[s] = *reinterpret_cast<const double2*>(P.x + (int64_t)min(j0 + s, jl) * n + c);
@@ -721,7 +722,7 @@ k_cg_ch(CgArgs<ZT> P) {
     }
     // the deferred x += alpha_prev p_old at the output rows (window rows 2 ..),
     // done first so that x and p_old leave the registers before the split
-    if constexpr (!FIRST) {
+    if constexpr (XUPD) {
 #pragma unroll
       for (int s = 0; s < RPW; ++s) {
         const int j = j0 + s;
@@ -1672,10 +1673,14 @@ static int launch_cg_ch_cfg(const OpDesc& A, const ZT* z, const ZT* p_old, ZT* p
   const int wpb = kStreamTPB / 64;
   const int blocks = std::min((P.tiles + wpb - 1) / wpb, kStreamMaxBlocks);
   if (first)
-    hipLaunchKernelGGL((k_cg_ch<RPW, ZT, WAVES, true>), dim3(blocks), dim3(kStreamTPB), 0, st, P);
+    hipLaunchKernelGGL((k_cg_ch<RPW, ZT, WAVES, true, false>), dim3(blocks), dim3(kStreamTPB), 0,
+                       st, P);
+  else if (x)
+    hipLaunchKernelGGL((k_cg_ch<RPW, ZT, WAVES, false, true>), dim3(blocks), dim3(kStreamTPB), 0,
+                       st, P);
   else
-    hipLaunchKernelGGL((k_cg_ch<RPW, ZT, WAVES, false>), dim3(blocks), dim3(kStreamTPB), 0, st,
-                       P);
+    hipLaunchKernelGGL((k_cg_ch<RPW, ZT, WAVES, false, false>), dim3(blocks), dim3(kStreamTPB), 0,
+                       st, P);
   return blocks;
 }
 

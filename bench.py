@@ -88,6 +88,9 @@ def log(msg):
 # so the step meets the 1e-10 forward-error bar on p as it does on phi.
 PRESSURE_RTOL = 1e-12
 
+# The live timing of the CG step records HIP events around every 4th launch.
+CG_TIMING_EVERY = 4
+
 
 def time_steps(g, n, steps, warmup, mg_precision):
     """Warm up on a copy of the initial state, then time `steps` steps from
@@ -110,7 +113,9 @@ def time_steps(g, n, steps, warmup, mg_precision):
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     stats = []
-    g.cg_timing(True)   # HIP events around every CG-step launch on the grid's stream
+    # HIP events on the grid's stream around every 4th CG-step launch (each
+    # event leaves the stream idle for a few microseconds)
+    g.cg_timing(CG_TIMING_EVERY)
     t0 = time.perf_counter()
     e0.record()
     for k in range(steps):
@@ -158,7 +163,8 @@ def cg_roofline(n, cg, z_bytes, kernel, traffic, x_in_step=True):
             "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
             "algorithmic_bytes": int(alg), "launch_us": round(us, 3), "launches": launches,
             "first_launches": first,
-            "timing": "HIP events on the grid's stream around every launch in the timed steps"}
+            "timing": f"HIP events on the grid's stream around every {CG_TIMING_EVERY}th launch "
+                      "in the timed steps"}
 
 
 def wrel(a, b):

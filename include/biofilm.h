@@ -404,15 +404,17 @@ int bf_copy(bf_grid* g, const double* x, double* y);
 int bf_wdot(bf_grid* g, const double* x, const double* y, double* out);
 
 /* Device time of the Cahn-Hilliard CG step kernel (p' = z + beta p, q = A p',
- * the partials of <p', q>_W and the deferred x += alpha p, the largest kernel
- * of a time step), for measuring it inside a timed run.  enable != 0 clears
- * the record and starts recording a pair of HIP events on the grid's stream
- * around every launch of the kernel in the grid's Cahn-Hilliard solves
- * (bf_solve_ch, the Cahn-Hilliard half of bf_step, ...); enable == 0 stops.
- * bf_grid_cg_timing_read synchronises the grid's stream and returns the
- * summed duration in ms, the number of launches, and how many of them were
- * the first step of a Krylov cycle (no beta p term, no x update: 20 instead of
- * 44 bytes per point); it then clears the record.  Outputs may be NULL. */
+ * the partials of <p', q>_W and, where the step does it, the deferred
+ * x += alpha p), for measuring it inside a timed run.  enable > 0 clears the
+ * record and starts recording a pair of HIP events on the grid's stream
+ * around every enable-th launch of the kernel in the grid's Cahn-Hilliard
+ * solves (bf_solve_ch, the Cahn-Hilliard half of bf_step, ...): 1 times
+ * every launch; a larger period lowers the cost of the events (each leaves
+ * the stream idle for a few microseconds).  enable == 0 stops; enable < 0 is
+ * BF_EINVAL.  bf_grid_cg_timing_read synchronises the grid's stream and
+ * returns the summed duration in ms of the recorded launches, their number,
+ * and how many of them were the first step of a Krylov cycle (no beta p term,
+ * no x update); it then clears the record.  Outputs may be NULL. */
 int bf_grid_cg_timing(bf_grid* g, int32_t enable);
 int bf_grid_cg_timing_read(bf_grid* g, double* total_ms, int64_t* launches,
                            int64_t* first_launches);

@@ -425,9 +425,10 @@ class Grid:
         _check(lib().bf_copy(self._h, self._ptr(x, "x"), self._ptr(y, "y")))
         return y
 
-    def cg_timing(self, enable: bool):
-        """Start (clearing the record) or stop timing the Cahn-Hilliard CG step kernel."""
-        _check(lib().bf_grid_cg_timing(self._h, 1 if enable else 0))
+    def cg_timing(self, every):
+        """Start timing every `every`-th launch of the Cahn-Hilliard CG step
+        kernel (True: every launch; clears the record), or stop (0 / False)."""
+        _check(lib().bf_grid_cg_timing(self._h, int(every)))
 
     def cg_timing_read(self):
         """(summed ms, launches, first-step launches) since timing started; clears the record."""

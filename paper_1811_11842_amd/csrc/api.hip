@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <atomic>
 #include <mutex>
 #include <string>
 #include <thread>
@@ -102,7 +103,9 @@ struct bf_grid {
   int32_t* counter = nullptr;
   double* h_scal = nullptr;   // pinned host mirror of scalars
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
-  hipEvent_t ev_scal = nullptr;  // marks the arrival of ||r||^2 in the pinned host scalars
+  // sequence number of the last ||r||^2 the CG loop asked the finalize kernel
+  // to mirror into the pinned host scalars (it arrives with h_scal[S_HSEQ])
+  double hseq = 0.0;
   // the right-hand side whose ||b||_W^2 is already in scal / h_scal[S_BN2]
   // (formed with the initial guess); the next CG solve of that b uses it
   const double* bn2_b = nullptr;
@@ -144,9 +147,10 @@ struct bf_grid {
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   bool overlap = true;
   // Timing of the CG step kernel (bf_grid_cg_timing): a pair of events on the
-  // stream around each launch while recording is on; the events are pooled
-  // and reused after each read.
-  bool cg_timing = false;
+  // stream around every cg_timing-th launch while recording is on (0: off);
+  // the events are pooled and reused after each read.
+  int cg_timing = 0;
+  int64_t cg_count = 0;  // launches since recording started
   std::vector<hipEvent_t> cg_ev;   // pool, 2 per recorded launch
   std::vector<uint8_t> cg_first;   // per recorded launch: a first step of a Krylov cycle
   size_t cg_used = 0;              // events of the pool in use
@@ -883,11 +887,27 @@ int read_scalars(bf_grid* g, int count) {
   return BF_OK;
 }
 
-// Wait for the event recorded after a finalize that also wrote its value into
-// the pinned host scalars (work queued in between keeps the GPU busy while
-// the host waits).
+// Wait until the finalize that mirrors its value into the pinned host scalars
+// with sequence number g->hseq has done so (work queued behind it keeps the GPU
+// busy while the host waits).  The kernel writes the value, then the number,
+// each followed by a system-scope fence, so the value is visible once the
+// number is.  An event recorded on the stream for this would leave the stream
+// idle for about 5 us per wait.  If the stream drains without the number
+// arriving, the wait fails instead of spinning on.
 int wait_scalars(bf_grid* g) {
-  HIPCHK(hipEventSynchronize(g->ev_scal));
+  const volatile double* seq = g->h_scal + S_HSEQ;
+  for (uint64_t spin = 1;; ++spin) {
+    if (*seq == g->hseq) break;
+    if ((spin & 0xffff) == 0) {
+      const hipError_t q = hipStreamQuery(g->stream);
+      if (q == hipSuccess) {
+        if (*seq == g->hseq) break;
+        return fail(BF_EHIP, "the residual norm did not reach the host");
+      }
+      if (q != hipErrorNotReady) HIPCHK(q);
+    }
+  }
+  std::atomic_thread_fence(std::memory_order_acquire);
   return BF_OK;
 }
 
@@ -1092,7 +1112,7 @@ int run_cg(bf_grid* g, int op, double c, const double* b, double* x, const bf_so
     };
     while (ks.iters < o.maxit) {
       // p' = z + beta p, q = A p' (+ <p', q>), and the deferred x += alpha p
-      const bool timed = g->cg_timing && op == BF_OP_CH;
+      const bool timed = g->cg_timing > 0 && op == BF_OP_CH && g->cg_count++ % g->cg_timing == 0;
       if (timed) TRY(cg_timing_mark(g, first));
       int npq;
       if (rm) {
@@ -1117,12 +1137,12 @@ int run_cg(bf_grid* g, int op, double c, const double* b, double* x, const bf_so
       first = false;
       launch_r_update(g->n, g->r, g->q, g->scal, g->partials, np, st, mixed ? g->r32 : nullptr);
       // ||r||^2 also lands in the pinned host scalars: an event then says it arrived
-      launch_finalize(g->partials, np, g->scal, F_STORE, S_RR, g->n, st, g->h_scal);
+      g->hseq += 1.0;
+      launch_finalize(g->partials, np, g->scal, F_STORE, S_RR, g->n, st, g->h_scal, g->hseq);
       ks.iters++;
       ks.x_updates++;
       bool deferred = false;
       if (ks.iters % o.check_every == 0 || ks.iters == o.maxit) {
-        HIPCHK(hipEventRecord(g->ev_scal, st));
         deferred = ks.iters < o.maxit && nt.predict(ks.iters) > 4.0 * o.rtol;
         if (!deferred) {
           TRY(wait_scalars(g));
@@ -1517,8 +1537,8 @@ int bf_grid_create(const bf_grid_desc* desc, bf_grid** out) {
   }
   if (s == BF_OK && hipHostMalloc((void**)&g->h_scal, sizeof(double) * kNumSlots) != hipSuccess)
     s = fail(BF_ENOMEM, "pinned host allocation failed");
-  if (s == BF_OK && (hipEventCreate(&g->ev0) != hipSuccess || hipEventCreate(&g->ev1) != hipSuccess ||
-                     hipEventCreateWithFlags(&g->ev_scal, hipEventDisableTiming) != hipSuccess))
+  if (s == BF_OK) std::memset(g->h_scal, 0, sizeof(double) * kNumSlots);
+  if (s == BF_OK && (hipEventCreate(&g->ev0) != hipSuccess || hipEventCreate(&g->ev1) != hipSuccess))
     s = fail(BF_EHIP, "event creation failed");
   if (s == BF_OK && hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking) != hipSuccess)
     s = fail(BF_EHIP, "capture stream creation failed");
@@ -1568,7 +1588,6 @@ int bf_grid_destroy(bf_grid* g) {
   if (g->h_scal) (void)hipHostFree(g->h_scal);
   if (g->ev0) (void)hipEventDestroy(g->ev0);
   if (g->ev1) (void)hipEventDestroy(g->ev1);
-  if (g->ev_scal) (void)hipEventDestroy(g->ev_scal);
   for (hipEvent_t e : g->cg_ev) (void)hipEventDestroy(e);
   delete g;
   return BF_OK;
@@ -1576,9 +1595,11 @@ int bf_grid_destroy(bf_grid* g) {
 
 int bf_grid_cg_timing(bf_grid* g, int32_t enable) {
   TRY(check_grid(g));
-  g->cg_timing = enable != 0;
+  if (enable < 0) return fail(BF_EINVAL, "timing period %d must be >= 0", (int)enable);
+  g->cg_timing = enable;
   if (g->cg_timing) {
     g->cg_used = 0;
+    g->cg_count = 0;
     g->cg_first.clear();
   }
   return BF_OK;

@@ -307,11 +307,14 @@ __device__ __forceinline__ double fin_sum(const double* __restrict__ p, int npar
   return block_sum_n<kFinTPB>((a0 + a1) + (a2 + a3));
 }
 
-// host (optional, F_STORE): pinned host memory that also receives the value,
-// so that the host reads it after an event instead of a separate copy.
+// host (optional, F_STORE): pinned host memory that also receives the value
+// and then, once the value is visible to the host, the sequence number hseq in
+// host[S_HSEQ]: the host waits for that number instead of for an event or a
+// copy (each system-scope fence writes the stores before it back to memory).
 __global__ void __launch_bounds__(kFinTPB) k_finalize(const double* __restrict__ partials, int nparts,
                                                       double* __restrict__ scal, int mode, int slot,
-                                                      double nn, double* __restrict__ host) {
+                                                      double nn, double* __restrict__ host,
+                                                      double hseq) {
   const double s = fin_sum(partials, nparts);
   if (threadIdx.x == 0) {
     switch (mode) {
@@ -319,6 +322,8 @@ __global__ void __launch_bounds__(kFinTPB) k_finalize(const double* __restrict__
         scal[slot] = s;
         if (host) {
           host[slot] = s;
+          __threadfence_system();
+          host[S_HSEQ] = hseq;
           __threadfence_system();
         }
         break;
@@ -1239,9 +1244,9 @@ void launch_residual_norms(const double* scal, double csq, double* out, hipStrea
 }
 
 void launch_finalize(const double* partials, int nparts, double* scal, int mode, int slot, int n,
-                     hipStream_t st, double* host) {
+                     hipStream_t st, double* host, double hseq) {
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFinTPB), 0, st, partials, nparts, scal, mode, slot,
-                     (double)n * (double)n, host);
+                     (double)n * (double)n, host, hseq);
 }
 
 int launch_cg_p(const OpDesc& A, const double* z, const double* p_old, double* p_new, double* q,

@@ -275,9 +275,10 @@ void launch_dot(int n, const double* x, const double* y, double* partials, int n
 void launch_wsum_diff(int n, const double* x, const double* y, double* partials, int nparts,
                       hipStream_t st);
 // Reduce partials in a fixed order and update scalars (see FinalizeMode);
-// host (F_STORE only): pinned host scalars that also receive scal[slot].
+// host (F_STORE only): pinned host scalars that also receive scal[slot] and,
+// after it, hseq in host[S_HSEQ].
 void launch_finalize(const double* partials, int nparts, double* scal, int mode, int slot,
-                     int n, hipStream_t st, double* host = nullptr);
+                     int n, hipStream_t st, double* host = nullptr, double hseq = 0.0);
 // Norms of a residual from the scalars of its reductions (scal[S_BN2] =
 // ||b||_W^2, scal[S_RTRUE] = ||r||_W^2, scal[S_ULP2] = sum_W ulp(x)^2):
 // out[0] = ||r||_W / ||b||_W, out[1] = sqrt(scal[S_ULP2] / 12 * csq) / ||b||_W

@@ -392,6 +392,38 @@ def test_maxit_reports_not_converged(dev):
     assert 0 < st.rel_res_true < 1
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_cg_step_timing_periods(dev, prec):
+    """bf_grid_cg_timing records every k-th launch of the CG step of the
+    grid's Cahn-Hilliard solves: period 1 every iteration (one first step
+    per Krylov cycle), period 3 the iterations 0, 3, 6, ...; a negative
+    period is rejected; the solve's result does not depend on the timing."""
+    n = 1024
+    g = grid(n)
+    b = to_dev(fh.rhs_ch(S.initial_phi(n), PRM["dt"], PRM["M"], PRM["Npoly"], PRM["chi"]), dev)
+    o = bf.default_opts(bf.OP_CH, rtol=1e-10,
+                        mg_precision=bf.MG_F32 if prec == "f32" else bf.MG_F64)
+    xs, its = [], []
+    for every in (1, 3, 0):
+        g.cg_timing(every)
+        x = g.field(0.0)
+        st = g.solve_ch(C_CH, b, x, o)
+        torch.cuda.synchronize()
+        xs.append(x)
+        its.append(st.iters)
+        if every:
+            ms, launches, first = g.cg_timing_read()
+            assert launches == -(-st.iters // every), (every, launches, st.iters)
+            assert ms > 0.0
+            if every == 1:
+                assert first == 1 + st.restarts  # each Krylov cycle starts with p = z
+    g.cg_timing(0)
+    assert its[0] == its[1] == its[2]
+    assert torch.equal(xs[0], xs[1]) and torch.equal(xs[0], xs[2])
+    with pytest.raises(bf.BiofilmError, match="EINVAL"):
+        g.cg_timing(-1)
+
+
 def test_nonfinite_input_rejected(dev):
     g = grid(64)
     b = to_dev(S.random_field(64, 1), dev)

@@ -45,7 +45,7 @@ import synthetic as S  # noqa: E402
 METRIC = "solve time/step + stencil SpMV HBM GB/s at 4096², mixed vs FP64 @1e-10"
 HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ["paper_1811_11842_amd/csrc/stream.hip", "paper_1811_11842_amd/csrc/stencil_ops.hpp",
-                  "paper_1811_11842_amd/csrc/common.hpp"]
+                  "paper_1811_11842_amd/csrc/common.hpp", "paper_1811_11842_amd/csrc/kernels.hip"]
 # HBM traffic per launch at 4096^2 from `rocprofv3 --pmc FETCH_SIZE` / `--pmc WRITE_SIZE`
 # (profiles/spmv_13pt_4096_counters.md for the SpMV and the sweep,
 # profiles/step_kernels_4096_counters.md for the CG step), KiB per dispatch, scaled by the ratio of known to
@@ -129,8 +129,9 @@ def time_steps(g, n, steps, warmup, mg_precision):
     wall = time.perf_counter() - t0
     ms = e0.elapsed_time(e1)
     cg = g.cg_timing_read()
+    ru = g.rupdate_timing_read()
     g.cg_timing(False)
-    return ms / steps, wall / steps * 1e3, stats, (phi, p), cg
+    return ms / steps, wall / steps * 1e3, stats, (phi, p), (cg, ru)
 
 
 # Algorithmic bytes per grid point of the Cahn-Hilliard CG step kernel: z and
@@ -151,6 +152,21 @@ def x_in_cg_step(n, mg_precision):
     """False where the library updates x in batches (float32 V-cycle, at least
     three float32 fields of (n+1) n nodes within 1 GiB)."""
     return not (mg_precision == bf.MG_F32 and 3 * 4 * (n + 1) * n <= 2 ** 30)
+
+
+# Algorithmic bytes per grid point of the residual update: r and q read, r
+# written (float64), and with the float32 V-cycle its float32 copy of r.
+def ru_roofline(n, ru, mixed, kernel, traffic):
+    total_ms, launches = ru
+    npts = (n + 1) * n
+    alg = (28 if mixed else 24) * npts
+    us = total_ms / launches * 1e3
+    gbs = alg / (us * 1e-6) / 1e9
+    return {"kernel": kernel, "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "algorithmic_bytes": int(alg), "launch_us": round(us, 3), "launches": launches,
+            "timing": f"HIP events on the grid's stream around every {CG_TIMING_EVERY}th launch "
+                      "in the Cahn-Hilliard solves of the timed steps"}
 
 
 def cg_roofline(n, cg, z_bytes, kernel, traffic, x_in_step=True):
@@ -524,21 +540,30 @@ def main():
         if not a.spmv_only:
             res = {}
             if a.precision in ("both", "mixed"):
-                ms_m, wall_m, st_m, fin_m, cg_m = time_steps(g, n, a.steps, a.warmup, bf.MG_F32)
+                ms_m, wall_m, st_m, fin_m, (cg_m, ru_m) = time_steps(g, n, a.steps, a.warmup,
+                                                                     bf.MG_F32)
                 res["mixed"] = fin_m
                 out.update({"value": round(ms_m, 4), "unit": "ms/step",
                             "ms_per_step": round(ms_m, 4)})
                 out.update(step_summary("", ms_m, wall_m, st_m))
-                out["roofline_step"] = cg_roofline(
+                # the kernel with the largest share of the step's time: the residual
+                # update of both solves' iterations (timed in the Cahn-Hilliard solve)
+                out["roofline_step"] = ru_roofline(
+                    n, ru_m, True, "k_r_update (residual update of the value's steps: r -= alpha q, "
+                    "||r||^2 partials, float32 copy of r)", recorded_traffic("r_update", n))
+                out["roofline_cg_step"] = cg_roofline(
                     n, cg_m, 4, "k_cg_ch<4,float,4> (Cahn-Hilliard CG step of the value's "
                     "steps: p' = z + beta p, q = A p' exactly rounded, <p', q>_W; z and p float32"
                     + ("; x += alpha p" if x_in_cg_step(n, bf.MG_F32) else
                        "; x updated in batches of 8 steps by k_x_accum") + ")",
                     recorded_traffic("cg_step", n), x_in_cg_step(n, bf.MG_F32))
             if a.precision in ("both", "f64"):
-                ms_d, wall_d, st_d, fin_d, cg_d = time_steps(g, n, a.steps, a.warmup, bf.MG_F64)
+                ms_d, wall_d, st_d, fin_d, (cg_d, ru_d) = time_steps(g, n, a.steps, a.warmup,
+                                                                     bf.MG_F64)
                 res["f64"] = fin_d
-                out["fp64_roofline_step"] = cg_roofline(
+                out["fp64_roofline_step"] = ru_roofline(
+                    n, ru_d, False, "k_r_update (the same update without the float32 copy)", None)
+                out["fp64_roofline_cg_step"] = cg_roofline(
                     n, cg_d, 8, "k_cg_ch<4,double,4> (the same step with float64 z and p)", None)
                 if a.precision == "f64":
                     out.update({"value": round(ms_d, 4), "unit": "ms/step",

@@ -418,6 +418,12 @@ int bf_wdot(bf_grid* g, const double* x, const double* y, double* out);
 int bf_grid_cg_timing(bf_grid* g, int32_t enable);
 int bf_grid_cg_timing_read(bf_grid* g, double* total_ms, int64_t* launches,
                            int64_t* first_launches);
+/* The same for the residual update of the same iterations (r -= alpha q,
+ * the partials of ||r||_W^2 and, with the float32 V-cycle, the float32 copy
+ * of r), recorded while bf_grid_cg_timing is on: synchronises the grid's
+ * stream, returns the summed duration in ms and the number of recorded
+ * launches, and clears that record.  Outputs may be NULL. */
+int bf_grid_rupdate_timing_read(bf_grid* g, double* total_ms, int64_t* launches);
 
 /* Message of the last failure on this thread ("" if none). */
 const char* bf_last_error(void);

@@ -140,6 +140,8 @@ def lib():
                                            ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                            ctypes.POINTER(ctypes.c_double)]),
             "bf_grid_cg_timing": (ctypes.c_int, [_P, ctypes.c_int32]),
+            "bf_grid_rupdate_timing_read": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double),
+                                                           ctypes.POINTER(ctypes.c_int64)]),
             "bf_grid_cg_timing_read": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double),
                                                       ctypes.POINTER(ctypes.c_int64),
                                                       ctypes.POINTER(ctypes.c_int64)]),
@@ -436,6 +438,12 @@ class Grid:
         _check(lib().bf_grid_cg_timing_read(self._h, ctypes.byref(ms), ctypes.byref(n),
                                             ctypes.byref(nf)))
         return ms.value, n.value, nf.value
+
+    def rupdate_timing_read(self):
+        """(summed ms, launches) of the residual updates timed with the CG steps; clears it."""
+        ms, n = ctypes.c_double(), ctypes.c_int64()
+        _check(lib().bf_grid_rupdate_timing_read(self._h, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
 
     def wdot(self, x, y) -> float:
         out = ctypes.c_double()

@@ -154,6 +154,8 @@ struct bf_grid {
   std::vector<hipEvent_t> cg_ev;   // pool, 2 per recorded launch
   std::vector<uint8_t> cg_first;   // per recorded launch: a first step of a Krylov cycle
   size_t cg_used = 0;              // events of the pool in use
+  std::vector<hipEvent_t> ru_ev;   // the same for the residual update (k_r_update)
+  size_t ru_used = 0;
 };
 
 namespace {
@@ -859,6 +861,21 @@ double* precondition_mob(bf_grid* g, double c, const bf_solver_opts& o, const do
 // Start the timing of one CG-step launch: takes a pair of events from the
 // pool (creating them on first use) and records the first on the stream; the
 // caller records the second after the launch.
+// A pair of events from the pool (created on demand): the first is recorded now,
+// the caller records the second after the launch.
+int timing_pair(bf_grid* g, std::vector<hipEvent_t>& pool, size_t& used) {
+  if (used + 2 > pool.size()) {
+    for (int k = 0; k < 2; ++k) {
+      hipEvent_t e = nullptr;
+      HIPCHK(hipEventCreate(&e));
+      pool.push_back(e);
+    }
+  }
+  HIPCHK(hipEventRecord(pool[used], g->stream));
+  used += 2;
+  return BF_OK;
+}
+
 int cg_timing_mark(bf_grid* g, bool first) {
   if (g->cg_used + 2 > g->cg_ev.size()) {
     for (int k = 0; k < 2; ++k) {
@@ -1135,7 +1152,9 @@ int run_cg(bf_grid* g, int op, double c, const double* b, double* x, const bf_so
         pending = true;
       }
       first = false;
+      if (timed) TRY(timing_pair(g, g->ru_ev, g->ru_used));
       launch_r_update(g->n, g->r, g->q, g->scal, g->partials, np, st, mixed ? g->r32 : nullptr);
+      if (timed) HIPCHK(hipEventRecord(g->ru_ev[g->ru_used - 1], st));
       // ||r||^2 also lands in the pinned host scalars: an event then says it arrived
       g->hseq += 1.0;
       launch_finalize(g->partials, np, g->scal, F_STORE, S_RR, g->n, st, g->h_scal, g->hseq);
@@ -1589,6 +1608,7 @@ int bf_grid_destroy(bf_grid* g) {
   if (g->ev0) (void)hipEventDestroy(g->ev0);
   if (g->ev1) (void)hipEventDestroy(g->ev1);
   for (hipEvent_t e : g->cg_ev) (void)hipEventDestroy(e);
+  for (hipEvent_t e : g->ru_ev) (void)hipEventDestroy(e);
   delete g;
   return BF_OK;
 }
@@ -1599,6 +1619,7 @@ int bf_grid_cg_timing(bf_grid* g, int32_t enable) {
   g->cg_timing = enable;
   if (g->cg_timing) {
     g->cg_used = 0;
+    g->ru_used = 0;
     g->cg_count = 0;
     g->cg_first.clear();
   }
@@ -1622,6 +1643,21 @@ int bf_grid_cg_timing_read(bf_grid* g, double* total_ms, int64_t* launches,
   if (first_launches) *first_launches = nf;
   g->cg_used = 0;
   g->cg_first.clear();
+  return BF_OK;
+}
+
+int bf_grid_rupdate_timing_read(bf_grid* g, double* total_ms, int64_t* launches) {
+  TRY(check_grid(g));
+  HIPCHK(hipStreamSynchronize(g->stream));
+  double tot = 0.0;
+  for (size_t k = 0; k + 1 < g->ru_used; k += 2) {
+    float ms = 0.0f;
+    HIPCHK(hipEventElapsedTime(&ms, g->ru_ev[k], g->ru_ev[k + 1]));
+    tot += ms;
+  }
+  if (total_ms) *total_ms = tot;
+  if (launches) *launches = (int64_t)(g->ru_used / 2);
+  g->ru_used = 0;
   return BF_OK;
 }
 

@@ -450,6 +450,9 @@ struct RingPtrs {
   const float* p[kRing];
 };
 
+typedef float bf_f4 __attribute__((ext_vector_type(4)));
+typedef double bf_d2 __attribute__((ext_vector_type(2)));
+
 template <int M>
 __global__ void __launch_bounds__(kBlock) k_x_accum(int64_t nquad, double* __restrict__ x,
                                                    RingPtrs R, const double* __restrict__ alpha) {
@@ -457,10 +460,13 @@ __global__ void __launch_bounds__(kBlock) k_x_accum(int64_t nquad, double* __res
 #pragma unroll
   for (int i = 0; i < M; ++i) a[i] = alpha[i];
   GRID_STRIDE(t, nquad) {
-    float4 pv[M];
+    // every value is used once: non-temporal loads and stores
+    bf_f4 pv[M];
 #pragma unroll
-    for (int i = 0; i < M; ++i) pv[i] = reinterpret_cast<const float4*>(R.p[i])[t];
-    double4 xv = reinterpret_cast<const double4*>(x)[t];
+    for (int i = 0; i < M; ++i)
+      pv[i] = __builtin_nontemporal_load(reinterpret_cast<const bf_f4*>(R.p[i]) + t);
+    bf_d2* xq = reinterpret_cast<bf_d2*>(x) + 2 * t;
+    bf_d2 x0 = __builtin_nontemporal_load(xq), x1 = __builtin_nontemporal_load(xq + 1);
     double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
 #pragma unroll
     for (int i = 0; i < M; ++i) {
@@ -469,11 +475,12 @@ __global__ void __launch_bounds__(kBlock) k_x_accum(int64_t nquad, double* __res
       s2 += a[i] * double(pv[i].z);
       s3 += a[i] * double(pv[i].w);
     }
-    xv.x += s0;
-    xv.y += s1;
-    xv.z += s2;
-    xv.w += s3;
-    reinterpret_cast<double4*>(x)[t] = xv;
+    x0.x += s0;
+    x0.y += s1;
+    x1.x += s2;
+    x1.y += s3;
+    __builtin_nontemporal_store(x0, xq);
+    __builtin_nontemporal_store(x1, xq + 1);
   }
 }
 

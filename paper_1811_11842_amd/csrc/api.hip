@@ -1562,6 +1562,8 @@ int bf_grid_create(const bf_grid_desc* desc, bf_grid** out) {
   if (s == BF_OK && hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking) != hipSuccess)
     s = fail(BF_EHIP, "capture stream creation failed");
   {
+    const char* nr = std::getenv("BF_NO_RING");
+    if (nr && nr[0] == '1') g->ring_m = 0;  // the CG step updates x itself
     const char* fb = std::getenv("BF_FLEX_BETA");
     if (fb && fb[0] == '1') g->flex_beta = true;
     const char* ng = std::getenv("BF_NO_GRAPHS");

@@ -136,6 +136,42 @@ def test_flexible_beta_matches_plain(dev, n, monkeypatch):
     assert not np.array_equal(xs[True], xs[False])  # the switch took effect
 
 
+@pytest.mark.parametrize("maxit", [5, 11, 200])
+def test_batched_iterate_update_matches_per_step(dev, maxit, monkeypatch):
+    """Float32 CG keeps up to 8 search directions and adds sum alpha_i p_i to
+    x once per batch; with BF_NO_RING=1 (read when a grid is created) the CG
+    step adds alpha p itself.  When the iteration limit ends the solve inside
+    a batch (maxit 5, 11) both stop at the same iteration with iterates equal
+    to rounding; whole solves meet the same bar against the exact solution."""
+    n = 512
+    phi = S.initial_phi(n)
+    b = to_dev(fh.rhs_ch(phi, PRM["dt"], PRM["M"], PRM["Npoly"], PRM["chi"]), dev)
+    o = opts(bf.OP_CH, rtol=1e-10, maxit=maxit)
+    res = {}
+    for ring in (True, False):
+        if not ring:
+            monkeypatch.setenv("BF_NO_RING", "1")
+        with bf.Grid(n) as g:
+            x = g.field(0.0)
+            st = g.solve_ch(C_CH, b, x, o)
+            res[ring] = (to_np(x), st)
+    monkeypatch.delenv("BF_NO_RING")
+    (xr, sr), (xs, ss) = res[True], res[False]
+    print(f"  maxit={maxit}: ring {sr.iters} it {sr.status} | per step {ss.iters} it {ss.status} "
+          f"| rel diff {relw(xr, xs):.1e}")
+    if maxit == 200:
+        # a whole solve: a restart would start from iterates that differ by
+        # rounding, so only the bar against the exact solution is shared
+        assert sr.status in (bf.OK, bf.AT_FLOOR) and ss.status in (bf.OK, bf.AT_FLOOR)
+        assert abs(sr.iters - ss.iters) <= 1
+        assert relw(xr, xs) <= 1e-11
+        assert relw(xr, spectral.solve_ch(to_np(b).astype(np.longdouble), C_CH)) <= 1e-10
+    else:
+        # inside the first Krylov cycle the two differ only in how x is summed
+        assert sr.status == ss.status == bf.NOT_CONVERGED and sr.iters == ss.iters == maxit
+        assert relw(xr, xs) <= 1e-13
+
+
 @pytest.mark.parametrize("n", [8, 64, 256, 1024])
 def test_solve_pressure_mixed_forward_error(dev, n):
     print(f"solve_pressure mixed n={n}", flush=True)

@@ -151,6 +151,8 @@ def cg_step_bytes(z_bytes, launches, first, x_in_step=True):
 def x_in_cg_step(n, mg_precision):
     """False where the library updates x in batches (float32 V-cycle, at least
     three float32 fields of (n+1) n nodes within 1 GiB)."""
+    if os.environ.get("BF_NO_RING") == "1":
+        return True
     return not (mg_precision == bf.MG_F32 and 3 * 4 * (n + 1) * n <= 2 ** 30)
 
 

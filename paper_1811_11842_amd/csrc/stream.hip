@@ -1437,7 +1437,9 @@ __global__ void __launch_bounds__(kStreamTPB) k_post(PostArgs<T, TO> P) {
 #pragma unroll
     for (int s = 0; s < RPW; ++s) {
       const int j = j0 + s;
-      if (j > jl) break;
+      // (continue, not break: with a break the compiler kept the 12-row
+      // windows of the reducing variants in scratch memory)
+      if (j > jl) continue;
       const int k = s + D * R;  // the row in the x0 / b window
       VecN<TO, 2> o;
       if constexpr (D == 1) {
@@ -1808,9 +1810,11 @@ static int small_level_rpw(int n, int dflt) {
 template <typename T>
 void stream_smooth3_resid(const OpDesc& A, const T* b, T* xout, T* r, double a0, double a1,
                           double g1, double a2, double g2, hipStream_t st) {
-  // 8 output rows per tile: the stage-two and -three halo rows are shared by
-  // more outputs (measured on the 4096^2 mixed step: 19.18 ms with 8, 19.29-19.36
-  // with 6, 19.40-19.42 with 4, 19.64 with 3)
+  // 12 output rows per tile above the small levels: the stage-two and -three
+  // halo rows are shared by more outputs (231 registers, two wavefronts per
+  // SIMD as with 8 rows at 187; with k_post at 12 rows as well the 4096^2
+  // mixed step took 9.98 ms against 10.07 with both at 8; 16 rows, 278
+  // registers, 10.23).  BF_S3R_RPW=4|8|12|16 sets the height.
   Smooth3RArgs<T> P;
   P.A = A;
   P.b = b;
@@ -1821,7 +1825,8 @@ void stream_smooth3_resid(const OpDesc& A, const T* b, T* xout, T* r, double a0,
   P.g1 = g1;
   P.a2 = a2;
   P.g2 = g2;
-  const int rpw = small_level_rpw(A.n, 8);
+  static const int rpw_env = env_int("BF_S3R_RPW", 12);
+  const int rpw = small_level_rpw(A.n, rpw_env);
   P.wstrips = (A.n + kS3RCols - 1) / kS3RCols;
   P.rgroups = (A.n + 1 + rpw - 1) / rpw;
   P.tiles = grouped_tiles(P.wstrips, P.rgroups);
@@ -1840,6 +1845,10 @@ void stream_smooth3_resid(const OpDesc& A, const T* b, T* xout, T* r, double a0,
     BF_S3R_GO(2);
   else if (rpw == 4)
     BF_S3R_GO(4);
+  else if (rpw == 12)
+    BF_S3R_GO(12);
+  else if (rpw == 16)
+    BF_S3R_GO(16);
   else
     BF_S3R_GO(8);
 #undef BF_S3R_GO
@@ -2030,7 +2039,8 @@ static int post_launch_rpw(const OpDesc& A, int degree, const T* x, const T* e, 
   return blocks;
 }
 
-// Tile rows: float64 2; float32 8 by default (BF_POST_RPW=4 or 6 selects another
+// Tile rows: float64 2; float32 12 by default above the small levels (233
+// registers for the 13-point operator; BF_POST_RPW=4, 6 or 8 selects another
 // height; the window of x0 .. x2 and b lives in registers).
 template <int EP, typename T, typename TO>
 static int post_launch(const OpDesc& A, int degree, const T* x, const T* e, const T* b,
@@ -2039,11 +2049,12 @@ static int post_launch(const OpDesc& A, int degree, const T* x, const T* e, cons
   if constexpr (sizeof(T) == 8) {
     return post_launch_rpw<EP, 2>(A, degree, x, e, b, q, out, a, g, partials, st);
   } else {
-    static const int rpw_env = env_int("BF_POST_RPW", 8);
+    static const int rpw_env = env_int("BF_POST_RPW", 12);
     const int rpw = small_level_rpw(A.n, rpw_env);
     if (rpw == 2) return post_launch_rpw<EP, 2>(A, degree, x, e, b, q, out, a, g, partials, st);
     if (rpw == 4) return post_launch_rpw<EP, 4>(A, degree, x, e, b, q, out, a, g, partials, st);
     if (rpw == 6) return post_launch_rpw<EP, 6>(A, degree, x, e, b, q, out, a, g, partials, st);
+    if (rpw == 12) return post_launch_rpw<EP, 12>(A, degree, x, e, b, q, out, a, g, partials, st);
     return post_launch_rpw<EP, 8>(A, degree, x, e, b, q, out, a, g, partials, st);
   }
 }

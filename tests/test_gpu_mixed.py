@@ -172,6 +172,30 @@ def test_batched_iterate_update_matches_per_step(dev, maxit, monkeypatch):
         assert relw(xr, xs) <= 1e-13
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_norm_read_every_k_iterations(dev, prec):
+    """check_every = 3: the host reads the residual norm (the value the
+    finalize kernel mirrors into pinned memory behind a sequence number)
+    only every third iteration and at the limit; the solve stops at the
+    first check past rtol, so it takes the plain solve's iterations rounded
+    up to a multiple of 3, and meets the same bar."""
+    n = 512
+    phi = S.initial_phi(n)
+    b = to_dev(fh.rhs_ch(phi, PRM["dt"], PRM["M"], PRM["Npoly"], PRM["chi"]), dev)
+    mg = bf.MG_F32 if prec == "f32" else bf.MG_F64
+    g = grid(n)
+    x1, x3 = g.field(0.0), g.field(0.0)
+    s1 = g.solve_ch(C_CH, b, x1, bf.default_opts(bf.OP_CH, rtol=1e-10, mg_precision=mg))
+    s3 = g.solve_ch(C_CH, b, x3, bf.default_opts(bf.OP_CH, rtol=1e-10, mg_precision=mg,
+                                                   check_every=3))
+    print(f"  {prec}: every iteration {s1.iters} it, every third {s3.iters} it")
+    assert s3.status in (bf.OK, bf.AT_FLOOR)
+    if s1.restarts == s3.restarts == 0:  # one Krylov cycle each
+        assert s3.iters % 3 == 0 and s1.iters <= s3.iters <= s1.iters + 2
+    xs = spectral.solve_ch(to_np(b).astype(np.longdouble), C_CH)
+    assert relw(to_np(x3), xs) <= 1e-10
+
+
 @pytest.mark.parametrize("n", [8, 64, 256, 1024])
 def test_solve_pressure_mixed_forward_error(dev, n):
     print(f"solve_pressure mixed n={n}", flush=True)

@@ -51,7 +51,7 @@ KERNEL_SOURCES = ["paper_1811_11842_amd/csrc/stream.hip", "paper_1811_11842_amd/
 # profiles/step_kernels_4096_counters.md for the CG step), KiB per dispatch, scaled by the ratio of known to
 # counted bytes of the bf_copy calibration kernel.  Valid only for the kernel sources
 # whose sha256 is recorded; otherwise the traffic is reported as null.
-TRAFFIC_RECORD = {"n": 4096, "fetch_scale": 1.9996, "write_scale": 1.0, "kernels": {"spmv": {"fetch_kib": 69687.1, "write_kib": 131104.1}, "smooth": {"fetch_kib": 200794.8, "write_kib": 131104.0}, "cg_step": {"fetch_kib": 103498.6, "write_kib": 202142.9}, "r_update": {"fetch_kib": 131120.5, "write_kib": 196688.1}}, "sources_sha256": "72f2dd4feafdb9e49e641d53b057d71f52d6e8a28340d3113775c3629f0d13ee"}
+TRAFFIC_RECORD = {"n": 4096, "fetch_scale": 1.9996, "write_scale": 1.0, "kernels": {"spmv": {"fetch_kib": 69688.1, "write_kib": 131104.0}, "smooth": {"fetch_kib": 200795.0, "write_kib": 131104.0}, "cg_step": {"fetch_kib": 103493.1, "write_kib": 202116.3}, "r_update": {"fetch_kib": 131120.5, "write_kib": 196688.0}}, "sources_sha256": "08fc34ec26a58f80c0ddf086b8d5b45ba38cdf257032414b5fe737d466124d13"}
 
 
 def parse():

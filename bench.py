@@ -139,7 +139,7 @@ def time_steps(g, n, steps, warmup, mg_precision):
 # z and the search directions p are float32 with the float32 V-cycle, float64
 # otherwise; q and x are float64.  The first step of a Krylov cycle reads z
 # only and writes p' and q.  With the float32 V-cycle on grids up to 8192^2 the
-# library keeps the directions of up to 8 steps and updates x in one separate
+# library keeps the directions of up to 16 steps and updates x in one separate
 # pass per batch (k_x_accum), so the step itself does not touch x.
 def cg_step_bytes(z_bytes, launches, first, x_in_step=True):
     p_bytes = z_bytes
@@ -557,7 +557,7 @@ def main():
                     n, cg_m, 4, "k_cg_ch<4,float,4> (Cahn-Hilliard CG step of the value's "
                     "steps: p' = z + beta p, q = A p' exactly rounded, <p', q>_W; z and p float32"
                     + ("; x += alpha p" if x_in_cg_step(n, bf.MG_F32) else
-                       "; x updated in batches of 8 steps by k_x_accum") + ")",
+                       "; x updated in batches of up to 16 steps by k_x_accum") + ")",
                     recorded_traffic("cg_step", n), x_in_cg_step(n, bf.MG_F32))
             if a.precision in ("both", "f64"):
                 ms_d, wall_d, st_d, fin_d, (cg_d, ru_d) = time_steps(g, n, a.steps, a.warmup,

@@ -178,7 +178,7 @@ bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
 // The float32 hierarchy and level-0 input of the mixed-precision V-cycle,
 // allocated on first use (half the bytes of the float64 one).
 // The ring of float32 search directions of CG with the float32 V-cycle: up
-// to kRing fields within 1 GiB (4096^2: 8; 8192^2: 3; none above, or when
+// to kRing fields within 1 GiB (4096^2: 16; 8192^2: 3; none above, or when
 // the allocation fails: the CG step then updates x itself).  Returns ring_m.
 int ensure_ring(bf_grid* g) {
   if (g->ring_m >= 0) return g->ring_m;

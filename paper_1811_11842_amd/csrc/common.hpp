@@ -32,12 +32,12 @@ enum Slot {
   S_GG = 12,   // initial guess: <A x0, A x0>_W
   S_GAMMA = 13,  // initial guess: its scale factor
   S_GM = 16,   // GMRES scalars start here (up to 64+ slots)
-  S_AHIST = 240,  // CG: alpha of the steps whose iterate update is pending (kRing slots)
+  S_AHIST = 224,  // CG: alpha of the steps whose iterate update is pending (kRing slots)
   S_HSEQ = 250,   // pinned host scalars only: sequence number of the last value mirrored there
   kNumSlots = 256
 };
 // Search directions of CG kept for one batched iterate update (float32 CG).
-constexpr int kRing = 8;
+constexpr int kRing = 16;
 
 enum FinalizeMode {
   F_STORE = 0,   // scal[slot] = sum

@@ -1302,6 +1302,8 @@ void launch_x_accum(int n, double* x, const float* const* p, int m, const double
     LAUNCH(k_x_accum<M_>, blocks, st, nquad, x, R, alpha); \
     break;
     BF_XACC(1) BF_XACC(2) BF_XACC(3) BF_XACC(4) BF_XACC(5) BF_XACC(6) BF_XACC(7) BF_XACC(8)
+    BF_XACC(9) BF_XACC(10) BF_XACC(11) BF_XACC(12) BF_XACC(13) BF_XACC(14) BF_XACC(15)
+    BF_XACC(16)
 #undef BF_XACC
     default:
       break;

@@ -51,7 +51,7 @@ KERNEL_SOURCES = ["paper_1811_11842_amd/csrc/stream.hip", "paper_1811_11842_amd/
 # profiles/step_kernels_4096_counters.md for the CG step), KiB per dispatch, scaled by the ratio of known to
 # counted bytes of the bf_copy calibration kernel.  Valid only for the kernel sources
 # whose sha256 is recorded; otherwise the traffic is reported as null.
-TRAFFIC_RECORD = {"n": 4096, "fetch_scale": 1.9996, "write_scale": 1.0, "kernels": {"spmv": {"fetch_kib": 69688.1, "write_kib": 131104.0}, "smooth": {"fetch_kib": 200795.0, "write_kib": 131104.0}, "cg_step": {"fetch_kib": 103493.1, "write_kib": 202116.3}, "r_update": {"fetch_kib": 131120.5, "write_kib": 196688.0}}, "sources_sha256": "08fc34ec26a58f80c0ddf086b8d5b45ba38cdf257032414b5fe737d466124d13"}
+TRAFFIC_RECORD = {"n": 4096, "fetch_scale": 1.9996, "write_scale": 1.0, "kernels": {"spmv": {"fetch_kib": 69688.0, "write_kib": 131104.0}, "smooth": {"fetch_kib": 200794.4, "write_kib": 131104.0}, "cg_step": {"fetch_kib": 103494.7, "write_kib": 202005.7}, "r_update": {"fetch_kib": 131120.5, "write_kib": 196688.1}}, "sources_sha256": "0b674dcfa35ae61826fa492e474ab23a78ca3361c59ee3d611f60eaac372ee6d"}
 
 
 def parse():

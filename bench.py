@@ -88,8 +88,10 @@ def log(msg):
 # so the step meets the 1e-10 forward-error bar on p as it does on phi.
 PRESSURE_RTOL = 1e-12
 
-# The live timing of the CG step records HIP events around every 4th launch.
-CG_TIMING_EVERY = 4
+# The live timing of the CG step and the residual update records HIP events
+# around every 8th launch (each event leaves the stream idle for a few
+# microseconds; 20 steps give about 34 samples of each kernel).
+CG_TIMING_EVERY = 8
 
 
 def time_steps(g, n, steps, warmup, mg_precision):
@@ -113,8 +115,6 @@ def time_steps(g, n, steps, warmup, mg_precision):
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     stats = []
-    # HIP events on the grid's stream around every 4th CG-step launch (each
-    # event leaves the stream idle for a few microseconds)
     g.cg_timing(CG_TIMING_EVERY)
     t0 = time.perf_counter()
     e0.record()

@@ -422,7 +422,9 @@ int bf_grid_cg_timing_read(bf_grid* g, double* total_ms, int64_t* launches,
  * the partials of ||r||_W^2 and, with the float32 V-cycle, the float32 copy
  * of r), recorded while bf_grid_cg_timing is on: synchronises the grid's
  * stream, returns the summed duration in ms and the number of recorded
- * launches, and clears that record.  Outputs may be NULL. */
+ * launches, and clears that record.  Outputs may be NULL.  Each record (two
+ * pooled events per recorded launch) grows until its read function, or
+ * bf_grid_cg_timing with enable > 0, clears it. */
 int bf_grid_rupdate_timing_read(bf_grid* g, double* total_ms, int64_t* launches);
 
 /* Message of the last failure on this thread ("" if none). */
